@@ -20,7 +20,8 @@
 //   * a batch whose new keys exceed the free indices c - t fails as a whole and
 //     leaves the map unchanged, unless auto-growth is asked for, in which case
 //     c is doubled until it fits (the x2 rule of Sec. 4.5);
-//   * rehash keeps every live index (h' = h[0..c) followed by c..c'-1);
+//   * rehash grows c to c' >= c and keeps every live index (h' = h[0..c)
+//     followed by c..c'-1); c' = c only rebuilds the table;
 //   * voxelize divides in binary32 and floors toward -infinity (Listing 1 of
 //     Sec. 6.1 computes floor(xyz / voxel_size) in float32).
 #include "ash_oracle.h"
@@ -82,7 +83,9 @@ int oracle_create(int64_t capacity, int32_t key_dim, int32_t n_values,
 void oracle_destroy(oracle_map* m) { delete m; }
 
 int oracle_rehash(oracle_map* m, int64_t new_capacity) {
-  if (new_capacity < (int64_t)m->M.size()) return ORACLE_E_INVALID;
+  // Growth only: live indices may sit anywhere below c, so keeping them
+  // rules out a smaller capacity.
+  if (new_capacity < m->c) return ORACLE_E_INVALID;
   // Keys, values and flags keep their indices; indices c..c'-1 are appended
   // to the heap below the old contents.
   m->kB.resize(new_capacity * m->key_dim, 0);

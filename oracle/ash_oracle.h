@@ -68,7 +68,7 @@ int oracle_erase(oracle_map* m, const int32_t* keys, int64_t n,
                  uint8_t* out_mask);
 /* Writes the live buffer indices in ascending order; returns their count. */
 int64_t oracle_active_indices(const oracle_map* m, int32_t* out_idx);
-/* new_capacity >= size; indices of live entries are kept. */
+/* new_capacity >= capacity; indices of live entries are kept. */
 int oracle_rehash(oracle_map* m, int64_t new_capacity);
 
 int64_t oracle_size(const oracle_map* m);

@@ -225,7 +225,7 @@ def test_rehash_keeps_indices_and_values():
     kb0 = m.key_buffer()
     vb0 = m.value_buffer(0)
     h0, t0 = m.heap(), m.heap_top
-    assert m.rehash(m.size - 1) != ORACLE_OK
+    assert m.rehash(m.size - 1) != ORACLE_OK and m.rehash(599) != ORACLE_OK
     assert m.rehash(1500) == ORACLE_OK
     assert m.capacity == 1500 and m.heap_top == t0
     assert np.array_equal(m.find(keys)[1], idx0)
