@@ -1,0 +1,209 @@
+/*
+ * ash.h -- C ABI of the MI355X (gfx950) spatial hash map.
+ *
+ * The operations follow ASH (Dong, Lao, Kaess, Koltun, "ASH: A Modern Framework
+ * for Parallel Spatial Hashing in 3D Perception", arXiv 2110.00511):
+ *   - keys live in a key buffer k^B and values in value buffers {v^B_j} of
+ *     capacity c; every call returns buffer indices and masks instead of
+ *     pointers to pairs, so callers chain tensor ops by advanced indexing
+ *     (Sec. 3 and Sec. 4.2, masked index-first query);
+ *   - buffer indices come from an index heap h whose top t rises on
+ *     allocation and falls on free (Sec. 4.3);
+ *   - insert is lazy: a key that is already present changes nothing, values
+ *     are copied only for the keys that are actually inserted (Sec. 4.3.1);
+ *   - activate inserts keys only, leaving their value rows to the caller
+ *     (Sec. 5.1);
+ *   - multi-value maps and hash sets (n_values = 0) (Sec. 4.7);
+ *   - rehash grows the buffers, x2 for auto-growth (Sec. 4.5);
+ *   - voxelize turns points into floor(p / voxel) keys and keeps one entry per
+ *     voxel with a hash-set insertion (Sec. 6.1, Listing 1).
+ *
+ * Conventions shared by every entry point:
+ *   - Pointers to keys, values, points and per-position outputs are DEVICE
+ *     pointers owned by the caller.  Arrays of value-buffer pointers
+ *     (values / out_values) are HOST arrays of n_values device pointers.
+ *     out_idx / out_mask may be NULL to skip that output.
+ *   - keys: n rows of key_dim int32 words, row-major; any int32 value is a
+ *     legal key word.  Each value buffer j holds rows of
+ *     value_elems[j] * sizeof(value_dtypes[j]) bytes, copied as raw bytes.
+ *   - Per-position results: out_idx[p] is the buffer index (int32) or -1,
+ *     out_mask[p] is 1 or 0 (uint8).
+ *   - In-batch duplicates are resolved deterministically: the lowest batch
+ *     position wins.  Indices are handed out in batch order from the heap
+ *     top, so results are independent of thread timing.
+ *   - Calls are asynchronous and ordered on `stream` (a hipStream_t, NULL =
+ *     the null stream) unless marked "synchronizes".  A map must not be used
+ *     from two streams at once.
+ *   - Host-detected errors (NULL pointers, bad sizes, n >= 2^31 - 3, allocator
+ *     failure) return immediately; nothing is launched and outputs are
+ *     untouched.
+ *   - A batch whose new keys exceed the free indices c - t is detected on the
+ *     device: the map is left bit-for-bit unchanged, outputs are idx -1 /
+ *     mask 0, and ash_device_status() reports ASH_E_CAPACITY.  With
+ *     ASH_F_AUTOGROW the map instead grows to the smallest c * 2^k that fits
+ *     (this path synchronizes).
+ *   - The map owns k^B, v^B, h, the slot table and its bookkeeping, all
+ *     obtained from the allocator given at creation (hipMalloc if NULL).
+ */
+#ifndef ASH_H
+#define ASH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ash_map* ash_map_t;
+
+typedef enum {
+  ASH_OK = 0,
+  ASH_E_INVALID = 1,     /* bad argument */
+  ASH_E_CAPACITY = 2,    /* not enough free buffer indices / table slots */
+  ASH_E_NOMEM = 3,       /* allocator returned NULL */
+  ASH_E_DEVICE = 4,      /* a HIP runtime call failed */
+  ASH_E_UNSUPPORTED = 5  /* size or tuning outside what the kernels handle */
+} ash_status_t;
+
+/* Value element types; values are moved as raw bytes, the type only sets the
+ * element size. */
+typedef enum {
+  ASH_U8 = 0, ASH_I32 = 1, ASH_F32 = 2, ASH_I64 = 3, ASH_F64 = 4, ASH_F16 = 5, ASH_BF16 = 6
+} ash_dtype_t;
+
+/* Device-memory provider.  alloc returns a device pointer of at least `bytes`
+ * bytes usable on `stream` (NULL on failure); free releases it after the work
+ * already queued on `stream`. */
+typedef struct {
+  void* (*alloc)(void* ctx, size_t bytes, void* stream);
+  void (*free)(void* ctx, void* ptr, void* stream);
+  void* ctx;
+} ash_allocator_t;
+
+#define ASH_F_AUTOGROW 1u
+
+/* Table tuning.  bucket_width W (1..64, power of two) aligns a key's home slot;
+ * probe_group g (4, 8, 16, 32 or 64) is the number of wavefront lanes that probe
+ * one key together, each reading one slot of a g-slot window; max_load in
+ * [0.1, 0.9] sets slots = ceil(capacity / max_load) rounded up to a multiple of
+ * W and g.  NULL tuning means W = 4, g = 4, max_load = 0.5, flags = 0. */
+typedef struct {
+  int32_t bucket_width;
+  int32_t probe_group;
+  float max_load;
+  uint32_t flags;
+} ash_tuning_t;
+
+/* Occupancy snapshot (synchronizes). */
+typedef struct {
+  int64_t size;        /* live keys = heap top t */
+  int64_t capacity;    /* c */
+  int64_t slots;       /* table slots */
+  int64_t used_slots;  /* live + tombstones */
+  int64_t tombstones;
+} ash_stats_t;
+
+/* Creates an empty map (Sec. 4.3: h = 0..c-1, t = 0).  capacity in
+ * [0, 2^31 - 3]; key_dim in [1, 4]; n_values in [0, 8]; value_elems[j] > 0.
+ * Synchronizes `stream` once the buffers are initialised. */
+ash_status_t ash_create(int64_t capacity, int32_t key_dim, int32_t n_values,
+                        const ash_dtype_t* value_dtypes, const int64_t* value_elems,
+                        const ash_allocator_t* allocator, const ash_tuning_t* tuning,
+                        void* stream, ash_map_t* out);
+ash_status_t ash_destroy(ash_map_t map);
+
+/* Lazy insertion (Sec. 4.3.1): for each new key (first occurrence in batch
+ * order) i = h[t], t += 1, k^B[i] = key, v^B_j[i] = values[j][p]; out_idx[p] =
+ * i and out_mask[p] = 1.  Keys already present and later duplicates: -1 / 0,
+ * nothing stored.  values: host array of n_values device pointers, each to n
+ * rows. */
+ash_status_t ash_insert(ash_map_t map, const int32_t* keys, int64_t n,
+                        const void* const* values, int32_t* out_idx,
+                        uint8_t* out_mask, void* stream);
+
+/* Activation (Sec. 5.1): insert without touching value rows. */
+ash_status_t ash_activate(ash_map_t map, const int32_t* keys, int64_t n,
+                          int32_t* out_idx, uint8_t* out_mask, void* stream);
+
+/* Masked query (Sec. 4.2): out_idx[p] = i with k^B[i] = key and mask 1, or -1
+ * / 0 on a miss.  out_values (nullable host array of n_values device pointers
+ * to n rows each) receives v^B_j[i] for hits; rows of misses are untouched. */
+ash_status_t ash_find(ash_map_t map, const int32_t* keys, int64_t n,
+                      int32_t* out_idx, uint8_t* out_mask,
+                      void* const* out_values, void* stream);
+
+/* Erase (Sec. 4.3: t falls on free): each present key (first occurrence in
+ * batch order) is removed and its index pushed back, t -= 1, h[t] = i, in batch
+ * order; out_mask[p] = 1 for those positions, 0 otherwise. */
+ash_status_t ash_erase(ash_map_t map, const int32_t* keys, int64_t n,
+                       uint8_t* out_mask, void* stream);
+
+/* Live buffer indices in ascending order (the active set gathered for
+ * rehashing, Sec. 4.5).  out_idx is a device array of at least `size`
+ * entries; *out_count (host) receives the count.  Synchronizes. */
+ash_status_t ash_active_indices(ash_map_t map, int32_t* out_idx,
+                                int64_t* out_count, void* stream);
+
+/* Rehash (Sec. 4.5) to new_capacity >= c: buffers grow, live indices and
+ * their rows are kept, h' = h[0..c) followed by c..c'-1, and the slot table is
+ * rebuilt without tombstones.  new_capacity == c only cleans the table;
+ * new_capacity < c is ASH_E_INVALID (live indices may lie anywhere below c).
+ * Buffer pointers obtained earlier become invalid.  Synchronizes. */
+ash_status_t ash_rehash(ash_map_t map, int64_t new_capacity, void* stream);
+
+/* Empties the map (state of a fresh ash_create) without reallocating. */
+ash_status_t ash_clear(ash_map_t map, void* stream);
+
+/* Live key count t (synchronizes) and capacity c (host-side, no sync). */
+ash_status_t ash_size(ash_map_t map, int64_t* out, void* stream);
+ash_status_t ash_capacity(ash_map_t map, int64_t* out);
+ash_status_t ash_stats(ash_map_t map, ash_stats_t* out, void* stream);
+
+/* Borrowed device pointers to k^B ([c][key_dim] int32), v^B_j ([c][row]) and
+ * the index heap h ([c] int32), valid until rehash / auto-growth / destroy
+ * (Sec. 4.2: the buffers are exposed for direct access and in-place use). */
+ash_status_t ash_key_buffer(ash_map_t map, int32_t** out);
+ash_status_t ash_value_buffer(ash_map_t map, int32_t j, void** out);
+ash_status_t ash_heap_buffer(ash_map_t map, int32_t** out);
+
+/* Returns and clears the sticky device-side error (ASH_E_CAPACITY after an
+ * overflowing batch).  Synchronizes. */
+ash_status_t ash_device_status(ash_map_t map, void* stream);
+
+/* Voxelization (Sec. 6.1, Listing 1).  points: n * 3 float32 (device).  For
+ * each point and axis, q = p / voxel in IEEE binary32 (correctly rounded
+ * division) and key = floor(q); a point whose q is not finite or whose floor
+ * lies outside int32 is rejected (out_point_voxel = -1).  Voxel ids are the
+ * ranks of first occurrence among accepted points.  Outputs (device):
+ * out_point_voxel[n], out_voxel_keys[n][3] and out_voxel_counts[n], of which
+ * the first *out_n_voxels rows are written.  *out_n_voxels is a host int64.
+ * voxel > 0 and finite.  Workspace comes from `allocator` (hipMalloc if NULL).
+ * Synchronizes. */
+ash_status_t ash_voxelize(const float* points, int64_t n, float voxel,
+                          int32_t* out_point_voxel, int32_t* out_voxel_keys,
+                          int32_t* out_voxel_counts, int64_t* out_n_voxels,
+                          const ash_allocator_t* allocator, void* stream);
+
+/* Per-kernel timing of one map (instrumentation).  While enabled, every
+ * kernel the map launches is bracketed by HIP events recorded on the launch
+ * stream.  ash_profile_collect synchronizes, writes up to max_entries
+ * aggregated records (kernel name, launches, summed milliseconds) and
+ * clears the records. */
+typedef struct {
+  char name[32];
+  int64_t launches;
+  double total_ms;
+} ash_kernel_time_t;
+
+ash_status_t ash_profile_enable(ash_map_t map, int32_t enable);
+ash_status_t ash_profile_collect(ash_map_t map, ash_kernel_time_t* out, int32_t max_entries,
+                                 int32_t* n_entries, void* stream);
+
+const char* ash_status_string(ash_status_t status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ASH_H */

@@ -1,0 +1,128 @@
+"""ctypes binding of libash.so with the C-ABI names of include/ash.h.
+
+Argument marshalling only: every step runs in the library's HIP kernels.
+torch must be imported first so that the library binds to the HIP runtime
+torch already loaded (one runtime per process).  Loading fails loudly when
+libash.so has not been built; there is no fallback path.
+"""
+import ctypes
+import os
+
+import torch  # noqa: F401  (loads the HIP runtime the library binds to)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libash.so")
+
+ASH_OK = 0
+ASH_E_INVALID = 1
+ASH_E_CAPACITY = 2
+ASH_E_NOMEM = 3
+ASH_E_DEVICE = 4
+ASH_E_UNSUPPORTED = 5
+ASH_F_AUTOGROW = 1
+
+ASH_U8, ASH_I32, ASH_F32, ASH_I64, ASH_F64, ASH_F16, ASH_BF16 = range(7)
+
+# Functions declared in include/ash.h: name -> (restype, argtypes)
+P = ctypes.c_void_p
+I32 = ctypes.c_int32
+I64 = ctypes.c_int64
+ST = ctypes.c_int
+
+
+class AshAllocator(ctypes.Structure):
+    _fields_ = [("alloc", ctypes.CFUNCTYPE(P, P, ctypes.c_size_t, P)),
+                ("free", ctypes.CFUNCTYPE(None, P, P, P)),
+                ("ctx", P)]
+
+
+class AshTuning(ctypes.Structure):
+    _fields_ = [("bucket_width", I32), ("probe_group", I32), ("max_load", ctypes.c_float), ("flags", ctypes.c_uint32)]
+
+
+class AshKernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", I64), ("total_ms", ctypes.c_double)]
+
+
+class AshStats(ctypes.Structure):
+    _fields_ = [("size", I64), ("capacity", I64), ("slots", I64), ("used_slots", I64), ("tombstones", I64)]
+
+
+SIGNATURES = {
+    "ash_create": (ST, [I64, I32, I32, P, P, P, P, P, ctypes.POINTER(P)]),
+    "ash_destroy": (ST, [P]),
+    "ash_insert": (ST, [P, P, I64, P, P, P, P]),
+    "ash_activate": (ST, [P, P, I64, P, P, P]),
+    "ash_find": (ST, [P, P, I64, P, P, P, P]),
+    "ash_erase": (ST, [P, P, I64, P, P]),
+    "ash_active_indices": (ST, [P, P, ctypes.POINTER(I64), P]),
+    "ash_rehash": (ST, [P, I64, P]),
+    "ash_clear": (ST, [P, P]),
+    "ash_size": (ST, [P, ctypes.POINTER(I64), P]),
+    "ash_capacity": (ST, [P, ctypes.POINTER(I64)]),
+    "ash_stats": (ST, [P, ctypes.POINTER(AshStats), P]),
+    "ash_key_buffer": (ST, [P, ctypes.POINTER(P)]),
+    "ash_value_buffer": (ST, [P, I32, ctypes.POINTER(P)]),
+    "ash_heap_buffer": (ST, [P, ctypes.POINTER(P)]),
+    "ash_device_status": (ST, [P, P]),
+    "ash_voxelize": (ST, [P, I64, ctypes.c_float, P, P, P, ctypes.POINTER(I64), P, P]),
+    "ash_profile_enable": (ST, [P, I32]),
+    "ash_profile_collect": (ST, [P, ctypes.POINTER(AshKernelTime), I32, ctypes.POINTER(I32), P]),
+    "ash_status_string": (ctypes.c_char_p, [ST]),
+}
+
+_lib = None
+
+
+def load(path=LIB_PATH):
+    """Loads libash.so (raises if it is missing) and declares every symbol."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2110_00511_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class AshError(RuntimeError):
+    def __init__(self, status, what):
+        self.status = status
+        msg = load().ash_status_string(status).decode()
+        super().__init__(f"{what}: {msg} (status {status})")
+
+
+def check(status, what):
+    if status != ASH_OK:
+        raise AshError(status, what)
+
+
+class TorchAllocator:
+    """Routes the library's device allocations to torch's caching allocator.
+
+    Each allocation is a uint8 tensor kept alive in `blocks` until the library
+    frees it, so map-owned buffers can be viewed as tensors without copies."""
+
+    def __init__(self, device):
+        self.device = torch.device(device)
+        self.blocks = {}
+        self._alloc = AshAllocator._fields_[0][1](self._do_alloc)
+        self._free = AshAllocator._fields_[1][1](self._do_free)
+        self.struct = AshAllocator(self._alloc, self._free, None)
+
+    def _do_alloc(self, ctx, nbytes, stream):
+        t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        ptr = t.data_ptr()
+        self.blocks[ptr] = t
+        return ptr
+
+    def _do_free(self, ctx, ptr, stream):
+        self.blocks.pop(ptr, None)
+
+    def tensor(self, ptr):
+        return self.blocks[ptr]

@@ -1,0 +1,725 @@
+// ash_api.hip -- host side of the C ABI declared in include/ash.h: argument
+// checks, buffer ownership, capacity policy and launch sequencing.  Every
+// step of every operation runs in the kernels of ash_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "ash.h"
+#include "ash_device.hpp"
+#include "ash_launch.hpp"
+
+using ash::Meta;
+using ash::TableRef;
+using ash::ValueSet;
+
+namespace {
+
+constexpr int64_t kMaxCount = (1ll << 31) - 3;  // positions and indices must fit PENDING(p)
+constexpr uint64_t kMaxSlots = (1ull << 32) - 128;
+
+#define ASH_HIP(call)                           \
+  do {                                          \
+    if ((call) != hipSuccess) return ASH_E_DEVICE; \
+  } while (0)
+
+#define ASH_TRY(call)                 \
+  do {                                \
+    ash_status_t st__ = (call);       \
+    if (st__ != ASH_OK) return st__;  \
+  } while (0)
+
+size_t dtype_size(ash_dtype_t t) {
+  switch (t) {
+    case ASH_U8: return 1;
+    case ASH_I32: case ASH_F32: return 4;
+    case ASH_I64: case ASH_F64: return 8;
+    case ASH_F16: case ASH_BF16: return 2;
+    default: return 0;
+  }
+}
+
+bool pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+
+struct DevMem {
+  ash_allocator_t a;
+  bool custom;
+  void* get(size_t bytes, hipStream_t st) {
+    bytes = std::max<size_t>(bytes, 256);
+    if (custom) return a.alloc(a.ctx, bytes, st);
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    return p;
+  }
+  void put(void* p, hipStream_t st) {
+    if (!p) return;
+    if (custom) {
+      a.free(a.ctx, p, st);
+    } else {
+      (void)hipStreamSynchronize(st);
+      (void)hipFree(p);
+    }
+  }
+};
+
+// Largest copy unit (16, 8, 4, 2, 1 bytes) dividing the row size and the
+// alignment of both base pointers.
+uint32_t copy_unit(uint32_t row_bytes, const void* a, const void* b) {
+  uintptr_t m = (uintptr_t)a | (uintptr_t)b | row_bytes;
+  for (uint32_t v = 16; v > 1; v >>= 1)
+    if ((m & (v - 1)) == 0) return v;
+  return 1;
+}
+
+uint32_t units_log2(uint32_t row_bytes, uint32_t vec) {
+  uint32_t u = row_bytes / vec;
+  if (!pow2(u)) return 0xFFu;
+  uint32_t l = 0;
+  while ((1u << l) < u) ++l;
+  return l;
+}
+
+// Event records of ash_profile_enable: one (start, stop) pair per launch.
+struct ProfRec {
+  const char* name;
+  hipEvent_t start, stop;
+};
+
+struct Prof {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<ProfRec> recs;
+  hipEvent_t next() {
+    if (used == pool.size()) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+};
+
+}  // namespace
+
+struct ash_map {
+  DevMem mem;
+  Prof prof;
+  int64_t c = 0;
+  int key_dim = 3;
+  int n_values = 0;
+  std::vector<uint32_t> row_bytes;
+  int W = 4, G = 4;
+  float max_load = 0.5f;
+  uint32_t flags = 0;
+  // device state
+  uint32_t* table = nullptr;
+  uint32_t nslots = 0;
+  int32_t* kB = nullptr;
+  std::vector<uint8_t*> vB;
+  int32_t* heap = nullptr;
+  uint8_t* active = nullptr;
+  int32_t* owner = nullptr;
+  Meta* meta = nullptr;
+  // per-call scratch
+  uint32_t* slot_of = nullptr;
+  int32_t* aux = nullptr;
+  int64_t scratch_n = 0;
+  uint64_t* scan_status = nullptr;
+  int64_t scan_tiles = 0;
+  // host-side upper bounds (exact after any synchronizing call)
+  int64_t live_ub = 0;
+  int64_t used_ub = 0;
+
+  int slot_words() const { return key_dim == 1 ? 2 : (key_dim <= 3 ? 4 : 8); }
+
+  TableRef ref() const {
+    TableRef r;
+    r.words = table;
+    r.nslots = nslots;
+    r.bucket_width = (uint32_t)W;
+    r.nbuckets = nslots / (uint32_t)W;
+    r.max_windows = nslots / (uint32_t)G + 1;
+    return r;
+  }
+};
+
+namespace {
+
+// Slots for a capacity: ceil(c / max_load) rounded up to the larger of W and
+// G (both powers of two), at least 64.
+ash_status_t slots_for(int64_t c, float max_load, int W, int G, uint32_t* out) {
+  const uint64_t unit = (uint64_t)std::max(W, G);
+  double want = std::ceil((double)c / (double)max_load);
+  uint64_t s = std::max<uint64_t>((uint64_t)want, 64);
+  s = (s + unit - 1) / unit * unit;
+  if (s > kMaxSlots) return ASH_E_UNSUPPORTED;
+  *out = (uint32_t)s;
+  return ASH_OK;
+}
+
+// Runs one launch, bracketed by events when profiling is on.
+template <typename F>
+hipError_t timed(ash_map* m, const char* name, hipStream_t st, F&& launch) {
+  if (!m->prof.on) return launch();
+  hipEvent_t a = m->prof.next(), b = m->prof.next();
+  if (!a || !b) return hipErrorOutOfMemory;
+  hipError_t e = hipEventRecord(a, st);
+  if (e != hipSuccess) return e;
+  e = launch();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(b, st);
+  m->prof.recs.push_back({name, a, b});
+  return e;
+}
+
+ash_status_t read_meta(ash_map* m, Meta* out, hipStream_t st) {
+  ASH_HIP(hipMemcpyAsync(out, m->meta, sizeof(Meta), hipMemcpyDeviceToHost, st));
+  ASH_HIP(hipStreamSynchronize(st));
+  m->live_ub = out->t;
+  m->used_ub = out->used;
+  return ASH_OK;
+}
+
+ash_status_t ensure_scratch(ash_map* m, int64_t n, hipStream_t st) {
+  if (n > m->scratch_n) {
+    m->mem.put(m->slot_of, st);
+    m->mem.put(m->aux, st);
+    m->slot_of = (uint32_t*)m->mem.get((size_t)n * 4, st);
+    m->aux = (int32_t*)m->mem.get((size_t)n * 4, st);
+    if (!m->slot_of || !m->aux) {
+      m->scratch_n = 0;
+      return ASH_E_NOMEM;
+    }
+    m->scratch_n = n;
+  }
+  const int64_t tiles = (std::max(n, m->c) + ash::kScanTile - 1) / ash::kScanTile + 1;
+  if (tiles > m->scan_tiles) {
+    m->mem.put(m->scan_status, st);
+    m->scan_status = (uint64_t*)m->mem.get((size_t)tiles * 8, st);
+    if (!m->scan_status) {
+      m->scan_tiles = 0;
+      return ASH_E_NOMEM;
+    }
+    ASH_HIP(ash::launch_fill_u32((uint32_t*)m->scan_status, 0u, (size_t)tiles * 2, st));
+    m->scan_tiles = tiles;
+  }
+  return ASH_OK;
+}
+
+void free_buffers(ash_map* m, hipStream_t st) {
+  m->mem.put(m->table, st);
+  m->mem.put(m->kB, st);
+  for (uint8_t* p : m->vB) m->mem.put(p, st);
+  m->mem.put(m->heap, st);
+  m->mem.put(m->active, st);
+  m->mem.put(m->owner, st);
+  m->table = nullptr;
+  m->kB = nullptr;
+  m->vB.assign(m->vB.size(), nullptr);
+  m->heap = nullptr;
+  m->active = nullptr;
+  m->owner = nullptr;
+}
+
+// Rebuilds the slot table of `m` (new slot array, tombstones dropped) from the
+// key buffer and the active flags, sized for max(c, room_for) keys.
+ash_status_t rebuild_table(ash_map* m, int64_t live, hipStream_t st, int64_t room_for = 0) {
+  uint32_t nslots;
+  ASH_TRY(slots_for(std::max(m->c, room_for), m->max_load, m->W, m->G, &nslots));
+  uint32_t* fresh = (uint32_t*)m->mem.get((size_t)nslots * m->slot_words() * 4, st);
+  if (!fresh) return ASH_E_NOMEM;
+  ASH_HIP(ash::launch_fill_u32(fresh, ash::kEmpty, (size_t)nslots * m->slot_words(), st));
+  m->mem.put(m->table, st);
+  m->table = fresh;
+  m->nslots = nslots;
+  if (m->c > 0) ASH_HIP(timed(m, "rebuild", st, [&] { return ash::launch_rebuild(m->key_dim, m->G, m->ref(), m->kB, m->active, (uint32_t)m->c, m->meta, st); }));
+  ASH_HIP(timed(m, "finalize", st, [&] { return ash::launch_finalize(m->meta, (uint32_t)m->c, ash::kFinalizeRebuild, 0, m->scan_status, 0, st); }));
+  // live keys now occupy exactly `live` slots and there are no tombstones
+  Meta h;
+  ASH_TRY(read_meta(m, &h, st));
+  h.used = (uint32_t)live;
+  h.tombs = 0;
+  ASH_HIP(hipMemcpyAsync(m->meta, &h, sizeof(Meta), hipMemcpyHostToDevice, st));
+  ASH_HIP(hipStreamSynchronize(st));
+  m->used_ub = live;
+  return (h.status & ash::kStatusTableFull) ? ASH_E_CAPACITY : ASH_OK;
+}
+
+ash_status_t grow(ash_map* m, int64_t new_c, hipStream_t st) {
+  Meta h;
+  ASH_TRY(read_meta(m, &h, st));
+  const int64_t live = h.t;
+  if (new_c < m->c) return ASH_E_INVALID;
+  if (new_c > kMaxCount) return ASH_E_UNSUPPORTED;
+  if (new_c != m->c) {
+    uint32_t probe_slots;
+    ASH_TRY(slots_for(new_c, m->max_load, m->W, m->G, &probe_slots));
+    const int64_t keep = m->c;
+    int32_t* kB = (int32_t*)m->mem.get((size_t)new_c * m->key_dim * 4, st);
+    int32_t* heap = (int32_t*)m->mem.get((size_t)new_c * 4, st);
+    uint8_t* active = (uint8_t*)m->mem.get((size_t)new_c, st);
+    int32_t* owner = (int32_t*)m->mem.get((size_t)new_c * 4, st);
+    std::vector<uint8_t*> vB(m->n_values, nullptr);
+    bool ok = kB && heap && active && owner;
+    for (int j = 0; j < m->n_values && ok; ++j) {
+      vB[j] = (uint8_t*)m->mem.get((size_t)new_c * m->row_bytes[j], st);
+      ok = vB[j] != nullptr;
+    }
+    if (!ok) {
+      m->mem.put(kB, st);
+      m->mem.put(heap, st);
+      m->mem.put(active, st);
+      m->mem.put(owner, st);
+      for (uint8_t* p : vB) m->mem.put(p, st);
+      return ASH_E_NOMEM;
+    }
+    // Live indices are < c and keep their rows; the heap keeps its contents
+    // and receives c .. new_c-1 above them (h' = h ++ [c, c')).
+    if (keep > 0) {
+      ASH_HIP(hipMemcpyAsync(kB, m->kB, (size_t)keep * m->key_dim * 4, hipMemcpyDeviceToDevice, st));
+      ASH_HIP(hipMemcpyAsync(heap, m->heap, (size_t)keep * 4, hipMemcpyDeviceToDevice, st));
+      ASH_HIP(hipMemcpyAsync(active, m->active, (size_t)keep, hipMemcpyDeviceToDevice, st));
+      for (int j = 0; j < m->n_values; ++j)
+        ASH_HIP(hipMemcpyAsync(vB[j], m->vB[j], (size_t)keep * m->row_bytes[j], hipMemcpyDeviceToDevice, st));
+    }
+    if (new_c > keep) {
+      ASH_HIP(ash::launch_iota(heap, (uint32_t)keep, (uint32_t)new_c, st));
+      ASH_HIP(hipMemsetAsync(active + keep, 0, (size_t)(new_c - keep), st));
+    }
+    ASH_HIP(ash::launch_fill_u32((uint32_t*)owner, 0x7FFFFFFFu, (size_t)new_c, st));
+    m->mem.put(m->kB, st);
+    m->mem.put(m->heap, st);
+    m->mem.put(m->active, st);
+    m->mem.put(m->owner, st);
+    for (uint8_t* p : m->vB) m->mem.put(p, st);
+    m->kB = kB;
+    m->heap = heap;
+    m->active = active;
+    m->owner = owner;
+    m->vB = vB;
+    m->c = new_c;
+    ASH_TRY(ensure_scratch(m, 0, st));
+  }
+  return rebuild_table(m, live, st);
+}
+
+// Keeps probe sequences short under erase churn: when the slots that may be
+// in use after this insert could pass halfway between the live limit and a
+// full table, count them exactly and, if needed, rebuild without tombstones.
+ash_status_t maybe_clean(ash_map* m, int64_t n, hipStream_t st) {
+  const int64_t limit = m->c + ((int64_t)m->nslots - m->c) / 2;
+  if (m->used_ub + std::min(n, m->c) <= limit) return ASH_OK;
+  Meta h;
+  ASH_TRY(read_meta(m, &h, st));
+  if ((int64_t)h.used + std::min<int64_t>(n, m->c - h.t) <= limit) return ASH_OK;
+  return rebuild_table(m, h.t, st);
+}
+
+ash_status_t check_keys(ash_map* m, const int32_t* keys, int64_t n) {
+  if (!m) return ASH_E_INVALID;
+  if (n < 0 || n > kMaxCount) return ASH_E_INVALID;
+  if (n > 0 && !keys) return ASH_E_INVALID;
+  return ASH_OK;
+}
+
+ValueSet make_values(const ash_map* m, const void* const* src, void* const* dst, bool to_buffer) {
+  ValueSet vs;
+  std::memset(&vs, 0, sizeof(vs));
+  vs.n = m->n_values;
+  for (int j = 0; j < m->n_values; ++j) {
+    const uint8_t* s = to_buffer ? (const uint8_t*)src[j] : m->vB[j];
+    uint8_t* d = to_buffer ? m->vB[j] : (uint8_t*)dst[j];
+    vs.src[j] = s;
+    vs.dst[j] = d;
+    vs.row_bytes[j] = m->row_bytes[j];
+    vs.vec[j] = copy_unit(m->row_bytes[j], s, d);
+    vs.units_log2[j] = units_log2(m->row_bytes[j], vs.vec[j]);
+  }
+  return vs;
+}
+
+ash_status_t insert_impl(ash_map* m, const int32_t* keys, int64_t n, const void* const* values, int32_t* out_idx,
+                         uint8_t* out_mask, hipStream_t st) {
+  ASH_TRY(check_keys(m, keys, n));
+  if (n == 0) return ASH_OK;
+  if (values) {
+    for (int j = 0; j < m->n_values; ++j)
+      if (!values[j]) return ASH_E_INVALID;
+  }
+  ValueSet vs;
+  std::memset(&vs, 0, sizeof(vs));
+  if (values && m->n_values > 0) vs = make_values(m, values, nullptr, true);
+  ASH_TRY(ensure_scratch(m, n, st));
+  ASH_TRY(maybe_clean(m, n, st));
+  const uint32_t un = (uint32_t)n;
+  const uint32_t last_tile = (un + ash::kScanTile - 1) / ash::kScanTile - 1;
+  if ((m->flags & ASH_F_AUTOGROW) && m->live_ub + n > m->c) {
+    Meta h;
+    ASH_TRY(read_meta(m, &h, st));
+    if ((int64_t)h.t + n > m->c) {
+      // The counting claim below must not run out of slots: give the table
+      // room for every position of the batch first.
+      if ((int64_t)h.used + n > (int64_t)m->c + ((int64_t)m->nslots - m->c) / 2)
+        ASH_TRY(rebuild_table(m, h.t, st, (int64_t)h.t + n));
+      ASH_HIP(timed(m, "claim", st, [&] { return ash::launch_claim(m->key_dim, m->G, m->ref(), keys, un, m->slot_of, m->meta, st); }));
+      ASH_TRY(read_meta(m, &h, st));
+      if (!h.fail && (int64_t)h.t + h.claims > m->c) {
+        // Roll the claims back silently, grow x2 until the batch fits, redo.
+        const int64_t need = (int64_t)h.t + h.claims;
+        ASH_HIP(timed(m, "commit", st, [&] { return ash::launch_commit(m->key_dim, m->ref(), keys, un, m->slot_of, m->kB, m->heap, m->active,
+                                   (uint32_t)m->c, vs, nullptr, nullptr, m->meta, m->scan_status, st); }));
+        ASH_HIP(timed(m, "finalize", st, [&] { return ash::launch_finalize(m->meta, (uint32_t)m->c, ash::kFinalizeInsert, 1, m->scan_status, last_tile, st); }));
+        int64_t new_c = std::max<int64_t>(m->c, 1);
+        while (new_c < need) new_c *= 2;
+        if (new_c > kMaxCount) return ASH_E_CAPACITY;
+        ASH_TRY(grow(m, new_c, st));
+        if (values && m->n_values > 0) vs = make_values(m, values, nullptr, true);
+        ASH_TRY(ensure_scratch(m, n, st));
+        ASH_HIP(timed(m, "claim", st, [&] { return ash::launch_claim(m->key_dim, m->G, m->ref(), keys, un, m->slot_of, m->meta, st); }));
+      }
+      ASH_HIP(timed(m, "commit", st, [&] { return ash::launch_commit(m->key_dim, m->ref(), keys, un, m->slot_of, m->kB, m->heap, m->active,
+                                 (uint32_t)m->c, vs, out_idx, out_mask, m->meta, m->scan_status, st); }));
+      ASH_HIP(timed(m, "finalize", st, [&] { return ash::launch_finalize(m->meta, (uint32_t)m->c, ash::kFinalizeInsert, 0, m->scan_status, last_tile, st); }));
+      m->live_ub = std::min(m->c, m->live_ub + n);
+      m->used_ub += std::min(n, m->c);
+      return ASH_OK;
+    }
+  }
+  ASH_HIP(timed(m, "claim", st, [&] { return ash::launch_claim(m->key_dim, m->G, m->ref(), keys, un, m->slot_of, m->meta, st); }));
+  ASH_HIP(timed(m, "commit", st, [&] { return ash::launch_commit(m->key_dim, m->ref(), keys, un, m->slot_of, m->kB, m->heap, m->active, (uint32_t)m->c,
+                             vs, out_idx, out_mask, m->meta, m->scan_status, st); }));
+  ASH_HIP(timed(m, "finalize", st, [&] { return ash::launch_finalize(m->meta, (uint32_t)m->c, ash::kFinalizeInsert, 0, m->scan_status, last_tile, st); }));
+  m->live_ub = std::min(m->c, m->live_ub + n);
+  m->used_ub += std::min(n, m->c);
+  return ASH_OK;
+}
+
+ash_status_t reset_state(ash_map* m, hipStream_t st) {
+  ASH_HIP(ash::launch_fill_u32(m->table, ash::kEmpty, (size_t)m->nslots * m->slot_words(), st));
+  ASH_HIP(ash::launch_iota(m->heap, 0, (uint32_t)m->c, st));
+  if (m->c > 0) ASH_HIP(hipMemsetAsync(m->active, 0, (size_t)m->c, st));
+  ASH_HIP(ash::launch_fill_u32((uint32_t*)m->owner, 0x7FFFFFFFu, (size_t)m->c, st));
+  ASH_HIP(ash::launch_reset_meta(m->meta, st));
+  m->live_ub = 0;
+  m->used_ub = 0;
+  return ASH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ash_status_t ash_create(int64_t capacity, int32_t key_dim, int32_t n_values, const ash_dtype_t* value_dtypes,
+                        const int64_t* value_elems, const ash_allocator_t* allocator, const ash_tuning_t* tuning,
+                        void* stream, ash_map_t* out) {
+  if (!out || capacity < 0 || capacity > kMaxCount || key_dim < 1 || key_dim > 4) return ASH_E_INVALID;
+  if (n_values < 0 || n_values > ash::kMaxValues) return ASH_E_INVALID;
+  if (n_values > 0 && (!value_dtypes || !value_elems)) return ASH_E_INVALID;
+  if (allocator && (!allocator->alloc || !allocator->free)) return ASH_E_INVALID;
+  std::vector<uint32_t> rb(n_values);
+  for (int j = 0; j < n_values; ++j) {
+    const size_t es = dtype_size(value_dtypes[j]);
+    if (es == 0 || value_elems[j] <= 0) return ASH_E_INVALID;
+    const uint64_t bytes = es * (uint64_t)value_elems[j];
+    if (bytes > (1u << 24)) return ASH_E_UNSUPPORTED;
+    rb[j] = (uint32_t)bytes;
+  }
+  int W = 4, G = 4;
+  float lf = 0.5f;
+  uint32_t flags = 0;
+  if (tuning) {
+    W = tuning->bucket_width;
+    G = tuning->probe_group;
+    lf = tuning->max_load;
+    flags = tuning->flags;
+  }
+  if (!pow2(W) || W > 64) return ASH_E_INVALID;
+  if (G != 4 && G != 8 && G != 16 && G != 32 && G != 64) return ASH_E_INVALID;
+  if (!(lf >= 0.1f && lf <= 0.9f)) return ASH_E_INVALID;
+  hipStream_t st = (hipStream_t)stream;
+
+  ash_map* m = new ash_map;
+  m->mem.custom = allocator != nullptr;
+  if (allocator) m->mem.a = *allocator;
+  m->c = capacity;
+  m->key_dim = key_dim;
+  m->n_values = n_values;
+  m->row_bytes = rb;
+  m->W = W;
+  m->G = G;
+  m->max_load = lf;
+  m->flags = flags;
+  m->vB.assign(n_values, nullptr);
+  ash_status_t s = slots_for(capacity, lf, W, G, &m->nslots);
+  if (s != ASH_OK) {
+    delete m;
+    return s;
+  }
+  m->table = (uint32_t*)m->mem.get((size_t)m->nslots * m->slot_words() * 4, st);
+  m->kB = (int32_t*)m->mem.get((size_t)capacity * key_dim * 4, st);
+  m->heap = (int32_t*)m->mem.get((size_t)capacity * 4, st);
+  m->active = (uint8_t*)m->mem.get((size_t)capacity, st);
+  m->owner = (int32_t*)m->mem.get((size_t)capacity * 4, st);
+  m->meta = (Meta*)m->mem.get(sizeof(Meta), st);
+  bool ok = m->table && m->kB && m->heap && m->active && m->owner && m->meta;
+  for (int j = 0; j < n_values && ok; ++j) {
+    m->vB[j] = (uint8_t*)m->mem.get((size_t)capacity * rb[j], st);
+    ok = m->vB[j] != nullptr;
+  }
+  if (ok) ok = ensure_scratch(m, 0, st) == ASH_OK;
+  if (!ok) {
+    ash_destroy(m);
+    return ASH_E_NOMEM;
+  }
+  if (hipMemsetAsync(m->meta, 0, sizeof(Meta), st) != hipSuccess || reset_state(m, st) != ASH_OK ||
+      hipStreamSynchronize(st) != hipSuccess) {
+    ash_destroy(m);
+    return ASH_E_DEVICE;
+  }
+  *out = m;
+  return ASH_OK;
+}
+
+ash_status_t ash_destroy(ash_map_t m) {
+  if (!m) return ASH_E_INVALID;
+  hipStream_t st = nullptr;
+  free_buffers(m, st);
+  m->mem.put(m->meta, st);
+  m->mem.put(m->slot_of, st);
+  m->mem.put(m->aux, st);
+  m->mem.put(m->scan_status, st);
+  for (hipEvent_t e : m->prof.pool) (void)hipEventDestroy(e);
+  delete m;
+  return ASH_OK;
+}
+
+ash_status_t ash_profile_enable(ash_map_t m, int32_t enable) {
+  if (!m) return ASH_E_INVALID;
+  m->prof.on = enable != 0;
+  return ASH_OK;
+}
+
+ash_status_t ash_profile_collect(ash_map_t m, ash_kernel_time_t* out, int32_t max_entries, int32_t* n_entries,
+                                 void* stream) {
+  if (!m || !n_entries || max_entries < 0 || (max_entries > 0 && !out)) return ASH_E_INVALID;
+  ASH_HIP(hipStreamSynchronize((hipStream_t)stream));
+  std::vector<ash_kernel_time_t> agg;
+  for (const ProfRec& r : m->prof.recs) {
+    float ms = 0.0f;
+    ASH_HIP(hipEventSynchronize(r.stop));
+    ASH_HIP(hipEventElapsedTime(&ms, r.start, r.stop));
+    size_t k = 0;
+    while (k < agg.size() && std::strcmp(agg[k].name, r.name) != 0) ++k;
+    if (k == agg.size()) {
+      ash_kernel_time_t t;
+      std::memset(&t, 0, sizeof(t));
+      std::strncpy(t.name, r.name, sizeof(t.name) - 1);
+      agg.push_back(t);
+    }
+    agg[k].launches += 1;
+    agg[k].total_ms += ms;
+  }
+  m->prof.recs.clear();
+  m->prof.used = 0;
+  const int32_t n = (int32_t)std::min<size_t>(agg.size(), (size_t)max_entries);
+  for (int32_t k = 0; k < n; ++k) out[k] = agg[k];
+  *n_entries = n;
+  return ASH_OK;
+}
+
+ash_status_t ash_insert(ash_map_t m, const int32_t* keys, int64_t n, const void* const* values, int32_t* out_idx,
+                        uint8_t* out_mask, void* stream) {
+  if (m && m->n_values > 0 && n > 0 && !values) return ASH_E_INVALID;
+  return insert_impl(m, keys, n, m && m->n_values > 0 ? values : nullptr, out_idx, out_mask, (hipStream_t)stream);
+}
+
+ash_status_t ash_activate(ash_map_t m, const int32_t* keys, int64_t n, int32_t* out_idx, uint8_t* out_mask,
+                          void* stream) {
+  return insert_impl(m, keys, n, nullptr, out_idx, out_mask, (hipStream_t)stream);
+}
+
+ash_status_t ash_find(ash_map_t m, const int32_t* keys, int64_t n, int32_t* out_idx, uint8_t* out_mask,
+                      void* const* out_values, void* stream) {
+  ASH_TRY(check_keys(m, keys, n));
+  if (n == 0) return ASH_OK;
+  hipStream_t st = (hipStream_t)stream;
+  ValueSet vs;
+  std::memset(&vs, 0, sizeof(vs));
+  if (out_values && m->n_values > 0) {
+    for (int j = 0; j < m->n_values; ++j)
+      if (!out_values[j]) return ASH_E_INVALID;
+    vs = make_values(m, nullptr, out_values, false);
+  }
+  ASH_HIP(timed(m, "find", st, [&] { return ash::launch_find(m->key_dim, m->G, m->ref(), keys, (uint32_t)n, out_idx, out_mask, vs, st); }));
+  return ASH_OK;
+}
+
+ash_status_t ash_erase(ash_map_t m, const int32_t* keys, int64_t n, uint8_t* out_mask, void* stream) {
+  ASH_TRY(check_keys(m, keys, n));
+  if (n == 0) return ASH_OK;
+  hipStream_t st = (hipStream_t)stream;
+  ASH_TRY(ensure_scratch(m, n, st));
+  const uint32_t un = (uint32_t)n;
+  const uint32_t last_tile = (un + ash::kScanTile - 1) / ash::kScanTile - 1;
+  ASH_HIP(timed(m, "erase_mark", st, [&] { return ash::launch_erase_mark(m->key_dim, m->G, m->ref(), keys, un, m->slot_of, m->aux, m->owner, st); }));
+  ASH_HIP(timed(m, "erase_commit", st, [&] { return ash::launch_erase_commit(m->key_dim, m->ref(), un, m->slot_of, m->aux, m->owner, m->heap, m->active,
+                                   out_mask, m->meta, m->scan_status, st); }));
+  ASH_HIP(timed(m, "finalize", st, [&] { return ash::launch_finalize(m->meta, (uint32_t)m->c, ash::kFinalizeErase, 0, m->scan_status, last_tile, st); }));
+  return ASH_OK;
+}
+
+ash_status_t ash_active_indices(ash_map_t m, int32_t* out_idx, int64_t* out_count, void* stream) {
+  if (!m || !out_count || (m->c > 0 && !out_idx)) return ASH_E_INVALID;
+  hipStream_t st = (hipStream_t)stream;
+  if (m->c == 0) {
+    *out_count = 0;
+    return ASH_OK;
+  }
+  const uint32_t last_tile = (uint32_t)((m->c + ash::kScanTile - 1) / ash::kScanTile - 1);
+  ASH_HIP(timed(m, "compact_active", st, [&] { return ash::launch_compact_active(m->active, (uint32_t)m->c, out_idx, m->meta, m->scan_status, st); }));
+  ASH_HIP(timed(m, "finalize", st, [&] { return ash::launch_finalize(m->meta, (uint32_t)m->c, ash::kFinalizeCount, 0, m->scan_status, last_tile, st); }));
+  Meta h;
+  ASH_TRY(read_meta(m, &h, st));
+  *out_count = h.result;
+  return ASH_OK;
+}
+
+ash_status_t ash_rehash(ash_map_t m, int64_t new_capacity, void* stream) {
+  if (!m || new_capacity < 0) return ASH_E_INVALID;
+  return grow(m, new_capacity, (hipStream_t)stream);
+}
+
+ash_status_t ash_clear(ash_map_t m, void* stream) {
+  if (!m) return ASH_E_INVALID;
+  return reset_state(m, (hipStream_t)stream);
+}
+
+ash_status_t ash_size(ash_map_t m, int64_t* out, void* stream) {
+  if (!m || !out) return ASH_E_INVALID;
+  Meta h;
+  ASH_TRY(read_meta(m, &h, (hipStream_t)stream));
+  *out = h.t;
+  return ASH_OK;
+}
+
+ash_status_t ash_capacity(ash_map_t m, int64_t* out) {
+  if (!m || !out) return ASH_E_INVALID;
+  *out = m->c;
+  return ASH_OK;
+}
+
+ash_status_t ash_stats(ash_map_t m, ash_stats_t* out, void* stream) {
+  if (!m || !out) return ASH_E_INVALID;
+  Meta h;
+  ASH_TRY(read_meta(m, &h, (hipStream_t)stream));
+  out->size = h.t;
+  out->capacity = m->c;
+  out->slots = m->nslots;
+  out->used_slots = h.used;
+  out->tombstones = h.tombs;
+  return ASH_OK;
+}
+
+ash_status_t ash_key_buffer(ash_map_t m, int32_t** out) {
+  if (!m || !out) return ASH_E_INVALID;
+  *out = m->kB;
+  return ASH_OK;
+}
+
+ash_status_t ash_value_buffer(ash_map_t m, int32_t j, void** out) {
+  if (!m || !out || j < 0 || j >= m->n_values) return ASH_E_INVALID;
+  *out = m->vB[j];
+  return ASH_OK;
+}
+
+ash_status_t ash_heap_buffer(ash_map_t m, int32_t** out) {
+  if (!m || !out) return ASH_E_INVALID;
+  *out = m->heap;
+  return ASH_OK;
+}
+
+ash_status_t ash_device_status(ash_map_t m, void* stream) {
+  if (!m) return ASH_E_INVALID;
+  hipStream_t st = (hipStream_t)stream;
+  Meta h;
+  ASH_TRY(read_meta(m, &h, st));
+  if (h.status == 0) return ASH_OK;
+  const uint32_t zero = 0;
+  ASH_HIP(hipMemcpyAsync(&m->meta->status, &zero, sizeof(zero), hipMemcpyHostToDevice, st));
+  ASH_HIP(hipStreamSynchronize(st));
+  return (h.status & ash::kStatusScanStall) ? ASH_E_DEVICE : ASH_E_CAPACITY;
+}
+
+ash_status_t ash_voxelize(const float* points, int64_t n, float voxel, int32_t* out_point_voxel,
+                          int32_t* out_voxel_keys, int32_t* out_voxel_counts, int64_t* out_n_voxels,
+                          const ash_allocator_t* allocator, void* stream) {
+  if (!out_n_voxels || n < 0 || n > kMaxCount) return ASH_E_INVALID;
+  if (!(voxel > 0.0f) || !std::isfinite(voxel)) return ASH_E_INVALID;
+  if (n > 0 && (!points || !out_point_voxel || !out_voxel_keys || !out_voxel_counts)) return ASH_E_INVALID;
+  if (allocator && (!allocator->alloc || !allocator->free)) return ASH_E_INVALID;
+  if (n == 0) {
+    *out_n_voxels = 0;
+    return ASH_OK;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  DevMem mem;
+  mem.custom = allocator != nullptr;
+  if (allocator) mem.a = *allocator;
+  constexpr int kW = 4, kG = 4;
+  constexpr float kLoad = 0.5f;
+  uint32_t nslots;
+  ASH_TRY(slots_for(n, kLoad, kW, kG, &nslots));
+  const uint32_t un = (uint32_t)n;
+  const int64_t tiles = (n + ash::kScanTile - 1) / ash::kScanTile;
+  uint32_t* table = (uint32_t*)mem.get((size_t)nslots * 16, st);
+  uint32_t* slot_of = (uint32_t*)mem.get((size_t)n * 4, st);
+  uint64_t* status = (uint64_t*)mem.get((size_t)tiles * 8 + sizeof(Meta), st);
+  ash_status_t rc = ASH_OK;
+  if (!table || !slot_of || !status) rc = ASH_E_NOMEM;
+  if (rc == ASH_OK) {
+    Meta* meta = (Meta*)(status + tiles);
+    TableRef tb;
+    tb.words = table;
+    tb.nslots = nslots;
+    tb.bucket_width = kW;
+    tb.nbuckets = nslots / kW;
+    tb.max_windows = nslots / kG + 1;
+    Meta h;
+    std::memset(&h, 0, sizeof(h));
+    h.epoch = 1;
+    bool ok = ash::launch_fill_u32(table, ash::kEmpty, (size_t)nslots * 4, st) == hipSuccess &&
+              ash::launch_fill_u32((uint32_t*)status, 0u, (size_t)tiles * 2, st) == hipSuccess &&
+              hipMemcpyAsync(meta, &h, sizeof(Meta), hipMemcpyHostToDevice, st) == hipSuccess &&
+              ash::launch_voxel_claim(kG, tb, points, voxel, un, slot_of, meta, st) == hipSuccess &&
+              ash::launch_voxel_commit(tb, points, voxel, un, slot_of, out_voxel_keys, out_voxel_counts, meta,
+                                       status, st) == hipSuccess &&
+              ash::launch_voxel_resolve(tb, un, slot_of, out_point_voxel, out_voxel_counts, st) == hipSuccess &&
+              hipMemcpyAsync(&h, meta, sizeof(Meta), hipMemcpyDeviceToHost, st) == hipSuccess &&
+              hipStreamSynchronize(st) == hipSuccess;
+    if (!ok) rc = ASH_E_DEVICE;
+    else if (h.fail) rc = ASH_E_CAPACITY;
+    else *out_n_voxels = h.claims;
+  }
+  mem.put(table, st);
+  mem.put(slot_of, st);
+  mem.put(status, st);
+  return rc;
+}
+
+const char* ash_status_string(ash_status_t s) {
+  switch (s) {
+    case ASH_OK: return "ok";
+    case ASH_E_INVALID: return "invalid argument";
+    case ASH_E_CAPACITY: return "capacity exceeded";
+    case ASH_E_NOMEM: return "allocation failed";
+    case ASH_E_DEVICE: return "HIP runtime error";
+    case ASH_E_UNSUPPORTED: return "unsupported size or tuning";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

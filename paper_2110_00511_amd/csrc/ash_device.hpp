@@ -1,0 +1,327 @@
+// ash_device.hpp -- device-side building blocks of the gfx950 hash map.
+//
+// Slot table.  Open addressing over buckets of W slots; a slot of S 32-bit
+// words holds the key in place plus a state word:
+//     words[0 .. KD-2]  key words k_0 .. k_{KD-2}
+//     words[S-2]        "tag word": k_{KD-1} once committed, a 32-bit hash tag
+//                        while a claim is pending (for KD = 1 the key itself)
+//     words[S-1]        state: EMPTY, TOMBSTONE, PENDING(p) or COMMITTED(i)
+// S = 2 (KD = 1), 4 (KD = 2, 3), 8 (KD = 4).  The (tag word, state) pair is
+// 8-byte aligned and is claimed with one 64-bit compare-and-swap.
+//
+// The paper's backends (Sec. 4.3-4.4) are separate chaining; this table is
+// bucketed open addressing, read by a group of g lanes of a 64-wide
+// wavefront that each load one slot of a g-slot window (the wavefront
+// counterpart of the warp-cooperative slab probing the paper builds on).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ash {
+
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+constexpr uint32_t kTomb = 0xFFFFFFFEu;
+constexpr uint32_t kPending = 0x80000000u;  // PENDING(p) = kPending + p
+constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
+constexpr uint64_t kEmptyPair = ~0ull;
+constexpr int kMaxValues = 8;
+constexpr int kBlock = 256;        // threads per block of every kernel
+constexpr int kScanItems = 4;      // positions per thread in scanning kernels
+constexpr int kScanTile = kBlock * kScanItems;
+
+// Sticky status bits kept in Meta::status.
+constexpr uint32_t kStatusCapacity = 1u;    // not enough free buffer indices
+constexpr uint32_t kStatusTableFull = 2u;   // probe found no empty slot
+constexpr uint32_t kStatusScanStall = 4u;   // a look-back wait hit its bound
+constexpr uint32_t kLookbackSpinLimit = 1u << 24;
+
+template <int KD>
+struct SlotWords {
+  static constexpr int value = KD == 1 ? 2 : (KD <= 3 ? 4 : 8);
+};
+
+// Device-resident bookkeeping of one map.  Only the finalize kernels write
+// t / used / tombs / epoch / ticket, so every other kernel may read them
+// with plain loads.
+struct Meta {
+  uint32_t t;       // heap top = number of live keys
+  uint32_t claims;  // new keys claimed by the insert in flight
+  uint32_t used;    // non-empty slots (live + tombstones)
+  uint32_t tombs;   // tombstones
+  uint32_t status;  // sticky error bits
+  uint32_t epoch;   // tag of the scan status words of the current launch
+  uint32_t ticket;  // tile ticket counter of the scanning kernel in flight
+  uint32_t result;  // total of the last scanning kernel
+  uint32_t fail;    // groups whose probe found no empty slot (claim/rebuild)
+  uint32_t pad[7];
+};
+
+struct TableRef {
+  uint32_t* words;
+  uint32_t nslots;
+  uint32_t nbuckets;
+  uint32_t bucket_width;
+  uint32_t max_windows;
+};
+
+// ---------------------------------------------------------------------------
+// Hashing.  The paper leaves the hash function open.  Words are folded with
+// the SplitMix64 output function (Steele, Lea and Flood, OOPSLA 2014), a
+// bijective 64-bit mixer; the home bucket is taken from the high 32 bits by
+// multiply-shift range reduction and the pending tag from the low 32 bits.
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+template <int KD>
+__device__ __forceinline__ uint64_t key_hash(const int32_t (&k)[KD]) {
+  uint64_t h = 0x9e3779b97f4a7c15ull * (uint64_t)KD;
+#pragma unroll
+  for (int d = 0; d < KD; d += 2) {
+    uint64_t w = (uint32_t)k[d];
+    if (d + 1 < KD) w |= (uint64_t)(uint32_t)k[d + 1] << 32;
+    h = mix64(h ^ w);
+  }
+  return h;
+}
+
+template <int KD>
+__device__ __forceinline__ uint32_t pending_tag(const int32_t (&k)[KD], uint64_t h) {
+  return KD == 1 ? (uint32_t)k[0] : (uint32_t)h;
+}
+
+__device__ __forceinline__ uint32_t home_slot(const TableRef& tb, uint64_t h) {
+  uint32_t b = (uint32_t)(((h >> 32) * (uint64_t)tb.nbuckets) >> 32);
+  return b * tb.bucket_width;
+}
+
+// ---------------------------------------------------------------------------
+// Slot access.
+template <int S>
+struct Slot {
+  uint32_t w[S];
+};
+
+template <int S>
+__device__ __forceinline__ Slot<S> load_slot(const uint32_t* p) {
+  Slot<S> s;
+  if constexpr (S == 2) {
+    uint2 v = *reinterpret_cast<const uint2*>(p);
+    s.w[0] = v.x; s.w[1] = v.y;
+  } else {
+#pragma unroll
+    for (int q = 0; q < S / 4; ++q) {
+      uint4 v = reinterpret_cast<const uint4*>(p)[q];
+      s.w[4 * q] = v.x; s.w[4 * q + 1] = v.y; s.w[4 * q + 2] = v.z; s.w[4 * q + 3] = v.w;
+    }
+  }
+  return s;
+}
+
+template <int S>
+__device__ __forceinline__ void store_slot(uint32_t* p, const Slot<S>& s) {
+  if constexpr (S == 2) {
+    *reinterpret_cast<uint2*>(p) = make_uint2(s.w[0], s.w[1]);
+  } else {
+#pragma unroll
+    for (int q = 0; q < S / 4; ++q)
+      reinterpret_cast<uint4*>(p)[q] = make_uint4(s.w[4 * q], s.w[4 * q + 1], s.w[4 * q + 2], s.w[4 * q + 3]);
+  }
+}
+
+// A committed slot holds key k iff its key words and tag word equal k.
+template <int KD, int S>
+__device__ __forceinline__ bool slot_holds(const Slot<S>& s, const int32_t (&k)[KD]) {
+  bool eq = s.w[S - 2] == (uint32_t)k[KD - 1];
+#pragma unroll
+  for (int d = 0; d < KD - 1; ++d) eq = eq && s.w[d] == (uint32_t)k[d];
+  return eq;
+}
+
+template <int KD, int S>
+__device__ __forceinline__ Slot<S> committed_slot(const int32_t (&k)[KD], uint32_t idx) {
+  Slot<S> s;
+#pragma unroll
+  for (int q = 0; q < S; ++q) s.w[q] = kEmpty;
+#pragma unroll
+  for (int d = 0; d < KD - 1; ++d) s.w[d] = (uint32_t)k[d];
+  s.w[S - 2] = (uint32_t)k[KD - 1];
+  s.w[S - 1] = idx;
+  return s;
+}
+
+__device__ __forceinline__ uint64_t cas_pair(uint32_t* pair, uint64_t expected, uint64_t desired) {
+  __hip_atomic_compare_exchange_strong(reinterpret_cast<uint64_t*>(pair), &expected, desired,
+                                       __ATOMIC_RELAXED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return expected;  // value found in memory (== the original expected on success)
+}
+
+__device__ __forceinline__ uint32_t atomic_min_u32(uint32_t* p, uint32_t v) {
+  return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t atomic_add_u32(uint32_t* p, uint32_t v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------------------
+// Lane groups of a wavefront.
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
+
+template <int G>
+__device__ __forceinline__ uint64_t group_ballot(bool pred) {
+  uint64_t b = __ballot(pred);
+  if constexpr (G == 64) {
+    return b;
+  } else {
+    const uint32_t shift = lane_id() & ~(uint32_t)(G - 1);
+    return (b >> shift) & ((1ull << G) - 1ull);
+  }
+}
+
+template <int G, typename T>
+__device__ __forceinline__ T group_bcast(T v, uint32_t sub) {
+  const int src = (int)((lane_id() & ~(uint32_t)(G - 1)) + sub);
+  return __shfl(v, src, 64);
+}
+
+__device__ __forceinline__ uint32_t first_lane(uint64_t m) { return (uint32_t)(__ffsll((unsigned long long)m) - 1); }
+
+// ---------------------------------------------------------------------------
+// Ordered ranks: block-wide scan plus single-pass decoupled look-back across
+// tiles (Merrill and Garland, "Single-pass Parallel Prefix Scan with
+// Decoupled Look-back", 2016).  Tiles are numbered by a ticket so that a tile
+// only waits on tiles that already started.  Status word of a tile:
+//   [63:32] epoch of the launch, [31] inclusive flag, [30:0] count.
+__device__ __forceinline__ uint64_t pack_status(uint32_t epoch, uint32_t inclusive, uint32_t v) {
+  return ((uint64_t)epoch << 32) | ((uint64_t)inclusive << 31) | (uint64_t)v;
+}
+
+// Called by one thread; returns the exclusive prefix of `tile`.  Every tile
+// of a launch publishes exactly once, and a tile only waits on tiles with a
+// smaller ticket, which are already running; the wait is still bounded so
+// that a broken invariant ends in a sticky error instead of a hang.
+__device__ inline uint32_t tile_lookback(uint64_t* status, uint32_t tile, uint32_t epoch, uint32_t aggregate,
+                                         uint32_t* status_bits) {
+  if (tile == 0) {
+    __hip_atomic_store(status, pack_status(epoch, 1, aggregate), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return 0;
+  }
+  __hip_atomic_store(status + tile, pack_status(epoch, 0, aggregate), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  uint32_t excl = 0;
+  uint32_t j = tile - 1;
+  uint32_t spins = 0;
+  while (true) {
+    uint64_t s = __hip_atomic_load(status + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((uint32_t)(s >> 32) != epoch) {
+      if (++spins == kLookbackSpinLimit) {
+        __hip_atomic_fetch_or(status_bits, kStatusScanStall, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    excl += (uint32_t)s & 0x7FFFFFFFu;
+    if (s & 0x80000000ull) break;
+    if (j == 0) break;  // tile 0 always publishes an inclusive value
+    --j;
+  }
+  __hip_atomic_store(status + tile, pack_status(epoch, 1, excl + aggregate), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+  return excl;
+}
+
+// Takes the next tile ticket (thread 0) and broadcasts it.
+__device__ __forceinline__ uint32_t take_ticket(uint32_t* counter, uint32_t* s_slot) {
+  if (threadIdx.x == 0) *s_slot = atomic_add_u32(counter, 1u);
+  __syncthreads();
+  return *s_slot;
+}
+
+// Exclusive block scan of kScanItems 0/1 flags per thread where the item of
+// thread t in row r is position base + r * kBlock + t.  Returns the rank of
+// each flagged item among the tile's flagged items (in position order) and the
+// tile total.  s_scratch needs kBlock / 64 + 1 uint64 words.
+__device__ inline void block_rank_rows(const bool (&flag)[kScanItems], uint32_t (&rank)[kScanItems],
+                                       uint32_t& total, uint64_t* s_scratch) {
+  const uint32_t lane = lane_id();
+  const uint32_t wave = threadIdx.x >> 6;
+  constexpr int kWaves = kBlock / 64;
+  // four 16-bit counters packed in one 64-bit word (each sum <= kBlock)
+  uint64_t v = 0;
+#pragma unroll
+  for (int r = 0; r < kScanItems; ++r) v |= (uint64_t)(flag[r] ? 1u : 0u) << (16 * r);
+  uint64_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint64_t y = __shfl_up(x, o, 64);
+    if (lane >= (uint32_t)o) x += y;
+  }
+  if (lane == 63) s_scratch[wave] = x;
+  __syncthreads();
+  uint64_t before = 0, all = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) {
+    uint64_t c = s_scratch[w];
+    if ((uint32_t)w < wave) before += c;
+    all += c;
+  }
+  const uint64_t excl = before + x - v;
+  uint32_t row_base = 0;
+#pragma unroll
+  for (int r = 0; r < kScanItems; ++r) {
+    rank[r] = row_base + (uint32_t)((excl >> (16 * r)) & 0xFFFFu);
+    row_base += (uint32_t)((all >> (16 * r)) & 0xFFFFu);
+  }
+  total = row_base;
+  __syncthreads();  // s_scratch may be reused by the caller
+}
+
+// ---------------------------------------------------------------------------
+// Value rows.  Each buffer j moves rows of row_bytes[j] bytes in units of
+// vec[j] bytes (16, 8, 4, 2 or 1, chosen on the host from the row size and
+// pointer alignment); consecutive lanes move consecutive units of a row, so
+// both the source and destination streams are coalesced.
+struct ValueSet {
+  int32_t n;
+  const uint8_t* src[kMaxValues];
+  uint8_t* dst[kMaxValues];
+  uint32_t row_bytes[kMaxValues];
+  uint32_t vec[kMaxValues];
+  uint32_t units_log2[kMaxValues];  // log2(row_bytes / vec), or 0xFF if not a power of two
+};
+
+template <typename V>
+__device__ inline void copy_rows_t(const uint8_t* __restrict__ src, uint8_t* __restrict__ dst, uint32_t row_bytes,
+                                   uint32_t units_log2, const uint2* pairs, uint32_t count) {
+  const uint32_t units = row_bytes / (uint32_t)sizeof(V);
+  const uint32_t total = count * units;
+  for (uint32_t e = threadIdx.x; e < total; e += blockDim.x) {
+    uint32_t w, c;
+    if (units_log2 != 0xFFu) {
+      w = e >> units_log2;
+      c = e & (units - 1u);
+    } else {
+      w = e / units;
+      c = e - w * units;
+    }
+    const uint2 pr = pairs[w];  // (source row, destination row)
+    const V v = reinterpret_cast<const V*>(src + (size_t)pr.x * row_bytes)[c];
+    reinterpret_cast<V*>(dst + (size_t)pr.y * row_bytes)[c] = v;
+  }
+}
+
+__device__ inline void copy_rows(const ValueSet& vs, int j, const uint2* pairs, uint32_t count) {
+  switch (vs.vec[j]) {
+    case 16: copy_rows_t<uint4>(vs.src[j], vs.dst[j], vs.row_bytes[j], vs.units_log2[j], pairs, count); break;
+    case 8: copy_rows_t<uint2>(vs.src[j], vs.dst[j], vs.row_bytes[j], vs.units_log2[j], pairs, count); break;
+    case 4: copy_rows_t<uint32_t>(vs.src[j], vs.dst[j], vs.row_bytes[j], vs.units_log2[j], pairs, count); break;
+    case 2: copy_rows_t<uint16_t>(vs.src[j], vs.dst[j], vs.row_bytes[j], vs.units_log2[j], pairs, count); break;
+    default: copy_rows_t<uint8_t>(vs.src[j], vs.dst[j], vs.row_bytes[j], vs.units_log2[j], pairs, count); break;
+  }
+}
+
+}  // namespace ash

@@ -1,0 +1,817 @@
+// ash_kernels.hip -- gfx950 kernels of the spatial hash map and their
+// launchers.  Operation semantics follow ASH (arXiv 2110.00511): lazy
+// insertion, activation, masked index query, erase with index-heap free,
+// active-set gathering, rehash and voxelization (Sec. 4.2-4.7, 5.1, 6.1).
+//
+// Insertion is split in two kernels so that no thread ever compares against a
+// partially written key (the race that forces the paper's three-pass
+// insertion in Sec. 4.4.2 cannot arise):
+//   claim  -- each position probes the table; a new key CASes the first EMPTY
+//             slot of its probe sequence to (tag, PENDING(p)); a position that
+//             meets a PENDING slot of the same key (checked against the
+//             read-only input batch) lowers it to PENDING(min) with atomicMin,
+//             so every new key ends with exactly one slot holding its lowest
+//             batch position;
+//   commit -- the position owning its PENDING slot is the winner; winners are
+//             ranked in batch order (block scan + decoupled look-back) and take
+//             i = h[t + rank]; the key, values and COMMITTED(i) are written.
+// A finalize kernel then moves t.  Erase mirrors this with an owner array.
+#include "ash_device.hpp"
+#include "ash_launch.hpp"
+
+#include <algorithm>
+
+namespace ash {
+
+// ---------------------------------------------------------------------------
+// Key sources: map keys read from the batch, or voxel keys computed from
+// points.  load() returns false for a point that is rejected.
+template <int KD>
+struct BatchKeys {
+  const int32_t* __restrict__ keys;
+  __device__ __forceinline__ bool load(uint32_t p, int32_t (&k)[KD]) const {
+    const int32_t* r = keys + (size_t)p * KD;
+#pragma unroll
+    for (int d = 0; d < KD; ++d) k[d] = r[d];
+    return true;
+  }
+};
+
+// Listing 1 of Sec. 6.1: floor(xyz / voxel_size) as int32.  The quotient is
+// the correctly rounded binary32 division (the build keeps IEEE division and
+// denormals); NaN, infinities and floors outside int32 fail the range test.
+struct VoxelKeys {
+  const float* __restrict__ points;
+  float voxel;
+  __device__ __forceinline__ bool load(uint32_t p, int32_t (&k)[3]) const {
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const float q = points[(size_t)p * 3 + d] / voxel;
+      const float f = floorf(q);
+      const bool in = f >= -2147483648.0f && f < 2147483648.0f;
+      ok = ok && in;
+      k[d] = in ? (int32_t)f : 0;
+    }
+    return ok;
+  }
+};
+
+template <int KD>
+__device__ __forceinline__ bool keys_equal(const int32_t (&a)[KD], const int32_t (&b)[KD]) {
+  bool eq = true;
+#pragma unroll
+  for (int d = 0; d < KD; ++d) eq = eq && a[d] == b[d];
+  return eq;
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Fill / init kernels.
+__global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, size_t n) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  const size_t n4 = n / 4;
+  uint4* p4 = reinterpret_cast<uint4*>(p);
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) p4[i] = make_uint4(v, v, v, v);
+  for (size_t i = n4 * 4 + (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_iota(int32_t* __restrict__ h, uint32_t from, uint32_t to) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t i = from + blockIdx.x * blockDim.x + threadIdx.x; i < to; i += stride) h[i] = (int32_t)i;
+}
+
+__global__ void k_reset_meta(Meta* m) {
+  m->t = 0; m->claims = 0; m->used = 0; m->tombs = 0; m->status = 0; m->ticket = 0; m->result = 0; m->fail = 0;
+  m->epoch = m->epoch + 1u == 0u ? 1u : m->epoch + 1u;
+}
+
+// ---------------------------------------------------------------------------
+// Claim (insert / activate / voxelize pass 1).  A group of G lanes owns one
+// position at a time; lane `sub` examines slot home + w*G + sub of window w.
+template <int KD, int G, typename Src>
+__global__ __launch_bounds__(kBlock) void k_claim(TableRef tb, Src src, uint32_t n, uint32_t rounds,
+                                                  uint32_t* __restrict__ slot_of, Meta* meta) {
+  constexpr int S = SlotWords<KD>::value;
+  constexpr uint32_t kGroups = kBlock / G;
+  const uint32_t sub = threadIdx.x & (G - 1);
+  const uint32_t grp = threadIdx.x / G;
+  const uint32_t tile_base = blockIdx.x * kGroups * rounds;
+  uint32_t claimed = 0;
+  uint32_t unresolved = 0;
+  for (uint32_t r = 0; r < rounds; ++r) {
+    const uint32_t p = tile_base + r * kGroups + grp;
+    if (p >= n) break;
+    int32_t k[KD];
+    const bool valid = src.load(p, k);
+    uint32_t out = kNoSlot;
+    if (valid) {
+      const uint64_t h = key_hash<KD>(k);
+      const uint32_t tag = pending_tag<KD>(k, h);
+      uint32_t base = home_slot(tb, h);
+      bool resolved = false;
+      for (uint32_t w = 0; w < tb.max_windows && !resolved; ++w) {
+        uint32_t s = base + sub;
+        if (s >= tb.nslots) s -= tb.nslots;
+        uint32_t* sp = tb.words + (size_t)s * S;
+        Slot<S> sl = load_slot<S>(sp);
+        while (true) {
+          const uint32_t st = sl.w[S - 1];
+          const bool hit_c = st < kPending && slot_holds<KD, S>(sl, k);
+          bool hit_p = false;
+          if (st >= kPending && st < kTomb && sl.w[S - 2] == tag && st - kPending < n) {
+            if constexpr (KD == 1) {
+              hit_p = true;  // the tag word of a 1-word key is the key
+            } else {
+              int32_t kq[KD];
+              src.load(st - kPending, kq);
+              hit_p = keys_equal<KD>(kq, k);
+            }
+          }
+          if (group_ballot<G>(hit_c)) {  // key already committed: not new
+            resolved = true;
+            break;
+          }
+          const uint64_t mp = group_ballot<G>(hit_p);
+          if (mp) {  // same key pending: keep the lowest position
+            const uint32_t L = first_lane(mp);
+            if (sub == L && st - kPending > p) atomic_min_u32(sp + S - 1, kPending + p);
+            out = group_bcast<G>(s, L);
+            resolved = true;
+            break;
+          }
+          const uint64_t me = group_ballot<G>(st == kEmpty);
+          if (!me) break;  // no empty slot in this window: next window
+          const uint32_t L = first_lane(me);
+          uint32_t won = 0;
+          if (sub == L) {
+            const uint64_t desired = ((uint64_t)(kPending + p) << 32) | tag;
+            const uint64_t found = cas_pair(sp + S - 2, kEmptyPair, desired);
+            won = found == kEmptyPair;
+            if (!won) {  // someone filled it first: look at what is there now
+              sl.w[S - 2] = (uint32_t)found;
+              sl.w[S - 1] = (uint32_t)(found >> 32);
+            }
+          }
+          won = group_bcast<G>(won, L);
+          if (won) {
+            out = group_bcast<G>(s, L);
+            claimed += sub == 0 ? 1u : 0u;
+            resolved = true;
+            break;
+          }
+        }
+        base += G;
+        if (base >= tb.nslots) base -= tb.nslots;
+      }
+      if (!resolved) unresolved = 1;
+    }
+    if (sub == 0) slot_of[p] = out;
+  }
+  const uint32_t wc = wave_sum(claimed);
+  const uint32_t wu = wave_sum(unresolved);
+  if (lane_id() == 0) {
+    if (wc) atomic_add_u32(&meta->claims, wc);
+    if (wu) atomic_add_u32(&meta->fail, 1u);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Commit (insert / activate pass 2).
+template <int KD>
+__global__ __launch_bounds__(kBlock) void k_commit(TableRef tb, const int32_t* __restrict__ keys, uint32_t n,
+                                                   const uint32_t* __restrict__ slot_of, int32_t* __restrict__ kB,
+                                                   const int32_t* __restrict__ heap, uint8_t* __restrict__ active,
+                                                   uint32_t cap, ValueSet vs, int32_t* __restrict__ out_idx,
+                                                   uint8_t* __restrict__ out_mask, Meta* meta,
+                                                   uint64_t* __restrict__ status) {
+  constexpr int S = SlotWords<KD>::value;
+  __shared__ uint32_t s_tile;
+  __shared__ uint32_t s_prefix;
+  __shared__ uint64_t s_scan[kBlock / 64 + 1];
+  __shared__ uint2 s_pairs[kScanTile];
+  const uint32_t tile = take_ticket(&meta->ticket, &s_tile);
+  const uint32_t t0 = meta->t;
+  const uint32_t claims = meta->claims;
+  const bool overflow = meta->fail != 0 || claims > cap - t0;
+  const uint32_t base = tile * kScanTile;
+  bool win[kScanItems];
+  uint32_t slot[kScanItems];
+#pragma unroll
+  for (int r = 0; r < kScanItems; ++r) {
+    const uint32_t p = base + r * kBlock + threadIdx.x;
+    slot[r] = p < n ? slot_of[p] : kNoSlot;
+    win[r] = slot[r] != kNoSlot && tb.words[(size_t)slot[r] * S + S - 1] == kPending + p;
+  }
+  if (overflow) {  // roll the claims back: the table is as before the call
+#pragma unroll
+    for (int r = 0; r < kScanItems; ++r) {
+      if (win[r]) *reinterpret_cast<uint2*>(tb.words + (size_t)slot[r] * S + S - 2) = make_uint2(kEmpty, kEmpty);
+      win[r] = false;  // every position reports a miss; tiles still publish
+    }
+  }
+  uint32_t rank[kScanItems];
+  uint32_t total;
+  block_rank_rows(win, rank, total, s_scan);
+  if (threadIdx.x == 0) s_prefix = tile_lookback(status, tile, meta->epoch, total, &meta->status);
+  __syncthreads();
+  const uint32_t prefix = s_prefix;
+  bool bad = false;
+#pragma unroll
+  for (int r = 0; r < kScanItems; ++r) {
+    const uint32_t p = base + r * kBlock + threadIdx.x;
+    if (p >= n) continue;
+    if (win[r] && t0 + prefix + rank[r] >= cap) bad = true;  // cannot happen: winners == claims
+    if (win[r] && t0 + prefix + rank[r] < cap) {
+      const uint32_t i = (uint32_t)heap[t0 + prefix + rank[r]];
+      int32_t k[KD];
+#pragma unroll
+      for (int d = 0; d < KD; ++d) {
+        k[d] = keys[(size_t)p * KD + d];
+        kB[(size_t)i * KD + d] = k[d];
+      }
+      store_slot<S>(tb.words + (size_t)slot[r] * S, committed_slot<KD, S>(k, i));
+      active[i] = 1;
+      s_pairs[rank[r]] = make_uint2(p, i);
+      if (out_idx) out_idx[p] = (int32_t)i;
+      if (out_mask) out_mask[p] = 1;
+    } else {
+      if (out_idx) out_idx[p] = -1;
+      if (out_mask) out_mask[p] = 0;
+    }
+  }
+  if (vs.n > 0 && !__syncthreads_or(bad)) {
+    for (int j = 0; j < vs.n; ++j) copy_rows(vs, j, s_pairs, total);
+  }
+}
+
+// Moves the heap top and resets per-launch counters.  Runs after the
+// scanning kernel, so every block of that kernel has read t / epoch.
+__global__ void k_finalize(Meta* m, uint32_t cap, int mode, int silent, const uint64_t* status, uint32_t last_tile) {
+  if (mode == kFinalizeInsert) {
+    const bool overflow = m->fail != 0 || m->claims > cap - m->t;
+    if (!overflow) {
+      m->t += m->claims;
+      m->used += m->claims;
+    } else if (!silent) {
+      m->status |= m->fail ? kStatusTableFull : kStatusCapacity;
+    }
+    m->claims = 0;
+    m->fail = 0;
+  } else if (mode == kFinalizeErase) {
+    const uint32_t total = (uint32_t)status[last_tile] & 0x7FFFFFFFu;
+    m->t -= total;
+    m->tombs += total;
+    m->result = total;
+  } else if (mode == kFinalizeCount) {
+    m->result = (uint32_t)status[last_tile] & 0x7FFFFFFFu;
+  } else if (mode == kFinalizeRebuild) {
+    if (m->fail) m->status |= kStatusTableFull;
+    m->fail = 0;
+  }
+  m->ticket = 0;
+  m->epoch = m->epoch + 1u == 0u ? 1u : m->epoch + 1u;
+}
+
+// ---------------------------------------------------------------------------
+// Find (masked query, Sec. 4.2) with optional value gather.  Probing stops at
+// the first window that holds an EMPTY slot: a key is always claimed at the
+// first EMPTY slot of its sequence and slots never return to EMPTY outside a
+// rebuild.
+template <int KD, int G>
+__global__ __launch_bounds__(kBlock) void k_find(TableRef tb, const int32_t* __restrict__ keys, uint32_t n,
+                                                 uint32_t rounds, int32_t* __restrict__ out_idx,
+                                                 uint8_t* __restrict__ out_mask, ValueSet vs) {
+  constexpr int S = SlotWords<KD>::value;
+  constexpr uint32_t kGroups = kBlock / G;
+  __shared__ uint2 s_pairs[kScanTile];
+  __shared__ uint32_t s_hits;
+  const uint32_t sub = threadIdx.x & (G - 1);
+  const uint32_t grp = threadIdx.x / G;
+  const uint32_t tile_base = blockIdx.x * kGroups * rounds;
+  if (vs.n > 0) {
+    if (threadIdx.x == 0) s_hits = 0;
+    __syncthreads();
+  }
+  for (uint32_t r = 0; r < rounds; ++r) {
+    const uint32_t p = tile_base + r * kGroups + grp;
+    if (p >= n) break;
+    int32_t k[KD];
+#pragma unroll
+    for (int d = 0; d < KD; ++d) k[d] = keys[(size_t)p * KD + d];
+    const uint64_t h = key_hash<KD>(k);
+    uint32_t base = home_slot(tb, h);
+    uint32_t idx = kNoSlot;
+    for (uint32_t w = 0; w < tb.max_windows; ++w) {
+      uint32_t s = base + sub;
+      if (s >= tb.nslots) s -= tb.nslots;
+      const Slot<S> sl = load_slot<S>(tb.words + (size_t)s * S);
+      const uint32_t st = sl.w[S - 1];
+      const uint64_t mh = group_ballot<G>(st < kPending && slot_holds<KD, S>(sl, k));
+      if (mh) {
+        idx = group_bcast<G>(st, first_lane(mh));
+        break;
+      }
+      if (group_ballot<G>(st == kEmpty)) break;
+      base += G;
+      if (base >= tb.nslots) base -= tb.nslots;
+    }
+    if (sub == 0) {
+      const bool hit = idx != kNoSlot;
+      if (out_idx) out_idx[p] = hit ? (int32_t)idx : -1;
+      if (out_mask) out_mask[p] = hit ? 1 : 0;
+      if (hit && vs.n > 0) s_pairs[atomicAdd(&s_hits, 1u)] = make_uint2(idx, p);
+    }
+  }
+  if (vs.n > 0) {
+    __syncthreads();
+    const uint32_t hits = s_hits;
+    for (int j = 0; j < vs.n; ++j) copy_rows(vs, j, s_pairs, hits);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Erase pass 1: locate each key; the lowest position per buffer index wins
+// through atomicMin on owner[i] (owner starts at INT32_MAX).
+template <int KD, int G>
+__global__ __launch_bounds__(kBlock) void k_erase_mark(TableRef tb, const int32_t* __restrict__ keys, uint32_t n,
+                                                       uint32_t rounds, uint32_t* __restrict__ slot_of,
+                                                       int32_t* __restrict__ found_idx,
+                                                       int32_t* __restrict__ owner) {
+  constexpr int S = SlotWords<KD>::value;
+  constexpr uint32_t kGroups = kBlock / G;
+  const uint32_t sub = threadIdx.x & (G - 1);
+  const uint32_t grp = threadIdx.x / G;
+  const uint32_t tile_base = blockIdx.x * kGroups * rounds;
+  for (uint32_t r = 0; r < rounds; ++r) {
+    const uint32_t p = tile_base + r * kGroups + grp;
+    if (p >= n) break;
+    int32_t k[KD];
+#pragma unroll
+    for (int d = 0; d < KD; ++d) k[d] = keys[(size_t)p * KD + d];
+    const uint64_t h = key_hash<KD>(k);
+    uint32_t base = home_slot(tb, h);
+    uint32_t idx = kNoSlot, where = kNoSlot;
+    for (uint32_t w = 0; w < tb.max_windows; ++w) {
+      uint32_t s = base + sub;
+      if (s >= tb.nslots) s -= tb.nslots;
+      const Slot<S> sl = load_slot<S>(tb.words + (size_t)s * S);
+      const uint32_t st = sl.w[S - 1];
+      const uint64_t mh = group_ballot<G>(st < kPending && slot_holds<KD, S>(sl, k));
+      if (mh) {
+        const uint32_t L = first_lane(mh);
+        if (sub == L) atomic_min_u32(reinterpret_cast<uint32_t*>(owner) + st, p);
+        idx = group_bcast<G>(st, L);
+        where = group_bcast<G>(s, L);
+        break;
+      }
+      if (group_ballot<G>(st == kEmpty)) break;
+      base += G;
+      if (base >= tb.nslots) base -= tb.nslots;
+    }
+    if (sub == 0) {
+      slot_of[p] = where;
+      found_idx[p] = idx == kNoSlot ? -1 : (int32_t)idx;
+    }
+  }
+}
+
+// Erase pass 2: winners tombstone their slot and push their index back on the
+// heap in batch order: the r-th winner writes h[t - 1 - r].
+template <int KD>
+__global__ __launch_bounds__(kBlock) void k_erase_commit(TableRef tb, uint32_t n, const uint32_t* __restrict__ slot_of,
+                                                         const int32_t* __restrict__ found_idx,
+                                                         int32_t* __restrict__ owner, int32_t* __restrict__ heap,
+                                                         uint8_t* __restrict__ active, uint8_t* __restrict__ out_mask,
+                                                         Meta* meta, uint64_t* __restrict__ status) {
+  constexpr int S = SlotWords<KD>::value;
+  __shared__ uint32_t s_tile;
+  __shared__ uint32_t s_prefix;
+  __shared__ uint64_t s_scan[kBlock / 64 + 1];
+  const uint32_t tile = take_ticket(&meta->ticket, &s_tile);
+  const uint32_t t0 = meta->t;
+  const uint32_t base = tile * kScanTile;
+  bool win[kScanItems];
+  int32_t idx[kScanItems];
+#pragma unroll
+  for (int r = 0; r < kScanItems; ++r) {
+    const uint32_t p = base + r * kBlock + threadIdx.x;
+    idx[r] = p < n ? found_idx[p] : -1;
+    win[r] = idx[r] >= 0 && (uint32_t)owner[idx[r]] == p;
+  }
+  uint32_t rank[kScanItems];
+  uint32_t total;
+  block_rank_rows(win, rank, total, s_scan);
+  if (threadIdx.x == 0) s_prefix = tile_lookback(status, tile, meta->epoch, total, &meta->status);
+  __syncthreads();
+  const uint32_t prefix = s_prefix;
+#pragma unroll
+  for (int r = 0; r < kScanItems; ++r) {
+    const uint32_t p = base + r * kBlock + threadIdx.x;
+    if (p >= n) continue;
+    if (win[r] && prefix + rank[r] < t0) {  // winners are distinct live indices: always true
+      const uint32_t i = (uint32_t)idx[r];
+      heap[t0 - 1u - (prefix + rank[r])] = (int32_t)i;
+      tb.words[(size_t)slot_of[p] * S + S - 1] = kTomb;
+      active[i] = 0;
+      owner[i] = 0x7FFFFFFF;
+    }
+    if (out_mask) out_mask[p] = win[r] ? 1 : 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Active indices (ascending) by compaction of the per-index flags.
+__global__ __launch_bounds__(kBlock) void k_compact_active(const uint8_t* __restrict__ active, uint32_t c,
+                                                           int32_t* __restrict__ out, Meta* meta,
+                                                           uint64_t* __restrict__ status) {
+  __shared__ uint32_t s_tile;
+  __shared__ uint32_t s_prefix;
+  __shared__ uint64_t s_scan[kBlock / 64 + 1];
+  const uint32_t tile = take_ticket(&meta->ticket, &s_tile);
+  const uint32_t base = tile * kScanTile;
+  bool on[kScanItems];
+#pragma unroll
+  for (int r = 0; r < kScanItems; ++r) {
+    const uint32_t i = base + r * kBlock + threadIdx.x;
+    on[r] = i < c && active[i] != 0;
+  }
+  uint32_t rank[kScanItems];
+  uint32_t total;
+  block_rank_rows(on, rank, total, s_scan);
+  if (threadIdx.x == 0) s_prefix = tile_lookback(status, tile, meta->epoch, total, &meta->status);
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kScanItems; ++r)
+    if (on[r]) out[s_prefix + rank[r]] = (int32_t)(base + r * kBlock + threadIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Rebuild a fresh table from (k^B[i], i) for every live index i (rehash,
+// Sec. 4.5).  Keys are distinct, so a position only looks for EMPTY slots.
+template <int KD, int G>
+__global__ __launch_bounds__(kBlock) void k_rebuild(TableRef tb, const int32_t* __restrict__ kB,
+                                                    const uint8_t* __restrict__ active, uint32_t c, uint32_t rounds,
+                                                    Meta* meta) {
+  constexpr int S = SlotWords<KD>::value;
+  constexpr uint32_t kGroups = kBlock / G;
+  const uint32_t sub = threadIdx.x & (G - 1);
+  const uint32_t grp = threadIdx.x / G;
+  const uint32_t tile_base = blockIdx.x * kGroups * rounds;
+  uint32_t unresolved = 0;
+  for (uint32_t r = 0; r < rounds; ++r) {
+    const uint32_t i = tile_base + r * kGroups + grp;
+    if (i >= c) break;
+    if (!active[i]) continue;
+    int32_t k[KD];
+#pragma unroll
+    for (int d = 0; d < KD; ++d) k[d] = kB[(size_t)i * KD + d];
+    const uint64_t h = key_hash<KD>(k);
+    uint32_t base = home_slot(tb, h);
+    bool done = false;
+    for (uint32_t w = 0; w < tb.max_windows && !done; ++w) {
+      uint32_t s = base + sub;
+      if (s >= tb.nslots) s -= tb.nslots;
+      uint32_t* sp = tb.words + (size_t)s * S;
+      uint32_t st = sp[S - 1];
+      while (true) {
+        const uint64_t me = group_ballot<G>(st == kEmpty);
+        if (!me) break;
+        const uint32_t L = first_lane(me);
+        uint32_t won = 0;
+        if (sub == L) {
+          const uint64_t desired = ((uint64_t)i << 32) | (uint32_t)k[KD - 1];
+          const uint64_t found = cas_pair(sp + S - 2, kEmptyPair, desired);
+          won = found == kEmptyPair;
+          if (won) {
+#pragma unroll
+            for (int d = 0; d < KD - 1; ++d) sp[d] = (uint32_t)k[d];
+          } else {
+            st = (uint32_t)(found >> 32);
+          }
+        }
+        if (group_bcast<G>(won, L)) {
+          done = true;
+          break;
+        }
+      }
+      base += G;
+      if (base >= tb.nslots) base -= tb.nslots;
+    }
+    if (!done) unresolved = 1;
+  }
+  if (wave_sum(unresolved) && lane_id() == 0) atomic_add_u32(&meta->fail, 1u);
+}
+
+// ---------------------------------------------------------------------------
+// Voxelization pass 2: the first occurrence of each voxel gets the id
+// rank-of-first-occurrence; its slot becomes COMMITTED(id).
+__global__ __launch_bounds__(kBlock) void k_voxel_commit(TableRef tb, VoxelKeys src, uint32_t n,
+                                                         const uint32_t* __restrict__ slot_of,
+                                                         int32_t* __restrict__ voxel_keys,
+                                                         int32_t* __restrict__ counts, Meta* meta,
+                                                         uint64_t* __restrict__ status) {
+  constexpr int S = SlotWords<3>::value;
+  __shared__ uint32_t s_tile;
+  __shared__ uint32_t s_prefix;
+  __shared__ uint64_t s_scan[kBlock / 64 + 1];
+  const uint32_t tile = take_ticket(&meta->ticket, &s_tile);
+  const uint32_t base = tile * kScanTile;
+  bool win[kScanItems];
+  uint32_t slot[kScanItems];
+#pragma unroll
+  for (int r = 0; r < kScanItems; ++r) {
+    const uint32_t p = base + r * kBlock + threadIdx.x;
+    slot[r] = p < n ? slot_of[p] : kNoSlot;
+    win[r] = slot[r] != kNoSlot && tb.words[(size_t)slot[r] * S + S - 1] == kPending + p;
+  }
+  uint32_t rank[kScanItems];
+  uint32_t total;
+  block_rank_rows(win, rank, total, s_scan);
+  if (threadIdx.x == 0) s_prefix = tile_lookback(status, tile, meta->epoch, total, &meta->status);
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kScanItems; ++r) {
+    if (!win[r]) continue;
+    const uint32_t p = base + r * kBlock + threadIdx.x;
+    const uint32_t id = s_prefix + rank[r];
+    int32_t k[3];
+    src.load(p, k);
+    voxel_keys[(size_t)id * 3 + 0] = k[0];
+    voxel_keys[(size_t)id * 3 + 1] = k[1];
+    voxel_keys[(size_t)id * 3 + 2] = k[2];
+    counts[id] = 0;
+    tb.words[(size_t)slot[r] * S + S - 1] = id;
+  }
+}
+
+// Voxelization pass 3: per-point voxel id and per-voxel counts.
+__global__ __launch_bounds__(kBlock) void k_voxel_resolve(TableRef tb, uint32_t n, const uint32_t* __restrict__ slot_of,
+                                                          int32_t* __restrict__ point_voxel,
+                                                          int32_t* __restrict__ counts) {
+  constexpr int S = SlotWords<3>::value;
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const uint32_t s = slot_of[p];
+  if (s == kNoSlot) {
+    point_voxel[p] = -1;
+    return;
+  }
+  const uint32_t id = tb.words[(size_t)s * S + S - 1];
+  if (id >= n) {  // cannot happen once every claimed slot is committed
+    point_voxel[p] = -1;
+    return;
+  }
+  point_voxel[p] = (int32_t)id;
+  atomic_add_u32(reinterpret_cast<uint32_t*>(counts) + id, 1u);
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+static inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  uint32_t grid = (uint32_t)std::min<size_t>((n / 4 + kBlock - 1) / kBlock + 1, 65536);
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid), dim3(kBlock), 0, st, p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_iota(int32_t* h, uint32_t from, uint32_t to, hipStream_t st) {
+  if (to <= from) return hipSuccess;
+  uint32_t grid = std::min<uint32_t>(cdiv(to - from, kBlock), 65536);
+  hipLaunchKernelGGL(k_iota, dim3(grid), dim3(kBlock), 0, st, h, from, to);
+  return hipGetLastError();
+}
+
+hipError_t launch_reset_meta(Meta* m, hipStream_t st) {
+  hipLaunchKernelGGL(k_reset_meta, dim3(1), dim3(1), 0, st, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(Meta* m, uint32_t cap, int mode, int silent, const uint64_t* status, uint32_t last_tile,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1), 0, st, m, cap, mode, silent, status, last_tile);
+  return hipGetLastError();
+}
+
+// Positions per block of the probing kernels: 256 (G lanes per position).
+template <int G>
+static inline uint32_t rounds_for() { return 256u / (kBlock / G); }
+
+template <int KD, int G>
+static hipError_t claim_kg(const TableRef& tb, const int32_t* keys, uint32_t n, uint32_t* slot_of, Meta* meta,
+                           hipStream_t st) {
+  const uint32_t rounds = rounds_for<G>();
+  const uint32_t grid = cdiv(n, (kBlock / G) * rounds);
+  hipLaunchKernelGGL((k_claim<KD, G, BatchKeys<KD>>), dim3(grid), dim3(kBlock), 0, st, tb, BatchKeys<KD>{keys}, n,
+                     rounds, slot_of, meta);
+  return hipGetLastError();
+}
+
+template <int KD, int G>
+static hipError_t find_kg(const TableRef& tb, const int32_t* keys, uint32_t n, int32_t* out_idx, uint8_t* out_mask,
+                          const ValueSet& vs, hipStream_t st) {
+  const uint32_t rounds = rounds_for<G>();
+  const uint32_t grid = cdiv(n, (kBlock / G) * rounds);
+  hipLaunchKernelGGL((k_find<KD, G>), dim3(grid), dim3(kBlock), 0, st, tb, keys, n, rounds, out_idx, out_mask, vs);
+  return hipGetLastError();
+}
+
+template <int KD, int G>
+static hipError_t erase_mark_kg(const TableRef& tb, const int32_t* keys, uint32_t n, uint32_t* slot_of,
+                                int32_t* found, int32_t* owner, hipStream_t st) {
+  const uint32_t rounds = rounds_for<G>();
+  const uint32_t grid = cdiv(n, (kBlock / G) * rounds);
+  hipLaunchKernelGGL((k_erase_mark<KD, G>), dim3(grid), dim3(kBlock), 0, st, tb, keys, n, rounds, slot_of, found,
+                     owner);
+  return hipGetLastError();
+}
+
+template <int KD, int G>
+static hipError_t rebuild_kg(const TableRef& tb, const int32_t* kB, const uint8_t* active, uint32_t c, Meta* meta,
+                             hipStream_t st) {
+  const uint32_t rounds = rounds_for<G>();
+  const uint32_t grid = cdiv(c, (kBlock / G) * rounds);
+  hipLaunchKernelGGL((k_rebuild<KD, G>), dim3(grid), dim3(kBlock), 0, st, tb, kB, active, c, rounds, meta);
+  return hipGetLastError();
+}
+
+template <int G>
+static hipError_t voxel_claim_g(const TableRef& tb, const float* pts, float voxel, uint32_t n, uint32_t* slot_of,
+                                Meta* meta, hipStream_t st) {
+  const uint32_t rounds = rounds_for<G>();
+  const uint32_t grid = cdiv(n, (kBlock / G) * rounds);
+  hipLaunchKernelGGL((k_claim<3, G, VoxelKeys>), dim3(grid), dim3(kBlock), 0, st, tb, VoxelKeys{pts, voxel}, n,
+                     rounds, slot_of, meta);
+  return hipGetLastError();
+}
+
+template <int KD>
+static hipError_t commit_k(const TableRef& tb, const int32_t* keys, uint32_t n, const uint32_t* slot_of, int32_t* kB,
+                           const int32_t* heap, uint8_t* active, uint32_t cap, const ValueSet& vs, int32_t* out_idx,
+                           uint8_t* out_mask, Meta* meta, uint64_t* status, hipStream_t st) {
+  hipLaunchKernelGGL((k_commit<KD>), dim3(cdiv(n, kScanTile)), dim3(kBlock), 0, st, tb, keys, n, slot_of, kB, heap,
+                     active, cap, vs, out_idx, out_mask, meta, status);
+  return hipGetLastError();
+}
+
+template <int KD>
+static hipError_t erase_commit_k(const TableRef& tb, uint32_t n, const uint32_t* slot_of, const int32_t* found,
+                                 int32_t* owner, int32_t* heap, uint8_t* active, uint8_t* out_mask, Meta* meta,
+                                 uint64_t* status, hipStream_t st) {
+  hipLaunchKernelGGL((k_erase_commit<KD>), dim3(cdiv(n, kScanTile)), dim3(kBlock), 0, st, tb, n, slot_of, found,
+                     owner, heap, active, out_mask, meta, status);
+  return hipGetLastError();
+}
+
+// Dispatch on the probe-group width G.
+template <template <int> class F, typename... A>
+static hipError_t with_g(int g, A&&... a) {
+  switch (g) {
+    case 4: return F<4>::run(a...);
+    case 8: return F<8>::run(a...);
+    case 16: return F<16>::run(a...);
+    case 32: return F<32>::run(a...);
+    case 64: return F<64>::run(a...);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int KD>
+struct ClaimG {
+  template <int G>
+  struct F {
+    template <typename... A>
+    static hipError_t run(A&&... a) { return claim_kg<KD, G>(a...); }
+  };
+};
+template <int KD>
+struct FindG {
+  template <int G>
+  struct F {
+    template <typename... A>
+    static hipError_t run(A&&... a) { return find_kg<KD, G>(a...); }
+  };
+};
+template <int KD>
+struct EraseMarkG {
+  template <int G>
+  struct F {
+    template <typename... A>
+    static hipError_t run(A&&... a) { return erase_mark_kg<KD, G>(a...); }
+  };
+};
+template <int KD>
+struct RebuildG {
+  template <int G>
+  struct F {
+    template <typename... A>
+    static hipError_t run(A&&... a) { return rebuild_kg<KD, G>(a...); }
+  };
+};
+template <int G>
+struct VoxelClaimG {
+  template <typename... A>
+  static hipError_t run(A&&... a) { return voxel_claim_g<G>(a...); }
+};
+
+hipError_t launch_claim(int kd, int g, const TableRef& tb, const int32_t* keys, uint32_t n, uint32_t* slot_of,
+                        Meta* meta, hipStream_t st) {
+  switch (kd) {
+    case 1: return with_g<ClaimG<1>::F>(g, tb, keys, n, slot_of, meta, st);
+    case 2: return with_g<ClaimG<2>::F>(g, tb, keys, n, slot_of, meta, st);
+    case 3: return with_g<ClaimG<3>::F>(g, tb, keys, n, slot_of, meta, st);
+    case 4: return with_g<ClaimG<4>::F>(g, tb, keys, n, slot_of, meta, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_commit(int kd, const TableRef& tb, const int32_t* keys, uint32_t n, const uint32_t* slot_of,
+                         int32_t* kB, const int32_t* heap, uint8_t* active, uint32_t cap, const ValueSet& vs,
+                         int32_t* out_idx, uint8_t* out_mask, Meta* meta, uint64_t* status, hipStream_t st) {
+  switch (kd) {
+    case 1: return commit_k<1>(tb, keys, n, slot_of, kB, heap, active, cap, vs, out_idx, out_mask, meta, status, st);
+    case 2: return commit_k<2>(tb, keys, n, slot_of, kB, heap, active, cap, vs, out_idx, out_mask, meta, status, st);
+    case 3: return commit_k<3>(tb, keys, n, slot_of, kB, heap, active, cap, vs, out_idx, out_mask, meta, status, st);
+    case 4: return commit_k<4>(tb, keys, n, slot_of, kB, heap, active, cap, vs, out_idx, out_mask, meta, status, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_find(int kd, int g, const TableRef& tb, const int32_t* keys, uint32_t n, int32_t* out_idx,
+                       uint8_t* out_mask, const ValueSet& vs, hipStream_t st) {
+  switch (kd) {
+    case 1: return with_g<FindG<1>::F>(g, tb, keys, n, out_idx, out_mask, vs, st);
+    case 2: return with_g<FindG<2>::F>(g, tb, keys, n, out_idx, out_mask, vs, st);
+    case 3: return with_g<FindG<3>::F>(g, tb, keys, n, out_idx, out_mask, vs, st);
+    case 4: return with_g<FindG<4>::F>(g, tb, keys, n, out_idx, out_mask, vs, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_erase_mark(int kd, int g, const TableRef& tb, const int32_t* keys, uint32_t n, uint32_t* slot_of,
+                             int32_t* found, int32_t* owner, hipStream_t st) {
+  switch (kd) {
+    case 1: return with_g<EraseMarkG<1>::F>(g, tb, keys, n, slot_of, found, owner, st);
+    case 2: return with_g<EraseMarkG<2>::F>(g, tb, keys, n, slot_of, found, owner, st);
+    case 3: return with_g<EraseMarkG<3>::F>(g, tb, keys, n, slot_of, found, owner, st);
+    case 4: return with_g<EraseMarkG<4>::F>(g, tb, keys, n, slot_of, found, owner, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_erase_commit(int kd, const TableRef& tb, uint32_t n, const uint32_t* slot_of, const int32_t* found,
+                               int32_t* owner, int32_t* heap, uint8_t* active, uint8_t* out_mask, Meta* meta,
+                               uint64_t* status, hipStream_t st) {
+  switch (kd) {
+    case 1: return erase_commit_k<1>(tb, n, slot_of, found, owner, heap, active, out_mask, meta, status, st);
+    case 2: return erase_commit_k<2>(tb, n, slot_of, found, owner, heap, active, out_mask, meta, status, st);
+    case 3: return erase_commit_k<3>(tb, n, slot_of, found, owner, heap, active, out_mask, meta, status, st);
+    case 4: return erase_commit_k<4>(tb, n, slot_of, found, owner, heap, active, out_mask, meta, status, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_compact_active(const uint8_t* active, uint32_t c, int32_t* out, Meta* meta, uint64_t* status,
+                                 hipStream_t st) {
+  hipLaunchKernelGGL(k_compact_active, dim3(cdiv(c, kScanTile)), dim3(kBlock), 0, st, active, c, out, meta, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_rebuild(int kd, int g, const TableRef& tb, const int32_t* kB, const uint8_t* active, uint32_t c,
+                          Meta* meta, hipStream_t st) {
+  switch (kd) {
+    case 1: return with_g<RebuildG<1>::F>(g, tb, kB, active, c, meta, st);
+    case 2: return with_g<RebuildG<2>::F>(g, tb, kB, active, c, meta, st);
+    case 3: return with_g<RebuildG<3>::F>(g, tb, kB, active, c, meta, st);
+    case 4: return with_g<RebuildG<4>::F>(g, tb, kB, active, c, meta, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_voxel_claim(int g, const TableRef& tb, const float* pts, float voxel, uint32_t n,
+                              uint32_t* slot_of, Meta* meta, hipStream_t st) {
+  return with_g<VoxelClaimG>(g, tb, pts, voxel, n, slot_of, meta, st);
+}
+
+hipError_t launch_voxel_commit(const TableRef& tb, const float* pts, float voxel, uint32_t n, const uint32_t* slot_of,
+                               int32_t* voxel_keys, int32_t* counts, Meta* meta, uint64_t* status, hipStream_t st) {
+  hipLaunchKernelGGL(k_voxel_commit, dim3(cdiv(n, kScanTile)), dim3(kBlock), 0, st, tb, VoxelKeys{pts, voxel}, n,
+                     slot_of, voxel_keys, counts, meta, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_voxel_resolve(const TableRef& tb, uint32_t n, const uint32_t* slot_of, int32_t* point_voxel,
+                                int32_t* counts, hipStream_t st) {
+  hipLaunchKernelGGL(k_voxel_resolve, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, tb, n, slot_of, point_voxel,
+                     counts);
+  return hipGetLastError();
+}
+
+}  // namespace ash

@@ -1,0 +1,211 @@
+"""Tensor interface of the MI355X hash map (ASH, arXiv 2110.00511).
+
+As in the paper's tensor interface (Sec. 3, Fig. 1), every call returns buffer
+indices and masks; keys and values are read and modified in place through
+the key / value buffers (advanced indexing with the returned indices).
+Inputs and outputs are torch tensors on the GPU; all work runs in libash.so.
+"""
+import ctypes
+
+import torch
+
+from . import _lib as L
+
+_DTYPES = {
+    torch.uint8: L.ASH_U8, torch.int32: L.ASH_I32, torch.float32: L.ASH_F32, torch.int64: L.ASH_I64,
+    torch.float64: L.ASH_F64, torch.float16: L.ASH_F16, torch.bfloat16: L.ASH_BF16,
+}
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _keys(keys, key_dim, device):
+    if not (keys.is_cuda and keys.dtype == torch.int32):
+        raise TypeError("keys must be an int32 tensor on the GPU")
+    keys = keys.reshape(-1, key_dim)
+    if not keys.is_contiguous():
+        keys = keys.contiguous()
+    return keys
+
+
+class HashMap:
+    """int32 keys of `key_dim` words -> one or more value buffers.
+
+    value_specs: sequence of (torch dtype, elements per row).  Tuning:
+    bucket_width W, probe_group g (lanes per key), max_load, autogrow."""
+
+    def __init__(self, capacity, key_dim=3, value_specs=(), device="cuda", bucket_width=4, probe_group=4,
+                 max_load=0.5, autogrow=False):
+        self._lib = L.load()
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.key_dim = int(key_dim)
+        self.value_specs = [(dt, int(e)) for dt, e in value_specs]
+        n = len(self.value_specs)
+        dts = (ctypes.c_int * max(n, 1))(*[_DTYPES[dt] for dt, _ in self.value_specs])
+        els = (ctypes.c_int64 * max(n, 1))(*[e for _, e in self.value_specs])
+        self._alloc = L.TorchAllocator(self.device)
+        tun = L.AshTuning(bucket_width, probe_group, max_load, L.ASH_F_AUTOGROW if autogrow else 0)
+        self._m = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            L.check(self._lib.ash_create(int(capacity), self.key_dim, n, ctypes.cast(dts, ctypes.c_void_p),
+                                         ctypes.cast(els, ctypes.c_void_p), ctypes.byref(self._alloc.struct),
+                                         ctypes.byref(tun), _stream(), ctypes.byref(self._m)), "ash_create")
+
+    def __del__(self):
+        m = getattr(self, "_m", None)
+        if m is not None and m.value:
+            self._lib.ash_destroy(m)
+            self._m = None
+
+    # -- operations ---------------------------------------------------------
+    def insert(self, keys, values=()):
+        keys = _keys(keys, self.key_dim, self.device)
+        n = keys.shape[0]
+        if len(values) != len(self.value_specs):
+            raise ValueError("one value tensor per value buffer is required")
+        vals = []
+        for v, (dt, e) in zip(values, self.value_specs):
+            if v.dtype != dt or not v.is_cuda:
+                raise TypeError(f"value tensor must be {dt} on the GPU")
+            vals.append(v.reshape(n, e).contiguous())
+        idx = torch.empty(n, dtype=torch.int32, device=self.device)
+        mask = torch.empty(n, dtype=torch.uint8, device=self.device)
+        arr = (ctypes.c_void_p * max(len(vals), 1))(*[v.data_ptr() for v in vals])
+        L.check(self._lib.ash_insert(self._m, _ptr(keys), n, ctypes.cast(arr, ctypes.c_void_p) if vals else None,
+                                     _ptr(idx), _ptr(mask), _stream()), "ash_insert")
+        return idx, mask.bool()
+
+    def activate(self, keys):
+        keys = _keys(keys, self.key_dim, self.device)
+        n = keys.shape[0]
+        idx = torch.empty(n, dtype=torch.int32, device=self.device)
+        mask = torch.empty(n, dtype=torch.uint8, device=self.device)
+        L.check(self._lib.ash_activate(self._m, _ptr(keys), n, _ptr(idx), _ptr(mask), _stream()), "ash_activate")
+        return idx, mask.bool()
+
+    def find(self, keys, gather=False, out_values=None):
+        keys = _keys(keys, self.key_dim, self.device)
+        n = keys.shape[0]
+        idx = torch.empty(n, dtype=torch.int32, device=self.device)
+        mask = torch.empty(n, dtype=torch.uint8, device=self.device)
+        outs = None
+        if gather:
+            outs = out_values if out_values is not None else [
+                torch.zeros((n, e), dtype=dt, device=self.device) for dt, e in self.value_specs]
+        arr = (ctypes.c_void_p * max(len(outs or []), 1))(*[o.data_ptr() for o in (outs or [])])
+        L.check(self._lib.ash_find(self._m, _ptr(keys), n, _ptr(idx), _ptr(mask),
+                                   ctypes.cast(arr, ctypes.c_void_p) if outs else None, _stream()), "ash_find")
+        return (idx, mask.bool(), outs) if gather else (idx, mask.bool())
+
+    def erase(self, keys):
+        keys = _keys(keys, self.key_dim, self.device)
+        n = keys.shape[0]
+        mask = torch.empty(n, dtype=torch.uint8, device=self.device)
+        L.check(self._lib.ash_erase(self._m, _ptr(keys), n, _ptr(mask), _stream()), "ash_erase")
+        return mask.bool()
+
+    def active_indices(self):
+        out = torch.empty(max(self.capacity, 1), dtype=torch.int32, device=self.device)
+        cnt = ctypes.c_int64()
+        L.check(self._lib.ash_active_indices(self._m, _ptr(out), ctypes.byref(cnt), _stream()), "ash_active_indices")
+        return out[: cnt.value]
+
+    def rehash(self, new_capacity):
+        L.check(self._lib.ash_rehash(self._m, int(new_capacity), _stream()), "ash_rehash")
+
+    def clear(self):
+        L.check(self._lib.ash_clear(self._m, _stream()), "ash_clear")
+
+    def device_status(self):
+        """Returns and clears the sticky device error as a status code."""
+        return self._lib.ash_device_status(self._m, _stream())
+
+    def profile(self, enable=True):
+        """Brackets every kernel launch of this map with HIP events."""
+        L.check(self._lib.ash_profile_enable(self._m, 1 if enable else 0), "ash_profile_enable")
+
+    def profile_collect(self):
+        """{kernel name: (launches, total milliseconds)} since the last collect."""
+        buf = (L.AshKernelTime * 32)()
+        n = ctypes.c_int32()
+        L.check(self._lib.ash_profile_collect(self._m, buf, 32, ctypes.byref(n), _stream()), "ash_profile_collect")
+        return {buf[i].name.decode(): (buf[i].launches, buf[i].total_ms) for i in range(n.value)}
+
+    # -- state --------------------------------------------------------------
+    def size(self):
+        out = ctypes.c_int64()
+        L.check(self._lib.ash_size(self._m, ctypes.byref(out), _stream()), "ash_size")
+        return out.value
+
+    @property
+    def capacity(self):
+        out = ctypes.c_int64()
+        L.check(self._lib.ash_capacity(self._m, ctypes.byref(out)), "ash_capacity")
+        return out.value
+
+    def stats(self):
+        s = L.AshStats()
+        L.check(self._lib.ash_stats(self._m, ctypes.byref(s), _stream()), "ash_stats")
+        return dict(size=s.size, capacity=s.capacity, slots=s.slots, used_slots=s.used_slots, tombstones=s.tombstones)
+
+    def _view(self, ptr, dtype, shape):
+        count = 1
+        for d in shape:
+            count *= d
+        base = self._alloc.tensor(ptr)
+        return base.view(dtype)[:count].view(*shape)
+
+    def key_buffer(self):
+        """k^B as a [capacity, key_dim] int32 tensor sharing the map's memory."""
+        p = ctypes.c_void_p()
+        L.check(self._lib.ash_key_buffer(self._m, ctypes.byref(p)), "ash_key_buffer")
+        return self._view(p.value, torch.int32, (self.capacity, self.key_dim))
+
+    def value_buffer(self, j=0):
+        """v^B_j as a [capacity, elems] tensor sharing the map's memory."""
+        p = ctypes.c_void_p()
+        L.check(self._lib.ash_value_buffer(self._m, j, ctypes.byref(p)), "ash_value_buffer")
+        dt, e = self.value_specs[j]
+        return self._view(p.value, dt, (self.capacity, e))
+
+    def heap_buffer(self):
+        """Index heap h as a [capacity] int32 tensor (t = size())."""
+        p = ctypes.c_void_p()
+        L.check(self._lib.ash_heap_buffer(self._m, ctypes.byref(p)), "ash_heap_buffer")
+        return self._view(p.value, torch.int32, (self.capacity,))
+
+
+class HashSet(HashMap):
+    """Hash map without value buffers (Sec. 4.7)."""
+
+    def __init__(self, capacity, key_dim=3, **kw):
+        super().__init__(capacity, key_dim=key_dim, value_specs=(), **kw)
+
+
+def voxelize(points, voxel_size):
+    """Point-cloud voxelization (Sec. 6.1): returns (point_voxel [n] int32,
+    voxel_keys [u, 3] int32, counts [u] int32), voxels in first-occurrence
+    order; rejected points (non-finite or out of int32 range) get -1."""
+    lib = L.load()
+    if not (points.is_cuda and points.dtype == torch.float32):
+        raise TypeError("points must be a float32 tensor on the GPU")
+    pts = points.reshape(-1, 3).contiguous()
+    n = pts.shape[0]
+    dev = pts.device
+    pv = torch.empty(n, dtype=torch.int32, device=dev)
+    vk = torch.empty((max(n, 1), 3), dtype=torch.int32, device=dev)
+    cnt = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    nv = ctypes.c_int64()
+    alloc = L.TorchAllocator(dev)
+    L.check(lib.ash_voxelize(_ptr(pts), n, ctypes.c_float(float(voxel_size)), _ptr(pv), _ptr(vk), _ptr(cnt),
+                             ctypes.byref(nv), ctypes.byref(alloc.struct), _stream()), "ash_voxelize")
+    u = nv.value
+    return pv, vk[:u], cnt[:u]

@@ -1,0 +1,70 @@
+"""The C-ABI library loads on a machine without a GPU and exports every
+function include/ash.h declares; the Python binding declares the same names.
+No compute call is made here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ash.h")
+LIB = os.path.join(ROOT, "paper_2110_00511_amd", "libash.so")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ash_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_2110_00511_amd.build import build
+        build()
+    import torch  # noqa: F401  (the binding loads torch's HIP runtime first)
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_operations():
+    names = declared()
+    for op in ("ash_create", "ash_destroy", "ash_insert", "ash_activate", "ash_find", "ash_erase",
+               "ash_active_indices", "ash_rehash", "ash_voxelize", "ash_size", "ash_device_status"):
+        assert op in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert not missing, f"not exported: {missing}"
+
+
+def test_binding_covers_the_header(lib):
+    from paper_2110_00511_amd import _lib
+    assert sorted(_lib.SIGNATURES) == declared()
+    _lib.load()
+
+
+def test_status_strings_and_host_side_errors(lib):
+    from paper_2110_00511_amd import _lib
+    L = _lib.load()
+    assert L.ash_status_string(0) == b"ok"
+    assert L.ash_status_string(2) == b"capacity exceeded"
+    out = ctypes.c_void_p()
+    # rejected before any device work: bad key_dim, bad capacity, NULL output
+    assert L.ash_create(10, 0, 0, None, None, None, None, None, ctypes.byref(out)) == _lib.ASH_E_INVALID
+    assert L.ash_create(10, 5, 0, None, None, None, None, None, ctypes.byref(out)) == _lib.ASH_E_INVALID
+    assert L.ash_create(-1, 3, 0, None, None, None, None, None, ctypes.byref(out)) == _lib.ASH_E_INVALID
+    assert L.ash_create(1 << 31, 3, 0, None, None, None, None, None, ctypes.byref(out)) == _lib.ASH_E_INVALID
+    assert L.ash_create(10, 3, 0, None, None, None, None, None, None) == _lib.ASH_E_INVALID
+    bad = _lib.AshTuning(4, 5, 0.5, 0)
+    assert L.ash_create(10, 3, 0, None, None, None, ctypes.byref(bad), None, ctypes.byref(out)) == _lib.ASH_E_INVALID
+    bad = _lib.AshTuning(4, 4, 0.95, 0)
+    assert L.ash_create(10, 3, 0, None, None, None, ctypes.byref(bad), None, ctypes.byref(out)) == _lib.ASH_E_INVALID
+    n = ctypes.c_int64()
+    assert L.ash_voxelize(None, 10, ctypes.c_float(0.01), None, None, None, ctypes.byref(n), None, None) == _lib.ASH_E_INVALID
+    assert L.ash_voxelize(None, 0, ctypes.c_float(-1.0), None, None, None, ctypes.byref(n), None, None) == _lib.ASH_E_INVALID
+    assert L.ash_voxelize(None, 0, ctypes.c_float(0.01), None, None, None, ctypes.byref(n), None, None) == _lib.ASH_OK
+    assert n.value == 0
+    assert L.ash_insert(None, None, 0, None, None, None, None) == _lib.ASH_E_INVALID
+    assert L.ash_destroy(None) == _lib.ASH_E_INVALID

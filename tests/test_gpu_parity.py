@@ -1,0 +1,360 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Buffer indices are handed out in batch order on both sides, so beyond the
+canonical checks (masks, key -> value maps, heap invariant) the GPU's indices,
+key buffer, value rows, heap and heap top must equal the oracle's exactly.
+Value rows of activated-only entries are excluded (the paper leaves them to
+the caller).  Every comparison is bit-exact (values compared as raw bits).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+import synth  # noqa: E402
+from oracle import ORACLE_E_CAPACITY, OracleMap  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ash():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2110_00511_amd as ash_mod
+    return ash_mod
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+def bits(a):
+    a = np.ascontiguousarray(a)
+    return a.view(np.uint8)
+
+
+class Pair:
+    """A GPU map and an oracle map driven with the same batches."""
+
+    def __init__(self, ash, capacity, key_dim=3, value_specs=(), **tuning):
+        self.gpu = ash.HashMap(capacity, key_dim=key_dim,
+                               value_specs=[(torch.from_numpy(np.zeros(1, dt)).dtype, e) for dt, e in value_specs],
+                               **tuning)
+        self.orc = OracleMap(capacity, key_dim, value_specs)
+        self.key_dim = key_dim
+        self.value_specs = [(np.dtype(dt), e) for dt, e in value_specs]
+        self.written = set()  # indices whose value rows were written by insert
+        self.overflowed = False  # an insert since the last check returned CAPACITY
+
+    def insert(self, keys, values):
+        gi, gm = self.gpu.insert(dev(keys), [dev(v) for v in values])
+        st, oi, om = self.orc.insert(keys, values, autogrow=self.gpu_autogrow())
+        gi, gm = host(gi), host(gm).astype(np.uint8)
+        self.overflowed |= st == ORACLE_E_CAPACITY
+        assert np.array_equal(gm, om), "insert masks differ"
+        assert np.array_equal(gi, oi), "insert indices differ"
+        self.written.update(oi[om == 1].tolist())
+        return st, oi, om
+
+    def activate(self, keys):
+        gi, gm = self.gpu.activate(dev(keys))
+        st, oi, om = self.orc.activate(keys, autogrow=self.gpu_autogrow())
+        self.overflowed |= st == ORACLE_E_CAPACITY
+        assert np.array_equal(host(gm).astype(np.uint8), om), "activate masks differ"
+        assert np.array_equal(host(gi), oi), "activate indices differ"
+        self.written.difference_update(oi[om == 1].tolist())
+        return st, oi, om
+
+    def find(self, keys, gather=True):
+        if gather and self.value_specs:
+            gi, gm, gout = self.gpu.find(dev(keys), gather=True)
+            st, oi, om, oout = self.orc.find(keys, gather=True, fill=0)
+            for j, (g, o) in enumerate(zip(gout, oout)):
+                g = host(g)
+                hit = om == 1
+                ok = np.isin(oi, list(self.written)) & hit
+                assert np.array_equal(bits(g[ok]), bits(o[ok])), f"gathered values of buffer {j} differ"
+                assert np.array_equal(bits(g[~hit]), bits(np.zeros_like(o[~hit]))), "miss rows were modified"
+        else:
+            gi, gm = self.gpu.find(dev(keys))
+            st, oi, om = self.orc.find(keys)
+        assert np.array_equal(host(gm).astype(np.uint8), om), "find masks differ"
+        assert np.array_equal(host(gi), oi), "find indices differ"
+        return oi, om
+
+    def erase(self, keys):
+        gm = self.gpu.erase(dev(keys))
+        st, om = self.orc.erase(keys)
+        assert np.array_equal(host(gm).astype(np.uint8), om), "erase masks differ"
+        return om
+
+    def gpu_autogrow(self):
+        return getattr(self, "autogrow", False)
+
+    def check_state(self):
+        g = self.gpu
+        o = self.orc
+        torch.cuda.synchronize()
+        assert g.capacity == o.capacity
+        assert g.size() == o.size == o.heap_top
+        assert np.array_equal(host(g.heap_buffer()), o.heap()), "index heaps differ"
+        act = host(g.active_indices())
+        assert np.array_equal(act, o.active_indices()), "active indices differ"
+        kb = host(g.key_buffer())
+        assert np.array_equal(kb[act], o.key_buffer()[act]), "key buffers differ on live indices"
+        live_written = np.array(sorted(set(act.tolist()) & self.written), dtype=np.int64)
+        for j in range(len(self.value_specs)):
+            gv = host(g.value_buffer(j))
+            assert np.array_equal(bits(gv[live_written]), bits(o.value_buffer(j)[live_written])), \
+                f"value buffer {j} differs on live written indices"
+        stats = g.stats()
+        assert stats["size"] == o.size
+        assert g.device_status() == (2 if self.overflowed else 0), "sticky status differs from the oracle's"
+        self.overflowed = False
+
+
+def plain_small_sequence(pair, d):
+    pair.insert(d["keys"], [d["values"]])
+    pair.check_state()
+    pair.find(d["find_keys"])
+    pair.erase(d["erase_keys"])
+    pair.check_state()
+    pair.find(d["find_keys"])
+    pair.find(d["keys"])
+
+
+def test_plain_small_sequence(ash):
+    """65,536-key insert / find / erase / re-find (the CPU-checkable workload)."""
+    d = synth.plain_small()
+    pair = Pair(ash, d["capacity"], 3, [(np.float32, 1)])
+    plain_small_sequence(pair, d)
+
+
+@pytest.mark.parametrize("g,w,lf", [(4, 4, 0.5), (8, 8, 0.7), (16, 4, 0.85), (32, 32, 0.5), (64, 16, 0.9)])
+def test_tuning_grid_same_results(ash, g, w, lf):
+    d = synth.plain_small(seed=11)
+    pair = Pair(ash, d["capacity"], 3, [(np.float32, 1)], probe_group=g, bucket_width=w, max_load=lf)
+    plain_small_sequence(pair, d)
+
+
+@pytest.mark.parametrize("key_dim", [1, 2, 3, 4])
+def test_key_dims_and_value_types(ash, key_dim):
+    rng = np.random.default_rng(100 + key_dim)
+    n = 30_000
+    keys = rng.integers(-20, 20, size=(n, key_dim), dtype=np.int32)
+    specs = [(np.float32, 3), (np.uint8, 5), (np.float64, 2), (np.int32, 16)]
+    vals = [rng.standard_normal((n, 3)).astype(np.float32), rng.integers(0, 255, (n, 5), dtype=np.uint8),
+            rng.standard_normal((n, 2)), rng.integers(-9, 9, (n, 16), dtype=np.int32)]
+    pair = Pair(ash, 2 * n, key_dim, specs)
+    pair.insert(keys, vals)
+    pair.find(np.concatenate([keys[: n // 2], rng.integers(20, 40, size=(n // 2, key_dim), dtype=np.int32)]))
+    pair.erase(keys[rng.choice(n, n // 3, replace=False)])
+    pair.insert(rng.integers(-25, 25, size=(n // 2, key_dim), dtype=np.int32),
+                [v[: n // 2] for v in vals])
+    pair.check_state()
+    pair.find(keys)
+
+
+def test_hash_set_and_activate(ash):
+    rng = np.random.default_rng(5)
+    keys = rng.integers(0, 50, size=(40_000, 3), dtype=np.int32)
+    pair = Pair(ash, 80_000, 3, [])
+    pair.activate(keys)
+    pair.find(keys)
+    pair.erase(keys[:10_000])
+    pair.activate(keys[5_000:20_000])
+    pair.check_state()
+    # a map with values: activate leaves value rows alone, insert after activate is a miss
+    pv = Pair(ash, 1000, 3, [(np.float32, 4)])
+    k = rng.integers(0, 8, size=(600, 3), dtype=np.int32)
+    pv.activate(k)
+    pv.insert(k, [rng.standard_normal((600, 4)).astype(np.float32)])
+    pv.check_state()
+
+
+def test_edge_cases(ash):
+    pair = Pair(ash, 64, 3, [(np.float32, 1)])
+    z = np.zeros((0, 3), np.int32)
+    pair.insert(z, [np.zeros((0, 1), np.float32)])
+    pair.find(z)
+    pair.erase(z)
+    lo, hi = np.iinfo(np.int32).min, np.iinfo(np.int32).max
+    ext = np.array([[lo, lo, lo], [hi, hi, hi], [lo, hi, 0], [-1, -1, -1], [lo, lo, lo], [0, 0, 0]], np.int32)
+    pair.insert(ext, [np.arange(6, dtype=np.float32).reshape(6, 1)])
+    pair.find(ext)
+    # all-identical keys: exactly one winner, the lowest position
+    same = np.full((5000, 3), 7, np.int32)
+    st, oi, om = pair.insert(same, [np.arange(5000, dtype=np.float32).reshape(-1, 1)])
+    assert om.sum() == 1 and om[0] == 1
+    pair.erase(same)
+    pair.check_state()
+
+
+def test_capacity_overflow_rolls_back(ash):
+    rng = np.random.default_rng(9)
+    pair = Pair(ash, 1000, 3, [(np.float32, 2)])
+    k1 = rng.integers(0, 100, size=(900, 3), dtype=np.int32)
+    pair.insert(k1, [rng.standard_normal((900, 2)).astype(np.float32)])
+    before = host(pair.gpu.heap_buffer()).copy(), host(pair.gpu.key_buffer()).copy()
+    k2 = rng.integers(100, 200, size=(300, 3), dtype=np.int32)
+    gi, gm = pair.gpu.insert(dev(k2), [dev(rng.standard_normal((300, 2)).astype(np.float32))])
+    st, oi, om = pair.orc.insert(k2, [np.zeros((300, 2), np.float32)])
+    assert st == ORACLE_E_CAPACITY
+    assert np.all(host(gi) == -1) and not host(gm).any()
+    assert pair.gpu.device_status() == 2  # ASH_E_CAPACITY, then cleared
+    assert np.array_equal(host(pair.gpu.heap_buffer()), before[0])
+    pair.check_state()
+    pair.find(np.concatenate([k1, k2]))
+
+
+def test_autogrow(ash):
+    rng = np.random.default_rng(13)
+    pair = Pair(ash, 100, 3, [(np.float32, 1)], autogrow=True)
+    pair.autogrow = True
+    for step in range(6):
+        k = rng.integers(0, 40, size=(700, 3), dtype=np.int32)
+        pair.insert(k, [rng.standard_normal((700, 1)).astype(np.float32)])
+        pair.erase(k[:100])
+    pair.check_state()
+    assert pair.gpu.capacity == pair.orc.capacity
+
+
+def test_rehash_keeps_indices(ash):
+    rng = np.random.default_rng(17)
+    keys = rng.integers(0, 60, size=(50_000, 3), dtype=np.int32)
+    pair = Pair(ash, 60_000, 3, [(np.float32, 8)])
+    pair.insert(keys, [rng.standard_normal((50_000, 8)).astype(np.float32)])
+    pair.erase(keys[:20_000])
+    for new_c in (60_000, 100_000, 250_000):
+        pair.gpu.rehash(new_c)
+        assert pair.orc.rehash(new_c) == 0
+        pair.check_state()
+        pair.find(keys)
+    assert pair.gpu.stats()["tombstones"] == 0
+
+
+@pytest.mark.parametrize("capacity", [27_000, 4096])
+def test_erase_insert_churn(ash, capacity):
+    """Tombstones pile up under churn and are cleaned by table rebuilds; the
+    smaller capacity also overflows on some batches (map unchanged, CAPACITY)."""
+    rng = np.random.default_rng(21)
+    pair = Pair(ash, capacity, 3, [(np.int32, 1)], max_load=0.5)
+    cleaned = False
+    prev_tombs = 0
+    for step in range(40):
+        k = rng.integers(0, 30, size=(3000, 3), dtype=np.int32)
+        pair.insert(k, [rng.integers(0, 1000, (3000, 1), dtype=np.int32)])
+        pair.erase(rng.integers(0, 30, size=(3000, 3), dtype=np.int32))
+        pair.find(k, gather=False)
+        s = pair.gpu.stats()
+        assert s["used_slots"] <= s["capacity"] + (s["slots"] - s["capacity"]) // 2 + 3000
+        cleaned |= s["tombstones"] < prev_tombs  # a rebuild dropped the tombstones
+        prev_tombs = s["tombstones"]
+        if step % 10 == 9:
+            pair.check_state()
+    assert cleaned
+
+
+def test_small_table_long_probes(ash):
+    """Capacity 200 at max_load 0.9: windows wrap the table end, probes are long."""
+    rng = np.random.default_rng(23)
+    pair = Pair(ash, 200, 2, [(np.float32, 1)], max_load=0.9, probe_group=4, bucket_width=4)
+    k = rng.integers(0, 1000, size=(2000, 2), dtype=np.int32)
+    pair.insert(k[:400], [rng.standard_normal((400, 1)).astype(np.float32)])
+    pair.find(k)
+    pair.erase(k[:150])
+    pair.insert(k[150:500], [rng.standard_normal((350, 1)).astype(np.float32)])
+    pair.check_state()
+    pair.find(k)
+
+
+# ---------------------------------------------------------------------------
+# Voxelization
+def check_voxelize(ash, pts, voxel):
+    from oracle import oracle_voxelize
+    gpv, gvk, gcnt = ash.voxelize(dev(pts), voxel)
+    opv, ovk, ocnt = oracle_voxelize(pts, voxel)
+    assert np.array_equal(host(gpv), opv), "per-point voxel ids differ"
+    assert np.array_equal(host(gvk), ovk), "voxel keys differ"
+    assert np.array_equal(host(gcnt), ocnt), "voxel counts differ"
+    return opv, ovk, ocnt
+
+
+@pytest.mark.parametrize("voxel", [0.005, 0.01, 0.02, 0.05])
+def test_voxelize_surface_points(ash, voxel):
+    check_voxelize(ash, synth.points(n=300_000, seed=31), voxel)
+
+
+def test_voxelize_boundaries_and_rejects(ash):
+    s = np.float32(0.1)
+    k = np.arange(-3000, 3000, dtype=np.float32)
+    x = (k * s).astype(np.float32)
+    x = np.concatenate([x, np.nextafter(x, np.float32(np.inf)), np.nextafter(x, np.float32(-np.inf))])
+    pts = np.stack([x, -x, x * np.float32(0.5)], axis=1)
+    check_voxelize(ash, pts, s)
+    big = np.float32(3e38)
+    tiny = np.float32(1e-40)  # denormal
+    rej = np.array([[np.nan, 0, 0], [0, np.inf, 0], [0, 0, -np.inf], [big, 0, 0], [1.0, 1.0, 1.0],
+                    [-big, 0, 0], [-tiny, tiny, -0.0], [np.float32(2147483520.0), 0, 0],
+                    [np.float32(2.0 ** 31), 0, 0], [np.float32(-2.0 ** 31), 0, 0]], np.float32)
+    check_voxelize(ash, rej, 1.0)
+    check_voxelize(ash, rej, 0.005)
+    check_voxelize(ash, np.array([[0.5, 0.5, 0.5]], np.float32), 0.01)
+    pv, vk, cnt = ash.voxelize(dev(np.zeros((0, 3), np.float32)), 0.01)
+    assert pv.numel() == 0 and vk.shape[0] == 0
+
+
+# ---------------------------------------------------------------------------
+# Full-size workloads: properties that hold at any size (exact).
+def _pack(keys):
+    k = keys.astype(np.int64) + (1 << 20)
+    return (k[:, 0] << 42) | (k[:, 1] << 21) | k[:, 2]
+
+
+@pytest.mark.parametrize("rho,channels", [(0.1, 1), (0.5, 8), (0.99, 32)])
+def test_plain_large_properties(ash, rho, channels):
+    d = synth.plain_large(rho=rho, channels=channels)
+    keys, vals = d["keys"], d["values"]
+    m = ash.HashMap(d["capacity"], 3, [(torch.float32, channels)])
+    gi, gm = m.insert(dev(keys), [dev(vals)])
+    gi, gm = host(gi), host(gm)
+    uniq, first = np.unique(_pack(keys), return_index=True)
+    first = np.sort(first)
+    want_mask = np.zeros(len(keys), bool)
+    want_mask[first] = True
+    assert np.array_equal(gm, want_mask)
+    want_idx = np.full(len(keys), -1, np.int32)
+    want_idx[first] = np.arange(len(first), dtype=np.int32)  # fresh heap: ranks
+    assert np.array_equal(gi, want_idx)
+    kb = host(m.key_buffer())
+    assert np.array_equal(kb[: len(first)], keys[first])
+    vb = host(m.value_buffer(0))
+    assert np.array_equal(bits(vb[: len(first)]), bits(vals[first]))
+    fk = d["find_keys"]
+    fi, fm, (fv,) = m.find(dev(fk), gather=True)
+    fi, fm, fv = host(fi), host(fm), host(fv)
+    pos = np.searchsorted(uniq, _pack(fk))
+    hit = (pos < len(uniq)) & (uniq[np.minimum(pos, len(uniq) - 1)] == _pack(fk))
+    assert np.array_equal(fm, hit)
+    rank_of_sorted = np.empty(len(uniq), np.int64)
+    order = np.argsort(_pack(keys[first]))
+    rank_of_sorted[:] = order  # sorted distinct key j has rank order[j]
+    assert np.array_equal(fi[hit], rank_of_sorted[pos[hit]].astype(np.int32))
+    assert np.all(fi[~hit] == -1)
+    assert np.array_equal(bits(fv[hit]), bits(vb[fi[hit]]))
+    ek = d["erase_keys"]
+    em = host(m.erase(dev(ek)))
+    efirst = np.unique(_pack(ek), return_index=True)[1]
+    want = np.zeros(len(ek), bool)
+    want[efirst] = True  # every erase key was inserted; its first occurrence wins
+    assert np.array_equal(em, want)
+    assert m.size() == len(first) - len(efirst)
+    fi2, fm2 = m.find(dev(fk))
+    erased = np.isin(_pack(fk), _pack(ek))
+    assert np.array_equal(host(fm2), hit & ~erased)
+    assert m.device_status() == 0
