@@ -84,10 +84,12 @@ typedef struct {
 #define ASH_F_AUTOGROW 1u
 
 /* Table tuning.  bucket_width W (1..64, power of two) aligns a key's home slot;
- * probe_group g (4, 8, 16, 32 or 64) is the number of wavefront lanes that probe
- * one key together, each reading one slot of a g-slot window; max_load in
- * [0.1, 0.9] sets slots = ceil(capacity / max_load) rounded up to a multiple of
- * W and g.  NULL tuning means W = 4, g = 4, max_load = 0.5, flags = 0. */
+ * probe_group g is the number of wavefront lanes that probe one key together:
+ * g in {4, 8, 16, 32, 64} lanes each read one slot of a g-slot window, g = 1
+ * gives every lane its own key and a window of one bucket (W in {2, 4, 8}).
+ * max_load in [0.1, 0.9] sets slots = ceil(capacity / max_load) rounded up to
+ * a multiple of W and g.  NULL tuning means W = 4, g = 4, max_load = 0.5,
+ * flags = 0. */
 typedef struct {
   int32_t bucket_width;
   int32_t probe_group;

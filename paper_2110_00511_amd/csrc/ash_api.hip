@@ -127,6 +127,7 @@ struct ash_map {
   // per-call scratch
   uint32_t* slot_of = nullptr;
   int32_t* aux = nullptr;
+  uint32_t* partial = nullptr;  // per-block new-key counts of the claim kernel
   int64_t scratch_n = 0;
   uint64_t* scan_status = nullptr;
   int64_t scan_tiles = 0;
@@ -142,7 +143,8 @@ struct ash_map {
     r.nslots = nslots;
     r.bucket_width = (uint32_t)W;
     r.nbuckets = nslots / (uint32_t)W;
-    r.max_windows = nslots / (uint32_t)G + 1;
+    r.window = (uint32_t)(G == 1 ? W : G);
+    r.max_windows = nslots / r.window + 1;
     return r;
   }
 };
@@ -188,9 +190,11 @@ ash_status_t ensure_scratch(ash_map* m, int64_t n, hipStream_t st) {
   if (n > m->scratch_n) {
     m->mem.put(m->slot_of, st);
     m->mem.put(m->aux, st);
+    m->mem.put(m->partial, st);
     m->slot_of = (uint32_t*)m->mem.get((size_t)n * 4, st);
     m->aux = (int32_t*)m->mem.get((size_t)n * 4, st);
-    if (!m->slot_of || !m->aux) {
+    m->partial = (uint32_t*)m->mem.get(((size_t)n / 256 + 2) * 4, st);
+    if (!m->slot_of || !m->aux || !m->partial) {
       m->scratch_n = 0;
       return ASH_E_NOMEM;
     }
@@ -236,8 +240,8 @@ ash_status_t rebuild_table(ash_map* m, int64_t live, hipStream_t st, int64_t roo
   m->mem.put(m->table, st);
   m->table = fresh;
   m->nslots = nslots;
-  if (m->c > 0) ASH_HIP(timed(m, "rebuild", st, [&] { return ash::launch_rebuild(m->key_dim, m->G, m->ref(), m->kB, m->active, (uint32_t)m->c, m->meta, st); }));
-  ASH_HIP(timed(m, "finalize", st, [&] { return ash::launch_finalize(m->meta, (uint32_t)m->c, ash::kFinalizeRebuild, 0, m->scan_status, 0, st); }));
+  if (m->c > 0) ASH_HIP(timed(m, "rebuild", st, [&] { return ash::launch_rebuild(m->key_dim, m->G, m->W, m->ref(), m->kB, m->active, (uint32_t)m->c, m->meta, st); }));
+  ASH_HIP(timed(m, "finalize", st, [&] { return ash::launch_finalize(m->meta, (uint32_t)m->c, ash::kFinalizeRebuild, 0, 0, m->scan_status, 0, st); }));
   // live keys now occupy exactly `live` slots and there are no tombstones
   Meta h;
   ASH_TRY(read_meta(m, &h, st));
@@ -357,42 +361,65 @@ ash_status_t insert_impl(ash_map* m, const int32_t* keys, int64_t n, const void*
   ASH_TRY(maybe_clean(m, n, st));
   const uint32_t un = (uint32_t)n;
   const uint32_t last_tile = (un + ash::kScanTile - 1) / ash::kScanTile - 1;
-  if ((m->flags & ASH_F_AUTOGROW) && m->live_ub + n > m->c) {
+  const uint32_t blocks = ash::claim_blocks(m->G, un);
+  auto claim = [&]() -> ash_status_t {
+    ASH_HIP(timed(m, "claim", st, [&] {
+      return ash::launch_claim(m->key_dim, m->G, m->W, m->ref(), keys, un, m->slot_of, m->partial, m->meta, st);
+    }));
+    return ASH_OK;
+  };
+  auto sum = [&]() -> ash_status_t {
+    ASH_HIP(timed(m, "sum_partials", st, [&] { return ash::launch_sum_partials(m->partial, blocks, m->meta, st); }));
+    return ASH_OK;
+  };
+  auto commit = [&](int check, int silent, int32_t* oi, uint8_t* om) -> ash_status_t {
+    ASH_HIP(timed(m, "commit", st, [&] {
+      return ash::launch_commit(m->key_dim, m->ref(), keys, un, m->slot_of, m->kB, m->heap, m->active,
+                                (uint32_t)m->c, vs, oi, om, m->meta, m->scan_status, check, st);
+    }));
+    ASH_HIP(timed(m, "finalize", st, [&] {
+      return ash::launch_finalize(m->meta, (uint32_t)m->c, ash::kFinalizeInsert, silent, check, m->scan_status,
+                                  last_tile, st);
+    }));
+    return ASH_OK;
+  };
+  // The capacity check needs the batch's count of new keys; when the host's
+  // bound on t plus n fits in c it cannot fail and the count is skipped.
+  int check = m->live_ub + n > m->c ? 1 : 0;
+  if (check && (m->flags & ASH_F_AUTOGROW)) {
     Meta h;
     ASH_TRY(read_meta(m, &h, st));
-    if ((int64_t)h.t + n > m->c) {
-      // The counting claim below must not run out of slots: give the table
-      // room for every position of the batch first.
+    check = (int64_t)h.t + n > m->c ? 1 : 0;
+    if (check) {
+      // The counting claim must not run out of slots: give the table room for
+      // every position of the batch first.
       if ((int64_t)h.used + n > (int64_t)m->c + ((int64_t)m->nslots - m->c) / 2)
         ASH_TRY(rebuild_table(m, h.t, st, (int64_t)h.t + n));
-      ASH_HIP(timed(m, "claim", st, [&] { return ash::launch_claim(m->key_dim, m->G, m->ref(), keys, un, m->slot_of, m->meta, st); }));
+      ASH_TRY(claim());
+      ASH_TRY(sum());
       ASH_TRY(read_meta(m, &h, st));
       if (!h.fail && (int64_t)h.t + h.claims > m->c) {
         // Roll the claims back silently, grow x2 until the batch fits, redo.
         const int64_t need = (int64_t)h.t + h.claims;
-        ASH_HIP(timed(m, "commit", st, [&] { return ash::launch_commit(m->key_dim, m->ref(), keys, un, m->slot_of, m->kB, m->heap, m->active,
-                                   (uint32_t)m->c, vs, nullptr, nullptr, m->meta, m->scan_status, st); }));
-        ASH_HIP(timed(m, "finalize", st, [&] { return ash::launch_finalize(m->meta, (uint32_t)m->c, ash::kFinalizeInsert, 1, m->scan_status, last_tile, st); }));
+        ASH_TRY(commit(1, 1, nullptr, nullptr));
         int64_t new_c = std::max<int64_t>(m->c, 1);
         while (new_c < need) new_c *= 2;
         if (new_c > kMaxCount) return ASH_E_CAPACITY;
         ASH_TRY(grow(m, new_c, st));
         if (values && m->n_values > 0) vs = make_values(m, values, nullptr, true);
         ASH_TRY(ensure_scratch(m, n, st));
-        ASH_HIP(timed(m, "claim", st, [&] { return ash::launch_claim(m->key_dim, m->G, m->ref(), keys, un, m->slot_of, m->meta, st); }));
+        ASH_TRY(claim());
+        check = 0;
       }
-      ASH_HIP(timed(m, "commit", st, [&] { return ash::launch_commit(m->key_dim, m->ref(), keys, un, m->slot_of, m->kB, m->heap, m->active,
-                                 (uint32_t)m->c, vs, out_idx, out_mask, m->meta, m->scan_status, st); }));
-      ASH_HIP(timed(m, "finalize", st, [&] { return ash::launch_finalize(m->meta, (uint32_t)m->c, ash::kFinalizeInsert, 0, m->scan_status, last_tile, st); }));
+      ASH_TRY(commit(check, 0, out_idx, out_mask));
       m->live_ub = std::min(m->c, m->live_ub + n);
       m->used_ub += std::min(n, m->c);
       return ASH_OK;
     }
   }
-  ASH_HIP(timed(m, "claim", st, [&] { return ash::launch_claim(m->key_dim, m->G, m->ref(), keys, un, m->slot_of, m->meta, st); }));
-  ASH_HIP(timed(m, "commit", st, [&] { return ash::launch_commit(m->key_dim, m->ref(), keys, un, m->slot_of, m->kB, m->heap, m->active, (uint32_t)m->c,
-                             vs, out_idx, out_mask, m->meta, m->scan_status, st); }));
-  ASH_HIP(timed(m, "finalize", st, [&] { return ash::launch_finalize(m->meta, (uint32_t)m->c, ash::kFinalizeInsert, 0, m->scan_status, last_tile, st); }));
+  ASH_TRY(claim());
+  if (check) ASH_TRY(sum());
+  ASH_TRY(commit(check, 0, out_idx, out_mask));
   m->live_ub = std::min(m->c, m->live_ub + n);
   m->used_ub += std::min(n, m->c);
   return ASH_OK;
@@ -438,7 +465,8 @@ ash_status_t ash_create(int64_t capacity, int32_t key_dim, int32_t n_values, con
     flags = tuning->flags;
   }
   if (!pow2(W) || W > 64) return ASH_E_INVALID;
-  if (G != 4 && G != 8 && G != 16 && G != 32 && G != 64) return ASH_E_INVALID;
+  if (G != 1 && G != 4 && G != 8 && G != 16 && G != 32 && G != 64) return ASH_E_INVALID;
+  if (G == 1 && W != 2 && W != 4 && W != 8) return ASH_E_INVALID;  // one lane reads a bucket
   if (!(lf >= 0.1f && lf <= 0.9f)) return ASH_E_INVALID;
   hipStream_t st = (hipStream_t)stream;
 
@@ -491,6 +519,7 @@ ash_status_t ash_destroy(ash_map_t m) {
   m->mem.put(m->meta, st);
   m->mem.put(m->slot_of, st);
   m->mem.put(m->aux, st);
+  m->mem.put(m->partial, st);
   m->mem.put(m->scan_status, st);
   for (hipEvent_t e : m->prof.pool) (void)hipEventDestroy(e);
   delete m;
@@ -554,7 +583,7 @@ ash_status_t ash_find(ash_map_t m, const int32_t* keys, int64_t n, int32_t* out_
       if (!out_values[j]) return ASH_E_INVALID;
     vs = make_values(m, nullptr, out_values, false);
   }
-  ASH_HIP(timed(m, "find", st, [&] { return ash::launch_find(m->key_dim, m->G, m->ref(), keys, (uint32_t)n, out_idx, out_mask, vs, st); }));
+  ASH_HIP(timed(m, "find", st, [&] { return ash::launch_find(m->key_dim, m->G, m->W, m->ref(), keys, (uint32_t)n, out_idx, out_mask, vs, st); }));
   return ASH_OK;
 }
 
@@ -565,10 +594,10 @@ ash_status_t ash_erase(ash_map_t m, const int32_t* keys, int64_t n, uint8_t* out
   ASH_TRY(ensure_scratch(m, n, st));
   const uint32_t un = (uint32_t)n;
   const uint32_t last_tile = (un + ash::kScanTile - 1) / ash::kScanTile - 1;
-  ASH_HIP(timed(m, "erase_mark", st, [&] { return ash::launch_erase_mark(m->key_dim, m->G, m->ref(), keys, un, m->slot_of, m->aux, m->owner, st); }));
+  ASH_HIP(timed(m, "erase_mark", st, [&] { return ash::launch_erase_mark(m->key_dim, m->G, m->W, m->ref(), keys, un, m->slot_of, m->aux, m->owner, st); }));
   ASH_HIP(timed(m, "erase_commit", st, [&] { return ash::launch_erase_commit(m->key_dim, m->ref(), un, m->slot_of, m->aux, m->owner, m->heap, m->active,
                                    out_mask, m->meta, m->scan_status, st); }));
-  ASH_HIP(timed(m, "finalize", st, [&] { return ash::launch_finalize(m->meta, (uint32_t)m->c, ash::kFinalizeErase, 0, m->scan_status, last_tile, st); }));
+  ASH_HIP(timed(m, "finalize", st, [&] { return ash::launch_finalize(m->meta, (uint32_t)m->c, ash::kFinalizeErase, 0, 0, m->scan_status, last_tile, st); }));
   return ASH_OK;
 }
 
@@ -581,7 +610,7 @@ ash_status_t ash_active_indices(ash_map_t m, int32_t* out_idx, int64_t* out_coun
   }
   const uint32_t last_tile = (uint32_t)((m->c + ash::kScanTile - 1) / ash::kScanTile - 1);
   ASH_HIP(timed(m, "compact_active", st, [&] { return ash::launch_compact_active(m->active, (uint32_t)m->c, out_idx, m->meta, m->scan_status, st); }));
-  ASH_HIP(timed(m, "finalize", st, [&] { return ash::launch_finalize(m->meta, (uint32_t)m->c, ash::kFinalizeCount, 0, m->scan_status, last_tile, st); }));
+  ASH_HIP(timed(m, "finalize", st, [&] { return ash::launch_finalize(m->meta, (uint32_t)m->c, ash::kFinalizeCount, 0, 0, m->scan_status, last_tile, st); }));
   Meta h;
   ASH_TRY(read_meta(m, &h, st));
   *out_count = h.result;
@@ -669,7 +698,7 @@ ash_status_t ash_voxelize(const float* points, int64_t n, float voxel, int32_t* 
   DevMem mem;
   mem.custom = allocator != nullptr;
   if (allocator) mem.a = *allocator;
-  constexpr int kW = 4, kG = 4;
+  constexpr int kW = 4, kG = 1;  // one lane per point, 4-slot buckets
   constexpr float kLoad = 0.5f;
   uint32_t nslots;
   ASH_TRY(slots_for(n, kLoad, kW, kG, &nslots));
@@ -677,9 +706,11 @@ ash_status_t ash_voxelize(const float* points, int64_t n, float voxel, int32_t* 
   const int64_t tiles = (n + ash::kScanTile - 1) / ash::kScanTile;
   uint32_t* table = (uint32_t*)mem.get((size_t)nslots * 16, st);
   uint32_t* slot_of = (uint32_t*)mem.get((size_t)n * 4, st);
+  const uint32_t blocks = ash::claim_blocks(kG, un);
+  uint32_t* partial = (uint32_t*)mem.get((size_t)blocks * 4, st);
   uint64_t* status = (uint64_t*)mem.get((size_t)tiles * 8 + sizeof(Meta), st);
   ash_status_t rc = ASH_OK;
-  if (!table || !slot_of || !status) rc = ASH_E_NOMEM;
+  if (!table || !slot_of || !partial || !status) rc = ASH_E_NOMEM;
   if (rc == ASH_OK) {
     Meta* meta = (Meta*)(status + tiles);
     TableRef tb;
@@ -687,14 +718,16 @@ ash_status_t ash_voxelize(const float* points, int64_t n, float voxel, int32_t* 
     tb.nslots = nslots;
     tb.bucket_width = kW;
     tb.nbuckets = nslots / kW;
-    tb.max_windows = nslots / kG + 1;
+    tb.window = kG == 1 ? kW : kG;
+    tb.max_windows = nslots / tb.window + 1;
     Meta h;
     std::memset(&h, 0, sizeof(h));
     h.epoch = 1;
     bool ok = ash::launch_fill_u32(table, ash::kEmpty, (size_t)nslots * 4, st) == hipSuccess &&
               ash::launch_fill_u32((uint32_t*)status, 0u, (size_t)tiles * 2, st) == hipSuccess &&
               hipMemcpyAsync(meta, &h, sizeof(Meta), hipMemcpyHostToDevice, st) == hipSuccess &&
-              ash::launch_voxel_claim(kG, tb, points, voxel, un, slot_of, meta, st) == hipSuccess &&
+              ash::launch_voxel_claim(kG, kW, tb, points, voxel, un, slot_of, partial, meta, st) == hipSuccess &&
+              ash::launch_sum_partials(partial, blocks, meta, st) == hipSuccess &&
               ash::launch_voxel_commit(tb, points, voxel, un, slot_of, out_voxel_keys, out_voxel_counts, meta,
                                        status, st) == hipSuccess &&
               ash::launch_voxel_resolve(tb, un, slot_of, out_point_voxel, out_voxel_counts, st) == hipSuccess &&
@@ -706,6 +739,7 @@ ash_status_t ash_voxelize(const float* points, int64_t n, float voxel, int32_t* 
   }
   mem.put(table, st);
   mem.put(slot_of, st);
+  mem.put(partial, st);
   mem.put(status, st);
   return rc;
 }

@@ -42,16 +42,17 @@ struct SlotWords {
 };
 
 // Device-resident bookkeeping of one map.  Only the finalize kernels write
-// t / used / tombs / epoch / ticket, so every other kernel may read them
-// with plain loads.
+// t / used / tombs / epoch, so every other kernel may read them with plain
+// loads.  No field is a per-wavefront counter: an atomic per wavefront on one
+// address serializes (about 11 ns each on MI355X).
 struct Meta {
   uint32_t t;       // heap top = number of live keys
-  uint32_t claims;  // new keys claimed by the insert in flight
+  uint32_t claims;  // summed new-key count of the insert in flight (when needed)
   uint32_t used;    // non-empty slots (live + tombstones)
   uint32_t tombs;   // tombstones
   uint32_t status;  // sticky error bits
   uint32_t epoch;   // tag of the scan status words of the current launch
-  uint32_t ticket;  // tile ticket counter of the scanning kernel in flight
+  uint32_t spare;
   uint32_t result;  // total of the last scanning kernel
   uint32_t fail;    // groups whose probe found no empty slot (claim/rebuild)
   uint32_t pad[7];
@@ -61,8 +62,9 @@ struct TableRef {
   uint32_t* words;
   uint32_t nslots;
   uint32_t nbuckets;
-  uint32_t bucket_width;
-  uint32_t max_windows;
+  uint32_t bucket_width;  // W: a key's home slot is a multiple of W
+  uint32_t window;        // slots examined per probe step (G, or W when G == 1)
+  uint32_t max_windows;   // probe steps that cover the whole table
 };
 
 // ---------------------------------------------------------------------------
@@ -193,52 +195,83 @@ __device__ __forceinline__ uint32_t first_lane(uint64_t m) { return (uint32_t)(_
 // ---------------------------------------------------------------------------
 // Ordered ranks: block-wide scan plus single-pass decoupled look-back across
 // tiles (Merrill and Garland, "Single-pass Parallel Prefix Scan with
-// Decoupled Look-back", 2016).  Tiles are numbered by a ticket so that a tile
-// only waits on tiles that already started.  Status word of a tile:
+// Decoupled Look-back", 2016).  Tile = blockIdx.x: workgroups are dispatched
+// in increasing order, so a tile only waits on tiles that already started.
+// Status word of a tile:
 //   [63:32] epoch of the launch, [31] inclusive flag, [30:0] count.
 __device__ __forceinline__ uint64_t pack_status(uint32_t epoch, uint32_t inclusive, uint32_t v) {
   return ((uint64_t)epoch << 32) | ((uint64_t)inclusive << 31) | (uint64_t)v;
 }
 
-// Called by one thread; returns the exclusive prefix of `tile`.  Every tile
-// of a launch publishes exactly once, and a tile only waits on tiles with a
-// smaller ticket, which are already running; the wait is still bounded so
-// that a broken invariant ends in a sticky error instead of a hang.
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Called by all 64 lanes of one wavefront; returns the exclusive prefix of
+// `tile` (uniform over the wave).  Lane j examines predecessor top - j, so
+// one probe covers 64 tiles: the prefix is complete at the nearest tile that
+// published an inclusive value, provided every tile in between published its
+// aggregate.  Every tile of a launch publishes exactly once and a tile only
+// waits on tiles with a smaller index, dispatched before it; the wait
+// is still bounded so that a broken invariant ends in a sticky error instead
+// of a hang.
 __device__ inline uint32_t tile_lookback(uint64_t* status, uint32_t tile, uint32_t epoch, uint32_t aggregate,
                                          uint32_t* status_bits) {
+  const uint32_t lane = lane_id();
   if (tile == 0) {
-    __hip_atomic_store(status, pack_status(epoch, 1, aggregate), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (lane == 0)
+      __hip_atomic_store(status, pack_status(epoch, 1, aggregate), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return 0;
   }
-  __hip_atomic_store(status + tile, pack_status(epoch, 0, aggregate), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (lane == 0)
+    __hip_atomic_store(status + tile, pack_status(epoch, 0, aggregate), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   uint32_t excl = 0;
-  uint32_t j = tile - 1;
+  int64_t top = (int64_t)tile - 1;
   uint32_t spins = 0;
   while (true) {
-    uint64_t s = __hip_atomic_load(status + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if ((uint32_t)(s >> 32) != epoch) {
-      if (++spins == kLookbackSpinLimit) {
-        __hip_atomic_fetch_or(status_bits, kStatusScanStall, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int64_t j = top - (int64_t)lane;
+    // positions before tile 0 read as an inclusive zero; tile 0 is always inclusive
+    const uint64_t s = j >= 0 ? __hip_atomic_load(status + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                              : pack_status(epoch, 1, 0);
+    const bool valid = (uint32_t)(s >> 32) == epoch;
+    const uint64_t invalid = __ballot(!valid);
+    const uint64_t incl = __ballot(valid && (s & 0x80000000ull));
+    if (incl) {
+      const uint32_t k = first_lane(incl);
+      const uint64_t need = k == 63 ? ~0ull : ((1ull << (k + 1)) - 1ull);
+      if ((invalid & need) == 0) {
+        excl += wave_sum_u32(lane <= k ? ((uint32_t)s & 0x7FFFFFFFu) : 0u);
         break;
       }
-      __builtin_amdgcn_s_sleep(1);
+    } else if (invalid == 0) {  // 64 aggregates and no inclusive value: keep walking
+      excl += wave_sum_u32((uint32_t)s & 0x7FFFFFFFu);
+      top -= 64;
       continue;
     }
-    excl += (uint32_t)s & 0x7FFFFFFFu;
-    if (s & 0x80000000ull) break;
-    if (j == 0) break;  // tile 0 always publishes an inclusive value
-    --j;
+    if (++spins == kLookbackSpinLimit) {
+      if (lane == 0) __hip_atomic_fetch_or(status_bits, kStatusScanStall, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      break;
+    }
+    __builtin_amdgcn_s_sleep(1);
   }
-  __hip_atomic_store(status + tile, pack_status(epoch, 1, excl + aggregate), __ATOMIC_RELAXED,
-                     __HIP_MEMORY_SCOPE_AGENT);
+  if (lane == 0)
+    __hip_atomic_store(status + tile, pack_status(epoch, 1, excl + aggregate), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
   return excl;
 }
 
-// Takes the next tile ticket (thread 0) and broadcasts it.
-__device__ __forceinline__ uint32_t take_ticket(uint32_t* counter, uint32_t* s_slot) {
-  if (threadIdx.x == 0) *s_slot = atomic_add_u32(counter, 1u);
+// Block-level wrapper: wave 0 runs the look-back, the prefix is broadcast
+// through LDS.
+__device__ __forceinline__ uint32_t block_lookback(uint64_t* status, uint32_t tile, uint32_t epoch,
+                                                   uint32_t aggregate, uint32_t* status_bits, uint32_t* s_prefix) {
+  if (threadIdx.x < 64) {
+    const uint32_t e = tile_lookback(status, tile, epoch, aggregate, status_bits);
+    if (threadIdx.x == 0) *s_prefix = e;
+  }
   __syncthreads();
-  return *s_slot;
+  return *s_prefix;
 }
 
 // Exclusive block scan of kScanItems 0/1 flags per thread where the item of

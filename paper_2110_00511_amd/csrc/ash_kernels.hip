@@ -87,19 +87,117 @@ __global__ __launch_bounds__(kBlock) void k_iota(int32_t* __restrict__ h, uint32
 }
 
 __global__ void k_reset_meta(Meta* m) {
-  m->t = 0; m->claims = 0; m->used = 0; m->tombs = 0; m->status = 0; m->ticket = 0; m->result = 0; m->fail = 0;
+  m->t = 0; m->claims = 0; m->used = 0; m->tombs = 0; m->status = 0; m->result = 0; m->fail = 0;
   m->epoch = m->epoch + 1u == 0u ? 1u : m->epoch + 1u;
 }
 
 // ---------------------------------------------------------------------------
-// Claim (insert / activate / voxelize pass 1).  A group of G lanes owns one
-// position at a time; lane `sub` examines slot home + w*G + sub of window w.
-template <int KD, int G, typename Src>
+// Probe windows.  One probe step examines `kSize` consecutive slots starting
+// at `base`: either G lanes of a wavefront hold one slot each (G > 1, group
+// decisions by ballot and lane broadcast), or one lane holds a whole bucket
+// of WL slots (G == 1, decisions by local bit masks).  Member L of a window
+// is slot base + L.  Results of mask() and of the uniform accessors are the
+// same on every lane of a group.
+template <int KD, int G, int WL>
+struct Window {
+  static constexpr int S = SlotWords<KD>::value;
+  static constexpr int kPer = G == 1 ? WL : 1;
+  static constexpr int kSize = G == 1 ? WL : G;
+  Slot<S> v[kPer];
+  uint32_t at[kPer];
+
+  __device__ __forceinline__ void load(const TableRef& tb, uint32_t base, uint32_t sub) {
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      uint32_t s = base + (G == 1 ? (uint32_t)j : sub);
+      if (s >= tb.nslots) s -= tb.nslots;
+      at[j] = s;
+      v[j] = load_slot<S>(tb.words + (size_t)s * S);
+    }
+  }
+
+  template <typename F>
+  __device__ __forceinline__ uint64_t mask(F&& pred) const {
+    if constexpr (G == 1) {
+      uint64_t m = 0;
+#pragma unroll
+      for (int j = 0; j < kPer; ++j) {
+        const Slot<S> sl = v[j];
+        m |= pred(sl) ? (1ull << j) : 0ull;
+      }
+      return m;
+    } else {
+      const Slot<S> sl = v[0];
+      return group_ballot<G>(pred(sl));
+    }
+  }
+
+  // (member selection in lane mode is an OR of masked words, which keeps the
+  // window in registers; a select chain would be folded into an indexed
+  // load from a stack copy)
+  __device__ __forceinline__ uint32_t word(uint32_t L, int w) const {
+    if constexpr (G == 1) {
+      uint32_t r = 0;
+#pragma unroll
+      for (int j = 0; j < kPer; ++j) r |= v[j].w[w] & (0u - (uint32_t)(L == (uint32_t)j));
+      return r;
+    } else {
+      return group_bcast<G>(v[0].w[w], L);
+    }
+  }
+
+  __device__ __forceinline__ uint32_t slot(uint32_t L) const {
+    if constexpr (G == 1) {
+      uint32_t r = 0;
+#pragma unroll
+      for (int j = 0; j < kPer; ++j) r |= at[j] & (0u - (uint32_t)(L == (uint32_t)j));
+      return r;
+    } else {
+      return group_bcast<G>(at[0], L);
+    }
+  }
+
+  // Replaces member L's tag word and state (on the lane that holds it).
+  __device__ __forceinline__ void set_pair(uint32_t L, uint32_t sub, uint32_t tagw, uint32_t st) {
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const uint32_t member = G == 1 ? (uint32_t)j : sub;
+      const uint32_t m = 0u - (uint32_t)(member == L);  // blend, not an indexed store
+      v[j].w[S - 2] = (v[j].w[S - 2] & ~m) | (tagw & m);
+      v[j].w[S - 1] = (v[j].w[S - 1] & ~m) | (st & m);
+    }
+  }
+};
+
+// Broadcast of a 64-bit value from the group leader (sub-lane 0).
+template <int G>
+__device__ __forceinline__ uint64_t leader_bcast64(uint64_t x) {
+  if constexpr (G == 1) {
+    return x;
+  } else {
+    const uint32_t lo = group_bcast<G>((uint32_t)x, 0u);
+    const uint32_t hi = group_bcast<G>((uint32_t)(x >> 32), 0u);
+    return ((uint64_t)hi << 32) | lo;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Claim (insert / activate / voxelize pass 1).  A group of G lanes (or one
+// lane when G == 1) owns one position at a time.  slot_of[p] receives the
+// claimed or matched slot of every position that may still win -- the
+// claimer and every position that lowered PENDING to itself -- and kNoSlot
+// for positions that already lost (key committed before, or a lower position
+// already pending).  kAllSlots keeps the matched slot for every accepted
+// position (voxelization needs it to resolve per-point ids).
+template <int KD, int G, int WL, typename Src, bool kAllSlots>
 __global__ __launch_bounds__(kBlock) void k_claim(TableRef tb, Src src, uint32_t n, uint32_t rounds,
-                                                  uint32_t* __restrict__ slot_of, Meta* meta) {
-  constexpr int S = SlotWords<KD>::value;
+                                                  uint32_t* __restrict__ slot_of, uint32_t* __restrict__ partial,
+                                                  Meta* meta) {
+  __shared__ uint32_t s_count[kBlock / 64];
+  using Win = Window<KD, G, WL>;
+  constexpr int S = Win::S;
   constexpr uint32_t kGroups = kBlock / G;
-  const uint32_t sub = threadIdx.x & (G - 1);
+  const uint32_t sub = G == 1 ? 0u : (threadIdx.x & (G - 1));
   const uint32_t grp = threadIdx.x / G;
   const uint32_t tile_base = blockIdx.x * kGroups * rounds;
   uint32_t claimed = 0;
@@ -113,71 +211,96 @@ __global__ __launch_bounds__(kBlock) void k_claim(TableRef tb, Src src, uint32_t
     if (valid) {
       const uint64_t h = key_hash<KD>(k);
       const uint32_t tag = pending_tag<KD>(k, h);
+      const uint64_t desired = ((uint64_t)(kPending + p) << 32) | tag;
       uint32_t base = home_slot(tb, h);
       bool resolved = false;
       for (uint32_t w = 0; w < tb.max_windows && !resolved; ++w) {
-        uint32_t s = base + sub;
-        if (s >= tb.nslots) s -= tb.nslots;
-        uint32_t* sp = tb.words + (size_t)s * S;
-        Slot<S> sl = load_slot<S>(sp);
+        Win win;
+        win.load(tb, base, sub);
         while (true) {
-          const uint32_t st = sl.w[S - 1];
-          const bool hit_c = st < kPending && slot_holds<KD, S>(sl, k);
-          bool hit_p = false;
-          if (st >= kPending && st < kTomb && sl.w[S - 2] == tag && st - kPending < n) {
+          // key committed by an earlier call: not new
+          const uint64_t mc = win.mask([&](const Slot<S> sl) {
+            return sl.w[S - 1] < kPending && slot_holds<KD, S>(sl, k);
+          });
+          if (mc) {
+            if (kAllSlots) out = win.slot(first_lane(mc));
+            resolved = true;
+            break;
+          }
+          // same key pending in this batch (compared against the read-only batch)
+          const uint64_t mp = win.mask([&](const Slot<S> sl) {
+            const uint32_t st = sl.w[S - 1];
+            if (!(st >= kPending && st < kTomb && sl.w[S - 2] == tag && st - kPending < n)) return false;
             if constexpr (KD == 1) {
-              hit_p = true;  // the tag word of a 1-word key is the key
+              return true;  // the tag word of a 1-word key is the key
             } else {
               int32_t kq[KD];
               src.load(st - kPending, kq);
-              hit_p = keys_equal<KD>(kq, k);
+              return keys_equal<KD>(kq, k);
             }
-          }
-          if (group_ballot<G>(hit_c)) {  // key already committed: not new
-            resolved = true;
-            break;
-          }
-          const uint64_t mp = group_ballot<G>(hit_p);
-          if (mp) {  // same key pending: keep the lowest position
+          });
+          if (mp) {
             const uint32_t L = first_lane(mp);
-            if (sub == L && st - kPending > p) atomic_min_u32(sp + S - 1, kPending + p);
-            out = group_bcast<G>(s, L);
+            const uint32_t q = win.word(L, S - 1) - kPending;
+            const uint32_t s = win.slot(L);
+            if (p < q && sub == 0) atomic_min_u32(tb.words + (size_t)s * S + S - 1, kPending + p);
+            out = (p < q || kAllSlots) ? s : kNoSlot;
             resolved = true;
             break;
           }
-          const uint64_t me = group_ballot<G>(st == kEmpty);
+          const uint64_t me = win.mask([&](const Slot<S> sl) { return sl.w[S - 1] == kEmpty; });
           if (!me) break;  // no empty slot in this window: next window
           const uint32_t L = first_lane(me);
-          uint32_t won = 0;
-          if (sub == L) {
-            const uint64_t desired = ((uint64_t)(kPending + p) << 32) | tag;
-            const uint64_t found = cas_pair(sp + S - 2, kEmptyPair, desired);
-            won = found == kEmptyPair;
-            if (!won) {  // someone filled it first: look at what is there now
-              sl.w[S - 2] = (uint32_t)found;
-              sl.w[S - 1] = (uint32_t)(found >> 32);
-            }
-          }
-          won = group_bcast<G>(won, L);
-          if (won) {
-            out = group_bcast<G>(s, L);
+          const uint32_t s = win.slot(L);
+          uint64_t found = 0;
+          if (sub == 0) found = cas_pair(tb.words + (size_t)s * S + S - 2, kEmptyPair, desired);
+          found = leader_bcast64<G>(found);
+          if (found == kEmptyPair) {
+            out = s;
             claimed += sub == 0 ? 1u : 0u;
             resolved = true;
             break;
           }
+          // someone filled it first: look at what is there now
+          win.set_pair(L, sub, (uint32_t)found, (uint32_t)(found >> 32));
         }
-        base += G;
+        base += tb.window;
         if (base >= tb.nslots) base -= tb.nslots;
       }
       if (!resolved) unresolved = 1;
     }
     if (sub == 0) slot_of[p] = out;
   }
+  // Per-block count of new keys (a single shared counter would serialize
+  // one atomic per wavefront); k_sum_partials adds them up when needed.
   const uint32_t wc = wave_sum(claimed);
   const uint32_t wu = wave_sum(unresolved);
   if (lane_id() == 0) {
-    if (wc) atomic_add_u32(&meta->claims, wc);
-    if (wu) atomic_add_u32(&meta->fail, 1u);
+    s_count[threadIdx.x >> 6] = wc;
+    if (wu) atomic_add_u32(&meta->fail, 1u);  // only when the table is full
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) c += s_count[w];
+    partial[blockIdx.x] = c;
+  }
+}
+
+// meta->claims = sum of the claim kernel's per-block counts (one block).
+__global__ __launch_bounds__(1024) void k_sum_partials(const uint32_t* __restrict__ partial, uint32_t count,
+                                                        Meta* meta) {
+  __shared__ uint32_t s_sum[1024 / 64];
+  uint32_t v = 0;
+  for (uint32_t i = threadIdx.x; i < count; i += blockDim.x) v += partial[i];
+  v = wave_sum(v);
+  if (lane_id() == 0) s_sum[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (int w = 0; w < 1024 / 64; ++w) t += s_sum[w];
+    meta->claims = t;
   }
 }
 
@@ -189,16 +312,16 @@ __global__ __launch_bounds__(kBlock) void k_commit(TableRef tb, const int32_t* _
                                                    const int32_t* __restrict__ heap, uint8_t* __restrict__ active,
                                                    uint32_t cap, ValueSet vs, int32_t* __restrict__ out_idx,
                                                    uint8_t* __restrict__ out_mask, Meta* meta,
-                                                   uint64_t* __restrict__ status) {
+                                                   uint64_t* __restrict__ status, int check) {
   constexpr int S = SlotWords<KD>::value;
-  __shared__ uint32_t s_tile;
   __shared__ uint32_t s_prefix;
   __shared__ uint64_t s_scan[kBlock / 64 + 1];
   __shared__ uint2 s_pairs[kScanTile];
-  const uint32_t tile = take_ticket(&meta->ticket, &s_tile);
+  const uint32_t tile = blockIdx.x;
   const uint32_t t0 = meta->t;
-  const uint32_t claims = meta->claims;
-  const bool overflow = meta->fail != 0 || claims > cap - t0;
+  // With check == 0 the host has proved t + new keys <= c (its bound on t
+  // plus n); otherwise meta->claims holds the summed count of new keys.
+  const bool overflow = meta->fail != 0 || (check && meta->claims > cap - t0);
   const uint32_t base = tile * kScanTile;
   bool win[kScanItems];
   uint32_t slot[kScanItems];
@@ -218,8 +341,7 @@ __global__ __launch_bounds__(kBlock) void k_commit(TableRef tb, const int32_t* _
   uint32_t rank[kScanItems];
   uint32_t total;
   block_rank_rows(win, rank, total, s_scan);
-  if (threadIdx.x == 0) s_prefix = tile_lookback(status, tile, meta->epoch, total, &meta->status);
-  __syncthreads();
+  block_lookback(status, tile, meta->epoch, total, &meta->status, &s_prefix);
   const uint32_t prefix = s_prefix;
   bool bad = false;
 #pragma unroll
@@ -251,13 +373,17 @@ __global__ __launch_bounds__(kBlock) void k_commit(TableRef tb, const int32_t* _
 }
 
 // Moves the heap top and resets per-launch counters.  Runs after the
-// scanning kernel, so every block of that kernel has read t / epoch.
-__global__ void k_finalize(Meta* m, uint32_t cap, int mode, int silent, const uint64_t* status, uint32_t last_tile) {
+// scanning kernel, so every block of that kernel has read t / epoch.  The
+// number of keys an insert added is the scan total of its commit (0 when the
+// batch was rolled back).
+__global__ void k_finalize(Meta* m, uint32_t cap, int mode, int silent, int check, const uint64_t* status,
+                           uint32_t last_tile) {
   if (mode == kFinalizeInsert) {
-    const bool overflow = m->fail != 0 || m->claims > cap - m->t;
+    const bool overflow = m->fail != 0 || (check && m->claims > cap - m->t);
     if (!overflow) {
-      m->t += m->claims;
-      m->used += m->claims;
+      const uint32_t total = (uint32_t)status[last_tile] & 0x7FFFFFFFu;
+      m->t += total;
+      m->used += total;
     } else if (!silent) {
       m->status |= m->fail ? kStatusTableFull : kStatusCapacity;
     }
@@ -274,7 +400,6 @@ __global__ void k_finalize(Meta* m, uint32_t cap, int mode, int silent, const ui
     if (m->fail) m->status |= kStatusTableFull;
     m->fail = 0;
   }
-  m->ticket = 0;
   m->epoch = m->epoch + 1u == 0u ? 1u : m->epoch + 1u;
 }
 
@@ -283,15 +408,16 @@ __global__ void k_finalize(Meta* m, uint32_t cap, int mode, int silent, const ui
 // the first window that holds an EMPTY slot: a key is always claimed at the
 // first EMPTY slot of its sequence and slots never return to EMPTY outside a
 // rebuild.
-template <int KD, int G>
+template <int KD, int G, int WL>
 __global__ __launch_bounds__(kBlock) void k_find(TableRef tb, const int32_t* __restrict__ keys, uint32_t n,
                                                  uint32_t rounds, int32_t* __restrict__ out_idx,
                                                  uint8_t* __restrict__ out_mask, ValueSet vs) {
-  constexpr int S = SlotWords<KD>::value;
+  using Win = Window<KD, G, WL>;
+  constexpr int S = Win::S;
   constexpr uint32_t kGroups = kBlock / G;
   __shared__ uint2 s_pairs[kScanTile];
   __shared__ uint32_t s_hits;
-  const uint32_t sub = threadIdx.x & (G - 1);
+  const uint32_t sub = G == 1 ? 0u : (threadIdx.x & (G - 1));
   const uint32_t grp = threadIdx.x / G;
   const uint32_t tile_base = blockIdx.x * kGroups * rounds;
   if (vs.n > 0) {
@@ -308,17 +434,17 @@ __global__ __launch_bounds__(kBlock) void k_find(TableRef tb, const int32_t* __r
     uint32_t base = home_slot(tb, h);
     uint32_t idx = kNoSlot;
     for (uint32_t w = 0; w < tb.max_windows; ++w) {
-      uint32_t s = base + sub;
-      if (s >= tb.nslots) s -= tb.nslots;
-      const Slot<S> sl = load_slot<S>(tb.words + (size_t)s * S);
-      const uint32_t st = sl.w[S - 1];
-      const uint64_t mh = group_ballot<G>(st < kPending && slot_holds<KD, S>(sl, k));
+      Win win;
+      win.load(tb, base, sub);
+      const uint64_t mh = win.mask([&](const Slot<S> sl) {
+        return sl.w[S - 1] < kPending && slot_holds<KD, S>(sl, k);
+      });
       if (mh) {
-        idx = group_bcast<G>(st, first_lane(mh));
+        idx = win.word(first_lane(mh), S - 1);
         break;
       }
-      if (group_ballot<G>(st == kEmpty)) break;
-      base += G;
+      if (win.mask([&](const Slot<S> sl) { return sl.w[S - 1] == kEmpty; })) break;
+      base += tb.window;
       if (base >= tb.nslots) base -= tb.nslots;
     }
     if (sub == 0) {
@@ -338,14 +464,15 @@ __global__ __launch_bounds__(kBlock) void k_find(TableRef tb, const int32_t* __r
 // ---------------------------------------------------------------------------
 // Erase pass 1: locate each key; the lowest position per buffer index wins
 // through atomicMin on owner[i] (owner starts at INT32_MAX).
-template <int KD, int G>
+template <int KD, int G, int WL>
 __global__ __launch_bounds__(kBlock) void k_erase_mark(TableRef tb, const int32_t* __restrict__ keys, uint32_t n,
                                                        uint32_t rounds, uint32_t* __restrict__ slot_of,
                                                        int32_t* __restrict__ found_idx,
                                                        int32_t* __restrict__ owner) {
-  constexpr int S = SlotWords<KD>::value;
+  using Win = Window<KD, G, WL>;
+  constexpr int S = Win::S;
   constexpr uint32_t kGroups = kBlock / G;
-  const uint32_t sub = threadIdx.x & (G - 1);
+  const uint32_t sub = G == 1 ? 0u : (threadIdx.x & (G - 1));
   const uint32_t grp = threadIdx.x / G;
   const uint32_t tile_base = blockIdx.x * kGroups * rounds;
   for (uint32_t r = 0; r < rounds; ++r) {
@@ -358,20 +485,20 @@ __global__ __launch_bounds__(kBlock) void k_erase_mark(TableRef tb, const int32_
     uint32_t base = home_slot(tb, h);
     uint32_t idx = kNoSlot, where = kNoSlot;
     for (uint32_t w = 0; w < tb.max_windows; ++w) {
-      uint32_t s = base + sub;
-      if (s >= tb.nslots) s -= tb.nslots;
-      const Slot<S> sl = load_slot<S>(tb.words + (size_t)s * S);
-      const uint32_t st = sl.w[S - 1];
-      const uint64_t mh = group_ballot<G>(st < kPending && slot_holds<KD, S>(sl, k));
+      Win win;
+      win.load(tb, base, sub);
+      const uint64_t mh = win.mask([&](const Slot<S> sl) {
+        return sl.w[S - 1] < kPending && slot_holds<KD, S>(sl, k);
+      });
       if (mh) {
         const uint32_t L = first_lane(mh);
-        if (sub == L) atomic_min_u32(reinterpret_cast<uint32_t*>(owner) + st, p);
-        idx = group_bcast<G>(st, L);
-        where = group_bcast<G>(s, L);
+        idx = win.word(L, S - 1);
+        where = win.slot(L);
+        if (sub == 0) atomic_min_u32(reinterpret_cast<uint32_t*>(owner) + idx, p);
         break;
       }
-      if (group_ballot<G>(st == kEmpty)) break;
-      base += G;
+      if (win.mask([&](const Slot<S> sl) { return sl.w[S - 1] == kEmpty; })) break;
+      base += tb.window;
       if (base >= tb.nslots) base -= tb.nslots;
     }
     if (sub == 0) {
@@ -390,10 +517,9 @@ __global__ __launch_bounds__(kBlock) void k_erase_commit(TableRef tb, uint32_t n
                                                          uint8_t* __restrict__ active, uint8_t* __restrict__ out_mask,
                                                          Meta* meta, uint64_t* __restrict__ status) {
   constexpr int S = SlotWords<KD>::value;
-  __shared__ uint32_t s_tile;
   __shared__ uint32_t s_prefix;
   __shared__ uint64_t s_scan[kBlock / 64 + 1];
-  const uint32_t tile = take_ticket(&meta->ticket, &s_tile);
+  const uint32_t tile = blockIdx.x;
   const uint32_t t0 = meta->t;
   const uint32_t base = tile * kScanTile;
   bool win[kScanItems];
@@ -407,8 +533,7 @@ __global__ __launch_bounds__(kBlock) void k_erase_commit(TableRef tb, uint32_t n
   uint32_t rank[kScanItems];
   uint32_t total;
   block_rank_rows(win, rank, total, s_scan);
-  if (threadIdx.x == 0) s_prefix = tile_lookback(status, tile, meta->epoch, total, &meta->status);
-  __syncthreads();
+  block_lookback(status, tile, meta->epoch, total, &meta->status, &s_prefix);
   const uint32_t prefix = s_prefix;
 #pragma unroll
   for (int r = 0; r < kScanItems; ++r) {
@@ -430,10 +555,9 @@ __global__ __launch_bounds__(kBlock) void k_erase_commit(TableRef tb, uint32_t n
 __global__ __launch_bounds__(kBlock) void k_compact_active(const uint8_t* __restrict__ active, uint32_t c,
                                                            int32_t* __restrict__ out, Meta* meta,
                                                            uint64_t* __restrict__ status) {
-  __shared__ uint32_t s_tile;
   __shared__ uint32_t s_prefix;
   __shared__ uint64_t s_scan[kBlock / 64 + 1];
-  const uint32_t tile = take_ticket(&meta->ticket, &s_tile);
+  const uint32_t tile = blockIdx.x;
   const uint32_t base = tile * kScanTile;
   bool on[kScanItems];
 #pragma unroll
@@ -444,8 +568,7 @@ __global__ __launch_bounds__(kBlock) void k_compact_active(const uint8_t* __rest
   uint32_t rank[kScanItems];
   uint32_t total;
   block_rank_rows(on, rank, total, s_scan);
-  if (threadIdx.x == 0) s_prefix = tile_lookback(status, tile, meta->epoch, total, &meta->status);
-  __syncthreads();
+  block_lookback(status, tile, meta->epoch, total, &meta->status, &s_prefix);
 #pragma unroll
   for (int r = 0; r < kScanItems; ++r)
     if (on[r]) out[s_prefix + rank[r]] = (int32_t)(base + r * kBlock + threadIdx.x);
@@ -453,14 +576,17 @@ __global__ __launch_bounds__(kBlock) void k_compact_active(const uint8_t* __rest
 
 // ---------------------------------------------------------------------------
 // Rebuild a fresh table from (k^B[i], i) for every live index i (rehash,
-// Sec. 4.5).  Keys are distinct, so a position only looks for EMPTY slots.
-template <int KD, int G>
+// Sec. 4.5).  Keys are distinct, so a position only looks for EMPTY slots;
+// the leader CASes (k_{KD-1}, COMMITTED(i)) into the first one and then
+// writes the other key words.
+template <int KD, int G, int WL>
 __global__ __launch_bounds__(kBlock) void k_rebuild(TableRef tb, const int32_t* __restrict__ kB,
                                                     const uint8_t* __restrict__ active, uint32_t c, uint32_t rounds,
                                                     Meta* meta) {
-  constexpr int S = SlotWords<KD>::value;
+  using Win = Window<KD, G, WL>;
+  constexpr int S = Win::S;
   constexpr uint32_t kGroups = kBlock / G;
-  const uint32_t sub = threadIdx.x & (G - 1);
+  const uint32_t sub = G == 1 ? 0u : (threadIdx.x & (G - 1));
   const uint32_t grp = threadIdx.x / G;
   const uint32_t tile_base = blockIdx.x * kGroups * rounds;
   uint32_t unresolved = 0;
@@ -472,35 +598,34 @@ __global__ __launch_bounds__(kBlock) void k_rebuild(TableRef tb, const int32_t* 
 #pragma unroll
     for (int d = 0; d < KD; ++d) k[d] = kB[(size_t)i * KD + d];
     const uint64_t h = key_hash<KD>(k);
+    const uint64_t desired = ((uint64_t)i << 32) | (uint32_t)k[KD - 1];
     uint32_t base = home_slot(tb, h);
     bool done = false;
     for (uint32_t w = 0; w < tb.max_windows && !done; ++w) {
-      uint32_t s = base + sub;
-      if (s >= tb.nslots) s -= tb.nslots;
-      uint32_t* sp = tb.words + (size_t)s * S;
-      uint32_t st = sp[S - 1];
+      Win win;
+      win.load(tb, base, sub);
       while (true) {
-        const uint64_t me = group_ballot<G>(st == kEmpty);
+        const uint64_t me = win.mask([&](const Slot<S> sl) { return sl.w[S - 1] == kEmpty; });
         if (!me) break;
         const uint32_t L = first_lane(me);
-        uint32_t won = 0;
-        if (sub == L) {
-          const uint64_t desired = ((uint64_t)i << 32) | (uint32_t)k[KD - 1];
-          const uint64_t found = cas_pair(sp + S - 2, kEmptyPair, desired);
-          won = found == kEmptyPair;
-          if (won) {
+        const uint32_t s = win.slot(L);
+        uint64_t found = 0;
+        if (sub == 0) {
+          uint32_t* sp = tb.words + (size_t)s * S;
+          found = cas_pair(sp + S - 2, kEmptyPair, desired);
+          if (found == kEmptyPair) {
 #pragma unroll
             for (int d = 0; d < KD - 1; ++d) sp[d] = (uint32_t)k[d];
-          } else {
-            st = (uint32_t)(found >> 32);
           }
         }
-        if (group_bcast<G>(won, L)) {
+        found = leader_bcast64<G>(found);
+        if (found == kEmptyPair) {
           done = true;
           break;
         }
+        win.set_pair(L, sub, (uint32_t)found, (uint32_t)(found >> 32));
       }
-      base += G;
+      base += tb.window;
       if (base >= tb.nslots) base -= tb.nslots;
     }
     if (!done) unresolved = 1;
@@ -517,10 +642,9 @@ __global__ __launch_bounds__(kBlock) void k_voxel_commit(TableRef tb, VoxelKeys 
                                                          int32_t* __restrict__ counts, Meta* meta,
                                                          uint64_t* __restrict__ status) {
   constexpr int S = SlotWords<3>::value;
-  __shared__ uint32_t s_tile;
   __shared__ uint32_t s_prefix;
   __shared__ uint64_t s_scan[kBlock / 64 + 1];
-  const uint32_t tile = take_ticket(&meta->ticket, &s_tile);
+  const uint32_t tile = blockIdx.x;
   const uint32_t base = tile * kScanTile;
   bool win[kScanItems];
   uint32_t slot[kScanItems];
@@ -533,8 +657,7 @@ __global__ __launch_bounds__(kBlock) void k_voxel_commit(TableRef tb, VoxelKeys 
   uint32_t rank[kScanItems];
   uint32_t total;
   block_rank_rows(win, rank, total, s_scan);
-  if (threadIdx.x == 0) s_prefix = tile_lookback(status, tile, meta->epoch, total, &meta->status);
-  __syncthreads();
+  block_lookback(status, tile, meta->epoch, total, &meta->status, &s_prefix);
 #pragma unroll
   for (int r = 0; r < kScanItems; ++r) {
     if (!win[r]) continue;
@@ -594,70 +717,116 @@ hipError_t launch_reset_meta(Meta* m, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(Meta* m, uint32_t cap, int mode, int silent, const uint64_t* status, uint32_t last_tile,
-                           hipStream_t st) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1), 0, st, m, cap, mode, silent, status, last_tile);
+hipError_t launch_finalize(Meta* m, uint32_t cap, int mode, int silent, int check, const uint64_t* status,
+                           uint32_t last_tile, hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1), 0, st, m, cap, mode, silent, check, status, last_tile);
   return hipGetLastError();
 }
 
-// Positions per block of the probing kernels: 256 (G lanes per position).
+hipError_t launch_sum_partials(const uint32_t* partial, uint32_t count, Meta* meta, hipStream_t st) {
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, st, partial, count, meta);
+  return hipGetLastError();
+}
+
+// Positions per block of the probing kernels: 256 (G lanes per position, so
+// a group takes G positions in turn).
 template <int G>
 static inline uint32_t rounds_for() { return 256u / (kBlock / G); }
 
-template <int KD, int G>
-static hipError_t claim_kg(const TableRef& tb, const int32_t* keys, uint32_t n, uint32_t* slot_of, Meta* meta,
-                           hipStream_t st) {
-  const uint32_t rounds = rounds_for<G>();
-  const uint32_t grid = cdiv(n, (kBlock / G) * rounds);
-  hipLaunchKernelGGL((k_claim<KD, G, BatchKeys<KD>>), dim3(grid), dim3(kBlock), 0, st, tb, BatchKeys<KD>{keys}, n,
-                     rounds, slot_of, meta);
-  return hipGetLastError();
+template <int KD, int G, int WL>
+struct ClaimK {
+  static hipError_t run(const TableRef& tb, const int32_t* keys, uint32_t n, uint32_t* slot_of, uint32_t* partial,
+                        Meta* meta, hipStream_t st) {
+    const uint32_t rounds = rounds_for<G>();
+    hipLaunchKernelGGL((k_claim<KD, G, WL, BatchKeys<KD>, false>), dim3(cdiv(n, (kBlock / G) * rounds)),
+                       dim3(kBlock), 0, st, tb, BatchKeys<KD>{keys}, n, rounds, slot_of, partial, meta);
+    return hipGetLastError();
+  }
+};
+
+template <int KD, int G, int WL>
+struct FindK {
+  static hipError_t run(const TableRef& tb, const int32_t* keys, uint32_t n, int32_t* out_idx, uint8_t* out_mask,
+                        const ValueSet& vs, hipStream_t st) {
+    const uint32_t rounds = rounds_for<G>();
+    hipLaunchKernelGGL((k_find<KD, G, WL>), dim3(cdiv(n, (kBlock / G) * rounds)), dim3(kBlock), 0, st, tb, keys, n,
+                       rounds, out_idx, out_mask, vs);
+    return hipGetLastError();
+  }
+};
+
+template <int KD, int G, int WL>
+struct EraseMarkK {
+  static hipError_t run(const TableRef& tb, const int32_t* keys, uint32_t n, uint32_t* slot_of, int32_t* found,
+                        int32_t* owner, hipStream_t st) {
+    const uint32_t rounds = rounds_for<G>();
+    hipLaunchKernelGGL((k_erase_mark<KD, G, WL>), dim3(cdiv(n, (kBlock / G) * rounds)), dim3(kBlock), 0, st, tb,
+                       keys, n, rounds, slot_of, found, owner);
+    return hipGetLastError();
+  }
+};
+
+template <int KD, int G, int WL>
+struct RebuildK {
+  static hipError_t run(const TableRef& tb, const int32_t* kB, const uint8_t* active, uint32_t c, Meta* meta,
+                        hipStream_t st) {
+    const uint32_t rounds = rounds_for<G>();
+    hipLaunchKernelGGL((k_rebuild<KD, G, WL>), dim3(cdiv(c, (kBlock / G) * rounds)), dim3(kBlock), 0, st, tb, kB,
+                       active, c, rounds, meta);
+    return hipGetLastError();
+  }
+};
+
+template <int KD, int G, int WL>
+struct VoxelClaimK {
+  static hipError_t run(const TableRef& tb, const float* pts, float voxel, uint32_t n, uint32_t* slot_of,
+                        uint32_t* partial, Meta* meta, hipStream_t st) {
+    const uint32_t rounds = rounds_for<G>();
+    hipLaunchKernelGGL((k_claim<3, G, WL, VoxelKeys, true>), dim3(cdiv(n, (kBlock / G) * rounds)), dim3(kBlock), 0,
+                       st, tb, VoxelKeys{pts, voxel}, n, rounds, slot_of, partial, meta);
+    return hipGetLastError();
+  }
+};
+
+// Dispatch on the probe shape: G lanes per key (WL = 1), or one lane per key
+// reading a bucket of WL slots (G = 1).
+template <int KD, template <int, int, int> class F, typename... A>
+static hipError_t with_probe(int g, int w, A&&... a) {
+  if (g == 1) {
+    switch (w) {
+      case 2: return F<KD, 1, 2>::run(a...);
+      case 4: return F<KD, 1, 4>::run(a...);
+      case 8: return F<KD, 1, 8>::run(a...);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  switch (g) {
+    case 4: return F<KD, 4, 1>::run(a...);
+    case 8: return F<KD, 8, 1>::run(a...);
+    case 16: return F<KD, 16, 1>::run(a...);
+    case 32: return F<KD, 32, 1>::run(a...);
+    case 64: return F<KD, 64, 1>::run(a...);
+    default: return hipErrorInvalidValue;
+  }
 }
 
-template <int KD, int G>
-static hipError_t find_kg(const TableRef& tb, const int32_t* keys, uint32_t n, int32_t* out_idx, uint8_t* out_mask,
-                          const ValueSet& vs, hipStream_t st) {
-  const uint32_t rounds = rounds_for<G>();
-  const uint32_t grid = cdiv(n, (kBlock / G) * rounds);
-  hipLaunchKernelGGL((k_find<KD, G>), dim3(grid), dim3(kBlock), 0, st, tb, keys, n, rounds, out_idx, out_mask, vs);
-  return hipGetLastError();
-}
-
-template <int KD, int G>
-static hipError_t erase_mark_kg(const TableRef& tb, const int32_t* keys, uint32_t n, uint32_t* slot_of,
-                                int32_t* found, int32_t* owner, hipStream_t st) {
-  const uint32_t rounds = rounds_for<G>();
-  const uint32_t grid = cdiv(n, (kBlock / G) * rounds);
-  hipLaunchKernelGGL((k_erase_mark<KD, G>), dim3(grid), dim3(kBlock), 0, st, tb, keys, n, rounds, slot_of, found,
-                     owner);
-  return hipGetLastError();
-}
-
-template <int KD, int G>
-static hipError_t rebuild_kg(const TableRef& tb, const int32_t* kB, const uint8_t* active, uint32_t c, Meta* meta,
-                             hipStream_t st) {
-  const uint32_t rounds = rounds_for<G>();
-  const uint32_t grid = cdiv(c, (kBlock / G) * rounds);
-  hipLaunchKernelGGL((k_rebuild<KD, G>), dim3(grid), dim3(kBlock), 0, st, tb, kB, active, c, rounds, meta);
-  return hipGetLastError();
-}
-
-template <int G>
-static hipError_t voxel_claim_g(const TableRef& tb, const float* pts, float voxel, uint32_t n, uint32_t* slot_of,
-                                Meta* meta, hipStream_t st) {
-  const uint32_t rounds = rounds_for<G>();
-  const uint32_t grid = cdiv(n, (kBlock / G) * rounds);
-  hipLaunchKernelGGL((k_claim<3, G, VoxelKeys>), dim3(grid), dim3(kBlock), 0, st, tb, VoxelKeys{pts, voxel}, n,
-                     rounds, slot_of, meta);
-  return hipGetLastError();
+template <template <int, int, int> class F, typename... A>
+static hipError_t with_kd_probe(int kd, int g, int w, A&&... a) {
+  switch (kd) {
+    case 1: return with_probe<1, F>(g, w, a...);
+    case 2: return with_probe<2, F>(g, w, a...);
+    case 3: return with_probe<3, F>(g, w, a...);
+    case 4: return with_probe<4, F>(g, w, a...);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <int KD>
 static hipError_t commit_k(const TableRef& tb, const int32_t* keys, uint32_t n, const uint32_t* slot_of, int32_t* kB,
                            const int32_t* heap, uint8_t* active, uint32_t cap, const ValueSet& vs, int32_t* out_idx,
-                           uint8_t* out_mask, Meta* meta, uint64_t* status, hipStream_t st) {
+                           uint8_t* out_mask, Meta* meta, uint64_t* status, int check, hipStream_t st) {
   hipLaunchKernelGGL((k_commit<KD>), dim3(cdiv(n, kScanTile)), dim3(kBlock), 0, st, tb, keys, n, slot_of, kB, heap,
-                     active, cap, vs, out_idx, out_mask, meta, status);
+                     active, cap, vs, out_idx, out_mask, meta, status, check);
   return hipGetLastError();
 }
 
@@ -670,100 +839,32 @@ static hipError_t erase_commit_k(const TableRef& tb, uint32_t n, const uint32_t*
   return hipGetLastError();
 }
 
-// Dispatch on the probe-group width G.
-template <template <int> class F, typename... A>
-static hipError_t with_g(int g, A&&... a) {
-  switch (g) {
-    case 4: return F<4>::run(a...);
-    case 8: return F<8>::run(a...);
-    case 16: return F<16>::run(a...);
-    case 32: return F<32>::run(a...);
-    case 64: return F<64>::run(a...);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-template <int KD>
-struct ClaimG {
-  template <int G>
-  struct F {
-    template <typename... A>
-    static hipError_t run(A&&... a) { return claim_kg<KD, G>(a...); }
-  };
-};
-template <int KD>
-struct FindG {
-  template <int G>
-  struct F {
-    template <typename... A>
-    static hipError_t run(A&&... a) { return find_kg<KD, G>(a...); }
-  };
-};
-template <int KD>
-struct EraseMarkG {
-  template <int G>
-  struct F {
-    template <typename... A>
-    static hipError_t run(A&&... a) { return erase_mark_kg<KD, G>(a...); }
-  };
-};
-template <int KD>
-struct RebuildG {
-  template <int G>
-  struct F {
-    template <typename... A>
-    static hipError_t run(A&&... a) { return rebuild_kg<KD, G>(a...); }
-  };
-};
-template <int G>
-struct VoxelClaimG {
-  template <typename... A>
-  static hipError_t run(A&&... a) { return voxel_claim_g<G>(a...); }
-};
-
-hipError_t launch_claim(int kd, int g, const TableRef& tb, const int32_t* keys, uint32_t n, uint32_t* slot_of,
-                        Meta* meta, hipStream_t st) {
-  switch (kd) {
-    case 1: return with_g<ClaimG<1>::F>(g, tb, keys, n, slot_of, meta, st);
-    case 2: return with_g<ClaimG<2>::F>(g, tb, keys, n, slot_of, meta, st);
-    case 3: return with_g<ClaimG<3>::F>(g, tb, keys, n, slot_of, meta, st);
-    case 4: return with_g<ClaimG<4>::F>(g, tb, keys, n, slot_of, meta, st);
-    default: return hipErrorInvalidValue;
-  }
+hipError_t launch_claim(int kd, int g, int w, const TableRef& tb, const int32_t* keys, uint32_t n, uint32_t* slot_of,
+                        uint32_t* partial, Meta* meta, hipStream_t st) {
+  return with_kd_probe<ClaimK>(kd, g, w, tb, keys, n, slot_of, partial, meta, st);
 }
 
 hipError_t launch_commit(int kd, const TableRef& tb, const int32_t* keys, uint32_t n, const uint32_t* slot_of,
                          int32_t* kB, const int32_t* heap, uint8_t* active, uint32_t cap, const ValueSet& vs,
-                         int32_t* out_idx, uint8_t* out_mask, Meta* meta, uint64_t* status, hipStream_t st) {
+                         int32_t* out_idx, uint8_t* out_mask, Meta* meta, uint64_t* status, int check,
+                         hipStream_t st) {
   switch (kd) {
-    case 1: return commit_k<1>(tb, keys, n, slot_of, kB, heap, active, cap, vs, out_idx, out_mask, meta, status, st);
-    case 2: return commit_k<2>(tb, keys, n, slot_of, kB, heap, active, cap, vs, out_idx, out_mask, meta, status, st);
-    case 3: return commit_k<3>(tb, keys, n, slot_of, kB, heap, active, cap, vs, out_idx, out_mask, meta, status, st);
-    case 4: return commit_k<4>(tb, keys, n, slot_of, kB, heap, active, cap, vs, out_idx, out_mask, meta, status, st);
+    case 1: return commit_k<1>(tb, keys, n, slot_of, kB, heap, active, cap, vs, out_idx, out_mask, meta, status, check, st);
+    case 2: return commit_k<2>(tb, keys, n, slot_of, kB, heap, active, cap, vs, out_idx, out_mask, meta, status, check, st);
+    case 3: return commit_k<3>(tb, keys, n, slot_of, kB, heap, active, cap, vs, out_idx, out_mask, meta, status, check, st);
+    case 4: return commit_k<4>(tb, keys, n, slot_of, kB, heap, active, cap, vs, out_idx, out_mask, meta, status, check, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_find(int kd, int g, const TableRef& tb, const int32_t* keys, uint32_t n, int32_t* out_idx,
+hipError_t launch_find(int kd, int g, int w, const TableRef& tb, const int32_t* keys, uint32_t n, int32_t* out_idx,
                        uint8_t* out_mask, const ValueSet& vs, hipStream_t st) {
-  switch (kd) {
-    case 1: return with_g<FindG<1>::F>(g, tb, keys, n, out_idx, out_mask, vs, st);
-    case 2: return with_g<FindG<2>::F>(g, tb, keys, n, out_idx, out_mask, vs, st);
-    case 3: return with_g<FindG<3>::F>(g, tb, keys, n, out_idx, out_mask, vs, st);
-    case 4: return with_g<FindG<4>::F>(g, tb, keys, n, out_idx, out_mask, vs, st);
-    default: return hipErrorInvalidValue;
-  }
+  return with_kd_probe<FindK>(kd, g, w, tb, keys, n, out_idx, out_mask, vs, st);
 }
 
-hipError_t launch_erase_mark(int kd, int g, const TableRef& tb, const int32_t* keys, uint32_t n, uint32_t* slot_of,
-                             int32_t* found, int32_t* owner, hipStream_t st) {
-  switch (kd) {
-    case 1: return with_g<EraseMarkG<1>::F>(g, tb, keys, n, slot_of, found, owner, st);
-    case 2: return with_g<EraseMarkG<2>::F>(g, tb, keys, n, slot_of, found, owner, st);
-    case 3: return with_g<EraseMarkG<3>::F>(g, tb, keys, n, slot_of, found, owner, st);
-    case 4: return with_g<EraseMarkG<4>::F>(g, tb, keys, n, slot_of, found, owner, st);
-    default: return hipErrorInvalidValue;
-  }
+hipError_t launch_erase_mark(int kd, int g, int w, const TableRef& tb, const int32_t* keys, uint32_t n,
+                             uint32_t* slot_of, int32_t* found, int32_t* owner, hipStream_t st) {
+  return with_kd_probe<EraseMarkK>(kd, g, w, tb, keys, n, slot_of, found, owner, st);
 }
 
 hipError_t launch_erase_commit(int kd, const TableRef& tb, uint32_t n, const uint32_t* slot_of, const int32_t* found,
@@ -784,21 +885,17 @@ hipError_t launch_compact_active(const uint8_t* active, uint32_t c, int32_t* out
   return hipGetLastError();
 }
 
-hipError_t launch_rebuild(int kd, int g, const TableRef& tb, const int32_t* kB, const uint8_t* active, uint32_t c,
-                          Meta* meta, hipStream_t st) {
-  switch (kd) {
-    case 1: return with_g<RebuildG<1>::F>(g, tb, kB, active, c, meta, st);
-    case 2: return with_g<RebuildG<2>::F>(g, tb, kB, active, c, meta, st);
-    case 3: return with_g<RebuildG<3>::F>(g, tb, kB, active, c, meta, st);
-    case 4: return with_g<RebuildG<4>::F>(g, tb, kB, active, c, meta, st);
-    default: return hipErrorInvalidValue;
-  }
+hipError_t launch_rebuild(int kd, int g, int w, const TableRef& tb, const int32_t* kB, const uint8_t* active,
+                          uint32_t c, Meta* meta, hipStream_t st) {
+  return with_kd_probe<RebuildK>(kd, g, w, tb, kB, active, c, meta, st);
 }
 
-hipError_t launch_voxel_claim(int g, const TableRef& tb, const float* pts, float voxel, uint32_t n,
-                              uint32_t* slot_of, Meta* meta, hipStream_t st) {
-  return with_g<VoxelClaimG>(g, tb, pts, voxel, n, slot_of, meta, st);
+hipError_t launch_voxel_claim(int g, int w, const TableRef& tb, const float* pts, float voxel, uint32_t n,
+                              uint32_t* slot_of, uint32_t* partial, Meta* meta, hipStream_t st) {
+  return with_probe<3, VoxelClaimK>(g, w, tb, pts, voxel, n, slot_of, partial, meta, st);
 }
+
+uint32_t claim_blocks(int g, uint32_t n) { return cdiv(n, 256u); }
 
 hipError_t launch_voxel_commit(const TableRef& tb, const float* pts, float voxel, uint32_t n, const uint32_t* slot_of,
                                int32_t* voxel_keys, int32_t* counts, Meta* meta, uint64_t* status, hipStream_t st) {

@@ -14,26 +14,30 @@ enum FinalizeMode { kFinalizeInsert = 0, kFinalizeErase = 1, kFinalizeCount = 2,
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t st);
 hipError_t launch_iota(int32_t* h, uint32_t from, uint32_t to, hipStream_t st);
 hipError_t launch_reset_meta(Meta* m, hipStream_t st);
-hipError_t launch_finalize(Meta* m, uint32_t cap, int mode, int silent, const uint64_t* status, uint32_t last_tile,
-                           hipStream_t st);
-hipError_t launch_claim(int kd, int g, const TableRef& tb, const int32_t* keys, uint32_t n, uint32_t* slot_of,
-                        Meta* meta, hipStream_t st);
+hipError_t launch_finalize(Meta* m, uint32_t cap, int mode, int silent, int check, const uint64_t* status,
+                           uint32_t last_tile, hipStream_t st);
+hipError_t launch_sum_partials(const uint32_t* partial, uint32_t count, Meta* meta, hipStream_t st);
+// Number of blocks (and per-block counts) of a claim launch over n positions.
+uint32_t claim_blocks(int g, uint32_t n);
+hipError_t launch_claim(int kd, int g, int w, const TableRef& tb, const int32_t* keys, uint32_t n, uint32_t* slot_of,
+                        uint32_t* partial, Meta* meta, hipStream_t st);
 hipError_t launch_commit(int kd, const TableRef& tb, const int32_t* keys, uint32_t n, const uint32_t* slot_of,
                          int32_t* kB, const int32_t* heap, uint8_t* active, uint32_t cap, const ValueSet& vs,
-                         int32_t* out_idx, uint8_t* out_mask, Meta* meta, uint64_t* status, hipStream_t st);
-hipError_t launch_find(int kd, int g, const TableRef& tb, const int32_t* keys, uint32_t n, int32_t* out_idx,
+                         int32_t* out_idx, uint8_t* out_mask, Meta* meta, uint64_t* status, int check,
+                         hipStream_t st);
+hipError_t launch_find(int kd, int g, int w, const TableRef& tb, const int32_t* keys, uint32_t n, int32_t* out_idx,
                        uint8_t* out_mask, const ValueSet& vs, hipStream_t st);
-hipError_t launch_erase_mark(int kd, int g, const TableRef& tb, const int32_t* keys, uint32_t n, uint32_t* slot_of,
+hipError_t launch_erase_mark(int kd, int g, int w, const TableRef& tb, const int32_t* keys, uint32_t n, uint32_t* slot_of,
                              int32_t* found, int32_t* owner, hipStream_t st);
 hipError_t launch_erase_commit(int kd, const TableRef& tb, uint32_t n, const uint32_t* slot_of, const int32_t* found,
                                int32_t* owner, int32_t* heap, uint8_t* active, uint8_t* out_mask, Meta* meta,
                                uint64_t* status, hipStream_t st);
 hipError_t launch_compact_active(const uint8_t* active, uint32_t c, int32_t* out, Meta* meta, uint64_t* status,
                                  hipStream_t st);
-hipError_t launch_rebuild(int kd, int g, const TableRef& tb, const int32_t* kB, const uint8_t* active, uint32_t c,
+hipError_t launch_rebuild(int kd, int g, int w, const TableRef& tb, const int32_t* kB, const uint8_t* active, uint32_t c,
                           Meta* meta, hipStream_t st);
-hipError_t launch_voxel_claim(int g, const TableRef& tb, const float* pts, float voxel, uint32_t n,
-                              uint32_t* slot_of, Meta* meta, hipStream_t st);
+hipError_t launch_voxel_claim(int g, int w, const TableRef& tb, const float* pts, float voxel, uint32_t n,
+                              uint32_t* slot_of, uint32_t* partial, Meta* meta, hipStream_t st);
 hipError_t launch_voxel_commit(const TableRef& tb, const float* pts, float voxel, uint32_t n, const uint32_t* slot_of,
                                int32_t* voxel_keys, int32_t* counts, Meta* meta, uint64_t* status, hipStream_t st);
 hipError_t launch_voxel_resolve(const TableRef& tb, uint32_t n, const uint32_t* slot_of, int32_t* point_voxel,

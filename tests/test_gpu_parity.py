@@ -135,7 +135,8 @@ def test_plain_small_sequence(ash):
     plain_small_sequence(pair, d)
 
 
-@pytest.mark.parametrize("g,w,lf", [(4, 4, 0.5), (8, 8, 0.7), (16, 4, 0.85), (32, 32, 0.5), (64, 16, 0.9)])
+@pytest.mark.parametrize("g,w,lf", [(1, 2, 0.5), (1, 4, 0.7), (1, 8, 0.9), (4, 4, 0.5), (8, 8, 0.7),
+                                     (16, 4, 0.85), (32, 32, 0.5), (64, 16, 0.9)])
 def test_tuning_grid_same_results(ash, g, w, lf):
     d = synth.plain_small(seed=11)
     pair = Pair(ash, d["capacity"], 3, [(np.float32, 1)], probe_group=g, bucket_width=w, max_load=lf)
@@ -260,10 +261,11 @@ def test_erase_insert_churn(ash, capacity):
     assert cleaned
 
 
-def test_small_table_long_probes(ash):
+@pytest.mark.parametrize("g", [1, 4])
+def test_small_table_long_probes(ash, g):
     """Capacity 200 at max_load 0.9: windows wrap the table end, probes are long."""
     rng = np.random.default_rng(23)
-    pair = Pair(ash, 200, 2, [(np.float32, 1)], max_load=0.9, probe_group=4, bucket_width=4)
+    pair = Pair(ash, 200, 2, [(np.float32, 1)], max_load=0.9, probe_group=g, bucket_width=4)
     k = rng.integers(0, 1000, size=(2000, 2), dtype=np.int32)
     pair.insert(k[:400], [rng.standard_normal((400, 1)).astype(np.float32)])
     pair.find(k)
