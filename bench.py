@@ -9,8 +9,9 @@ second over the whole step (insert + find + erase positions / step time).
 
 Per-kernel durations come from HIP events the library records around each
 launch on the launch stream (ash_profile_enable) during the timed steps; the
-dominant kernel's roofline uses the granule accounting (each random access
-costs one 64-byte DRAM granule) stated in the design doc.
+dominant kernel's roofline counts algorithmic DRAM bytes with the per-access
+costs measured on MI355X (a random read moves a 128-byte line, a 64-bit CAS
+64 bytes, a small store 32 bytes), as stated in the design doc.
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 3] [--rho 0.5] [--channels 8]
 """
@@ -27,30 +28,40 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
-GRANULE = 64           # bytes per random DRAM access in the granule accounting
+
+# DRAM cost of one access of each kind on MI355X, measured with rocprofv3 on a
+# random-access microbenchmark (FETCH_SIZE x2 calibrated, WRITE_SIZE x1):
+READ_LINE = 128   # a random read fills one 128-byte L2 line
+CAS64 = 64        # a device-scope 64-bit CAS is done at the memory side
+ATOM32 = 32       # a 32-bit atomic
+STORE = 32        # a small random store writes a 32-byte sector
 
 
-def kernel_bytes(name, n, u, eta, channels, win, e):
-    """Algorithmic bytes of one launch over n positions (granule accounting).
+def kernel_bytes(name, n, u, d, e, channels):
+    """Algorithmic DRAM bytes of one launch over n positions.
 
-    claim   : key 12 B streamed + one random slot window (g)
-    commit  : idx 4 + mask 1 streamed + the claimed slot line (g) for new keys
-              + per new key: k^B 12 + heap 4 + value read 4C + value write 4C
-    find    : key 12 + idx 4 + mask 1 streamed + one random window (g)
-    erase_mark   : key 12 streamed + one window (g) + owner update for hits (g)
-    erase_commit : mask 1 streamed + for winners: slot (g), heap 4, flags
+    u = fraction of positions holding a new key, d = fraction that are later
+    duplicates of a new key in the same batch, e = fraction of erase positions
+    that free an index, C = float channels per value row.
+
+    claim        : key 12 (stream) + slot window (line) + claim CAS for new keys
+                   + one read of the first occurrence's key per in-batch duplicate
+    commit       : idx 4 + mask 1 (stream) + per new key: k^B 12, heap 4,
+                   value read 4C and write 4C (streams)
+    find         : key 12 + idx 4 + mask 1 (stream) + slot window (line)
+    erase_mark   : key 12 (stream) + slot window (line) + owner election (64-bit atomic)
+    erase_commit : mask 1 (stream) + per freed index: heap 4 + tombstone store
     """
-    g = GRANULE
     if name == "claim":
-        return n * (12 + g)
+        return n * (12 + READ_LINE + u * CAS64 + d * READ_LINE)
     if name == "commit":
-        return n * (5 + u * (g + 16 + 8 * channels))
+        return n * (5 + u * (16 + 8 * channels))
     if name == "find":
-        return n * (17 + g)
+        return n * (17 + READ_LINE)
     if name == "erase_mark":
-        return n * (12 + g + g * win)
+        return n * (12 + READ_LINE + CAS64)
     if name == "erase_commit":
-        return n * (1 + e * (g + 4 + 1))
+        return n * (1 + e * (4 + STORE))
     return None
 
 
@@ -66,6 +77,8 @@ def main():
     ap.add_argument("--max-load", type=float, default=0.5)
     ap.add_argument("--cpu-sample", type=int, default=2_000_000,
                     help="positions of the workload the oracle runs for cpu_baseline (0 = skip)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed steps, copy 256 MiB once (reference kernel for byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU sharding is a design note only"}))
@@ -110,6 +123,7 @@ def main():
         step()
     torch.cuda.synchronize()
     u = float(mask.sum().item()) / n
+    dup = 1.0 - u  # fresh map each step: every non-new position repeats a new key of the batch
     eta = float(fmask.sum().item()) / nf
     e = float(emask.sum().item()) / ne
     assert m.device_status() == 0
@@ -124,6 +138,12 @@ def main():
     t1 = time.perf_counter()
     kernels = m.profile_collect()
     m.profile(False)
+    if args.copy_calibration:
+        a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda").fill_(1)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     ops = n + nf + ne
     value = ops / (ms_per_step * 1e-3) / 1e6
@@ -132,13 +152,13 @@ def main():
     for name, (launches, total) in kernels.items():
         avg = total / launches
         units = {"claim": n, "commit": n, "find": nf, "erase_mark": ne, "erase_commit": ne}.get(name)
-        b = kernel_bytes(name, units, u, eta, args.channels, 1.0, e) if units else None
+        b = kernel_bytes(name, units, u, dup, e, args.channels) if units else None
         per_kernel[name] = {"launches_per_step": launches / args.steps, "avg_ms": round(avg, 4),
                             "GBps": round(b / (avg * 1e-3) / 1e9, 1) if b else None}
     dom = max((k for k in per_kernel if per_kernel[k]["GBps"] is not None),
               key=lambda k: kernels[k][1])
     dom_units = {"claim": n, "commit": n, "find": nf, "erase_mark": ne, "erase_commit": ne}[dom]
-    dom_bytes = kernel_bytes(dom, dom_units, u, eta, args.channels, 1.0, e)
+    dom_bytes = kernel_bytes(dom, dom_units, u, dup, e, args.channels)
     achieved = dom_bytes / (per_kernel[dom]["avg_ms"] * 1e-3) / 1e9
 
     cpu = None
@@ -177,7 +197,7 @@ def main():
                                 "erase_win_fraction": round(e, 4)}},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "granule_bytes": GRANULE},
+                     "access_bytes": {"read_line": READ_LINE, "cas64": CAS64, "atomic32": ATOM32, "store": STORE}},
         "kernels": per_kernel,
         "cpu_baseline": cpu,
     }

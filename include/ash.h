@@ -187,6 +187,47 @@ ash_status_t ash_voxelize(const float* points, int64_t n, float voxel,
                           int32_t* out_voxel_counts, int64_t* out_n_voxels,
                           const ash_allocator_t* allocator, void* stream);
 
+/* Batched maps (many independent maps of uneven sizes at once).  One op is
+ * one map's work: an insert batch, then a find batch, with the meaning of
+ * ash_insert followed by ash_find on that map (insert_values / find_values
+ * are host arrays of n_values device pointers; outputs may be NULL).  With
+ * fused = 1 all ops run in one persistent cooperative launch whose phases
+ * (claims, commits, heap tops, finds) are separated by grid barriers and
+ * whose tiles are spread over every resident block, each map keeping its own
+ * probe shape; fused = 0 runs the same work op by op through the single-map
+ * path.  Maps must be distinct, share key_dim and not use ASH_F_AUTOGROW
+ * (ASH_E_UNSUPPORTED otherwise).  Capacity overflow of one map rolls back
+ * that map's batch only, as in ash_insert. */
+typedef struct {
+  ash_map_t map;
+  const int32_t* insert_keys;
+  int64_t n_insert;
+  const void* const* insert_values;
+  int32_t* insert_idx;
+  uint8_t* insert_mask;
+  const int32_t* find_keys;
+  int64_t n_find;
+  void* const* find_values;
+  int32_t* find_idx;
+  uint8_t* find_mask;
+} ash_batch_op_t;
+
+ash_status_t ash_batched(const ash_batch_op_t* ops, int32_t n_ops, int32_t fused, void* stream);
+
+/* Autotuner for the table shape.  Times insert + find of a synthetic batch on
+ * this device -- n_insert keys uniform in a cube sized for the expected ratio
+ * of distinct keys, then n_insert finds with half hits -- for every
+ * (bucket_width, probe_group, max_load) of the sweep W in {4, 8, 16, 32},
+ * g in {1 (W <= 8), 4, 8, 16, 64}, max_load in {0.5, 0.7, 0.85}, and writes
+ * the fastest to *out (flags 0) and its time in ms to *out_ms (nullable).
+ * Results are cached per (key_dim, value bytes, log2 capacity, log2 n_insert,
+ * distinct ratio in tenths).  Synchronizes. */
+ash_status_t ash_autotune(int64_t capacity, int32_t key_dim, int32_t n_values,
+                          const ash_dtype_t* value_dtypes, const int64_t* value_elems,
+                          int64_t n_insert, double distinct_ratio,
+                          const ash_allocator_t* allocator, void* stream,
+                          ash_tuning_t* out, double* out_ms);
+
 /* Per-kernel timing of one map (instrumentation).  While enabled, every
  * kernel the map launches is bracketed by HIP events recorded on the launch
  * stream.  ash_profile_collect synchronizes, writes up to max_entries

@@ -44,6 +44,12 @@ class AshKernelTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", I64), ("total_ms", ctypes.c_double)]
 
 
+class AshBatchOp(ctypes.Structure):
+    _fields_ = [("map", P), ("insert_keys", P), ("n_insert", I64), ("insert_values", P), ("insert_idx", P),
+                ("insert_mask", P), ("find_keys", P), ("n_find", I64), ("find_values", P), ("find_idx", P),
+                ("find_mask", P)]
+
+
 class AshStats(ctypes.Structure):
     _fields_ = [("size", I64), ("capacity", I64), ("slots", I64), ("used_slots", I64), ("tombstones", I64)]
 
@@ -66,6 +72,9 @@ SIGNATURES = {
     "ash_heap_buffer": (ST, [P, ctypes.POINTER(P)]),
     "ash_device_status": (ST, [P, P]),
     "ash_voxelize": (ST, [P, I64, ctypes.c_float, P, P, P, ctypes.POINTER(I64), P, P]),
+    "ash_batched": (ST, [ctypes.POINTER(AshBatchOp), I32, I32, P]),
+    "ash_autotune": (ST, [I64, I32, I32, P, P, I64, ctypes.c_double, P, P, ctypes.POINTER(AshTuning),
+                          ctypes.POINTER(ctypes.c_double)]),
     "ash_profile_enable": (ST, [P, I32]),
     "ash_profile_collect": (ST, [P, ctypes.POINTER(AshKernelTime), I32, ctypes.POINTER(I32), P]),
     "ash_status_string": (ctypes.c_char_p, [ST]),

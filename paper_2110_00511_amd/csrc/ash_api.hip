@@ -6,6 +6,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "ash.h"
@@ -121,13 +124,14 @@ struct ash_map {
   int32_t* kB = nullptr;
   std::vector<uint8_t*> vB;
   int32_t* heap = nullptr;
-  uint8_t* active = nullptr;
-  int32_t* owner = nullptr;
+  uint64_t* owner = nullptr;  // erase election: (epoch << 32) | ~position
+  uint32_t erase_epoch = 0;
   Meta* meta = nullptr;
   // per-call scratch
   uint32_t* slot_of = nullptr;
   int32_t* aux = nullptr;
   uint32_t* partial = nullptr;  // per-block new-key counts of the claim kernel
+  uint8_t* lost = nullptr;      // displaced candidates; all zero between calls
   int64_t scratch_n = 0;
   uint64_t* scan_status = nullptr;
   int64_t scan_tiles = 0;
@@ -191,13 +195,17 @@ ash_status_t ensure_scratch(ash_map* m, int64_t n, hipStream_t st) {
     m->mem.put(m->slot_of, st);
     m->mem.put(m->aux, st);
     m->mem.put(m->partial, st);
+    m->mem.put(m->lost, st);
+    const size_t lost_bytes = ((size_t)n + 3) / 4 * 4;
     m->slot_of = (uint32_t*)m->mem.get((size_t)n * 4, st);
     m->aux = (int32_t*)m->mem.get((size_t)n * 4, st);
     m->partial = (uint32_t*)m->mem.get(((size_t)n / 256 + 2) * 4, st);
-    if (!m->slot_of || !m->aux || !m->partial) {
+    m->lost = (uint8_t*)m->mem.get(lost_bytes, st);
+    if (!m->slot_of || !m->aux || !m->partial || !m->lost) {
       m->scratch_n = 0;
       return ASH_E_NOMEM;
     }
+    ASH_HIP(ash::launch_fill_u32((uint32_t*)m->lost, 0u, lost_bytes / 4, st));
     m->scratch_n = n;
   }
   const int64_t tiles = (std::max(n, m->c) + ash::kScanTile - 1) / ash::kScanTile + 1;
@@ -219,28 +227,30 @@ void free_buffers(ash_map* m, hipStream_t st) {
   m->mem.put(m->kB, st);
   for (uint8_t* p : m->vB) m->mem.put(p, st);
   m->mem.put(m->heap, st);
-  m->mem.put(m->active, st);
   m->mem.put(m->owner, st);
   m->table = nullptr;
   m->kB = nullptr;
   m->vB.assign(m->vB.size(), nullptr);
   m->heap = nullptr;
-  m->active = nullptr;
   m->owner = nullptr;
 }
 
 // Rebuilds the slot table of `m` (new slot array, tombstones dropped) from the
-// key buffer and the active flags, sized for max(c, room_for) keys.
+// committed slots of the old table, sized for max(c, room_for) keys.
 ash_status_t rebuild_table(ash_map* m, int64_t live, hipStream_t st, int64_t room_for = 0) {
   uint32_t nslots;
   ASH_TRY(slots_for(std::max(m->c, room_for), m->max_load, m->W, m->G, &nslots));
   uint32_t* fresh = (uint32_t*)m->mem.get((size_t)nslots * m->slot_words() * 4, st);
   if (!fresh) return ASH_E_NOMEM;
   ASH_HIP(ash::launch_fill_u32(fresh, ash::kEmpty, (size_t)nslots * m->slot_words(), st));
-  m->mem.put(m->table, st);
+  uint32_t* old = m->table;
+  const uint32_t old_slots = m->nslots;
   m->table = fresh;
   m->nslots = nslots;
-  if (m->c > 0) ASH_HIP(timed(m, "rebuild", st, [&] { return ash::launch_rebuild(m->key_dim, m->G, m->W, m->ref(), m->kB, m->active, (uint32_t)m->c, m->meta, st); }));
+  ASH_HIP(timed(m, "rebuild", st, [&] {
+    return ash::launch_rebuild(m->key_dim, m->G, m->W, m->ref(), old, old_slots, m->meta, st);
+  }));
+  m->mem.put(old, st);
   ASH_HIP(timed(m, "finalize", st, [&] { return ash::launch_finalize(m->meta, (uint32_t)m->c, ash::kFinalizeRebuild, 0, 0, m->scan_status, 0, st); }));
   // live keys now occupy exactly `live` slots and there are no tombstones
   Meta h;
@@ -265,10 +275,9 @@ ash_status_t grow(ash_map* m, int64_t new_c, hipStream_t st) {
     const int64_t keep = m->c;
     int32_t* kB = (int32_t*)m->mem.get((size_t)new_c * m->key_dim * 4, st);
     int32_t* heap = (int32_t*)m->mem.get((size_t)new_c * 4, st);
-    uint8_t* active = (uint8_t*)m->mem.get((size_t)new_c, st);
-    int32_t* owner = (int32_t*)m->mem.get((size_t)new_c * 4, st);
+    uint64_t* owner = (uint64_t*)m->mem.get((size_t)new_c * 8, st);
     std::vector<uint8_t*> vB(m->n_values, nullptr);
-    bool ok = kB && heap && active && owner;
+    bool ok = kB && heap && owner;
     for (int j = 0; j < m->n_values && ok; ++j) {
       vB[j] = (uint8_t*)m->mem.get((size_t)new_c * m->row_bytes[j], st);
       ok = vB[j] != nullptr;
@@ -276,7 +285,6 @@ ash_status_t grow(ash_map* m, int64_t new_c, hipStream_t st) {
     if (!ok) {
       m->mem.put(kB, st);
       m->mem.put(heap, st);
-      m->mem.put(active, st);
       m->mem.put(owner, st);
       for (uint8_t* p : vB) m->mem.put(p, st);
       return ASH_E_NOMEM;
@@ -286,23 +294,19 @@ ash_status_t grow(ash_map* m, int64_t new_c, hipStream_t st) {
     if (keep > 0) {
       ASH_HIP(hipMemcpyAsync(kB, m->kB, (size_t)keep * m->key_dim * 4, hipMemcpyDeviceToDevice, st));
       ASH_HIP(hipMemcpyAsync(heap, m->heap, (size_t)keep * 4, hipMemcpyDeviceToDevice, st));
-      ASH_HIP(hipMemcpyAsync(active, m->active, (size_t)keep, hipMemcpyDeviceToDevice, st));
       for (int j = 0; j < m->n_values; ++j)
         ASH_HIP(hipMemcpyAsync(vB[j], m->vB[j], (size_t)keep * m->row_bytes[j], hipMemcpyDeviceToDevice, st));
     }
-    if (new_c > keep) {
-      ASH_HIP(ash::launch_iota(heap, (uint32_t)keep, (uint32_t)new_c, st));
-      ASH_HIP(hipMemsetAsync(active + keep, 0, (size_t)(new_c - keep), st));
-    }
-    ASH_HIP(ash::launch_fill_u32((uint32_t*)owner, 0x7FFFFFFFu, (size_t)new_c, st));
+    if (new_c > keep) ASH_HIP(ash::launch_iota(heap, (uint32_t)keep, (uint32_t)new_c, st));
+    // a zero owner entry carries epoch 0, older than every erase call
+    ASH_HIP(ash::launch_fill_u32((uint32_t*)owner, 0u, (size_t)new_c * 2, st));
+    m->erase_epoch = 0;
     m->mem.put(m->kB, st);
     m->mem.put(m->heap, st);
-    m->mem.put(m->active, st);
     m->mem.put(m->owner, st);
     for (uint8_t* p : m->vB) m->mem.put(p, st);
     m->kB = kB;
     m->heap = heap;
-    m->active = active;
     m->owner = owner;
     m->vB = vB;
     m->c = new_c;
@@ -364,7 +368,8 @@ ash_status_t insert_impl(ash_map* m, const int32_t* keys, int64_t n, const void*
   const uint32_t blocks = ash::claim_blocks(m->G, un);
   auto claim = [&]() -> ash_status_t {
     ASH_HIP(timed(m, "claim", st, [&] {
-      return ash::launch_claim(m->key_dim, m->G, m->W, m->ref(), keys, un, m->slot_of, m->partial, m->meta, st);
+      return ash::launch_claim(m->key_dim, m->G, m->W, m->ref(), keys, un, m->slot_of, m->lost, m->partial, m->meta,
+                               st);
     }));
     return ASH_OK;
   };
@@ -374,7 +379,7 @@ ash_status_t insert_impl(ash_map* m, const int32_t* keys, int64_t n, const void*
   };
   auto commit = [&](int check, int silent, int32_t* oi, uint8_t* om) -> ash_status_t {
     ASH_HIP(timed(m, "commit", st, [&] {
-      return ash::launch_commit(m->key_dim, m->ref(), keys, un, m->slot_of, m->kB, m->heap, m->active,
+      return ash::launch_commit(m->key_dim, m->ref(), keys, un, m->slot_of, m->lost, m->kB, m->heap,
                                 (uint32_t)m->c, vs, oi, om, m->meta, m->scan_status, check, st);
     }));
     ASH_HIP(timed(m, "finalize", st, [&] {
@@ -428,8 +433,6 @@ ash_status_t insert_impl(ash_map* m, const int32_t* keys, int64_t n, const void*
 ash_status_t reset_state(ash_map* m, hipStream_t st) {
   ASH_HIP(ash::launch_fill_u32(m->table, ash::kEmpty, (size_t)m->nslots * m->slot_words(), st));
   ASH_HIP(ash::launch_iota(m->heap, 0, (uint32_t)m->c, st));
-  if (m->c > 0) ASH_HIP(hipMemsetAsync(m->active, 0, (size_t)m->c, st));
-  ASH_HIP(ash::launch_fill_u32((uint32_t*)m->owner, 0x7FFFFFFFu, (size_t)m->c, st));
   ASH_HIP(ash::launch_reset_meta(m->meta, st));
   m->live_ub = 0;
   m->used_ub = 0;
@@ -490,10 +493,9 @@ ash_status_t ash_create(int64_t capacity, int32_t key_dim, int32_t n_values, con
   m->table = (uint32_t*)m->mem.get((size_t)m->nslots * m->slot_words() * 4, st);
   m->kB = (int32_t*)m->mem.get((size_t)capacity * key_dim * 4, st);
   m->heap = (int32_t*)m->mem.get((size_t)capacity * 4, st);
-  m->active = (uint8_t*)m->mem.get((size_t)capacity, st);
-  m->owner = (int32_t*)m->mem.get((size_t)capacity * 4, st);
+  m->owner = (uint64_t*)m->mem.get((size_t)capacity * 8, st);
   m->meta = (Meta*)m->mem.get(sizeof(Meta), st);
-  bool ok = m->table && m->kB && m->heap && m->active && m->owner && m->meta;
+  bool ok = m->table && m->kB && m->heap && m->owner && m->meta;
   for (int j = 0; j < n_values && ok; ++j) {
     m->vB[j] = (uint8_t*)m->mem.get((size_t)capacity * rb[j], st);
     ok = m->vB[j] != nullptr;
@@ -503,8 +505,9 @@ ash_status_t ash_create(int64_t capacity, int32_t key_dim, int32_t n_values, con
     ash_destroy(m);
     return ASH_E_NOMEM;
   }
-  if (hipMemsetAsync(m->meta, 0, sizeof(Meta), st) != hipSuccess || reset_state(m, st) != ASH_OK ||
-      hipStreamSynchronize(st) != hipSuccess) {
+  if (hipMemsetAsync(m->meta, 0, sizeof(Meta), st) != hipSuccess ||
+      ash::launch_fill_u32((uint32_t*)m->owner, 0u, (size_t)capacity * 2, st) != hipSuccess ||
+      reset_state(m, st) != ASH_OK || hipStreamSynchronize(st) != hipSuccess) {
     ash_destroy(m);
     return ASH_E_DEVICE;
   }
@@ -520,6 +523,7 @@ ash_status_t ash_destroy(ash_map_t m) {
   m->mem.put(m->slot_of, st);
   m->mem.put(m->aux, st);
   m->mem.put(m->partial, st);
+  m->mem.put(m->lost, st);
   m->mem.put(m->scan_status, st);
   for (hipEvent_t e : m->prof.pool) (void)hipEventDestroy(e);
   delete m;
@@ -594,9 +598,19 @@ ash_status_t ash_erase(ash_map_t m, const int32_t* keys, int64_t n, uint8_t* out
   ASH_TRY(ensure_scratch(m, n, st));
   const uint32_t un = (uint32_t)n;
   const uint32_t last_tile = (un + ash::kScanTile - 1) / ash::kScanTile - 1;
-  ASH_HIP(timed(m, "erase_mark", st, [&] { return ash::launch_erase_mark(m->key_dim, m->G, m->W, m->ref(), keys, un, m->slot_of, m->aux, m->owner, st); }));
-  ASH_HIP(timed(m, "erase_commit", st, [&] { return ash::launch_erase_commit(m->key_dim, m->ref(), un, m->slot_of, m->aux, m->owner, m->heap, m->active,
-                                   out_mask, m->meta, m->scan_status, st); }));
+  if (++m->erase_epoch == 0) {  // epochs wrapped: start the owner entries afresh
+    ASH_HIP(ash::launch_fill_u32((uint32_t*)m->owner, 0u, (size_t)m->c * 2, st));
+    m->erase_epoch = 1;
+  }
+  const uint32_t epoch = m->erase_epoch;
+  ASH_HIP(timed(m, "erase_mark", st, [&] {
+    return ash::launch_erase_mark(m->key_dim, m->G, m->W, m->ref(), keys, un, epoch, m->slot_of, m->aux, m->owner,
+                                  m->lost, st);
+  }));
+  ASH_HIP(timed(m, "erase_commit", st, [&] {
+    return ash::launch_erase_commit(m->key_dim, m->ref(), un, m->slot_of, m->aux, m->lost, m->heap, out_mask, m->meta,
+                                    m->scan_status, st);
+  }));
   ASH_HIP(timed(m, "finalize", st, [&] { return ash::launch_finalize(m->meta, (uint32_t)m->c, ash::kFinalizeErase, 0, 0, m->scan_status, last_tile, st); }));
   return ASH_OK;
 }
@@ -608,13 +622,25 @@ ash_status_t ash_active_indices(ash_map_t m, int32_t* out_idx, int64_t* out_coun
     *out_count = 0;
     return ASH_OK;
   }
+  const size_t flag_bytes = ((size_t)m->c + 3) / 4 * 4;
+  uint8_t* flags = (uint8_t*)m->mem.get(flag_bytes, st);
+  if (!flags) return ASH_E_NOMEM;
   const uint32_t last_tile = (uint32_t)((m->c + ash::kScanTile - 1) / ash::kScanTile - 1);
-  ASH_HIP(timed(m, "compact_active", st, [&] { return ash::launch_compact_active(m->active, (uint32_t)m->c, out_idx, m->meta, m->scan_status, st); }));
-  ASH_HIP(timed(m, "finalize", st, [&] { return ash::launch_finalize(m->meta, (uint32_t)m->c, ash::kFinalizeCount, 0, 0, m->scan_status, last_tile, st); }));
+  ash_status_t rc = ASH_OK;
+  if (ash::launch_fill_u32((uint32_t*)flags, 0u, flag_bytes / 4, st) != hipSuccess ||
+      timed(m, "active_indices", st, [&] {
+        return ash::launch_active_indices(m->key_dim, m->ref(), flags, (uint32_t)m->c, out_idx, m->meta,
+                                          m->scan_status, st);
+      }) != hipSuccess ||
+      timed(m, "finalize", st, [&] {
+        return ash::launch_finalize(m->meta, (uint32_t)m->c, ash::kFinalizeCount, 0, 0, m->scan_status, last_tile, st);
+      }) != hipSuccess)
+    rc = ASH_E_DEVICE;
   Meta h;
-  ASH_TRY(read_meta(m, &h, st));
-  *out_count = h.result;
-  return ASH_OK;
+  if (rc == ASH_OK) rc = read_meta(m, &h, st);
+  m->mem.put(flags, st);
+  if (rc == ASH_OK) *out_count = h.result;
+  return rc;
 }
 
 ash_status_t ash_rehash(ash_map_t m, int64_t new_capacity, void* stream) {
@@ -702,15 +728,18 @@ ash_status_t ash_voxelize(const float* points, int64_t n, float voxel, int32_t* 
   constexpr float kLoad = 0.5f;
   uint32_t nslots;
   ASH_TRY(slots_for(n, kLoad, kW, kG, &nslots));
+  if (nslots >= 0x7FFFFFFFu) return ASH_E_UNSUPPORTED;  // slot_of keeps a candidate bit
   const uint32_t un = (uint32_t)n;
   const int64_t tiles = (n + ash::kScanTile - 1) / ash::kScanTile;
   uint32_t* table = (uint32_t*)mem.get((size_t)nslots * 16, st);
   uint32_t* slot_of = (uint32_t*)mem.get((size_t)n * 4, st);
   const uint32_t blocks = ash::claim_blocks(kG, un);
   uint32_t* partial = (uint32_t*)mem.get((size_t)blocks * 4, st);
+  const size_t lost_bytes = ((size_t)n + 3) / 4 * 4;
+  uint8_t* lost = (uint8_t*)mem.get(lost_bytes, st);
   uint64_t* status = (uint64_t*)mem.get((size_t)tiles * 8 + sizeof(Meta), st);
   ash_status_t rc = ASH_OK;
-  if (!table || !slot_of || !partial || !status) rc = ASH_E_NOMEM;
+  if (!table || !slot_of || !partial || !lost || !status) rc = ASH_E_NOMEM;
   if (rc == ASH_OK) {
     Meta* meta = (Meta*)(status + tiles);
     TableRef tb;
@@ -725,10 +754,11 @@ ash_status_t ash_voxelize(const float* points, int64_t n, float voxel, int32_t* 
     h.epoch = 1;
     bool ok = ash::launch_fill_u32(table, ash::kEmpty, (size_t)nslots * 4, st) == hipSuccess &&
               ash::launch_fill_u32((uint32_t*)status, 0u, (size_t)tiles * 2, st) == hipSuccess &&
+              ash::launch_fill_u32((uint32_t*)lost, 0u, lost_bytes / 4, st) == hipSuccess &&
               hipMemcpyAsync(meta, &h, sizeof(Meta), hipMemcpyHostToDevice, st) == hipSuccess &&
-              ash::launch_voxel_claim(kG, kW, tb, points, voxel, un, slot_of, partial, meta, st) == hipSuccess &&
+              ash::launch_voxel_claim(kG, kW, tb, points, voxel, un, slot_of, lost, partial, meta, st) == hipSuccess &&
               ash::launch_sum_partials(partial, blocks, meta, st) == hipSuccess &&
-              ash::launch_voxel_commit(tb, points, voxel, un, slot_of, out_voxel_keys, out_voxel_counts, meta,
+              ash::launch_voxel_commit(tb, points, voxel, un, slot_of, lost, out_voxel_keys, out_voxel_counts, meta,
                                        status, st) == hipSuccess &&
               ash::launch_voxel_resolve(tb, un, slot_of, out_point_voxel, out_voxel_counts, st) == hipSuccess &&
               hipMemcpyAsync(&h, meta, sizeof(Meta), hipMemcpyDeviceToHost, st) == hipSuccess &&
@@ -740,8 +770,217 @@ ash_status_t ash_voxelize(const float* points, int64_t n, float voxel, int32_t* 
   mem.put(table, st);
   mem.put(slot_of, st);
   mem.put(partial, st);
+  mem.put(lost, st);
   mem.put(status, st);
   return rc;
+}
+
+ash_status_t ash_batched(const ash_batch_op_t* ops, int32_t n_ops, int32_t fused, void* stream) {
+  if (n_ops < 0 || (n_ops > 0 && !ops)) return ASH_E_INVALID;
+  if (n_ops == 0) return ASH_OK;
+  hipStream_t st = (hipStream_t)stream;
+  const int kd = ops[0].map ? ops[0].map->key_dim : 0;
+  std::vector<ash_map*> seen;
+  for (int32_t i = 0; i < n_ops; ++i) {
+    const ash_batch_op_t& op = ops[i];
+    ash_map* m = op.map;
+    if (!m || m->key_dim != kd) return ASH_E_INVALID;
+    if (m->flags & ASH_F_AUTOGROW) return ASH_E_UNSUPPORTED;
+    if (std::find(seen.begin(), seen.end(), m) != seen.end()) return ASH_E_INVALID;
+    seen.push_back(m);
+    ASH_TRY(check_keys(m, op.insert_keys, op.n_insert));
+    ASH_TRY(check_keys(m, op.find_keys, op.n_find));
+    if (m->n_values > 0 && op.n_insert > 0) {
+      if (!op.insert_values) return ASH_E_INVALID;
+      for (int j = 0; j < m->n_values; ++j)
+        if (!op.insert_values[j]) return ASH_E_INVALID;
+    }
+    if (op.find_values)
+      for (int j = 0; j < m->n_values; ++j)
+        if (!op.find_values[j]) return ASH_E_INVALID;
+  }
+  if (!fused) {  // the plain single-map path, op by op
+    for (int32_t i = 0; i < n_ops; ++i) {
+      const ash_batch_op_t& op = ops[i];
+      ASH_TRY(insert_impl(op.map, op.insert_keys, op.n_insert, op.map->n_values > 0 ? op.insert_values : nullptr,
+                          op.insert_idx, op.insert_mask, st));
+      ASH_TRY(ash_find(op.map, op.find_keys, op.n_find, op.find_idx, op.find_mask, op.find_values, stream));
+    }
+    return ASH_OK;
+  }
+  std::vector<ash::BatchItem> items(n_ops);
+  uint32_t claim_tiles = 0, commit_tiles = 0, find_tiles = 0;
+  int32_t any_check = 0;
+  for (int32_t i = 0; i < n_ops; ++i) {
+    const ash_batch_op_t& op = ops[i];
+    ash_map* m = op.map;
+    ASH_TRY(ensure_scratch(m, std::max<int64_t>(op.n_insert, 1), st));
+    ASH_TRY(maybe_clean(m, op.n_insert, st));
+    ash::BatchItem& it = items[i];
+    std::memset(&it, 0, sizeof(it));
+    it.tb = m->ref();
+    it.g = m->G;
+    it.w = m->W;
+    it.cap = (uint32_t)m->c;
+    it.check = m->live_ub + op.n_insert > m->c ? 1 : 0;
+    any_check |= it.check;
+    it.meta = m->meta;
+    it.status = m->scan_status;
+    it.ikeys = op.insert_keys;
+    it.n_insert = (uint32_t)op.n_insert;
+    it.claim0 = claim_tiles;
+    it.commit0 = commit_tiles;
+    it.find0 = find_tiles;
+    claim_tiles += (uint32_t)((op.n_insert + 255) / 256);
+    commit_tiles += (uint32_t)((op.n_insert + ash::kScanTile - 1) / ash::kScanTile);
+    find_tiles += (uint32_t)((op.n_find + 255) / 256);
+    it.slot_of = m->slot_of;
+    it.lost = m->lost;
+    it.partial = m->partial;
+    it.kB = m->kB;
+    it.heap = m->heap;
+    it.iidx = op.insert_idx;
+    it.imask = op.insert_mask;
+    it.fkeys = op.find_keys;
+    it.n_find = (uint32_t)op.n_find;
+    it.fidx = op.find_idx;
+    it.fmask = op.find_mask;
+    if (m->n_values > 0 && op.n_insert > 0) it.vin = make_values(m, op.insert_values, nullptr, true);
+    if (m->n_values > 0 && op.find_values) it.vout = make_values(m, nullptr, op.find_values, false);
+  }
+  ash_map* m0 = ops[0].map;
+  const size_t bytes = sizeof(ash::BatchItem) * (size_t)n_ops;
+  ash::BatchItem* dev = (ash::BatchItem*)m0->mem.get(bytes, st);
+  if (!dev) return ASH_E_NOMEM;
+  ash_status_t rc = ASH_OK;
+  if (hipMemcpyAsync(dev, items.data(), bytes, hipMemcpyHostToDevice, st) != hipSuccess ||
+      timed(m0, "batched", st, [&] {
+        return ash::launch_batched(kd, dev, n_ops, claim_tiles, commit_tiles, find_tiles, any_check, st);
+      }) != hipSuccess)
+    rc = ASH_E_DEVICE;
+  m0->mem.put(dev, st);
+  if (rc != ASH_OK) return rc;
+  for (int32_t i = 0; i < n_ops; ++i) {
+    ash_map* m = ops[i].map;
+    m->live_ub = std::min(m->c, m->live_ub + ops[i].n_insert);
+    m->used_ub += std::min(ops[i].n_insert, m->c);
+  }
+  return ASH_OK;
+}
+
+namespace {
+
+typedef std::tuple<int, int64_t, int, int, int> TuneKey;
+std::mutex g_tune_mu;
+std::map<TuneKey, std::pair<ash_tuning_t, double>> g_tune_cache;
+
+int log2_floor(int64_t x) {
+  int l = 0;
+  while (x > 1) {
+    x >>= 1;
+    ++l;
+  }
+  return l;
+}
+
+// Cube side whose n uniform draws give about `ratio * n` distinct keys:
+// L^d (1 - exp(-n / L^d)) = ratio * n, solved for x = n / L^d by bisection.
+uint32_t cube_side(int64_t n, int kd, double ratio) {
+  ratio = std::min(std::max(ratio, 1e-3), 0.999);
+  double lo = 1e-6, hi = 1e3;
+  for (int it = 0; it < 200; ++it) {
+    const double x = 0.5 * (lo + hi);
+    if ((1.0 - std::exp(-x)) / x > ratio) lo = x;
+    else hi = x;
+  }
+  const double cells = (double)n / (0.5 * (lo + hi));
+  return (uint32_t)std::max(2.0, std::ceil(std::pow(cells, 1.0 / kd)));
+}
+
+}  // namespace
+
+ash_status_t ash_autotune(int64_t capacity, int32_t key_dim, int32_t n_values, const ash_dtype_t* value_dtypes,
+                          const int64_t* value_elems, int64_t n_insert, double distinct_ratio,
+                          const ash_allocator_t* allocator, void* stream, ash_tuning_t* out, double* out_ms) {
+  if (!out || capacity <= 0 || capacity > kMaxCount || key_dim < 1 || key_dim > 4) return ASH_E_INVALID;
+  if (n_insert <= 0 || n_insert > kMaxCount || !(distinct_ratio > 0.0) || distinct_ratio > 1.0) return ASH_E_INVALID;
+  if (n_values < 0 || n_values > ash::kMaxValues || (n_values > 0 && (!value_dtypes || !value_elems)))
+    return ASH_E_INVALID;
+  int64_t row = 0;
+  for (int j = 0; j < n_values; ++j) row += (int64_t)dtype_size(value_dtypes[j]) * value_elems[j];
+  const TuneKey key(key_dim, row, log2_floor(capacity), log2_floor(n_insert), (int)std::lround(distinct_ratio * 10));
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      *out = it->second.first;
+      if (out_ms) *out_ms = it->second.second;
+      return ASH_OK;
+    }
+  }
+  hipStream_t st = (hipStream_t)stream;
+  DevMem mem;
+  mem.custom = allocator != nullptr;
+  if (allocator) mem.a = *allocator;
+  const uint32_t n = (uint32_t)n_insert;
+  int32_t* keys = (int32_t*)mem.get((size_t)n * key_dim * 4, st);
+  int32_t* fkeys = (int32_t*)mem.get((size_t)n * key_dim * 4, st);
+  std::vector<void*> vals(n_values, nullptr);
+  bool ok = keys && fkeys;
+  for (int j = 0; j < n_values && ok; ++j) {
+    vals[j] = mem.get((size_t)n * dtype_size(value_dtypes[j]) * value_elems[j], st);
+    ok = vals[j] != nullptr;
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ok = ok && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+  ok = ok && ash::launch_synth_keys(keys, n, key_dim, cube_side(n_insert, key_dim, distinct_ratio), 0x5eedull, fkeys,
+                                   n, st) == hipSuccess;
+  ash_tuning_t best;
+  std::memset(&best, 0, sizeof(best));
+  double best_ms = 1e30;
+  const int widths[] = {4, 8, 16, 32};
+  const int groups[] = {1, 4, 8, 16, 64};
+  const float loads[] = {0.5f, 0.7f, 0.85f};
+  for (int g : groups) {
+    for (int w : widths) {
+      if (g == 1 && w > 8) continue;
+      for (float lf : loads) {
+        if (!ok) break;
+        ash_tuning_t t = {w, g, lf, 0u};
+        ash_map* m = nullptr;
+        if (ash_create(capacity, key_dim, n_values, value_dtypes, value_elems, allocator, &t, stream, &m) != ASH_OK)
+          continue;  // e.g. not enough memory for this load factor
+        double ms = 1e30;
+        for (int rep = 0; rep < 4 && ok; ++rep) {
+          ok = ash_clear(m, stream) == ASH_OK && hipEventRecord(e0, st) == hipSuccess &&
+               insert_impl(m, keys, n_insert, n_values ? vals.data() : nullptr, nullptr, nullptr, st) == ASH_OK &&
+               ash_find(m, fkeys, n_insert, nullptr, nullptr, nullptr, stream) == ASH_OK &&
+               hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+          float f = 0.0f;
+          if (ok && rep > 0 && hipEventElapsedTime(&f, e0, e1) == hipSuccess) ms = std::min(ms, (double)f);
+        }
+        ash_destroy(m);
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = t;
+        }
+      }
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  mem.put(keys, st);
+  mem.put(fkeys, st);
+  for (void* v : vals) mem.put(v, st);
+  if (!ok) return ASH_E_DEVICE;
+  if (best_ms >= 1e30) return ASH_E_NOMEM;
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune_cache[key] = {best, best_ms};
+  }
+  *out = best;
+  if (out_ms) *out_ms = best_ms;
+  return ASH_OK;
 }
 
 const char* ash_status_string(ash_status_t s) {

@@ -357,4 +357,33 @@ __device__ inline void copy_rows(const ValueSet& vs, int j, const uint2* pairs, 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Batched maps: one descriptor per (map, insert batch, find batch).  The
+// persistent kernel walks flat tile lists; claim0 / commit0 / find0 are the
+// first flat tile of this item in each phase.
+struct BatchItem {
+  TableRef tb;
+  int32_t g, w;         // probe shape of the map
+  uint32_t cap;
+  int32_t check;        // new keys must be summed for the capacity check
+  Meta* meta;
+  uint64_t* status;     // scan status words of the map
+  const int32_t* ikeys;
+  uint32_t n_insert;
+  uint32_t claim0, commit0, find0;
+  uint32_t* slot_of;
+  uint8_t* lost;
+  uint32_t* partial;
+  int32_t* kB;
+  const int32_t* heap;
+  int32_t* iidx;
+  uint8_t* imask;
+  const int32_t* fkeys;
+  uint32_t n_find;
+  int32_t* fidx;
+  uint8_t* fmask;
+  ValueSet vin;         // insert values -> v^B
+  ValueSet vout;        // v^B -> find outputs
+};
+
 }  // namespace ash

@@ -15,7 +15,19 @@
 //   commit -- the position owning its PENDING slot is the winner; winners are
 //             ranked in batch order (block scan + decoupled look-back) and take
 //             i = h[t + rank]; the key, values and COMMITTED(i) are written.
-// A finalize kernel then moves t.  Erase mirrors this with an owner array.
+// A finalize kernel then moves t.  Erase elects the lowest position per
+// buffer index with an epoch-tagged atomicMax on owner[i] and pushes winners'
+// indices back in batch order.
+//
+// Traffic model behind the layout (measured on MI355X with rocprofv3): a
+// random read fills a 128-byte L2 line, a device-scope atomic is performed at
+// the memory side (64 bytes for a 64-bit CAS, 32 for a 32-bit op) and a small
+// random store costs a 32-byte write.  So the second pass never re-reads the
+// table: positions displaced during the claim are marked in a per-position
+// `lost` byte array by whoever displaced them, using the value returned by
+// the atomic.
+#include <hip/hip_cooperative_groups.h>
+
 #include "ash_device.hpp"
 #include "ash_launch.hpp"
 
@@ -71,6 +83,17 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
   return v;
 }
 
+// Block-shared scratch of the tile functions.  Every kernel declares one and
+// passes it down, so a persistent kernel that dispatches several probe shapes
+// holds a single copy.
+struct TileLds {
+  uint2 pairs[kScanTile];          // (source row, destination row) of value copies
+  uint64_t scan[kBlock / 64 + 1];  // block_rank_rows
+  uint32_t count[16];              // per-wavefront partial sums (up to 1024 threads)
+  uint32_t prefix;                 // look-back result
+  uint32_t hits;                   // gathered rows of a find tile
+};
+
 // ---------------------------------------------------------------------------
 // Fill / init kernels.
 __global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, size_t n) {
@@ -90,6 +113,11 @@ __global__ void k_reset_meta(Meta* m) {
   m->t = 0; m->claims = 0; m->used = 0; m->tombs = 0; m->status = 0; m->result = 0; m->fail = 0;
   m->epoch = m->epoch + 1u == 0u ? 1u : m->epoch + 1u;
 }
+
+// Positions per block of the probing kernels: 256 (G lanes per position, so a
+// group takes G positions in turn).
+template <int G>
+__host__ __device__ constexpr uint32_t rounds_for_dev() { return 256u / (kBlock / G); }
 
 // ---------------------------------------------------------------------------
 // Probe windows.  One probe step examines `kSize` consecutive slots starting
@@ -183,23 +211,29 @@ __device__ __forceinline__ uint64_t leader_bcast64(uint64_t x) {
 
 // ---------------------------------------------------------------------------
 // Claim (insert / activate / voxelize pass 1).  A group of G lanes (or one
-// lane when G == 1) owns one position at a time.  slot_of[p] receives the
-// claimed or matched slot of every position that may still win -- the
-// claimer and every position that lowered PENDING to itself -- and kNoSlot
-// for positions that already lost (key committed before, or a lower position
-// already pending).  kAllSlots keeps the matched slot for every accepted
-// position (voxelization needs it to resolve per-point ids).
-template <int KD, int G, int WL, typename Src, bool kAllSlots>
-__global__ __launch_bounds__(kBlock) void k_claim(TableRef tb, Src src, uint32_t n, uint32_t rounds,
-                                                  uint32_t* __restrict__ slot_of, uint32_t* __restrict__ partial,
-                                                  Meta* meta) {
-  __shared__ uint32_t s_count[kBlock / 64];
+// lane when G == 1) owns one position at a time.  Every position ends as
+//   - a loser: the key was committed by an earlier call, or a lower position
+//     of the same key already holds the pending slot;
+//   - a candidate: it CASed the slot, or lowered PENDING(q) to PENDING(p) with
+//     an atomicMin that returned q > p -- in which case it sets lost[q], since
+//     q can no longer win.
+// After the kernel, the winner of each claimed slot is its unique candidate
+// with lost == 0.  Map claims write slot_of[p] = slot for candidates and
+// kNoSlot for losers; voxel claims (kVoxel) keep the slot for every accepted
+// point and mark candidates with kCandidate (the table has < 2^31 slots).
+constexpr uint32_t kCandidate = 0x80000000u;
+
+template <int KD, int G, int WL, typename Src, bool kVoxel>
+__device__ __forceinline__ void claim_tile(const TableRef& tb, const Src& src, uint32_t n, uint32_t tile,
+                                           uint32_t rounds, uint32_t* __restrict__ slot_of,
+                                           uint8_t* __restrict__ lost, uint32_t* __restrict__ partial, Meta* meta,
+                                           TileLds& lds) {
   using Win = Window<KD, G, WL>;
   constexpr int S = Win::S;
   constexpr uint32_t kGroups = kBlock / G;
   const uint32_t sub = G == 1 ? 0u : (threadIdx.x & (G - 1));
   const uint32_t grp = threadIdx.x / G;
-  const uint32_t tile_base = blockIdx.x * kGroups * rounds;
+  const uint32_t tile_base = tile * kGroups * rounds;
   uint32_t claimed = 0;
   uint32_t unresolved = 0;
   for (uint32_t r = 0; r < rounds; ++r) {
@@ -223,7 +257,7 @@ __global__ __launch_bounds__(kBlock) void k_claim(TableRef tb, Src src, uint32_t
             return sl.w[S - 1] < kPending && slot_holds<KD, S>(sl, k);
           });
           if (mc) {
-            if (kAllSlots) out = win.slot(first_lane(mc));
+            if (kVoxel) out = win.slot(first_lane(mc));
             resolved = true;
             break;
           }
@@ -243,8 +277,19 @@ __global__ __launch_bounds__(kBlock) void k_claim(TableRef tb, Src src, uint32_t
             const uint32_t L = first_lane(mp);
             const uint32_t q = win.word(L, S - 1) - kPending;
             const uint32_t s = win.slot(L);
-            if (p < q && sub == 0) atomic_min_u32(tb.words + (size_t)s * S + S - 1, kPending + p);
-            out = (p < q || kAllSlots) ? s : kNoSlot;
+            uint32_t cand = 0;
+            if (p < q && sub == 0) {
+              const uint32_t old = __hip_atomic_fetch_min(tb.words + (size_t)s * S + S - 1, kPending + p,
+                                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              if (old > kPending + p) {  // p now holds the slot; the previous holder lost
+                const uint32_t prev = old - kPending;
+                if (prev < n) lost[prev] = 1;
+                cand = 1;
+              }
+            }
+            cand = G == 1 ? cand : group_bcast<G>(cand, 0u);
+            if (kVoxel) out = s | (cand ? kCandidate : 0u);
+            else out = cand ? s : kNoSlot;
             resolved = true;
             break;
           }
@@ -256,7 +301,7 @@ __global__ __launch_bounds__(kBlock) void k_claim(TableRef tb, Src src, uint32_t
           if (sub == 0) found = cas_pair(tb.words + (size_t)s * S + S - 2, kEmptyPair, desired);
           found = leader_bcast64<G>(found);
           if (found == kEmptyPair) {
-            out = s;
+            out = kVoxel ? (s | kCandidate) : s;
             claimed += sub == 0 ? 1u : 0u;
             resolved = true;
             break;
@@ -276,48 +321,64 @@ __global__ __launch_bounds__(kBlock) void k_claim(TableRef tb, Src src, uint32_t
   const uint32_t wc = wave_sum(claimed);
   const uint32_t wu = wave_sum(unresolved);
   if (lane_id() == 0) {
-    s_count[threadIdx.x >> 6] = wc;
+    lds.count[threadIdx.x >> 6] = wc;
     if (wu) atomic_add_u32(&meta->fail, 1u);  // only when the table is full
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t c = 0;
 #pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) c += s_count[w];
-    partial[blockIdx.x] = c;
+    for (int w = 0; w < kBlock / 64; ++w) c += lds.count[w];
+    partial[tile] = c;
   }
+  __syncthreads();  // the scratch is reused by the next tile of a persistent block
+}
+
+template <int KD, int G, int WL, typename Src, bool kVoxel>
+__global__ __launch_bounds__(kBlock) void k_claim(TableRef tb, Src src, uint32_t n, uint32_t rounds,
+                                                  uint32_t* __restrict__ slot_of, uint8_t* __restrict__ lost,
+                                                  uint32_t* __restrict__ partial, Meta* meta) {
+  __shared__ TileLds lds;
+  claim_tile<KD, G, WL, Src, kVoxel>(tb, src, n, blockIdx.x, rounds, slot_of, lost, partial, meta, lds);
 }
 
 // meta->claims = sum of the claim kernel's per-block counts (one block).
-__global__ __launch_bounds__(1024) void k_sum_partials(const uint32_t* __restrict__ partial, uint32_t count,
-                                                        Meta* meta) {
-  __shared__ uint32_t s_sum[1024 / 64];
+template <int kThreads>
+__device__ __forceinline__ void sum_partials_block(const uint32_t* __restrict__ partial, uint32_t count, Meta* meta,
+                                                   TileLds& lds) {
+  uint32_t* s_sum = lds.count;
   uint32_t v = 0;
-  for (uint32_t i = threadIdx.x; i < count; i += blockDim.x) v += partial[i];
+  for (uint32_t i = threadIdx.x; i < count; i += kThreads) v += partial[i];
   v = wave_sum(v);
   if (lane_id() == 0) s_sum[threadIdx.x >> 6] = v;
   __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t t = 0;
-    for (int w = 0; w < 1024 / 64; ++w) t += s_sum[w];
+    for (int w = 0; w < kThreads / 64; ++w) t += s_sum[w];
     meta->claims = t;
   }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(1024) void k_sum_partials(const uint32_t* __restrict__ partial, uint32_t count,
+                                                        Meta* meta) {
+  __shared__ TileLds lds;
+  sum_partials_block<1024>(partial, count, meta, lds);
 }
 
 // ---------------------------------------------------------------------------
-// Commit (insert / activate pass 2).
+// Commit (insert / activate pass 2).  Winners are the candidates not marked
+// lost; they are ranked in batch order and take i = h[t + rank].  The lost
+// bytes read here are cleared again, so the array is all zero between calls.
 template <int KD>
-__global__ __launch_bounds__(kBlock) void k_commit(TableRef tb, const int32_t* __restrict__ keys, uint32_t n,
-                                                   const uint32_t* __restrict__ slot_of, int32_t* __restrict__ kB,
-                                                   const int32_t* __restrict__ heap, uint8_t* __restrict__ active,
-                                                   uint32_t cap, ValueSet vs, int32_t* __restrict__ out_idx,
-                                                   uint8_t* __restrict__ out_mask, Meta* meta,
-                                                   uint64_t* __restrict__ status, int check) {
+__device__ __forceinline__ void commit_tile(const TableRef& tb, const int32_t* __restrict__ keys, uint32_t n,
+                                            uint32_t tile, const uint32_t* __restrict__ slot_of,
+                                            uint8_t* __restrict__ lost, int32_t* __restrict__ kB,
+                                            const int32_t* __restrict__ heap, uint32_t cap, const ValueSet& vs,
+                                            int32_t* __restrict__ out_idx, uint8_t* __restrict__ out_mask,
+                                            Meta* meta, uint64_t* __restrict__ status, int check, TileLds& lds) {
   constexpr int S = SlotWords<KD>::value;
-  __shared__ uint32_t s_prefix;
-  __shared__ uint64_t s_scan[kBlock / 64 + 1];
-  __shared__ uint2 s_pairs[kScanTile];
-  const uint32_t tile = blockIdx.x;
+  uint2* s_pairs = lds.pairs;
   const uint32_t t0 = meta->t;
   // With check == 0 the host has proved t + new keys <= c (its bound on t
   // plus n); otherwise meta->claims holds the summed count of new keys.
@@ -328,8 +389,14 @@ __global__ __launch_bounds__(kBlock) void k_commit(TableRef tb, const int32_t* _
 #pragma unroll
   for (int r = 0; r < kScanItems; ++r) {
     const uint32_t p = base + r * kBlock + threadIdx.x;
-    slot[r] = p < n ? slot_of[p] : kNoSlot;
-    win[r] = slot[r] != kNoSlot && tb.words[(size_t)slot[r] * S + S - 1] == kPending + p;
+    slot[r] = kNoSlot;
+    win[r] = false;
+    if (p < n) {
+      slot[r] = slot_of[p];
+      const uint8_t l = lost[p];
+      if (l) lost[p] = 0;
+      win[r] = slot[r] != kNoSlot && l == 0;
+    }
   }
   if (overflow) {  // roll the claims back: the table is as before the call
 #pragma unroll
@@ -340,9 +407,8 @@ __global__ __launch_bounds__(kBlock) void k_commit(TableRef tb, const int32_t* _
   }
   uint32_t rank[kScanItems];
   uint32_t total;
-  block_rank_rows(win, rank, total, s_scan);
-  block_lookback(status, tile, meta->epoch, total, &meta->status, &s_prefix);
-  const uint32_t prefix = s_prefix;
+  block_rank_rows(win, rank, total, lds.scan);
+  const uint32_t prefix = block_lookback(status, tile, meta->epoch, total, &meta->status, &lds.prefix);
   bool bad = false;
 #pragma unroll
   for (int r = 0; r < kScanItems; ++r) {
@@ -358,7 +424,6 @@ __global__ __launch_bounds__(kBlock) void k_commit(TableRef tb, const int32_t* _
         kB[(size_t)i * KD + d] = k[d];
       }
       store_slot<S>(tb.words + (size_t)slot[r] * S, committed_slot<KD, S>(k, i));
-      active[i] = 1;
       s_pairs[rank[r]] = make_uint2(p, i);
       if (out_idx) out_idx[p] = (int32_t)i;
       if (out_mask) out_mask[p] = 1;
@@ -370,14 +435,27 @@ __global__ __launch_bounds__(kBlock) void k_commit(TableRef tb, const int32_t* _
   if (vs.n > 0 && !__syncthreads_or(bad)) {
     for (int j = 0; j < vs.n; ++j) copy_rows(vs, j, s_pairs, total);
   }
+  __syncthreads();  // LDS is reused by the next tile of a persistent block
+}
+
+template <int KD>
+__global__ __launch_bounds__(kBlock) void k_commit(TableRef tb, const int32_t* __restrict__ keys, uint32_t n,
+                                                   const uint32_t* __restrict__ slot_of, uint8_t* __restrict__ lost,
+                                                   int32_t* __restrict__ kB, const int32_t* __restrict__ heap,
+                                                   uint32_t cap, ValueSet vs, int32_t* __restrict__ out_idx,
+                                                   uint8_t* __restrict__ out_mask, Meta* meta,
+                                                   uint64_t* __restrict__ status, int check) {
+  __shared__ TileLds lds;
+  commit_tile<KD>(tb, keys, n, blockIdx.x, slot_of, lost, kB, heap, cap, vs, out_idx, out_mask, meta, status, check,
+                  lds);
 }
 
 // Moves the heap top and resets per-launch counters.  Runs after the
 // scanning kernel, so every block of that kernel has read t / epoch.  The
 // number of keys an insert added is the scan total of its commit (0 when the
 // batch was rolled back).
-__global__ void k_finalize(Meta* m, uint32_t cap, int mode, int silent, int check, const uint64_t* status,
-                           uint32_t last_tile) {
+__device__ __forceinline__ void finalize_map(Meta* m, uint32_t cap, int mode, int silent, int check,
+                                             const uint64_t* status, uint32_t last_tile) {
   if (mode == kFinalizeInsert) {
     const bool overflow = m->fail != 0 || (check && m->claims > cap - m->t);
     if (!overflow) {
@@ -403,23 +481,28 @@ __global__ void k_finalize(Meta* m, uint32_t cap, int mode, int silent, int chec
   m->epoch = m->epoch + 1u == 0u ? 1u : m->epoch + 1u;
 }
 
+__global__ void k_finalize(Meta* m, uint32_t cap, int mode, int silent, int check, const uint64_t* status,
+                           uint32_t last_tile) {
+  finalize_map(m, cap, mode, silent, check, status, last_tile);
+}
+
 // ---------------------------------------------------------------------------
 // Find (masked query, Sec. 4.2) with optional value gather.  Probing stops at
 // the first window that holds an EMPTY slot: a key is always claimed at the
 // first EMPTY slot of its sequence and slots never return to EMPTY outside a
 // rebuild.
 template <int KD, int G, int WL>
-__global__ __launch_bounds__(kBlock) void k_find(TableRef tb, const int32_t* __restrict__ keys, uint32_t n,
-                                                 uint32_t rounds, int32_t* __restrict__ out_idx,
-                                                 uint8_t* __restrict__ out_mask, ValueSet vs) {
+__device__ __forceinline__ void find_tile(const TableRef& tb, const int32_t* __restrict__ keys, uint32_t n,
+                                          uint32_t tile, uint32_t rounds, int32_t* __restrict__ out_idx,
+                                          uint8_t* __restrict__ out_mask, const ValueSet& vs, TileLds& lds) {
   using Win = Window<KD, G, WL>;
   constexpr int S = Win::S;
   constexpr uint32_t kGroups = kBlock / G;
-  __shared__ uint2 s_pairs[kScanTile];
-  __shared__ uint32_t s_hits;
+  uint2* s_pairs = lds.pairs;
+  uint32_t& s_hits = lds.hits;
   const uint32_t sub = G == 1 ? 0u : (threadIdx.x & (G - 1));
   const uint32_t grp = threadIdx.x / G;
-  const uint32_t tile_base = blockIdx.x * kGroups * rounds;
+  const uint32_t tile_base = tile * kGroups * rounds;
   if (vs.n > 0) {
     if (threadIdx.x == 0) s_hits = 0;
     __syncthreads();
@@ -458,17 +541,32 @@ __global__ __launch_bounds__(kBlock) void k_find(TableRef tb, const int32_t* __r
     __syncthreads();
     const uint32_t hits = s_hits;
     for (int j = 0; j < vs.n; ++j) copy_rows(vs, j, s_pairs, hits);
+    __syncthreads();  // LDS is reused by the next tile of a persistent block
   }
 }
 
+template <int KD, int G, int WL>
+__global__ __launch_bounds__(kBlock) void k_find(TableRef tb, const int32_t* __restrict__ keys, uint32_t n,
+                                                 uint32_t rounds, int32_t* __restrict__ out_idx,
+                                                 uint8_t* __restrict__ out_mask, ValueSet vs) {
+  __shared__ TileLds lds;
+  find_tile<KD, G, WL>(tb, keys, n, blockIdx.x, rounds, out_idx, out_mask, vs, lds);
+}
+
 // ---------------------------------------------------------------------------
-// Erase pass 1: locate each key; the lowest position per buffer index wins
-// through atomicMin on owner[i] (owner starts at INT32_MAX).
+// Erase pass 1: locate each key and elect the lowest position per buffer
+// index.  owner[i] holds (epoch << 32) | ~p of the call that wrote it, and
+// positions race with a 64-bit atomicMax: entries of earlier calls (smaller
+// epoch) lose to any position of this call, and within the call the largest
+// ~p is the lowest p -- so owner never needs clearing.  The returned value
+// tells each position whether it displaced an earlier holder (lost[holder]
+// = 1) or lost itself.
 template <int KD, int G, int WL>
 __global__ __launch_bounds__(kBlock) void k_erase_mark(TableRef tb, const int32_t* __restrict__ keys, uint32_t n,
-                                                       uint32_t rounds, uint32_t* __restrict__ slot_of,
-                                                       int32_t* __restrict__ found_idx,
-                                                       int32_t* __restrict__ owner) {
+                                                       uint32_t rounds, uint32_t epoch,
+                                                       uint32_t* __restrict__ slot_of,
+                                                       int32_t* __restrict__ found_idx, uint64_t* __restrict__ owner,
+                                                       uint8_t* __restrict__ lost) {
   using Win = Window<KD, G, WL>;
   constexpr int S = Win::S;
   constexpr uint32_t kGroups = kBlock / G;
@@ -494,7 +592,6 @@ __global__ __launch_bounds__(kBlock) void k_erase_mark(TableRef tb, const int32_
         const uint32_t L = first_lane(mh);
         idx = win.word(L, S - 1);
         where = win.slot(L);
-        if (sub == 0) atomic_min_u32(reinterpret_cast<uint32_t*>(owner) + idx, p);
         break;
       }
       if (win.mask([&](const Slot<S> sl) { return sl.w[S - 1] == kEmpty; })) break;
@@ -502,20 +599,33 @@ __global__ __launch_bounds__(kBlock) void k_erase_mark(TableRef tb, const int32_
       if (base >= tb.nslots) base -= tb.nslots;
     }
     if (sub == 0) {
-      slot_of[p] = where;
-      found_idx[p] = idx == kNoSlot ? -1 : (int32_t)idx;
+      bool cand = false;
+      if (idx != kNoSlot) {
+        const uint64_t mine = ((uint64_t)epoch << 32) | (uint64_t)(~p);
+        const uint64_t old = __hip_atomic_fetch_max(owner + idx, mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((uint32_t)(old >> 32) != epoch) {
+          cand = true;  // first position of this call for the index
+        } else {
+          const uint32_t prev = ~(uint32_t)old;
+          cand = prev > p;
+          if (cand && prev < n) lost[prev] = 1;
+        }
+      }
+      slot_of[p] = cand ? where : kNoSlot;
+      found_idx[p] = cand ? (int32_t)idx : -1;
     }
   }
 }
 
-// Erase pass 2: winners tombstone their slot and push their index back on the
-// heap in batch order: the r-th winner writes h[t - 1 - r].
+// Erase pass 2: winners (candidates not marked lost) tombstone their slot and
+// push their index back on the heap in batch order: the r-th winner writes
+// h[t - 1 - r].
 template <int KD>
 __global__ __launch_bounds__(kBlock) void k_erase_commit(TableRef tb, uint32_t n, const uint32_t* __restrict__ slot_of,
                                                          const int32_t* __restrict__ found_idx,
-                                                         int32_t* __restrict__ owner, int32_t* __restrict__ heap,
-                                                         uint8_t* __restrict__ active, uint8_t* __restrict__ out_mask,
-                                                         Meta* meta, uint64_t* __restrict__ status) {
+                                                         uint8_t* __restrict__ lost, int32_t* __restrict__ heap,
+                                                         uint8_t* __restrict__ out_mask, Meta* meta,
+                                                         uint64_t* __restrict__ status) {
   constexpr int S = SlotWords<KD>::value;
   __shared__ uint32_t s_prefix;
   __shared__ uint64_t s_scan[kBlock / 64 + 1];
@@ -527,8 +637,14 @@ __global__ __launch_bounds__(kBlock) void k_erase_commit(TableRef tb, uint32_t n
 #pragma unroll
   for (int r = 0; r < kScanItems; ++r) {
     const uint32_t p = base + r * kBlock + threadIdx.x;
-    idx[r] = p < n ? found_idx[p] : -1;
-    win[r] = idx[r] >= 0 && (uint32_t)owner[idx[r]] == p;
+    idx[r] = -1;
+    win[r] = false;
+    if (p < n) {
+      idx[r] = found_idx[p];
+      const uint8_t l = lost[p];
+      if (l) lost[p] = 0;
+      win[r] = idx[r] >= 0 && l == 0;
+    }
   }
   uint32_t rank[kScanItems];
   uint32_t total;
@@ -540,21 +656,28 @@ __global__ __launch_bounds__(kBlock) void k_erase_commit(TableRef tb, uint32_t n
     const uint32_t p = base + r * kBlock + threadIdx.x;
     if (p >= n) continue;
     if (win[r] && prefix + rank[r] < t0) {  // winners are distinct live indices: always true
-      const uint32_t i = (uint32_t)idx[r];
-      heap[t0 - 1u - (prefix + rank[r])] = (int32_t)i;
+      heap[t0 - 1u - (prefix + rank[r])] = idx[r];
       tb.words[(size_t)slot_of[p] * S + S - 1] = kTomb;
-      active[i] = 0;
-      owner[i] = 0x7FFFFFFF;
     }
     if (out_mask) out_mask[p] = win[r] ? 1 : 0;
   }
 }
 
 // ---------------------------------------------------------------------------
-// Active indices (ascending) by compaction of the per-index flags.
-__global__ __launch_bounds__(kBlock) void k_compact_active(const uint8_t* __restrict__ active, uint32_t c,
-                                                           int32_t* __restrict__ out, Meta* meta,
-                                                           uint64_t* __restrict__ status) {
+// Active indices (ascending): flags[i] = 1 for every committed slot, then a
+// compaction of the flags.
+template <int S>
+__global__ __launch_bounds__(kBlock) void k_mark_live(TableRef tb, uint8_t* __restrict__ flags, uint32_t c) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < tb.nslots; s += stride) {
+    const uint32_t st = tb.words[(size_t)s * S + S - 1];
+    if (st < kPending && st < c) flags[st] = 1;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_compact_flags(const uint8_t* __restrict__ flags, uint32_t c,
+                                                          int32_t* __restrict__ out, Meta* meta,
+                                                          uint64_t* __restrict__ status) {
   __shared__ uint32_t s_prefix;
   __shared__ uint64_t s_scan[kBlock / 64 + 1];
   const uint32_t tile = blockIdx.x;
@@ -563,7 +686,7 @@ __global__ __launch_bounds__(kBlock) void k_compact_active(const uint8_t* __rest
 #pragma unroll
   for (int r = 0; r < kScanItems; ++r) {
     const uint32_t i = base + r * kBlock + threadIdx.x;
-    on[r] = i < c && active[i] != 0;
+    on[r] = i < c && flags[i] != 0;
   }
   uint32_t rank[kScanItems];
   uint32_t total;
@@ -575,14 +698,13 @@ __global__ __launch_bounds__(kBlock) void k_compact_active(const uint8_t* __rest
 }
 
 // ---------------------------------------------------------------------------
-// Rebuild a fresh table from (k^B[i], i) for every live index i (rehash,
-// Sec. 4.5).  Keys are distinct, so a position only looks for EMPTY slots;
-// the leader CASes (k_{KD-1}, COMMITTED(i)) into the first one and then
-// writes the other key words.
+// Rebuild (rehash, Sec. 4.5): every committed slot of the old table is
+// inserted into a fresh table as (key, COMMITTED(i)); tombstones are dropped.
+// Keys are distinct, so a position only looks for EMPTY slots: the leader
+// CASes (k_{KD-1}, i) into the first one and then writes the other key words.
 template <int KD, int G, int WL>
-__global__ __launch_bounds__(kBlock) void k_rebuild(TableRef tb, const int32_t* __restrict__ kB,
-                                                    const uint8_t* __restrict__ active, uint32_t c, uint32_t rounds,
-                                                    Meta* meta) {
+__global__ __launch_bounds__(kBlock) void k_rebuild(TableRef tb, const uint32_t* __restrict__ old_words,
+                                                    uint32_t old_slots, uint32_t rounds, Meta* meta) {
   using Win = Window<KD, G, WL>;
   constexpr int S = Win::S;
   constexpr uint32_t kGroups = kBlock / G;
@@ -591,12 +713,15 @@ __global__ __launch_bounds__(kBlock) void k_rebuild(TableRef tb, const int32_t* 
   const uint32_t tile_base = blockIdx.x * kGroups * rounds;
   uint32_t unresolved = 0;
   for (uint32_t r = 0; r < rounds; ++r) {
-    const uint32_t i = tile_base + r * kGroups + grp;
-    if (i >= c) break;
-    if (!active[i]) continue;
+    const uint32_t os = tile_base + r * kGroups + grp;
+    if (os >= old_slots) break;
+    const Slot<S> old = load_slot<S>(old_words + (size_t)os * S);
+    const uint32_t i = old.w[S - 1];
+    if (i >= kPending) continue;  // empty or tombstone
     int32_t k[KD];
 #pragma unroll
-    for (int d = 0; d < KD; ++d) k[d] = kB[(size_t)i * KD + d];
+    for (int d = 0; d < KD - 1; ++d) k[d] = (int32_t)old.w[d];
+    k[KD - 1] = (int32_t)old.w[S - 2];
     const uint64_t h = key_hash<KD>(k);
     const uint64_t desired = ((uint64_t)i << 32) | (uint32_t)k[KD - 1];
     uint32_t base = home_slot(tb, h);
@@ -634,10 +759,11 @@ __global__ __launch_bounds__(kBlock) void k_rebuild(TableRef tb, const int32_t* 
 }
 
 // ---------------------------------------------------------------------------
-// Voxelization pass 2: the first occurrence of each voxel gets the id
-// rank-of-first-occurrence; its slot becomes COMMITTED(id).
+// Voxelization pass 2: the first occurrence of each voxel (its winner) gets
+// the id rank-of-first-occurrence; its slot becomes COMMITTED(id).
 __global__ __launch_bounds__(kBlock) void k_voxel_commit(TableRef tb, VoxelKeys src, uint32_t n,
                                                          const uint32_t* __restrict__ slot_of,
+                                                         uint8_t* __restrict__ lost,
                                                          int32_t* __restrict__ voxel_keys,
                                                          int32_t* __restrict__ counts, Meta* meta,
                                                          uint64_t* __restrict__ status) {
@@ -651,8 +777,15 @@ __global__ __launch_bounds__(kBlock) void k_voxel_commit(TableRef tb, VoxelKeys 
 #pragma unroll
   for (int r = 0; r < kScanItems; ++r) {
     const uint32_t p = base + r * kBlock + threadIdx.x;
-    slot[r] = p < n ? slot_of[p] : kNoSlot;
-    win[r] = slot[r] != kNoSlot && tb.words[(size_t)slot[r] * S + S - 1] == kPending + p;
+    slot[r] = kNoSlot;
+    win[r] = false;
+    if (p < n) {
+      const uint32_t so = slot_of[p];
+      const uint8_t l = lost[p];
+      if (l) lost[p] = 0;
+      win[r] = so != kNoSlot && (so & kCandidate) && l == 0;
+      slot[r] = so & ~kCandidate;
+    }
   }
   uint32_t rank[kScanItems];
   uint32_t total;
@@ -680,18 +813,137 @@ __global__ __launch_bounds__(kBlock) void k_voxel_resolve(TableRef tb, uint32_t 
   constexpr int S = SlotWords<3>::value;
   const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
-  const uint32_t s = slot_of[p];
-  if (s == kNoSlot) {
+  const uint32_t so = slot_of[p];
+  if (so == kNoSlot) {
     point_voxel[p] = -1;
     return;
   }
-  const uint32_t id = tb.words[(size_t)s * S + S - 1];
+  const uint32_t id = tb.words[(size_t)(so & ~kCandidate) * S + S - 1];
   if (id >= n) {  // cannot happen once every claimed slot is committed
     point_voxel[p] = -1;
     return;
   }
   point_voxel[p] = (int32_t)id;
   atomic_add_u32(reinterpret_cast<uint32_t*>(counts) + id, 1u);
+}
+
+// ---------------------------------------------------------------------------
+// Batched maps in one persistent cooperative launch.  Phases, separated by
+// grid barriers: claims of every item -> (per-map new-key sums, only when a
+// capacity check is needed) -> commits -> per-map finalize -> finds.  Each
+// phase walks a flat list of tiles strided over the resident blocks; a block
+// takes its tiles in increasing order and all blocks are co-resident, so the
+// per-map look-back of the commit phase (which only waits on lower tiles of
+// the same map) always completes.  Each item keeps its own probe shape.
+template <uint32_t BatchItem::*kFirst>
+__device__ __forceinline__ int item_of(const BatchItem* __restrict__ items, int n_items, uint32_t t) {
+  int lo = 0, hi = n_items - 1;  // last item whose first tile <= t
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (items[mid].*kFirst <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <int KD>
+__device__ __forceinline__ void batched_claim(const BatchItem& it, uint32_t tile, TileLds& lds) {
+  const BatchKeys<KD> src{it.ikeys};
+  switch (it.g == 1 ? it.w : 100 + it.g) {
+    case 2: claim_tile<KD, 1, 2, BatchKeys<KD>, false>(it.tb, src, it.n_insert, tile, rounds_for_dev<1>(), it.slot_of, it.lost, it.partial, it.meta, lds); break;
+    case 4: claim_tile<KD, 1, 4, BatchKeys<KD>, false>(it.tb, src, it.n_insert, tile, rounds_for_dev<1>(), it.slot_of, it.lost, it.partial, it.meta, lds); break;
+    case 8: claim_tile<KD, 1, 8, BatchKeys<KD>, false>(it.tb, src, it.n_insert, tile, rounds_for_dev<1>(), it.slot_of, it.lost, it.partial, it.meta, lds); break;
+    case 104: claim_tile<KD, 4, 1, BatchKeys<KD>, false>(it.tb, src, it.n_insert, tile, rounds_for_dev<4>(), it.slot_of, it.lost, it.partial, it.meta, lds); break;
+    case 108: claim_tile<KD, 8, 1, BatchKeys<KD>, false>(it.tb, src, it.n_insert, tile, rounds_for_dev<8>(), it.slot_of, it.lost, it.partial, it.meta, lds); break;
+    case 116: claim_tile<KD, 16, 1, BatchKeys<KD>, false>(it.tb, src, it.n_insert, tile, rounds_for_dev<16>(), it.slot_of, it.lost, it.partial, it.meta, lds); break;
+    case 132: claim_tile<KD, 32, 1, BatchKeys<KD>, false>(it.tb, src, it.n_insert, tile, rounds_for_dev<32>(), it.slot_of, it.lost, it.partial, it.meta, lds); break;
+    case 164: claim_tile<KD, 64, 1, BatchKeys<KD>, false>(it.tb, src, it.n_insert, tile, rounds_for_dev<64>(), it.slot_of, it.lost, it.partial, it.meta, lds); break;
+    default: break;
+  }
+}
+
+template <int KD>
+__device__ __forceinline__ void batched_find(const BatchItem& it, uint32_t tile, TileLds& lds) {
+  switch (it.g == 1 ? it.w : 100 + it.g) {
+    case 2: find_tile<KD, 1, 2>(it.tb, it.fkeys, it.n_find, tile, rounds_for_dev<1>(), it.fidx, it.fmask, it.vout, lds); break;
+    case 4: find_tile<KD, 1, 4>(it.tb, it.fkeys, it.n_find, tile, rounds_for_dev<1>(), it.fidx, it.fmask, it.vout, lds); break;
+    case 8: find_tile<KD, 1, 8>(it.tb, it.fkeys, it.n_find, tile, rounds_for_dev<1>(), it.fidx, it.fmask, it.vout, lds); break;
+    case 104: find_tile<KD, 4, 1>(it.tb, it.fkeys, it.n_find, tile, rounds_for_dev<4>(), it.fidx, it.fmask, it.vout, lds); break;
+    case 108: find_tile<KD, 8, 1>(it.tb, it.fkeys, it.n_find, tile, rounds_for_dev<8>(), it.fidx, it.fmask, it.vout, lds); break;
+    case 116: find_tile<KD, 16, 1>(it.tb, it.fkeys, it.n_find, tile, rounds_for_dev<16>(), it.fidx, it.fmask, it.vout, lds); break;
+    case 132: find_tile<KD, 32, 1>(it.tb, it.fkeys, it.n_find, tile, rounds_for_dev<32>(), it.fidx, it.fmask, it.vout, lds); break;
+    case 164: find_tile<KD, 64, 1>(it.tb, it.fkeys, it.n_find, tile, rounds_for_dev<64>(), it.fidx, it.fmask, it.vout, lds); break;
+    default: break;
+  }
+}
+
+template <int KD>
+__global__ __launch_bounds__(kBlock) void k_batched(const BatchItem* __restrict__ items, int32_t n_items,
+                                                    uint32_t claim_tiles, uint32_t commit_tiles, uint32_t find_tiles,
+                                                    int32_t any_check) {
+  __shared__ TileLds lds;
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  for (uint32_t t = blockIdx.x; t < claim_tiles; t += gridDim.x) {
+    const BatchItem& it = items[item_of<&BatchItem::claim0>(items, n_items, t)];
+    batched_claim<KD>(it, t - it.claim0, lds);
+  }
+  grid.sync();
+  if (any_check) {
+    for (int m = blockIdx.x; m < n_items; m += gridDim.x) {
+      const BatchItem& it = items[m];
+      if (it.check && it.n_insert) sum_partials_block<kBlock>(it.partial, (it.n_insert + 255u) / 256u, it.meta, lds);
+    }
+    grid.sync();
+  }
+  for (uint32_t t = blockIdx.x; t < commit_tiles; t += gridDim.x) {
+    const BatchItem& it = items[item_of<&BatchItem::commit0>(items, n_items, t)];
+    commit_tile<KD>(it.tb, it.ikeys, it.n_insert, t - it.commit0, it.slot_of, it.lost, it.kB, it.heap, it.cap,
+                    it.vin, it.iidx, it.imask, it.meta, it.status, it.check, lds);
+  }
+  grid.sync();
+  for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < n_items; m += gridDim.x * blockDim.x) {
+    const BatchItem& it = items[m];
+    if (it.n_insert)
+      finalize_map(it.meta, it.cap, kFinalizeInsert, 0, it.check, it.status, (it.n_insert + kScanTile - 1) / kScanTile - 1);
+  }
+  grid.sync();
+  for (uint32_t t = blockIdx.x; t < find_tiles; t += gridDim.x) {
+    const BatchItem& it = items[item_of<&BatchItem::find0>(items, n_items, t)];
+    batched_find<KD>(it, t - it.find0, lds);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Synthetic workload of the autotuner: key words uniform in [0, side) from a
+// counter-based hash of (seed, word index); find keys alternate between a
+// key of the insert batch (recomputed, not read back) and a key from
+// [side, 2 side), which is never inserted.
+__device__ __forceinline__ int32_t synth_word(uint64_t seed, uint64_t i, uint32_t side) {
+  return (int32_t)(((mix64(seed ^ (i * 0x9e3779b97f4a7c15ull)) >> 32) * (uint64_t)side) >> 32);
+}
+
+__global__ __launch_bounds__(kBlock) void k_synth_keys(int32_t* __restrict__ keys, uint32_t n, int kd,
+                                                       uint32_t side, uint64_t seed, int32_t* __restrict__ fkeys,
+                                                       uint32_t nf) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride)
+    for (int d = 0; d < kd; ++d) keys[(size_t)p * kd + d] = synth_word(seed, (uint64_t)p * kd + d, side);
+  for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nf; q += stride) {
+    if (q & 1u) {
+      for (int d = 0; d < kd; ++d)
+        fkeys[(size_t)q * kd + d] = (int32_t)side + synth_word(seed + 1, (uint64_t)q * kd + d, side);
+    } else {
+      const uint32_t src = (uint32_t)(((mix64(seed + 2 + q) >> 32) * (uint64_t)n) >> 32);
+      for (int d = 0; d < kd; ++d) fkeys[(size_t)q * kd + d] = synth_word(seed, (uint64_t)src * kd + d, side);
+    }
+  }
+}
+
+hipError_t launch_synth_keys(int32_t* keys, uint32_t n, int kd, uint32_t side, uint64_t seed, int32_t* fkeys,
+                             uint32_t nf, hipStream_t st) {
+  const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>((std::max(n, nf) + kBlock - 1) / kBlock, 8192));
+  hipLaunchKernelGGL(k_synth_keys, dim3(grid), dim3(kBlock), 0, st, keys, n, kd, side, seed, fkeys, nf);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -733,13 +985,15 @@ hipError_t launch_sum_partials(const uint32_t* partial, uint32_t count, Meta* me
 template <int G>
 static inline uint32_t rounds_for() { return 256u / (kBlock / G); }
 
+uint32_t claim_blocks(int g, uint32_t n) { return cdiv(n, 256u); }
+
 template <int KD, int G, int WL>
 struct ClaimK {
-  static hipError_t run(const TableRef& tb, const int32_t* keys, uint32_t n, uint32_t* slot_of, uint32_t* partial,
-                        Meta* meta, hipStream_t st) {
+  static hipError_t run(const TableRef& tb, const int32_t* keys, uint32_t n, uint32_t* slot_of, uint8_t* lost,
+                        uint32_t* partial, Meta* meta, hipStream_t st) {
     const uint32_t rounds = rounds_for<G>();
     hipLaunchKernelGGL((k_claim<KD, G, WL, BatchKeys<KD>, false>), dim3(cdiv(n, (kBlock / G) * rounds)),
-                       dim3(kBlock), 0, st, tb, BatchKeys<KD>{keys}, n, rounds, slot_of, partial, meta);
+                       dim3(kBlock), 0, st, tb, BatchKeys<KD>{keys}, n, rounds, slot_of, lost, partial, meta);
     return hipGetLastError();
   }
 };
@@ -757,22 +1011,22 @@ struct FindK {
 
 template <int KD, int G, int WL>
 struct EraseMarkK {
-  static hipError_t run(const TableRef& tb, const int32_t* keys, uint32_t n, uint32_t* slot_of, int32_t* found,
-                        int32_t* owner, hipStream_t st) {
+  static hipError_t run(const TableRef& tb, const int32_t* keys, uint32_t n, uint32_t epoch, uint32_t* slot_of,
+                        int32_t* found, uint64_t* owner, uint8_t* lost, hipStream_t st) {
     const uint32_t rounds = rounds_for<G>();
     hipLaunchKernelGGL((k_erase_mark<KD, G, WL>), dim3(cdiv(n, (kBlock / G) * rounds)), dim3(kBlock), 0, st, tb,
-                       keys, n, rounds, slot_of, found, owner);
+                       keys, n, rounds, epoch, slot_of, found, owner, lost);
     return hipGetLastError();
   }
 };
 
 template <int KD, int G, int WL>
 struct RebuildK {
-  static hipError_t run(const TableRef& tb, const int32_t* kB, const uint8_t* active, uint32_t c, Meta* meta,
+  static hipError_t run(const TableRef& tb, const uint32_t* old_words, uint32_t old_slots, Meta* meta,
                         hipStream_t st) {
     const uint32_t rounds = rounds_for<G>();
-    hipLaunchKernelGGL((k_rebuild<KD, G, WL>), dim3(cdiv(c, (kBlock / G) * rounds)), dim3(kBlock), 0, st, tb, kB,
-                       active, c, rounds, meta);
+    hipLaunchKernelGGL((k_rebuild<KD, G, WL>), dim3(cdiv(old_slots, (kBlock / G) * rounds)), dim3(kBlock), 0, st,
+                       tb, old_words, old_slots, rounds, meta);
     return hipGetLastError();
   }
 };
@@ -780,10 +1034,10 @@ struct RebuildK {
 template <int KD, int G, int WL>
 struct VoxelClaimK {
   static hipError_t run(const TableRef& tb, const float* pts, float voxel, uint32_t n, uint32_t* slot_of,
-                        uint32_t* partial, Meta* meta, hipStream_t st) {
+                        uint8_t* lost, uint32_t* partial, Meta* meta, hipStream_t st) {
     const uint32_t rounds = rounds_for<G>();
     hipLaunchKernelGGL((k_claim<3, G, WL, VoxelKeys, true>), dim3(cdiv(n, (kBlock / G) * rounds)), dim3(kBlock), 0,
-                       st, tb, VoxelKeys{pts, voxel}, n, rounds, slot_of, partial, meta);
+                       st, tb, VoxelKeys{pts, voxel}, n, rounds, slot_of, lost, partial, meta);
     return hipGetLastError();
   }
 };
@@ -821,38 +1075,30 @@ static hipError_t with_kd_probe(int kd, int g, int w, A&&... a) {
   }
 }
 
-template <int KD>
-static hipError_t commit_k(const TableRef& tb, const int32_t* keys, uint32_t n, const uint32_t* slot_of, int32_t* kB,
-                           const int32_t* heap, uint8_t* active, uint32_t cap, const ValueSet& vs, int32_t* out_idx,
-                           uint8_t* out_mask, Meta* meta, uint64_t* status, int check, hipStream_t st) {
-  hipLaunchKernelGGL((k_commit<KD>), dim3(cdiv(n, kScanTile)), dim3(kBlock), 0, st, tb, keys, n, slot_of, kB, heap,
-                     active, cap, vs, out_idx, out_mask, meta, status, check);
-  return hipGetLastError();
-}
-
-template <int KD>
-static hipError_t erase_commit_k(const TableRef& tb, uint32_t n, const uint32_t* slot_of, const int32_t* found,
-                                 int32_t* owner, int32_t* heap, uint8_t* active, uint8_t* out_mask, Meta* meta,
-                                 uint64_t* status, hipStream_t st) {
-  hipLaunchKernelGGL((k_erase_commit<KD>), dim3(cdiv(n, kScanTile)), dim3(kBlock), 0, st, tb, n, slot_of, found,
-                     owner, heap, active, out_mask, meta, status);
-  return hipGetLastError();
-}
-
 hipError_t launch_claim(int kd, int g, int w, const TableRef& tb, const int32_t* keys, uint32_t n, uint32_t* slot_of,
-                        uint32_t* partial, Meta* meta, hipStream_t st) {
-  return with_kd_probe<ClaimK>(kd, g, w, tb, keys, n, slot_of, partial, meta, st);
+                        uint8_t* lost, uint32_t* partial, Meta* meta, hipStream_t st) {
+  return with_kd_probe<ClaimK>(kd, g, w, tb, keys, n, slot_of, lost, partial, meta, st);
+}
+
+template <int KD>
+static hipError_t commit_k(const TableRef& tb, const int32_t* keys, uint32_t n, const uint32_t* slot_of,
+                           uint8_t* lost, int32_t* kB, const int32_t* heap, uint32_t cap, const ValueSet& vs,
+                           int32_t* out_idx, uint8_t* out_mask, Meta* meta, uint64_t* status, int check,
+                           hipStream_t st) {
+  hipLaunchKernelGGL((k_commit<KD>), dim3(cdiv(n, kScanTile)), dim3(kBlock), 0, st, tb, keys, n, slot_of, lost, kB,
+                     heap, cap, vs, out_idx, out_mask, meta, status, check);
+  return hipGetLastError();
 }
 
 hipError_t launch_commit(int kd, const TableRef& tb, const int32_t* keys, uint32_t n, const uint32_t* slot_of,
-                         int32_t* kB, const int32_t* heap, uint8_t* active, uint32_t cap, const ValueSet& vs,
+                         uint8_t* lost, int32_t* kB, const int32_t* heap, uint32_t cap, const ValueSet& vs,
                          int32_t* out_idx, uint8_t* out_mask, Meta* meta, uint64_t* status, int check,
                          hipStream_t st) {
   switch (kd) {
-    case 1: return commit_k<1>(tb, keys, n, slot_of, kB, heap, active, cap, vs, out_idx, out_mask, meta, status, check, st);
-    case 2: return commit_k<2>(tb, keys, n, slot_of, kB, heap, active, cap, vs, out_idx, out_mask, meta, status, check, st);
-    case 3: return commit_k<3>(tb, keys, n, slot_of, kB, heap, active, cap, vs, out_idx, out_mask, meta, status, check, st);
-    case 4: return commit_k<4>(tb, keys, n, slot_of, kB, heap, active, cap, vs, out_idx, out_mask, meta, status, check, st);
+    case 1: return commit_k<1>(tb, keys, n, slot_of, lost, kB, heap, cap, vs, out_idx, out_mask, meta, status, check, st);
+    case 2: return commit_k<2>(tb, keys, n, slot_of, lost, kB, heap, cap, vs, out_idx, out_mask, meta, status, check, st);
+    case 3: return commit_k<3>(tb, keys, n, slot_of, lost, kB, heap, cap, vs, out_idx, out_mask, meta, status, check, st);
+    case 4: return commit_k<4>(tb, keys, n, slot_of, lost, kB, heap, cap, vs, out_idx, out_mask, meta, status, check, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -863,44 +1109,63 @@ hipError_t launch_find(int kd, int g, int w, const TableRef& tb, const int32_t* 
 }
 
 hipError_t launch_erase_mark(int kd, int g, int w, const TableRef& tb, const int32_t* keys, uint32_t n,
-                             uint32_t* slot_of, int32_t* found, int32_t* owner, hipStream_t st) {
-  return with_kd_probe<EraseMarkK>(kd, g, w, tb, keys, n, slot_of, found, owner, st);
+                             uint32_t epoch, uint32_t* slot_of, int32_t* found, uint64_t* owner, uint8_t* lost,
+                             hipStream_t st) {
+  return with_kd_probe<EraseMarkK>(kd, g, w, tb, keys, n, epoch, slot_of, found, owner, lost, st);
+}
+
+template <int KD>
+static hipError_t erase_commit_k(const TableRef& tb, uint32_t n, const uint32_t* slot_of, const int32_t* found,
+                                 uint8_t* lost, int32_t* heap, uint8_t* out_mask, Meta* meta, uint64_t* status,
+                                 hipStream_t st) {
+  hipLaunchKernelGGL((k_erase_commit<KD>), dim3(cdiv(n, kScanTile)), dim3(kBlock), 0, st, tb, n, slot_of, found,
+                     lost, heap, out_mask, meta, status);
+  return hipGetLastError();
 }
 
 hipError_t launch_erase_commit(int kd, const TableRef& tb, uint32_t n, const uint32_t* slot_of, const int32_t* found,
-                               int32_t* owner, int32_t* heap, uint8_t* active, uint8_t* out_mask, Meta* meta,
-                               uint64_t* status, hipStream_t st) {
+                               uint8_t* lost, int32_t* heap, uint8_t* out_mask, Meta* meta, uint64_t* status,
+                               hipStream_t st) {
   switch (kd) {
-    case 1: return erase_commit_k<1>(tb, n, slot_of, found, owner, heap, active, out_mask, meta, status, st);
-    case 2: return erase_commit_k<2>(tb, n, slot_of, found, owner, heap, active, out_mask, meta, status, st);
-    case 3: return erase_commit_k<3>(tb, n, slot_of, found, owner, heap, active, out_mask, meta, status, st);
-    case 4: return erase_commit_k<4>(tb, n, slot_of, found, owner, heap, active, out_mask, meta, status, st);
+    case 1: return erase_commit_k<1>(tb, n, slot_of, found, lost, heap, out_mask, meta, status, st);
+    case 2: return erase_commit_k<2>(tb, n, slot_of, found, lost, heap, out_mask, meta, status, st);
+    case 3: return erase_commit_k<3>(tb, n, slot_of, found, lost, heap, out_mask, meta, status, st);
+    case 4: return erase_commit_k<4>(tb, n, slot_of, found, lost, heap, out_mask, meta, status, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_compact_active(const uint8_t* active, uint32_t c, int32_t* out, Meta* meta, uint64_t* status,
-                                 hipStream_t st) {
-  hipLaunchKernelGGL(k_compact_active, dim3(cdiv(c, kScanTile)), dim3(kBlock), 0, st, active, c, out, meta, status);
+hipError_t launch_active_indices(int kd, const TableRef& tb, uint8_t* flags, uint32_t c, int32_t* out, Meta* meta,
+                                 uint64_t* status, hipStream_t st) {
+  const uint32_t grid = std::min<uint32_t>(cdiv(tb.nslots, kBlock), 8192);
+  switch (kd) {
+    case 1: hipLaunchKernelGGL(k_mark_live<2>, dim3(grid), dim3(kBlock), 0, st, tb, flags, c); break;
+    case 2:
+    case 3: hipLaunchKernelGGL(k_mark_live<4>, dim3(grid), dim3(kBlock), 0, st, tb, flags, c); break;
+    case 4: hipLaunchKernelGGL(k_mark_live<8>, dim3(grid), dim3(kBlock), 0, st, tb, flags, c); break;
+    default: return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_compact_flags, dim3(cdiv(c, kScanTile)), dim3(kBlock), 0, st, flags, c, out, meta, status);
   return hipGetLastError();
 }
 
-hipError_t launch_rebuild(int kd, int g, int w, const TableRef& tb, const int32_t* kB, const uint8_t* active,
-                          uint32_t c, Meta* meta, hipStream_t st) {
-  return with_kd_probe<RebuildK>(kd, g, w, tb, kB, active, c, meta, st);
+hipError_t launch_rebuild(int kd, int g, int w, const TableRef& tb, const uint32_t* old_words, uint32_t old_slots,
+                          Meta* meta, hipStream_t st) {
+  return with_kd_probe<RebuildK>(kd, g, w, tb, old_words, old_slots, meta, st);
 }
 
 hipError_t launch_voxel_claim(int g, int w, const TableRef& tb, const float* pts, float voxel, uint32_t n,
-                              uint32_t* slot_of, uint32_t* partial, Meta* meta, hipStream_t st) {
-  return with_probe<3, VoxelClaimK>(g, w, tb, pts, voxel, n, slot_of, partial, meta, st);
+                              uint32_t* slot_of, uint8_t* lost, uint32_t* partial, Meta* meta, hipStream_t st) {
+  return with_probe<3, VoxelClaimK>(g, w, tb, pts, voxel, n, slot_of, lost, partial, meta, st);
 }
 
-uint32_t claim_blocks(int g, uint32_t n) { return cdiv(n, 256u); }
-
 hipError_t launch_voxel_commit(const TableRef& tb, const float* pts, float voxel, uint32_t n, const uint32_t* slot_of,
-                               int32_t* voxel_keys, int32_t* counts, Meta* meta, uint64_t* status, hipStream_t st) {
+                               uint8_t* lost, int32_t* voxel_keys, int32_t* counts, Meta* meta, uint64_t* status,
+                               hipStream_t st) {
   hipLaunchKernelGGL(k_voxel_commit, dim3(cdiv(n, kScanTile)), dim3(kBlock), 0, st, tb, VoxelKeys{pts, voxel}, n,
-                     slot_of, voxel_keys, counts, meta, status);
+                     slot_of, lost, voxel_keys, counts, meta, status);
   return hipGetLastError();
 }
 
@@ -909,6 +1174,36 @@ hipError_t launch_voxel_resolve(const TableRef& tb, uint32_t n, const uint32_t* 
   hipLaunchKernelGGL(k_voxel_resolve, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, tb, n, slot_of, point_voxel,
                      counts);
   return hipGetLastError();
+}
+
+template <int KD>
+static hipError_t batched_k(const BatchItem* items, int32_t n_items, uint32_t claim_tiles, uint32_t commit_tiles,
+                            uint32_t find_tiles, int32_t any_check, hipStream_t st) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  int cus = 0, per_cu = 0;
+  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batched<KD>, kBlock, 0);
+  if (e != hipSuccess) return e;
+  if (per_cu < 1) return hipErrorInvalidConfiguration;
+  const uint32_t work = std::max(std::max(claim_tiles, commit_tiles), std::max(find_tiles, (uint32_t)n_items));
+  const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>((uint32_t)(cus * per_cu), work));
+  void* args[] = {(void*)&items, (void*)&n_items, (void*)&claim_tiles, (void*)&commit_tiles, (void*)&find_tiles,
+                  (void*)&any_check};
+  return hipLaunchCooperativeKernel((const void*)k_batched<KD>, dim3(grid), dim3(kBlock), args, 0, st);
+}
+
+hipError_t launch_batched(int kd, const BatchItem* items, int32_t n_items, uint32_t claim_tiles, uint32_t commit_tiles,
+                          uint32_t find_tiles, int32_t any_check, hipStream_t st) {
+  switch (kd) {
+    case 1: return batched_k<1>(items, n_items, claim_tiles, commit_tiles, find_tiles, any_check, st);
+    case 2: return batched_k<2>(items, n_items, claim_tiles, commit_tiles, find_tiles, any_check, st);
+    case 3: return batched_k<3>(items, n_items, claim_tiles, commit_tiles, find_tiles, any_check, st);
+    case 4: return batched_k<4>(items, n_items, claim_tiles, commit_tiles, find_tiles, any_check, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace ash

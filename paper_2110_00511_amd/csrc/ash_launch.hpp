@@ -20,27 +20,38 @@ hipError_t launch_sum_partials(const uint32_t* partial, uint32_t count, Meta* me
 // Number of blocks (and per-block counts) of a claim launch over n positions.
 uint32_t claim_blocks(int g, uint32_t n);
 hipError_t launch_claim(int kd, int g, int w, const TableRef& tb, const int32_t* keys, uint32_t n, uint32_t* slot_of,
-                        uint32_t* partial, Meta* meta, hipStream_t st);
+                        uint8_t* lost, uint32_t* partial, Meta* meta, hipStream_t st);
 hipError_t launch_commit(int kd, const TableRef& tb, const int32_t* keys, uint32_t n, const uint32_t* slot_of,
-                         int32_t* kB, const int32_t* heap, uint8_t* active, uint32_t cap, const ValueSet& vs,
+                         uint8_t* lost, int32_t* kB, const int32_t* heap, uint32_t cap, const ValueSet& vs,
                          int32_t* out_idx, uint8_t* out_mask, Meta* meta, uint64_t* status, int check,
                          hipStream_t st);
 hipError_t launch_find(int kd, int g, int w, const TableRef& tb, const int32_t* keys, uint32_t n, int32_t* out_idx,
                        uint8_t* out_mask, const ValueSet& vs, hipStream_t st);
-hipError_t launch_erase_mark(int kd, int g, int w, const TableRef& tb, const int32_t* keys, uint32_t n, uint32_t* slot_of,
-                             int32_t* found, int32_t* owner, hipStream_t st);
+hipError_t launch_erase_mark(int kd, int g, int w, const TableRef& tb, const int32_t* keys, uint32_t n,
+                             uint32_t epoch, uint32_t* slot_of, int32_t* found, uint64_t* owner, uint8_t* lost,
+                             hipStream_t st);
 hipError_t launch_erase_commit(int kd, const TableRef& tb, uint32_t n, const uint32_t* slot_of, const int32_t* found,
-                               int32_t* owner, int32_t* heap, uint8_t* active, uint8_t* out_mask, Meta* meta,
-                               uint64_t* status, hipStream_t st);
-hipError_t launch_compact_active(const uint8_t* active, uint32_t c, int32_t* out, Meta* meta, uint64_t* status,
-                                 hipStream_t st);
-hipError_t launch_rebuild(int kd, int g, int w, const TableRef& tb, const int32_t* kB, const uint8_t* active, uint32_t c,
+                               uint8_t* lost, int32_t* heap, uint8_t* out_mask, Meta* meta, uint64_t* status,
+                               hipStream_t st);
+hipError_t launch_active_indices(int kd, const TableRef& tb, uint8_t* flags, uint32_t c, int32_t* out, Meta* meta,
+                                 uint64_t* status, hipStream_t st);
+hipError_t launch_rebuild(int kd, int g, int w, const TableRef& tb, const uint32_t* old_words, uint32_t old_slots,
                           Meta* meta, hipStream_t st);
 hipError_t launch_voxel_claim(int g, int w, const TableRef& tb, const float* pts, float voxel, uint32_t n,
-                              uint32_t* slot_of, uint32_t* partial, Meta* meta, hipStream_t st);
+                              uint32_t* slot_of, uint8_t* lost, uint32_t* partial, Meta* meta, hipStream_t st);
 hipError_t launch_voxel_commit(const TableRef& tb, const float* pts, float voxel, uint32_t n, const uint32_t* slot_of,
-                               int32_t* voxel_keys, int32_t* counts, Meta* meta, uint64_t* status, hipStream_t st);
+                               uint8_t* lost, int32_t* voxel_keys, int32_t* counts, Meta* meta, uint64_t* status,
+                               hipStream_t st);
 hipError_t launch_voxel_resolve(const TableRef& tb, uint32_t n, const uint32_t* slot_of, int32_t* point_voxel,
                                 int32_t* counts, hipStream_t st);
+
+// Inserts then finds of n_items independent maps in one cooperative launch.
+// items is a device array; tile counts are the flat totals of each phase.
+hipError_t launch_batched(int kd, const BatchItem* items, int32_t n_items, uint32_t claim_tiles, uint32_t commit_tiles,
+                          uint32_t find_tiles, int32_t any_check, hipStream_t st);
+
+// Synthetic keys of the autotuner (uniform in [0, side)^kd; finds half hits).
+hipError_t launch_synth_keys(int32_t* keys, uint32_t n, int kd, uint32_t side, uint64_t seed, int32_t* fkeys,
+                             uint32_t nf, hipStream_t st);
 
 }  // namespace ash

@@ -209,3 +209,63 @@ def voxelize(points, voxel_size):
                              ctypes.byref(nv), ctypes.byref(alloc.struct), _stream()), "ash_voxelize")
     u = nv.value
     return pv, vk[:u], cnt[:u]
+
+
+def autotune(capacity, n_insert, distinct_ratio, key_dim=3, value_specs=(), device="cuda"):
+    """Table shape for a map of `capacity` receiving batches of `n_insert`
+    keys with the given distinct ratio: times insert + find of a synthetic
+    batch for every point of the sweep on this GPU.  Returns
+    (dict(bucket_width, probe_group, max_load), milliseconds)."""
+    lib = L.load()
+    specs = [(dt, int(e)) for dt, e in value_specs]
+    n = len(specs)
+    dts = (ctypes.c_int * max(n, 1))(*[_DTYPES[dt] for dt, _ in specs])
+    els = (ctypes.c_int64 * max(n, 1))(*[e for _, e in specs])
+    alloc = L.TorchAllocator(device)
+    out = L.AshTuning()
+    ms = ctypes.c_double()
+    L.check(lib.ash_autotune(int(capacity), int(key_dim), n, ctypes.cast(dts, ctypes.c_void_p),
+                             ctypes.cast(els, ctypes.c_void_p), int(n_insert), float(distinct_ratio),
+                             ctypes.byref(alloc.struct), _stream(), ctypes.byref(out), ctypes.byref(ms)),
+            "ash_autotune")
+    return dict(bucket_width=out.bucket_width, probe_group=out.probe_group, max_load=out.max_load), ms.value
+
+
+def batched(ops, fused=True):
+    """Inserts then finds on many maps at once (one persistent launch when
+    fused).  ops: list of dicts with keys map, insert_keys, insert_values,
+    find_keys, gather (bool).  Returns a list of dicts with insert_idx,
+    insert_mask, find_idx, find_mask and find_values."""
+    lib = L.load()
+    arr = (L.AshBatchOp * max(len(ops), 1))()
+    keep = []
+    results = []
+    for i, op in enumerate(ops):
+        m = op["map"]
+        ik = _keys(op["insert_keys"], m.key_dim, m.device)
+        fk = _keys(op["find_keys"], m.key_dim, m.device)
+        ni, nf = ik.shape[0], fk.shape[0]
+        vals = [v.reshape(ni, e).contiguous() for v, (dt, e) in zip(op.get("insert_values", ()), m.value_specs)]
+        if len(vals) != len(m.value_specs):
+            raise ValueError("one value tensor per value buffer is required")
+        res = dict(insert_idx=torch.empty(ni, dtype=torch.int32, device=m.device),
+                   insert_mask=torch.empty(ni, dtype=torch.uint8, device=m.device),
+                   find_idx=torch.empty(nf, dtype=torch.int32, device=m.device),
+                   find_mask=torch.empty(nf, dtype=torch.uint8, device=m.device), find_values=None)
+        vin = (ctypes.c_void_p * max(len(vals), 1))(*[v.data_ptr() for v in vals])
+        vout = None
+        if op.get("gather") and m.value_specs:
+            res["find_values"] = [torch.zeros((nf, e), dtype=dt, device=m.device) for dt, e in m.value_specs]
+            vout = (ctypes.c_void_p * len(m.value_specs))(*[o.data_ptr() for o in res["find_values"]])
+        keep.extend([ik, fk, vals, vin, vout])
+        arr[i] = L.AshBatchOp(m._m, ik.data_ptr(), ni, ctypes.cast(vin, ctypes.c_void_p) if vals else None,
+                              res["insert_idx"].data_ptr(), res["insert_mask"].data_ptr(), fk.data_ptr(), nf,
+                              ctypes.cast(vout, ctypes.c_void_p) if vout is not None else None,
+                              res["find_idx"].data_ptr(), res["find_mask"].data_ptr())
+        results.append(res)
+    L.check(lib.ash_batched(arr, len(ops), 1 if fused else 0, _stream()), "ash_batched")
+    for r in results:
+        r["insert_mask"] = r["insert_mask"].bool()
+        r["find_mask"] = r["find_mask"].bool()
+    return results
+

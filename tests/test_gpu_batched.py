@@ -1,0 +1,127 @@
+"""Batched maps: many independent maps of uneven sizes in one persistent
+launch.  Each map's results must equal the oracle's for the same insert and
+find batches (and therefore the op-by-op single-map path), bit for bit."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import ORACLE_E_CAPACITY, OracleMap  # noqa: E402
+from tests.test_gpu_parity import bits, dev, host  # noqa: E402
+
+SHAPES = [(4, 4, 0.5), (1, 4, 0.7), (8, 8, 0.85), (64, 16, 0.5), (16, 4, 0.7), (1, 8, 0.5), (32, 32, 0.85),
+          (1, 2, 0.5)]
+
+
+@pytest.fixture(scope="module")
+def ash():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2110_00511_amd as ash_mod
+    return ash_mod
+
+
+def make_case(rng, u, channels=8):
+    side = max(2, int(round((2 * u / 1.5936) ** (1 / 3))))
+    keys = rng.integers(0, side, size=(2 * u, 3), dtype=np.int32)
+    vals = rng.standard_normal((2 * u, channels)).astype(np.float32)
+    present = keys[rng.integers(0, 2 * u, size=u)]
+    absent = rng.integers(side, 2 * side, size=(u, 3), dtype=np.int32)
+    finds = np.concatenate([present, absent])[rng.permutation(2 * u)]
+    return keys, vals, np.ascontiguousarray(finds)
+
+
+def run_round(ash, maps, oracles, cases, fused):
+    ops = [dict(map=m, insert_keys=dev(k), insert_values=[dev(v)], find_keys=dev(f), gather=True)
+           for m, (k, v, f) in zip(maps, cases)]
+    res = ash.batched(ops, fused=fused)
+    statuses = []
+    for r, o, (k, v, f) in zip(res, oracles, cases):
+        st, oi, om = o.insert(k, [v])
+        statuses.append(st)
+        assert np.array_equal(host(r["insert_mask"]).astype(np.uint8), om)
+        assert np.array_equal(host(r["insert_idx"]), oi)
+        st, fi, fm, (fv,) = o.find(f, gather=True, fill=0)
+        assert np.array_equal(host(r["find_mask"]).astype(np.uint8), fm)
+        assert np.array_equal(host(r["find_idx"]), fi)
+        assert np.array_equal(bits(host(r["find_values"][0])), bits(fv))
+    return statuses
+
+
+def check_maps(maps, oracles):
+    torch.cuda.synchronize()
+    for m, o in zip(maps, oracles):
+        assert m.size() == o.size
+        assert np.array_equal(host(m.heap_buffer()), o.heap())
+        act = host(m.active_indices())
+        assert np.array_equal(act, o.active_indices())
+        assert np.array_equal(host(m.key_buffer())[act], o.key_buffer()[act])
+        assert np.array_equal(bits(host(m.value_buffer(0))[act]), bits(o.value_buffer(0)[act]))
+
+
+@pytest.mark.parametrize("fused", [True, False])
+def test_batched_maps_match_oracle(ash, fused):
+    rng = np.random.default_rng(40)
+    sizes = [1000, 3000, 20000, 70000, 5000, 150000, 40000, 2000]
+    maps, oracles, cases = [], [], []
+    for u, (g, w, lf) in zip(sizes, SHAPES):
+        maps.append(ash.HashMap(2 * u, 3, [(torch.float32, 8)], probe_group=g, bucket_width=w, max_load=lf))
+        oracles.append(OracleMap(2 * u, 3, [(np.float32, 8)]))
+        cases.append(make_case(rng, u))
+    run_round(ash, maps, oracles, cases, fused)
+    check_maps(maps, oracles)
+    # a second round on the populated maps: re-inserted keys are misses, new
+    # keys take the next heap indices
+    cases2 = [make_case(rng, max(u // 4, 1)) for u in sizes]
+    run_round(ash, maps, oracles, cases2, fused)
+    check_maps(maps, oracles)
+    for m in maps:
+        assert m.device_status() == 0
+
+
+def test_batched_overflow_is_per_map(ash):
+    rng = np.random.default_rng(41)
+    sizes = [4000, 6000, 9000]
+    caps = [8000, 1000, 18000]  # the middle map cannot take its batch
+    maps = [ash.HashMap(c, 3, [(torch.float32, 8)]) for c in caps]
+    oracles = [OracleMap(c, 3, [(np.float32, 8)]) for c in caps]
+    cases = [make_case(rng, u) for u in sizes]
+    statuses = run_round(ash, maps, oracles, cases, True)
+    assert statuses[1] == ORACLE_E_CAPACITY and statuses[0] == 0 and statuses[2] == 0
+    assert [m.device_status() for m in maps] == [0, 2, 0]
+    check_maps(maps, oracles)
+
+
+def test_batched_empty_ops_and_hash_sets(ash):
+    rng = np.random.default_rng(42)
+    a = ash.HashSet(5000, 3)
+    b = ash.HashSet(5000, 3)
+    oa, ob = OracleMap(5000, 3), OracleMap(5000, 3)
+    ka = rng.integers(0, 20, size=(3000, 3), dtype=np.int32)
+    empty = np.zeros((0, 3), np.int32)
+    res = ash.batched([dict(map=a, insert_keys=dev(ka), find_keys=dev(empty)),
+                       dict(map=b, insert_keys=dev(empty), find_keys=dev(ka))])
+    st, oi, om = oa.insert(ka)
+    assert np.array_equal(host(res[0]["insert_idx"]), oi)
+    st, fi, fm = ob.find(ka)
+    assert np.array_equal(host(res[1]["find_mask"]).astype(np.uint8), fm)
+    assert a.size() == oa.size and b.size() == 0
+
+
+def test_autotune_picks_a_valid_shape(ash):
+    tun, ms = ash.autotune(40_000, 20_000, 0.5, key_dim=3, value_specs=[(torch.float32, 8)])
+    assert tun["probe_group"] in (1, 4, 8, 16, 64)
+    assert tun["bucket_width"] in (4, 8, 16, 32)
+    assert min(abs(tun["max_load"] - x) for x in (0.5, 0.7, 0.85)) < 1e-6
+    assert ms > 0
+    # cached: the second call returns the same answer at once
+    tun2, ms2 = ash.autotune(40_000, 20_000, 0.5, key_dim=3, value_specs=[(torch.float32, 8)])
+    assert tun2 == tun and ms2 == ms
+    rng = np.random.default_rng(43)
+    m = ash.HashMap(40_000, 3, [(torch.float32, 8)], **tun)
+    o = OracleMap(40_000, 3, [(np.float32, 8)])
+    k, v, f = make_case(rng, 20_000)
+    run_round(ash, [m], [o], [(k, v, f)], True)
+    check_maps([m], [o])
