@@ -228,6 +228,61 @@ ash_status_t ash_autotune(int64_t capacity, int32_t key_dim, int32_t n_values,
                           const ash_allocator_t* allocator, void* stream,
                           ash_tuning_t* out, double* out_ms);
 
+/* Served map (continuous batching).  A server owns one map (the caller must
+ * not use the map while it is served) and a worker thread with its own HIP
+ * stream.  Requests run in arrival order; requests of one kind that are
+ * waiting when the worker is ready are fused into one device batch,
+ * concatenated in arrival order, so each request's results equal those of
+ * running the requests one after another (lowest batch position = earliest
+ * request).  An insert joins a fused batch only while the batch's positions
+ * fit the free index-heap slots c - t.  Up to in_flight batches are queued on
+ * the device while the next one is formed; a completion thread stamps each
+ * request's completion time.  Keys, values and outputs are device buffers
+ * owned by the caller; they must hold their data when the request is
+ * submitted (the server's stream waits on no other stream) and stay valid
+ * until the request completes. */
+typedef struct ash_server* ash_server_t;
+
+typedef enum { ASH_REQ_FIND = 0, ASH_REQ_INSERT = 1, ASH_REQ_ERASE = 2 } ash_req_kind_t;
+
+typedef struct {
+  int32_t kind;                 /* ash_req_kind_t */
+  const int32_t* keys;          /* n rows of key_dim int32 */
+  int64_t n;
+  const void* const* values;    /* insert: host array of n_values device pointers */
+  int32_t* out_idx;             /* insert / find, nullable */
+  uint8_t* out_mask;            /* nullable */
+  void* const* out_values;      /* find: nullable host array of n_values device pointers */
+} ash_request_t;
+
+typedef struct {
+  int32_t max_fused;  /* requests per device batch (default 256) */
+  int64_t max_batch;  /* positions per fused device batch (default 2^22) */
+  int32_t in_flight;  /* device batches queued at once (default 4) */
+  int32_t fuse;       /* 0: every request is its own device batch */
+} ash_server_config_t;
+
+/* cfg NULL = defaults.  Maps with ASH_F_AUTOGROW are not served
+ * (ASH_E_UNSUPPORTED). */
+ash_status_t ash_server_create(ash_map_t map, const ash_server_config_t* cfg, ash_server_t* out);
+/* Thread safe; *out_ticket identifies the request for ash_server_wait. */
+ash_status_t ash_server_submit(ash_server_t server, const ash_request_t* req, int64_t* out_ticket);
+/* Blocks until the request completed; returns its status (that of the
+ * operation it ran in) and its latency from submission in seconds. */
+ash_status_t ash_server_wait(ash_server_t server, int64_t ticket, double* out_latency_s);
+/* Submits reqs[i] at arrival_s[i] seconds after the call (a trace replay),
+ * then waits for all: latencies from the scheduled arrivals, per-request
+ * statuses (nullable outputs) and the time from the call to the last
+ * completion. */
+ash_status_t ash_server_replay(ash_server_t server, const ash_request_t* reqs, int64_t n,
+                               const double* arrival_s, double* out_latency_s, int32_t* out_status,
+                               double* out_span_s);
+/* Device batches launched and requests they carried so far. */
+ash_status_t ash_server_stats(ash_server_t server, int64_t* out_batches, int64_t* out_requests);
+/* Runs the remaining requests, then stops the threads and frees the server
+ * (not the map). */
+ash_status_t ash_server_destroy(ash_server_t server);
+
 /* Per-kernel timing of one map (instrumentation).  While enabled, every
  * kernel the map launches is bracketed by HIP events recorded on the launch
  * stream.  ash_profile_collect synchronizes, writes up to max_entries

@@ -50,6 +50,15 @@ class AshBatchOp(ctypes.Structure):
                 ("find_mask", P)]
 
 
+class AshRequest(ctypes.Structure):
+    _fields_ = [("kind", I32), ("keys", P), ("n", I64), ("values", P), ("out_idx", P), ("out_mask", P),
+                ("out_values", P)]
+
+
+class AshServerConfig(ctypes.Structure):
+    _fields_ = [("max_fused", I32), ("max_batch", I64), ("in_flight", I32), ("fuse", I32)]
+
+
 class AshStats(ctypes.Structure):
     _fields_ = [("size", I64), ("capacity", I64), ("slots", I64), ("used_slots", I64), ("tombstones", I64)]
 
@@ -75,6 +84,12 @@ SIGNATURES = {
     "ash_batched": (ST, [ctypes.POINTER(AshBatchOp), I32, I32, P]),
     "ash_autotune": (ST, [I64, I32, I32, P, P, I64, ctypes.c_double, P, P, ctypes.POINTER(AshTuning),
                           ctypes.POINTER(ctypes.c_double)]),
+    "ash_server_create": (ST, [P, P, ctypes.POINTER(P)]),
+    "ash_server_submit": (ST, [P, ctypes.POINTER(AshRequest), ctypes.POINTER(I64)]),
+    "ash_server_wait": (ST, [P, I64, ctypes.POINTER(ctypes.c_double)]),
+    "ash_server_replay": (ST, [P, ctypes.POINTER(AshRequest), I64, P, P, P, ctypes.POINTER(ctypes.c_double)]),
+    "ash_server_stats": (ST, [P, ctypes.POINTER(I64), ctypes.POINTER(I64)]),
+    "ash_server_destroy": (ST, [P]),
     "ash_profile_enable": (ST, [P, I32]),
     "ash_profile_collect": (ST, [P, ctypes.POINTER(AshKernelTime), I32, ctypes.POINTER(I32), P]),
     "ash_status_string": (ctypes.c_char_p, [ST]),
@@ -124,14 +139,24 @@ class TorchAllocator:
         self._free = AshAllocator._fields_[1][1](self._do_free)
         self.struct = AshAllocator(self._alloc, self._free, None)
 
+    def _stream(self, stream):
+        if not stream:
+            return torch.cuda.current_stream(self.device)
+        return torch.cuda.ExternalStream(stream, device=self.device)
+
     def _do_alloc(self, ctx, nbytes, stream):
-        t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        # allocate on the stream the library will use the block on, so that
+        # torch only reuses it in that stream's order
+        with torch.cuda.stream(self._stream(stream)):
+            t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
         ptr = t.data_ptr()
         self.blocks[ptr] = t
         return ptr
 
     def _do_free(self, ctx, ptr, stream):
-        self.blocks.pop(ptr, None)
+        t = self.blocks.pop(ptr, None)
+        if t is not None and stream:
+            t.record_stream(self._stream(stream))
 
     def tensor(self, ptr):
         return self.blocks[ptr]

@@ -14,7 +14,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libash.so")
-SOURCES = [os.path.join(HERE, "csrc", "ash_kernels.hip"), os.path.join(HERE, "csrc", "ash_api.hip")]
+SOURCES = [os.path.join(HERE, "csrc", name) for name in ("ash_kernels.hip", "ash_api.hip", "ash_serve.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -28,6 +28,7 @@ FLAGS = [
     "-fno-gpu-flush-denormals-to-zero",
     "-fhip-fp32-correctly-rounded-divide-sqrt",
     "-fno-fast-math",
+    "-pthread",
 ]
 
 

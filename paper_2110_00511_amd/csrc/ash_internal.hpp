@@ -1,0 +1,161 @@
+// ash_internal.hpp -- host-side state of a map shared by the C-ABI
+// implementation files (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "ash.h"
+#include "ash_device.hpp"
+
+using ash::Meta;
+using ash::TableRef;
+using ash::ValueSet;
+
+namespace ash_host {
+
+constexpr int64_t kMaxCount = (1ll << 31) - 3;  // positions and indices must fit PENDING(p)
+constexpr uint64_t kMaxSlots = (1ull << 32) - 128;
+
+#define ASH_HIP(call)                           \
+  do {                                          \
+    if ((call) != hipSuccess) return ASH_E_DEVICE; \
+  } while (0)
+
+#define ASH_TRY(call)                 \
+  do {                                \
+    ash_status_t st__ = (call);       \
+    if (st__ != ASH_OK) return st__;  \
+  } while (0)
+
+inline size_t dtype_size(ash_dtype_t t) {
+  switch (t) {
+    case ASH_U8: return 1;
+    case ASH_I32: case ASH_F32: return 4;
+    case ASH_I64: case ASH_F64: return 8;
+    case ASH_F16: case ASH_BF16: return 2;
+    default: return 0;
+  }
+}
+
+inline bool pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+
+struct DevMem {
+  ash_allocator_t a;
+  bool custom;
+  void* get(size_t bytes, hipStream_t st) {
+    bytes = std::max<size_t>(bytes, 256);
+    if (custom) return a.alloc(a.ctx, bytes, st);
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    return p;
+  }
+  void put(void* p, hipStream_t st) {
+    if (!p) return;
+    if (custom) {
+      a.free(a.ctx, p, st);
+    } else {
+      (void)hipStreamSynchronize(st);
+      (void)hipFree(p);
+    }
+  }
+};
+
+// Largest copy unit (16, 8, 4, 2, 1 bytes) dividing the row size and the
+// alignment of both base pointers.
+inline uint32_t copy_unit(uint32_t row_bytes, const void* a, const void* b) {
+  uintptr_t m = (uintptr_t)a | (uintptr_t)b | row_bytes;
+  for (uint32_t v = 16; v > 1; v >>= 1)
+    if ((m & (v - 1)) == 0) return v;
+  return 1;
+}
+
+inline uint32_t units_log2(uint32_t row_bytes, uint32_t vec) {
+  uint32_t u = row_bytes / vec;
+  if (!pow2(u)) return 0xFFu;
+  uint32_t l = 0;
+  while ((1u << l) < u) ++l;
+  return l;
+}
+
+// Event records of ash_profile_enable: one (start, stop) pair per launch.
+struct ProfRec {
+  const char* name;
+  hipEvent_t start, stop;
+};
+
+struct Prof {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<ProfRec> recs;
+  hipEvent_t next() {
+    if (used == pool.size()) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+};
+
+}  // namespace ash_host
+
+struct ash_map {
+  ash_host::DevMem mem;
+  ash_host::Prof prof;
+  int64_t c = 0;
+  int key_dim = 3;
+  int n_values = 0;
+  std::vector<uint32_t> row_bytes;
+  int W = 4, G = 4;
+  float max_load = 0.5f;
+  uint32_t flags = 0;
+  // device state
+  uint32_t* table = nullptr;
+  uint32_t nslots = 0;
+  int32_t* kB = nullptr;
+  std::vector<uint8_t*> vB;
+  int32_t* heap = nullptr;
+  uint64_t* owner = nullptr;  // erase election: (epoch << 32) | ~position
+  uint32_t erase_epoch = 0;
+  Meta* meta = nullptr;
+  // per-call scratch
+  uint32_t* slot_of = nullptr;
+  int32_t* aux = nullptr;
+  uint32_t* partial = nullptr;  // per-block new-key counts of the claim kernel
+  uint8_t* lost = nullptr;      // displaced candidates; all zero between calls
+  int64_t scratch_n = 0;
+  uint64_t* scan_status = nullptr;
+  int64_t scan_tiles = 0;
+  // host-side upper bounds (exact after any synchronizing call)
+  int64_t live_ub = 0;
+  int64_t used_ub = 0;
+
+  int slot_words() const { return key_dim == 1 ? 2 : (key_dim <= 3 ? 4 : 8); }
+
+  TableRef ref() const {
+    TableRef r;
+    r.words = table;
+    r.nslots = nslots;
+    r.bucket_width = (uint32_t)W;
+    r.nbuckets = nslots / (uint32_t)W;
+    r.window = (uint32_t)(G == 1 ? W : G);
+    r.max_windows = nslots / r.window + 1;
+    return r;
+  }
+};
+
+
+namespace ash_host {
+
+// Implemented in ash_api.hip.
+ash_status_t read_meta(ash_map* m, Meta* out, hipStream_t st);
+ash_status_t ensure_scratch(ash_map* m, int64_t n, hipStream_t st);
+ash_status_t insert_impl(ash_map* m, const int32_t* keys, int64_t n, const void* const* values, int32_t* out_idx,
+                         uint8_t* out_mask, hipStream_t st);
+
+}  // namespace ash_host

@@ -946,6 +946,49 @@ hipError_t launch_synth_keys(int32_t* keys, uint32_t n, int kd, uint32_t side, u
   return hipGetLastError();
 }
 
+// Copies the rows whose mask byte is 1 (a served find's hits from the fused
+// batch back to the request's own buffer; rows of misses stay untouched).
+template <typename U>
+__global__ __launch_bounds__(kBlock) void k_copy_masked_rows(const uint8_t* __restrict__ mask,
+                                                             const U* __restrict__ src, U* __restrict__ dst,
+                                                             uint64_t rows, uint32_t units) {
+  const uint64_t total = rows * units;
+  for (uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x; e < total; e += (uint64_t)gridDim.x * kBlock) {
+    const uint64_t r = e / units;
+    if (mask[r]) dst[e] = src[e];
+  }
+}
+
+hipError_t launch_copy_masked_rows(const uint8_t* mask, const void* src, void* dst, uint64_t rows,
+                                   uint32_t row_bytes, uint32_t vec, hipStream_t st) {
+  if (rows == 0 || row_bytes == 0) return hipSuccess;
+  const uint32_t units = row_bytes / vec;
+  const uint32_t grid = std::max<uint32_t>(1, (uint32_t)std::min<uint64_t>((rows * units + kBlock - 1) / kBlock, 8192));
+  switch (vec) {
+    case 16:
+      hipLaunchKernelGGL(k_copy_masked_rows<uint4>, dim3(grid), dim3(kBlock), 0, st, mask, (const uint4*)src,
+                         (uint4*)dst, rows, units);
+      break;
+    case 8:
+      hipLaunchKernelGGL(k_copy_masked_rows<uint2>, dim3(grid), dim3(kBlock), 0, st, mask, (const uint2*)src,
+                         (uint2*)dst, rows, units);
+      break;
+    case 4:
+      hipLaunchKernelGGL(k_copy_masked_rows<uint32_t>, dim3(grid), dim3(kBlock), 0, st, mask, (const uint32_t*)src,
+                         (uint32_t*)dst, rows, units);
+      break;
+    case 2:
+      hipLaunchKernelGGL(k_copy_masked_rows<uint16_t>, dim3(grid), dim3(kBlock), 0, st, mask, (const uint16_t*)src,
+                         (uint16_t*)dst, rows, units);
+      break;
+    default:
+      hipLaunchKernelGGL(k_copy_masked_rows<uint8_t>, dim3(grid), dim3(kBlock), 0, st, mask, (const uint8_t*)src,
+                         (uint8_t*)dst, rows, row_bytes);
+      break;
+  }
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Launchers.
 static inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }

@@ -12,6 +12,9 @@ namespace ash {
 enum FinalizeMode { kFinalizeInsert = 0, kFinalizeErase = 1, kFinalizeCount = 2, kFinalizeRebuild = 3 };
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t st);
+// dst row r = src row r where mask[r] == 1 (rows of row_bytes, copied in vec-byte units).
+hipError_t launch_copy_masked_rows(const uint8_t* mask, const void* src, void* dst, uint64_t rows,
+                                   uint32_t row_bytes, uint32_t vec, hipStream_t st);
 hipError_t launch_iota(int32_t* h, uint32_t from, uint32_t to, hipStream_t st);
 hipError_t launch_reset_meta(Meta* m, hipStream_t st);
 hipError_t launch_finalize(Meta* m, uint32_t cap, int mode, int silent, int check, const uint64_t* status,

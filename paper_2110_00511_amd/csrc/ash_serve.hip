@@ -1,0 +1,416 @@
+// ash_serve.hip -- served map: continuous batching of insert / find / erase
+// requests on one device-resident map (host runtime around the C ABI).
+//
+// A worker thread owns the map and a HIP stream.  Requests are admitted in
+// arrival order; consecutive requests of the same kind that are waiting when
+// the worker is ready are fused into one device batch, concatenated in
+// arrival order, so that the lowest-batch-position rule of insert and erase
+// makes an earlier request win exactly as it would when the requests run one
+// after another.  Finds never fuse with inserts or erases, and batches run in
+// order on one stream, so every request sees the map that serial execution
+// would show it.  An insert joins a fused batch only while the positions of
+// the batch fit the free heap slots c - t (t bounded on the host, read back
+// from the device when the bound is too loose): a fused insert can therefore
+// never overflow where the separate requests would not.  A completion thread
+// waits on each batch's event and stamps the completion time of its
+// requests.  Up to `in_flight` batches are queued on the device while the
+// worker forms the next one, so arrivals overlap with device work.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "ash.h"
+#include "ash_internal.hpp"
+#include "ash_launch.hpp"
+
+using namespace ash_host;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Req {
+  ash_request_t r;
+  std::vector<const void*> values;
+  std::vector<void*> out_values;
+  double arrival = 0.0;  // seconds since the server started
+  double done = -1.0;
+  ash_status_t status = ASH_OK;
+  bool finished = false;
+};
+
+// Staging of one fused batch in flight.
+struct Stage {
+  int64_t cap = 0;
+  int32_t* keys = nullptr;
+  std::vector<uint8_t*> vals;
+  std::vector<uint8_t*> outv;
+  int32_t* idx = nullptr;
+  uint8_t* mask = nullptr;
+};
+
+struct Batch {
+  std::vector<Req*> reqs;
+  hipEvent_t done = nullptr;
+  int stage = -1;
+};
+
+}  // namespace
+
+struct ash_server {
+  ash_map* map = nullptr;
+  ash_server_config_t cfg;
+  hipStream_t stream = nullptr;
+  Clock::time_point t0;
+  std::mutex mu;
+  std::condition_variable cv_queue, cv_flight, cv_done;
+  std::deque<Req*> queue;                  // submitted, not launched yet
+  std::deque<Batch> flight;                // launched, not completed yet
+  std::vector<std::unique_ptr<Req>> reqs;  // every request by ticket
+  std::vector<Stage> stages;
+  std::vector<int> free_stages;
+  std::vector<hipEvent_t> free_events;
+  bool stop = false;
+  bool worker_done = false;
+  int device = 0;
+  int64_t batches = 0, fused_requests = 0;
+  std::thread worker, completer;
+};
+
+namespace {
+
+double now_s(const ash_server* s) { return std::chrono::duration<double>(Clock::now() - s->t0).count(); }
+
+ash_status_t stage_alloc(ash_server* s, Stage& g) {
+  ash_map* m = s->map;
+  const int64_t n = s->cfg.max_batch;
+  g.cap = n;
+  if (hipMalloc(&g.keys, (size_t)n * m->key_dim * 4) != hipSuccess) return ASH_E_NOMEM;
+  if (hipMalloc(&g.idx, (size_t)n * 4) != hipSuccess) return ASH_E_NOMEM;
+  if (hipMalloc(&g.mask, (size_t)n) != hipSuccess) return ASH_E_NOMEM;
+  g.vals.assign(m->n_values, nullptr);
+  g.outv.assign(m->n_values, nullptr);
+  for (int j = 0; j < m->n_values; ++j) {
+    if (hipMalloc(&g.vals[j], (size_t)n * m->row_bytes[j]) != hipSuccess) return ASH_E_NOMEM;
+    if (hipMalloc(&g.outv[j], (size_t)n * m->row_bytes[j]) != hipSuccess) return ASH_E_NOMEM;
+  }
+  return ASH_OK;
+}
+
+void stage_free(Stage& g) {
+  (void)hipFree(g.keys);
+  (void)hipFree(g.idx);
+  (void)hipFree(g.mask);
+  for (uint8_t* p : g.vals) (void)hipFree(p);
+  for (uint8_t* p : g.outv) (void)hipFree(p);
+}
+
+// Runs one request directly on its own buffers.
+ash_status_t run_one(ash_server* s, Req* q) {
+  ash_map* m = s->map;
+  const ash_request_t& r = q->r;
+  switch (r.kind) {
+    case ASH_REQ_INSERT:
+      return insert_impl(m, r.keys, r.n, m->n_values > 0 ? q->values.data() : nullptr, r.out_idx, r.out_mask,
+                         s->stream);
+    case ASH_REQ_FIND:
+      return ash_find(m, r.keys, r.n, r.out_idx, r.out_mask, q->out_values.empty() ? nullptr : q->out_values.data(),
+                      s->stream);
+    case ASH_REQ_ERASE:
+      return ash_erase(m, r.keys, r.n, r.out_mask, s->stream);
+    default:
+      return ASH_E_INVALID;
+  }
+}
+
+// Runs requests of one kind as one device batch through staging buffers.
+ash_status_t run_fused(ash_server* s, const std::vector<Req*>& run, Stage& g) {
+  ash_map* m = s->map;
+  hipStream_t st = s->stream;
+  const int kind = run[0]->r.kind;
+  const size_t kbytes = (size_t)m->key_dim * 4;
+  int64_t off = 0;
+  for (Req* q : run) {  // gather in arrival order
+    ASH_HIP(hipMemcpyAsync(g.keys + off * m->key_dim, q->r.keys, (size_t)q->r.n * kbytes, hipMemcpyDeviceToDevice,
+                           st));
+    if (kind == ASH_REQ_INSERT)
+      for (int j = 0; j < m->n_values; ++j)
+        ASH_HIP(hipMemcpyAsync(g.vals[j] + off * m->row_bytes[j], q->values[j], (size_t)q->r.n * m->row_bytes[j],
+                               hipMemcpyDeviceToDevice, st));
+    off += q->r.n;
+  }
+  bool gather = false;
+  for (Req* q : run) gather = gather || !q->out_values.empty();
+  std::vector<const void*> vin(g.vals.begin(), g.vals.end());
+  std::vector<void*> vout(g.outv.begin(), g.outv.end());
+  switch (kind) {
+    case ASH_REQ_INSERT:
+      ASH_TRY(insert_impl(m, g.keys, off, m->n_values > 0 ? vin.data() : nullptr, g.idx, g.mask, st));
+      break;
+    case ASH_REQ_FIND:
+      ASH_TRY(ash_find(m, g.keys, off, g.idx, g.mask, gather && m->n_values > 0 ? vout.data() : nullptr, st));
+      break;
+    case ASH_REQ_ERASE:
+      ASH_TRY(ash_erase(m, g.keys, off, g.mask, st));
+      break;
+    default:
+      return ASH_E_INVALID;
+  }
+  off = 0;
+  for (Req* q : run) {  // scatter the per-position results back
+    const ash_request_t& r = q->r;
+    if (r.out_idx && kind != ASH_REQ_ERASE)
+      ASH_HIP(hipMemcpyAsync(r.out_idx, g.idx + off, (size_t)r.n * 4, hipMemcpyDeviceToDevice, st));
+    if (r.out_mask) ASH_HIP(hipMemcpyAsync(r.out_mask, g.mask + off, (size_t)r.n, hipMemcpyDeviceToDevice, st));
+    if (kind == ASH_REQ_FIND && !q->out_values.empty())
+      for (int j = 0; j < m->n_values; ++j) {  // hits only: a find leaves the rows of misses untouched
+        const uint8_t* src = g.outv[j] + off * m->row_bytes[j];
+        ASH_HIP(ash::launch_copy_masked_rows(g.mask + off, src, q->out_values[j], (uint64_t)r.n, m->row_bytes[j],
+                                        copy_unit(m->row_bytes[j], src, q->out_values[j]), st));
+      }
+    off += r.n;
+  }
+  return ASH_OK;
+}
+
+// Free heap slots the next insert batch may assume: c minus the host's bound
+// on t (exact after any readback).
+int64_t insert_room(const ash_server* s) { return s->map->c - s->map->live_ub; }
+
+// Takes the longest run at the queue head that may share a device batch
+// (called with the queue lock held; only the worker pops the queue).
+std::vector<Req*> take_run(ash_server* s) {
+  std::vector<Req*> run;
+  Req* head = s->queue.front();
+  s->queue.pop_front();
+  run.push_back(head);
+  if (!s->cfg.fuse || head->r.n > s->cfg.max_batch) return run;
+  const int kind = head->r.kind;
+  int64_t total = head->r.n;
+  int64_t room = INT64_MAX;
+  if (kind == ASH_REQ_INSERT) {
+    room = insert_room(s);
+    if (total > room) return run;  // runs alone: it fails or succeeds exactly as on its own
+  }
+  while (!s->queue.empty() && (int)run.size() < s->cfg.max_fused) {
+    Req* q = s->queue.front();
+    if (q->r.kind != kind || total + q->r.n > s->cfg.max_batch || total + q->r.n > room) break;
+    total += q->r.n;
+    run.push_back(q);
+    s->queue.pop_front();
+  }
+  return run;
+}
+
+void worker_loop(ash_server* s) {
+  (void)hipSetDevice(s->device);
+  while (true) {
+    std::vector<Req*> run;
+    int stage = -1;
+    hipEvent_t ev = nullptr;
+    bool refresh = false;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv_queue.wait(lk, [&] { return s->stop || !s->queue.empty(); });
+      if (s->queue.empty()) return;  // stop requested and nothing left
+      const Req* head = s->queue.front();
+      refresh = s->cfg.fuse && head->r.kind == ASH_REQ_INSERT && head->r.n <= s->cfg.max_batch &&
+                head->r.n > insert_room(s);
+    }
+    if (refresh) {  // the bound on t is too loose for the head insert: read t back
+      Meta h;
+      (void)read_meta(s->map, &h, s->stream);
+    }
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      // a free stage and event: wait for the completion thread to retire a batch
+      s->cv_done.wait(lk, [&] { return !s->free_stages.empty() && !s->free_events.empty(); });
+      run = take_run(s);
+      stage = s->free_stages.back();
+      s->free_stages.pop_back();
+      ev = s->free_events.back();
+      s->free_events.pop_back();
+    }
+    ash_status_t rc = run.size() == 1 ? run_one(s, run[0]) : run_fused(s, run, s->stages[stage]);
+    if (hipEventRecord(ev, s->stream) != hipSuccess && rc == ASH_OK) rc = ASH_E_DEVICE;
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      for (Req* q : run) q->status = rc;
+      Batch b;
+      b.reqs = run;
+      b.done = ev;
+      b.stage = stage;
+      s->flight.push_back(b);
+      s->batches += 1;
+      s->fused_requests += (int64_t)run.size();
+    }
+    s->cv_flight.notify_one();
+  }
+}
+
+void completer_loop(ash_server* s) {
+  (void)hipSetDevice(s->device);
+  while (true) {
+    Batch b;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv_flight.wait(lk, [&] { return !s->flight.empty() || s->worker_done; });
+      if (s->flight.empty()) return;
+      b = s->flight.front();
+    }
+    const hipError_t e = hipEventSynchronize(b.done);
+    const double t = now_s(s);
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->flight.pop_front();
+      for (Req* q : b.reqs) {
+        if (e != hipSuccess && q->status == ASH_OK) q->status = ASH_E_DEVICE;
+        q->done = t;
+        q->finished = true;
+      }
+      s->free_stages.push_back(b.stage);
+      s->free_events.push_back(b.done);
+    }
+    s->cv_done.notify_all();
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+ash_status_t ash_server_create(ash_map_t map, const ash_server_config_t* cfg, ash_server_t* out) {
+  if (!map || !out) return ASH_E_INVALID;
+  if (map->flags & ASH_F_AUTOGROW) return ASH_E_UNSUPPORTED;  // admission needs a fixed capacity
+  ash_server_config_t c = {256, 1 << 22, 4, 1};
+  if (cfg) c = *cfg;
+  if (c.max_fused < 1 || c.max_batch < 1 || c.max_batch > (1ll << 30) || c.in_flight < 1 || c.in_flight > 64)
+    return ASH_E_INVALID;
+  std::unique_ptr<ash_server> s(new ash_server);
+  s->map = map;
+  s->cfg = c;
+  if (hipGetDevice(&s->device) != hipSuccess) return ASH_E_DEVICE;
+  if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) return ASH_E_DEVICE;
+  s->stages.resize(c.in_flight);
+  for (int i = 0; i < c.in_flight; ++i) {
+    ash_status_t rc = c.fuse ? stage_alloc(s.get(), s->stages[i]) : ASH_OK;
+    if (rc != ASH_OK) {
+      for (Stage& g : s->stages) stage_free(g);
+      (void)hipStreamDestroy(s->stream);
+      return rc;
+    }
+    s->free_stages.push_back(i);
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return ASH_E_DEVICE;
+    s->free_events.push_back(e);
+  }
+  // size the map's scratch for a full fused batch once, on the server stream
+  if (ensure_scratch(map, c.fuse ? c.max_batch : 1, s->stream) != ASH_OK ||
+      hipStreamSynchronize(s->stream) != hipSuccess)
+    return ASH_E_NOMEM;
+  s->t0 = Clock::now();
+  ash_server* raw = s.release();
+  raw->worker = std::thread(worker_loop, raw);
+  raw->completer = std::thread(completer_loop, raw);
+  *out = raw;
+  return ASH_OK;
+}
+
+ash_status_t ash_server_submit(ash_server_t s, const ash_request_t* req, int64_t* out_ticket) {
+  if (!s || !req || !out_ticket) return ASH_E_INVALID;
+  ash_map* m = s->map;
+  const ash_request_t& r = *req;
+  if (r.kind < ASH_REQ_FIND || r.kind > ASH_REQ_ERASE || r.n < 0 || (r.n > 0 && !r.keys)) return ASH_E_INVALID;
+  if (r.kind == ASH_REQ_INSERT && m->n_values > 0 && r.n > 0 && !r.values) return ASH_E_INVALID;
+  std::unique_ptr<Req> q(new Req);
+  q->r = r;
+  if (r.kind == ASH_REQ_INSERT && m->n_values > 0 && r.values) q->values.assign(r.values, r.values + m->n_values);
+  if (r.kind == ASH_REQ_FIND && r.out_values) q->out_values.assign(r.out_values, r.out_values + m->n_values);
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) return ASH_E_INVALID;
+    q->arrival = now_s(s);
+    *out_ticket = (int64_t)s->reqs.size();
+    s->queue.push_back(q.get());
+    s->reqs.push_back(std::move(q));
+  }
+  s->cv_queue.notify_one();
+  return ASH_OK;
+}
+
+ash_status_t ash_server_wait(ash_server_t s, int64_t ticket, double* out_latency_s) {
+  if (!s) return ASH_E_INVALID;
+  std::unique_lock<std::mutex> lk(s->mu);
+  if (ticket < 0 || ticket >= (int64_t)s->reqs.size()) return ASH_E_INVALID;
+  Req* q = s->reqs[ticket].get();
+  s->cv_done.wait(lk, [&] { return q->finished; });
+  if (out_latency_s) *out_latency_s = q->done - q->arrival;
+  return q->status;
+}
+
+ash_status_t ash_server_replay(ash_server_t s, const ash_request_t* reqs, int64_t n, const double* arrival_s,
+                               double* out_latency_s, int32_t* out_status, double* out_span_s) {
+  if (!s || n < 0 || (n > 0 && (!reqs || !arrival_s))) return ASH_E_INVALID;
+  const double base = now_s(s);
+  std::vector<int64_t> tickets(n);
+  for (int64_t i = 0; i < n; ++i) {
+    const double due = base + arrival_s[i];
+    double t = now_s(s);
+    while (t < due) {  // submit at the scheduled arrival time
+      if (due - t > 200e-6) std::this_thread::sleep_for(std::chrono::duration<double>(due - t - 100e-6));
+      t = now_s(s);
+    }
+    ASH_TRY(ash_server_submit(s, &reqs[i], &tickets[i]));
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->reqs[tickets[i]]->arrival = due;  // latency counts from the scheduled arrival
+  }
+  double last = base;
+  for (int64_t i = 0; i < n; ++i) {
+    double lat = 0.0;
+    const ash_status_t st = ash_server_wait(s, tickets[i], &lat);
+    if (out_latency_s) out_latency_s[i] = lat;
+    if (out_status) out_status[i] = st;
+    std::lock_guard<std::mutex> lk(s->mu);
+    last = std::max(last, s->reqs[tickets[i]]->done);
+  }
+  if (out_span_s) *out_span_s = last - base;
+  return ASH_OK;
+}
+
+ash_status_t ash_server_stats(ash_server_t s, int64_t* out_batches, int64_t* out_requests) {
+  if (!s) return ASH_E_INVALID;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (out_batches) *out_batches = s->batches;
+  if (out_requests) *out_requests = s->fused_requests;
+  return ASH_OK;
+}
+
+ash_status_t ash_server_destroy(ash_server_t s) {
+  if (!s) return ASH_E_INVALID;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv_queue.notify_all();
+  s->worker.join();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->worker_done = true;
+  }
+  s->cv_flight.notify_all();
+  s->completer.join();
+  (void)hipStreamSynchronize(s->stream);
+  for (Stage& g : s->stages) stage_free(g);
+  for (hipEvent_t e : s->free_events) (void)hipEventDestroy(e);
+  (void)hipStreamDestroy(s->stream);
+  delete s;
+  return ASH_OK;
+}
+
+}  // extern "C"

@@ -269,3 +269,82 @@ def batched(ops, fused=True):
         r["find_mask"] = r["find_mask"].bool()
     return results
 
+
+class Server:
+    """Served map: continuous batching of insert / find / erase requests on a
+    device-resident map (see ash_server_* in include/ash.h).  The map must not
+    be used directly while it is served."""
+
+    FIND, INSERT, ERASE = 0, 1, 2
+
+    def __init__(self, hashmap, max_fused=256, max_batch=1 << 22, in_flight=4, fuse=True):
+        self._lib = L.load()
+        self.map = hashmap
+        cfg = L.AshServerConfig(max_fused, max_batch, in_flight, 1 if fuse else 0)
+        self._s = ctypes.c_void_p()
+        L.check(self._lib.ash_server_create(hashmap._m, ctypes.byref(cfg), ctypes.byref(self._s)),
+                "ash_server_create")
+        self._keep = {}
+
+    def request(self, kind, keys, values=(), out_idx=None, out_mask=None, out_values=None):
+        """Builds an ash_request_t over device tensors (kept alive by the caller)."""
+        m = self.map
+        keys = _keys(keys, m.key_dim, m.device)
+        vin = (ctypes.c_void_p * max(len(values), 1))(*[v.data_ptr() for v in values])
+        vout = None
+        if out_values is not None:
+            vout = (ctypes.c_void_p * max(len(out_values), 1))(*[o.data_ptr() for o in out_values])
+        r = L.AshRequest(kind, keys.data_ptr(), keys.shape[0],
+                         ctypes.cast(vin, ctypes.c_void_p) if values else None,
+                         out_idx.data_ptr() if out_idx is not None else None,
+                         out_mask.data_ptr() if out_mask is not None else None,
+                         ctypes.cast(vout, ctypes.c_void_p) if vout is not None else None)
+        return r, (keys, vin, vout)
+
+    def submit(self, kind, keys, values=(), out_idx=None, out_mask=None, out_values=None):
+        r, keep = self.request(kind, keys, values, out_idx, out_mask, out_values)
+        # the server's stream does not wait on torch's: the tensors must be ready
+        torch.cuda.current_stream(self.map.device).synchronize()
+        t = ctypes.c_int64()
+        L.check(self._lib.ash_server_submit(self._s, ctypes.byref(r), ctypes.byref(t)), "ash_server_submit")
+        self._keep[t.value] = keep
+        return t.value
+
+    def wait(self, ticket):
+        """(status, latency in seconds) of a submitted request."""
+        lat = ctypes.c_double()
+        st = self._lib.ash_server_wait(self._s, int(ticket), ctypes.byref(lat))
+        self._keep.pop(ticket, None)
+        return st, lat.value
+
+    def replay(self, requests, arrivals_s):
+        """Submits ctypes requests at their arrival times; returns
+        (latencies s, statuses, span s)."""
+        import numpy as np
+        n = len(requests)
+        arr = (L.AshRequest * max(n, 1))(*requests)
+        at = np.ascontiguousarray(arrivals_s, dtype=np.float64)
+        lat = np.zeros(n, np.float64)
+        sts = np.zeros(n, np.int32)
+        span = ctypes.c_double()
+        torch.cuda.current_stream(self.map.device).synchronize()
+        L.check(self._lib.ash_server_replay(self._s, arr, n, at.ctypes.data, lat.ctypes.data, sts.ctypes.data,
+                                            ctypes.byref(span)), "ash_server_replay")
+        return lat, sts, span.value
+
+    def stats(self):
+        b, r = ctypes.c_int64(), ctypes.c_int64()
+        L.check(self._lib.ash_server_stats(self._s, ctypes.byref(b), ctypes.byref(r)), "ash_server_stats")
+        return dict(batches=b.value, requests=r.value)
+
+    def close(self):
+        if self._s is not None and self._s.value:
+            L.check(self._lib.ash_server_destroy(self._s), "ash_server_destroy")
+            self._s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+

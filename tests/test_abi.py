@@ -68,3 +68,18 @@ def test_status_strings_and_host_side_errors(lib):
     assert n.value == 0
     assert L.ash_insert(None, None, 0, None, None, None, None) == _lib.ASH_E_INVALID
     assert L.ash_destroy(None) == _lib.ASH_E_INVALID
+
+
+def test_server_and_batched_reject_bad_arguments_on_the_host(lib):
+    """Argument checks that return before any HIP call (no device needed)."""
+    from paper_2110_00511_amd import _lib
+    L = _lib.load()
+    out = ctypes.c_void_p()
+    assert L.ash_server_create(None, None, ctypes.byref(out)) == _lib.ASH_E_INVALID
+    t = ctypes.c_int64()
+    req = _lib.AshRequest(0, None, 0, None, None, None, None)
+    assert L.ash_server_submit(None, ctypes.byref(req), ctypes.byref(t)) == _lib.ASH_E_INVALID
+    assert L.ash_server_wait(None, 0, None) == _lib.ASH_E_INVALID
+    assert L.ash_server_stats(None, None, None) == _lib.ASH_E_INVALID
+    assert L.ash_server_destroy(None) == _lib.ASH_E_INVALID
+    assert L.ash_server_replay(None, None, 0, None, None, None, None) == _lib.ASH_E_INVALID

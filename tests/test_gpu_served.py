@@ -1,0 +1,123 @@
+"""Served map: a request stream through the continuous-batching server must
+give every request the results it gets when the requests run one after
+another -- checked against the oracle replaying the stream serially, with
+requests fused in the mix (all arriving at once, or spread out) and with one
+request per device batch."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import OracleMap  # noqa: E402
+from tests.test_gpu_parity import bits, dev, host  # noqa: E402
+
+FIND, INSERT, ERASE = 0, 1, 2
+
+
+@pytest.fixture(scope="module")
+def ash():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2110_00511_amd as ash_mod
+    return ash_mod
+
+
+def make_stream(rng, n_req, side, lo=16, hi=4096, channels=4):
+    reqs = []
+    kinds = rng.choice(3, size=n_req, p=[0.6, 0.3, 0.1])
+    for k in kinds:
+        m = int(np.exp(rng.uniform(np.log(lo), np.log(hi))))
+        keys = rng.integers(0, side, size=(m, 3), dtype=np.int32)
+        vals = rng.standard_normal((m, channels)).astype(np.float32) if k == INSERT else None
+        reqs.append((int(k), keys, vals))
+    return reqs
+
+
+def run_served(ash, capacity, preload, reqs, arrivals, channels=4, **cfg):
+    m = ash.HashMap(capacity, 3, [(torch.float32, channels)])
+    pk, pv = preload
+    m.insert(dev(pk), [dev(pv)])
+    torch.cuda.synchronize()
+    srv = ash.Server(m, **cfg)
+    outs, built, keep = [], [], []
+    for kind, keys, vals in reqs:
+        n = len(keys)
+        o = dict(idx=torch.full((n,), -7, dtype=torch.int32, device="cuda"),
+                 mask=torch.full((n,), 7, dtype=torch.uint8, device="cuda"),
+                 vals=[torch.zeros((n, channels), dtype=torch.float32, device="cuda")] if kind == FIND else None)
+        kd = dev(keys)
+        vd = [dev(vals)] if vals is not None else []
+        r, k = srv.request(kind, kd, vd, out_idx=o["idx"] if kind != ERASE else None, out_mask=o["mask"],
+                           out_values=o["vals"])
+        built.append(r)
+        keep.append((kd, vd, k, o))
+        outs.append(o)
+    lat, sts, span = srv.replay(built, arrivals)
+    stats = srv.stats()
+    srv.close()
+    torch.cuda.synchronize()
+    return m, outs, lat, sts, stats
+
+
+def check_against_oracle(capacity, preload, reqs, m, outs, channels=4):
+    o = OracleMap(capacity, 3, [(np.float32, channels)])
+    pk, pv = preload
+    o.insert(pk, [pv])
+    written = set(o.active_indices().tolist())
+    for (kind, keys, vals), out in zip(reqs, outs):
+        if kind == INSERT:
+            st, oi, om = o.insert(keys, [vals])
+            written.update(oi[om == 1].tolist())
+            assert np.array_equal(host(out["mask"]), om)
+            assert np.array_equal(host(out["idx"]), oi)
+        elif kind == FIND:
+            st, oi, om, (ov,) = o.find(keys, gather=True, fill=0)
+            assert np.array_equal(host(out["mask"]), om)
+            assert np.array_equal(host(out["idx"]), oi)
+            assert np.array_equal(bits(host(out["vals"][0])), bits(ov))
+        else:
+            st, om = o.erase(keys)
+            assert np.array_equal(host(out["mask"]), om)
+    assert m.size() == o.size
+    assert np.array_equal(host(m.heap_buffer()), o.heap())
+    act = host(m.active_indices())
+    assert np.array_equal(act, o.active_indices())
+    assert np.array_equal(host(m.key_buffer())[act], o.key_buffer()[act])
+
+
+@pytest.mark.parametrize("mode", ["burst", "spread", "unfused"])
+def test_served_results_equal_serial_replay(ash, mode):
+    rng = np.random.default_rng(70)
+    side, capacity = 40, 60_000
+    pre = rng.choice(side ** 3, size=20_000, replace=False)
+    pk = np.stack([pre // (side * side), (pre // side) % side, pre % side], axis=1).astype(np.int32)
+    pv = rng.standard_normal((len(pk), 4)).astype(np.float32)
+    reqs = make_stream(rng, 300, side)
+    if mode == "burst":
+        arrivals = np.zeros(len(reqs))  # everything waits: maximal fusion
+    else:
+        arrivals = np.cumsum(rng.exponential(50e-6, size=len(reqs)))
+    cfg = dict(fuse=mode != "unfused", max_fused=64, max_batch=1 << 16, in_flight=3)
+    m, outs, lat, sts, stats = run_served(ash, capacity, (pk, pv), reqs, arrivals, **cfg)
+    assert np.all(sts == 0) and np.all(lat >= 0)
+    check_against_oracle(capacity, (pk, pv), reqs, m, outs)
+    if mode == "burst":
+        assert stats["batches"] < len(reqs)  # requests were fused
+    if mode == "unfused":
+        assert stats["batches"] == len(reqs)
+
+
+def test_served_tight_capacity_matches_serial(ash):
+    """Inserts that overflow fail on their own, exactly as in serial order,
+    even when the server would fuse them."""
+    rng = np.random.default_rng(71)
+    side, capacity = 30, 12_000
+    pre = rng.choice(side ** 3, size=9_000, replace=False)
+    pk = np.stack([pre // (side * side), (pre // side) % side, pre % side], axis=1).astype(np.int32)
+    pv = rng.standard_normal((len(pk), 4)).astype(np.float32)
+    reqs = make_stream(rng, 200, side, lo=64, hi=3000)
+    m, outs, lat, sts, stats = run_served(ash, capacity, (pk, pv), reqs, np.zeros(len(reqs)), fuse=True,
+                                          max_fused=32, max_batch=1 << 15, in_flight=2)
+    check_against_oracle(capacity, (pk, pv), reqs, m, outs)
