@@ -11,7 +11,9 @@ Per-kernel durations come from HIP events the library records around each
 launch on the launch stream (ash_profile_enable) during the timed steps; the
 dominant kernel's roofline counts algorithmic DRAM bytes with the per-access
 costs measured on MI355X (a random read moves a 128-byte line, a 64-bit CAS
-64 bytes, a small store 32 bytes), as stated in the design doc.
+64 bytes, a small store 32 bytes).  `traffic` is the HBM bytes per launch of
+that kernel measured with rocprofv3 counters on the same sources and workload
+(null otherwise).
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 3] [--rho 0.5] [--channels 8]
 """
@@ -35,6 +37,33 @@ READ_LINE = 128   # a random read fills one 128-byte L2 line
 CAS64 = 64        # a device-scope 64-bit CAS is done at the memory side
 ATOM32 = 32       # a 32-bit atomic
 STORE = 32        # a small random store writes a 32-byte sector
+
+# HBM bytes per launch at the default workload, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE runs scaled by what they read for a 256 MiB copy (fetch x1.9998,
+# write x1.0000).  They hold for the kernel sources with these SHA-256 digests
+# only: traffic is reported as null for any other sources or workload.
+MEASURED_TRAFFIC = {
+    "claim": 2.4241e9,
+    "commit": 0.9237e9,
+    "find": 1.4429e9,
+    "erase_mark": 0.8949e9,
+    "erase_commit": 0.1803e9,
+}
+MEASURED_SOURCES = {
+    "ash_kernels.hip": "6be69b754e335cb200bfa0f0065d715fa413fd7f4ea3b2262887441ff0b39200",
+    "ash_device.hpp": "53549ea800af68db75124fd6d26ff907d385dba589f4b3d66c7f13438aa221df",
+}
+
+
+def traffic_applies(args):
+    """True when the kernels and the workload are the ones the counters were taken on."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2110_00511_amd", "csrc")
+    for name, digest in MEASURED_SOURCES.items():
+        with open(os.path.join(csrc, name), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != digest:
+                return False
+    return (args.rho, args.channels, args.probe_group, args.bucket_width, args.max_load) == (0.5, 8, 4, 4, 0.5)
 
 
 def kernel_bytes(name, n, u, d, e, channels):
@@ -170,6 +199,8 @@ def main():
     dom_units = {"claim": n, "commit": n, "find": nf, "erase_mark": ne, "erase_commit": ne}[dom]
     dom_bytes = kernel_bytes(dom, dom_units, u, dup, e, args.channels)
     achieved = dom_bytes / (per_kernel[dom]["avg_ms"] * 1e-3) / 1e9
+    alg_bytes = dom_bytes
+    traffic = round(MEASURED_TRAFFIC[dom] / 1e9, 4) if dom in MEASURED_TRAFFIC and traffic_applies(args) else None
 
     cpu = None
     if args.cpu_sample > 0:
@@ -206,7 +237,8 @@ def main():
                    "measured": {"new_key_fraction": round(u, 4), "find_hit_rate": round(eta, 4),
                                 "erase_win_fraction": round(e, 4)}},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "traffic_unit": "GB per launch", "algorithmic_GB_per_launch": round(alg_bytes / 1e9, 4),
                      "access_bytes": {"read_line": READ_LINE, "cas64": CAS64, "atomic32": ATOM32, "store": STORE}},
         "kernels": per_kernel,
         "cpu_baseline": cpu,

@@ -9,12 +9,16 @@
 // after another.  Finds never fuse with inserts or erases, and batches run in
 // order on one stream, so every request sees the map that serial execution
 // would show it.  An insert joins a fused batch only while the positions of
-// the batch fit the free heap slots c - t (t bounded on the host, read back
-// from the device when the bound is too loose): a fused insert can therefore
-// never overflow where the separate requests would not.  A completion thread
-// waits on each batch's event and stamps the completion time of its
-// requests.  Up to `in_flight` batches are queued on the device while the
-// worker forms the next one, so arrivals overlap with device work.
+// the batch fit the free heap slots c - t: a fused insert can therefore never
+// overflow where the separate requests would not.  A completion thread waits
+// on each batch's event and stamps the completion time of its requests.  Up
+// to `in_flight` batches are queued on the device while the worker forms the
+// next one, so arrivals overlap with device work.
+//
+// The host never waits for the device to learn t: every batch ends with an
+// asynchronous copy of the map's counters into pinned memory, and the bound
+// the worker uses is the last retired batch's exact counters plus what the
+// batches still in flight may add (their insert positions).
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -59,6 +63,8 @@ struct Batch {
   std::vector<Req*> reqs;
   hipEvent_t done = nullptr;
   int stage = -1;
+  int64_t add_live = 0;  // upper bound on what the batch adds to t
+  int64_t add_used = 0;  // ... and to the occupied slots
 };
 
 }  // namespace
@@ -76,6 +82,9 @@ struct ash_server {
   std::vector<Stage> stages;
   std::vector<int> free_stages;
   std::vector<hipEvent_t> free_events;
+  Meta* snaps = nullptr;  // pinned: the map's counters after each stage's batch
+  int64_t conf_t = 0, conf_used = 0;    // exact, after the last retired batch
+  int64_t add_live = 0, add_used = 0;  // summed over the batches in flight
   bool stop = false;
   bool worker_done = false;
   int device = 0;
@@ -179,9 +188,12 @@ ash_status_t run_fused(ash_server* s, const std::vector<Req*>& run, Stage& g) {
   return ASH_OK;
 }
 
-// Free heap slots the next insert batch may assume: c minus the host's bound
-// on t (exact after any readback).
-int64_t insert_room(const ash_server* s) { return s->map->c - s->map->live_ub; }
+// Bounds on t and on the occupied slots once every launched batch has run.
+int64_t live_bound(const ash_server* s) { return std::min(s->map->c, s->conf_t + s->add_live); }
+int64_t used_bound(const ash_server* s) { return s->conf_used + s->add_used; }
+
+// Free heap slots the next insert batch may assume.
+int64_t insert_room(const ash_server* s) { return s->map->c - live_bound(s); }
 
 // Takes the longest run at the queue head that may share a device batch
 // (called with the queue lock held; only the worker pops the queue).
@@ -214,21 +226,11 @@ void worker_loop(ash_server* s) {
     std::vector<Req*> run;
     int stage = -1;
     hipEvent_t ev = nullptr;
-    bool refresh = false;
+    ash_map* m = s->map;
     {
       std::unique_lock<std::mutex> lk(s->mu);
       s->cv_queue.wait(lk, [&] { return s->stop || !s->queue.empty(); });
       if (s->queue.empty()) return;  // stop requested and nothing left
-      const Req* head = s->queue.front();
-      refresh = s->cfg.fuse && head->r.kind == ASH_REQ_INSERT && head->r.n <= s->cfg.max_batch &&
-                head->r.n > insert_room(s);
-    }
-    if (refresh) {  // the bound on t is too loose for the head insert: read t back
-      Meta h;
-      (void)read_meta(s->map, &h, s->stream);
-    }
-    {
-      std::unique_lock<std::mutex> lk(s->mu);
       // a free stage and event: wait for the completion thread to retire a batch
       s->cv_done.wait(lk, [&] { return !s->free_stages.empty() && !s->free_events.empty(); });
       run = take_run(s);
@@ -236,8 +238,18 @@ void worker_loop(ash_server* s) {
       s->free_stages.pop_back();
       ev = s->free_events.back();
       s->free_events.pop_back();
+      // the map's own checks (capacity count, tombstone cleaning) start from
+      // the server's bounds instead of the ones it accumulated alone
+      m->live_ub = live_bound(s);
+      m->used_ub = used_bound(s);
     }
+    const int kind = run[0]->r.kind;
+    int64_t total = 0;
+    for (Req* q : run) total += q->r.n;
     ash_status_t rc = run.size() == 1 ? run_one(s, run[0]) : run_fused(s, run, s->stages[stage]);
+    if (hipMemcpyAsync(&s->snaps[stage], m->meta, sizeof(Meta), hipMemcpyDeviceToHost, s->stream) != hipSuccess &&
+        rc == ASH_OK)
+      rc = ASH_E_DEVICE;
     if (hipEventRecord(ev, s->stream) != hipSuccess && rc == ASH_OK) rc = ASH_E_DEVICE;
     {
       std::lock_guard<std::mutex> lk(s->mu);
@@ -246,6 +258,12 @@ void worker_loop(ash_server* s) {
       b.reqs = run;
       b.done = ev;
       b.stage = stage;
+      if (kind == ASH_REQ_INSERT) {
+        b.add_live = total;
+        b.add_used = std::min(total, m->c);
+      }
+      s->add_live += b.add_live;
+      s->add_used += b.add_used;
       s->flight.push_back(b);
       s->batches += 1;
       s->fused_requests += (int64_t)run.size();
@@ -269,6 +287,12 @@ void completer_loop(ash_server* s) {
     {
       std::lock_guard<std::mutex> lk(s->mu);
       s->flight.pop_front();
+      s->add_live -= b.add_live;
+      s->add_used -= b.add_used;
+      if (e == hipSuccess) {  // the batch's counter copy has landed
+        s->conf_t = s->snaps[b.stage].t;
+        s->conf_used = s->snaps[b.stage].used;
+      }
       for (Req* q : b.reqs) {
         if (e != hipSuccess && q->status == ASH_OK) q->status = ASH_E_DEVICE;
         q->done = t;
@@ -279,6 +303,41 @@ void completer_loop(ash_server* s) {
     }
     s->cv_done.notify_all();
   }
+}
+
+// Device resources of a server: stream, staging, events, counter snapshots,
+// the map's scratch sized for a full batch, and the exact starting counters.
+ash_status_t setup(ash_server* s) {
+  const ash_server_config_t& c = s->cfg;
+  if (hipGetDevice(&s->device) != hipSuccess) return ASH_E_DEVICE;
+  if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) return ASH_E_DEVICE;
+  s->stages.resize(c.in_flight);
+  for (int i = 0; i < c.in_flight; ++i) {
+    if (c.fuse) ASH_TRY(stage_alloc(s, s->stages[i]));
+    s->free_stages.push_back(i);
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return ASH_E_DEVICE;
+    s->free_events.push_back(e);
+  }
+  if (hipHostMalloc((void**)&s->snaps, sizeof(Meta) * c.in_flight, hipHostMallocDefault) != hipSuccess) {
+    s->snaps = nullptr;
+    return ASH_E_NOMEM;
+  }
+  Meta h;
+  ASH_TRY(ensure_scratch(s->map, c.fuse ? c.max_batch : 1, s->stream));
+  ASH_TRY(read_meta(s->map, &h, s->stream));
+  s->conf_t = h.t;
+  s->conf_used = h.used;
+  return ASH_OK;
+}
+
+// Frees what setup() made (the threads are not running or have been joined).
+void release(ash_server* s) {
+  if (s->stream) (void)hipStreamSynchronize(s->stream);
+  for (Stage& g : s->stages) stage_free(g);
+  for (hipEvent_t e : s->free_events) (void)hipEventDestroy(e);
+  if (s->snaps) (void)hipHostFree(s->snaps);
+  if (s->stream) (void)hipStreamDestroy(s->stream);
 }
 
 }  // namespace
@@ -295,25 +354,11 @@ ash_status_t ash_server_create(ash_map_t map, const ash_server_config_t* cfg, as
   std::unique_ptr<ash_server> s(new ash_server);
   s->map = map;
   s->cfg = c;
-  if (hipGetDevice(&s->device) != hipSuccess) return ASH_E_DEVICE;
-  if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) return ASH_E_DEVICE;
-  s->stages.resize(c.in_flight);
-  for (int i = 0; i < c.in_flight; ++i) {
-    ash_status_t rc = c.fuse ? stage_alloc(s.get(), s->stages[i]) : ASH_OK;
-    if (rc != ASH_OK) {
-      for (Stage& g : s->stages) stage_free(g);
-      (void)hipStreamDestroy(s->stream);
-      return rc;
-    }
-    s->free_stages.push_back(i);
-    hipEvent_t e = nullptr;
-    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return ASH_E_DEVICE;
-    s->free_events.push_back(e);
+  ash_status_t rc = setup(s.get());
+  if (rc != ASH_OK) {
+    release(s.get());
+    return rc;
   }
-  // size the map's scratch for a full fused batch once, on the server stream
-  if (ensure_scratch(map, c.fuse ? c.max_batch : 1, s->stream) != ASH_OK ||
-      hipStreamSynchronize(s->stream) != hipSuccess)
-    return ASH_E_NOMEM;
   s->t0 = Clock::now();
   ash_server* raw = s.release();
   raw->worker = std::thread(worker_loop, raw);
@@ -405,10 +450,7 @@ ash_status_t ash_server_destroy(ash_server_t s) {
   }
   s->cv_flight.notify_all();
   s->completer.join();
-  (void)hipStreamSynchronize(s->stream);
-  for (Stage& g : s->stages) stage_free(g);
-  for (hipEvent_t e : s->free_events) (void)hipEventDestroy(e);
-  (void)hipStreamDestroy(s->stream);
+  release(s);
   delete s;
   return ASH_OK;
 }
