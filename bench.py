@@ -76,7 +76,8 @@ def kernel_bytes(name, n, u, d, e, channels):
     claim        : key 12 (stream) + slot window (line) + claim CAS for new keys
                    + one read of the first occurrence's key per in-batch duplicate
     commit       : idx 4 + mask 1 (stream) + per new key: k^B 12, heap 4,
-                   value read 4C and write 4C (streams)
+                   winner list 4
+    values       : per new key: winner list 4, heap 4, value read 4C and write 4C
     find         : key 12 + idx 4 + mask 1 (stream) + slot window (line)
     erase_mark   : key 12 (stream) + slot window (line) + owner election (64-bit atomic)
     erase_commit : mask 1 (stream) + per freed index: heap 4 + tombstone store
@@ -84,7 +85,9 @@ def kernel_bytes(name, n, u, d, e, channels):
     if name == "claim":
         return n * (12 + READ_LINE + u * CAS64 + d * READ_LINE)
     if name == "commit":
-        return n * (5 + u * (16 + 8 * channels))
+        return n * (5 + u * 20)
+    if name == "values":
+        return n * u * (8 + 8 * channels)
     if name == "find":
         return n * (17 + READ_LINE)
     if name == "erase_mark":
@@ -187,16 +190,56 @@ def main():
     ops = n + nf + ne
     value = ops / (ms_per_step * 1e-3) / 1e6
 
+    # Practical ceiling: a 1 GiB device-to-device copy (1 GiB read + 1 GiB
+    # written per copy), timed after the steps on torch's stream.
+    ca = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    cb = torch.empty_like(ca)
+    cb.copy_(ca)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(5):
+        cb.copy_(ca)
+    ev1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * (1 << 30) / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
+    del ca, cb
+
+    # Per-operation byte accountings of insert and find.  payload: the bytes
+    # the method must touch; survey granule: the survey formulas, each
+    # unavoidable random access counted as one DRAM granule g (g = 128 B, the
+    # line a random 16 B read fills here; they assume a separate k^B read per
+    # find hit, which this design does not make); design: the per-kernel
+    # algorithmic bytes of this implementation (kernel_bytes).
+    def avg_ms(name):
+        return kernels[name][1] / kernels[name][0] if name in kernels else 0.0
+    g = READ_LINE
+    C = args.channels
+    ins_ms = avg_ms("claim") + avg_ms("commit") + avg_ms("finalize") + avg_ms("sum_partials") + avg_ms("values")
+    find_ms = avg_ms("find")
+    accounting = {"granule_B": g, "copy_ceiling_GBps": round(copy_gbs, 1)}
+    ins_design = sum(kernel_bytes(k, n, u, dup, e, C) for k in ("claim", "commit", "values")) / n
+    for op, cnt, ms, pay, gran, des in (
+            ("insert", n, ins_ms, 25 + 12 * (1 - u) + u * (24 + 8 * C), 17 + 2 * g + u * (16 + 8 * C), ins_design),
+            ("find", nf, find_ms, 25 + 12 * eta, 17 + g * (1 + eta), kernel_bytes("find", 1, u, dup, e, C))):
+        rate = cnt / (ms * 1e-3)
+        accounting[op] = {"Mops": round(rate / 1e6, 1), "ms": round(ms, 4),
+                          "payload_B_per_op": round(pay, 1), "payload_GBps": round(rate * pay / 1e9, 1),
+                          "survey_granule_B_per_op": round(gran, 1),
+                          "survey_granule_GBps": round(rate * gran / 1e9, 1),
+                          "design_B_per_op": round(des, 1), "design_GBps": round(rate * des / 1e9, 1),
+                          "design_frac_of_peak": round(rate * des / 1e9 / HBM_PEAK_GBS, 4),
+                          "design_frac_of_copy": round(rate * des / 1e9 / copy_gbs, 4)}
+
     per_kernel = {}
     for name, (launches, total) in kernels.items():
         avg = total / launches
-        units = {"claim": n, "commit": n, "find": nf, "erase_mark": ne, "erase_commit": ne}.get(name)
+        units = {"claim": n, "commit": n, "values": n, "find": nf, "erase_mark": ne, "erase_commit": ne}.get(name)
         b = kernel_bytes(name, units, u, dup, e, args.channels) if units else None
         per_kernel[name] = {"launches_per_step": launches / args.steps, "avg_ms": round(avg, 4),
                             "GBps": round(b / (avg * 1e-3) / 1e9, 1) if b else None}
     dom = max((k for k in per_kernel if per_kernel[k]["GBps"] is not None),
               key=lambda k: kernels[k][1])
-    dom_units = {"claim": n, "commit": n, "find": nf, "erase_mark": ne, "erase_commit": ne}[dom]
+    dom_units = {"claim": n, "commit": n, "values": n, "find": nf, "erase_mark": ne, "erase_commit": ne}[dom]
     dom_bytes = kernel_bytes(dom, dom_units, u, dup, e, args.channels)
     achieved = dom_bytes / (per_kernel[dom]["avg_ms"] * 1e-3) / 1e9
     alg_bytes = dom_bytes
@@ -241,6 +284,7 @@ def main():
                      "traffic_unit": "GB per launch", "algorithmic_GB_per_launch": round(alg_bytes / 1e9, 4),
                      "access_bytes": {"read_line": READ_LINE, "cas64": CAS64, "atomic32": ATOM32, "store": STORE}},
         "kernels": per_kernel,
+        "accounting": accounting,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -246,14 +246,24 @@ ash_status_t insert_impl(ash_map* m, const int32_t* keys, int64_t n, const void*
     return ASH_OK;
   };
   auto commit = [&](int check, int silent, int32_t* oi, uint8_t* om) -> ash_status_t {
+    // Rows of 64 bytes or more move in a separate pass over the winners, whose
+    // positions go to aux (erase's scratch, idle during an insert); shorter
+    // rows are copied inside the commit.
+    uint32_t row_total = 0;
+    for (int j = 0; j < vs.n; ++j) row_total += vs.row_bytes[j];
+    uint32_t* wlist = row_total >= kSplitRowBytes ? reinterpret_cast<uint32_t*>(m->aux) : nullptr;
     ASH_HIP(timed(m, "commit", st, [&] {
       return ash::launch_commit(m->key_dim, m->ref(), keys, un, m->slot_of, m->lost, m->kB, m->heap,
-                                (uint32_t)m->c, vs, oi, om, m->meta, m->scan_status, check, st);
+                                (uint32_t)m->c, vs, oi, om, m->meta, m->scan_status, check, wlist, st);
     }));
     ASH_HIP(timed(m, "finalize", st, [&] {
       return ash::launch_finalize(m->meta, (uint32_t)m->c, ash::kFinalizeInsert, silent, check, m->scan_status,
                                   last_tile, st);
     }));
+    if (wlist)
+      ASH_HIP(timed(m, "values", st, [&] {
+        return ash::launch_scatter_values(vs, wlist, m->heap, m->meta, un, (uint32_t)m->c, st);
+      }));
     return ASH_OK;
   };
   // The capacity check needs the batch's count of new keys; when the host's

@@ -17,6 +17,11 @@ using ash::ValueSet;
 
 namespace ash_host {
 
+// Value bytes per row from which an insert copies rows in a pass of its own
+// after the commit instead of inside it (measured: 4 and 32 B rows copy
+// faster inside, 128 B rows 10-15% faster on their own).
+constexpr uint32_t kSplitRowBytes = 64;
+
 constexpr int64_t kMaxCount = (1ll << 31) - 3;  // positions and indices must fit PENDING(p)
 constexpr uint64_t kMaxSlots = (1ull << 32) - 128;
 

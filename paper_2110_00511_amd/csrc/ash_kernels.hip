@@ -370,13 +370,20 @@ __global__ __launch_bounds__(1024) void k_sum_partials(const uint32_t* __restric
 // Commit (insert / activate pass 2).  Winners are the candidates not marked
 // lost; they are ranked in batch order and take i = h[t + rank].  The lost
 // bytes read here are cleared again, so the array is all zero between calls.
-template <int KD>
+// Value rows are copied by the block right after the ranking (kInline), or
+// left to k_scatter_values: then each winner writes its position at its
+// global rank, wlist[prefix + rank] = p, and the rows move after the
+// finalize in a separate pass over the winners only.  The block copy is a
+// dependent chain per tile, which costs little for short rows; the separate
+// pass keeps many more loads in flight and wins for long rows.
+template <int KD, bool kInline>
 __device__ __forceinline__ void commit_tile(const TableRef& tb, const int32_t* __restrict__ keys, uint32_t n,
                                             uint32_t tile, const uint32_t* __restrict__ slot_of,
                                             uint8_t* __restrict__ lost, int32_t* __restrict__ kB,
                                             const int32_t* __restrict__ heap, uint32_t cap, const ValueSet& vs,
                                             int32_t* __restrict__ out_idx, uint8_t* __restrict__ out_mask,
-                                            Meta* meta, uint64_t* __restrict__ status, int check, TileLds& lds) {
+                                            Meta* meta, uint64_t* __restrict__ status, int check,
+                                            uint32_t* __restrict__ wlist, TileLds& lds) {
   constexpr int S = SlotWords<KD>::value;
   uint2* s_pairs = lds.pairs;
   const uint32_t t0 = meta->t;
@@ -424,7 +431,8 @@ __device__ __forceinline__ void commit_tile(const TableRef& tb, const int32_t* _
         kB[(size_t)i * KD + d] = k[d];
       }
       store_slot<S>(tb.words + (size_t)slot[r] * S, committed_slot<KD, S>(k, i));
-      s_pairs[rank[r]] = make_uint2(p, i);
+      if constexpr (kInline) s_pairs[rank[r]] = make_uint2(p, i);
+      else if (wlist) wlist[prefix + rank[r]] = p;
       if (out_idx) out_idx[p] = (int32_t)i;
       if (out_mask) out_mask[p] = 1;
     } else {
@@ -432,22 +440,57 @@ __device__ __forceinline__ void commit_tile(const TableRef& tb, const int32_t* _
       if (out_mask) out_mask[p] = 0;
     }
   }
-  if (vs.n > 0 && !__syncthreads_or(bad)) {
-    for (int j = 0; j < vs.n; ++j) copy_rows(vs, j, s_pairs, total);
+  if constexpr (kInline) {
+    if (vs.n > 0 && !__syncthreads_or(bad)) {
+      for (int j = 0; j < vs.n; ++j) copy_rows(vs, j, s_pairs, total);
+    }
   }
   __syncthreads();  // LDS is reused by the next tile of a persistent block
 }
 
-template <int KD>
+// Value rows of an insert's winners, after its finalize: the finalize left
+// the number of winners in meta->result and moved t past their indices, so
+// winner w (in batch order) went to i = h[t - total + w] from position
+// wlist[w].  dst row i = src row p, in units of V; threads past the winners
+// only read the two counters.
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_scatter_values(const uint32_t* __restrict__ wlist,
+                                                           const int32_t* __restrict__ heap, const Meta* meta,
+                                                           const uint8_t* __restrict__ src, uint8_t* __restrict__ dst,
+                                                           uint32_t row_bytes, uint32_t units_log2, uint32_t n,
+                                                           uint32_t cap) {
+  const uint32_t total = meta->result;
+  const uint32_t base = meta->t - total;
+  const uint32_t units = row_bytes / (uint32_t)sizeof(V);
+  const uint64_t items = (uint64_t)total * units;
+  for (uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x; e < items; e += (uint64_t)gridDim.x * kBlock) {
+    uint32_t w, c;
+    if (units_log2 != 0xFFu) {
+      w = (uint32_t)(e >> units_log2);
+      c = (uint32_t)e & (units - 1u);
+    } else {
+      w = (uint32_t)(e / units);
+      c = (uint32_t)(e - (uint64_t)w * units);
+    }
+    const uint32_t p = wlist[w];
+    const uint32_t i = (uint32_t)heap[base + w];
+    if (p >= n || i >= cap) continue;  // cannot happen: every winner listed itself
+    const V v = reinterpret_cast<const V*>(src + (size_t)p * row_bytes)[c];
+    reinterpret_cast<V*>(dst + (size_t)i * row_bytes)[c] = v;
+  }
+}
+
+template <int KD, bool kInline>
 __global__ __launch_bounds__(kBlock) void k_commit(TableRef tb, const int32_t* __restrict__ keys, uint32_t n,
                                                    const uint32_t* __restrict__ slot_of, uint8_t* __restrict__ lost,
                                                    int32_t* __restrict__ kB, const int32_t* __restrict__ heap,
                                                    uint32_t cap, ValueSet vs, int32_t* __restrict__ out_idx,
                                                    uint8_t* __restrict__ out_mask, Meta* meta,
-                                                   uint64_t* __restrict__ status, int check) {
+                                                   uint64_t* __restrict__ status, int check,
+                                                   uint32_t* __restrict__ wlist) {
   __shared__ TileLds lds;
-  commit_tile<KD>(tb, keys, n, blockIdx.x, slot_of, lost, kB, heap, cap, vs, out_idx, out_mask, meta, status, check,
-                  lds);
+  commit_tile<KD, kInline>(tb, keys, n, blockIdx.x, slot_of, lost, kB, heap, cap, vs, out_idx, out_mask, meta,
+                           status, check, wlist, lds);
 }
 
 // Moves the heap top and resets per-launch counters.  Runs after the
@@ -462,8 +505,10 @@ __device__ __forceinline__ void finalize_map(Meta* m, uint32_t cap, int mode, in
       const uint32_t total = (uint32_t)status[last_tile] & 0x7FFFFFFFu;
       m->t += total;
       m->used += total;
-    } else if (!silent) {
-      m->status |= m->fail ? kStatusTableFull : kStatusCapacity;
+      m->result = total;
+    } else {
+      m->result = 0;
+      if (!silent) m->status |= m->fail ? kStatusTableFull : kStatusCapacity;
     }
     m->claims = 0;
     m->fail = 0;
@@ -897,8 +942,8 @@ __global__ __launch_bounds__(kBlock) void k_batched(const BatchItem* __restrict_
   }
   for (uint32_t t = blockIdx.x; t < commit_tiles; t += gridDim.x) {
     const BatchItem& it = items[item_of<&BatchItem::commit0>(items, n_items, t)];
-    commit_tile<KD>(it.tb, it.ikeys, it.n_insert, t - it.commit0, it.slot_of, it.lost, it.kB, it.heap, it.cap,
-                    it.vin, it.iidx, it.imask, it.meta, it.status, it.check, lds);
+    commit_tile<KD, true>(it.tb, it.ikeys, it.n_insert, t - it.commit0, it.slot_of, it.lost, it.kB, it.heap, it.cap,
+                          it.vin, it.iidx, it.imask, it.meta, it.status, it.check, nullptr, lds);
   }
   grid.sync();
   for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < n_items; m += gridDim.x * blockDim.x) {
@@ -1127,21 +1172,60 @@ template <int KD>
 static hipError_t commit_k(const TableRef& tb, const int32_t* keys, uint32_t n, const uint32_t* slot_of,
                            uint8_t* lost, int32_t* kB, const int32_t* heap, uint32_t cap, const ValueSet& vs,
                            int32_t* out_idx, uint8_t* out_mask, Meta* meta, uint64_t* status, int check,
-                           hipStream_t st) {
-  hipLaunchKernelGGL((k_commit<KD>), dim3(cdiv(n, kScanTile)), dim3(kBlock), 0, st, tb, keys, n, slot_of, lost, kB,
-                     heap, cap, vs, out_idx, out_mask, meta, status, check);
+                           uint32_t* wlist, hipStream_t st) {
+  if (wlist)
+    hipLaunchKernelGGL((k_commit<KD, false>), dim3(cdiv(n, kScanTile)), dim3(kBlock), 0, st, tb, keys, n, slot_of,
+                       lost, kB, heap, cap, vs, out_idx, out_mask, meta, status, check, wlist);
+  else
+    hipLaunchKernelGGL((k_commit<KD, true>), dim3(cdiv(n, kScanTile)), dim3(kBlock), 0, st, tb, keys, n, slot_of,
+                       lost, kB, heap, cap, vs, out_idx, out_mask, meta, status, check, wlist);
   return hipGetLastError();
+}
+
+hipError_t launch_scatter_values(const ValueSet& vs, const uint32_t* wlist, const int32_t* heap, const Meta* meta,
+                                 uint32_t n, uint32_t cap, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  for (int j = 0; j < vs.n && e == hipSuccess; ++j) {
+    const uint64_t units = vs.row_bytes[j] / vs.vec[j];
+    // sized for every position winning; the kernel reads the actual count
+    const uint32_t grid =
+        (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(((uint64_t)n * units + kBlock - 1) / kBlock, 16384));
+    switch (vs.vec[j]) {
+      case 16:
+        hipLaunchKernelGGL(k_scatter_values<uint4>, dim3(grid), dim3(kBlock), 0, st, wlist, heap, meta, vs.src[j],
+                           vs.dst[j], vs.row_bytes[j], vs.units_log2[j], n, cap);
+        break;
+      case 8:
+        hipLaunchKernelGGL(k_scatter_values<uint2>, dim3(grid), dim3(kBlock), 0, st, wlist, heap, meta, vs.src[j],
+                           vs.dst[j], vs.row_bytes[j], vs.units_log2[j], n, cap);
+        break;
+      case 4:
+        hipLaunchKernelGGL(k_scatter_values<uint32_t>, dim3(grid), dim3(kBlock), 0, st, wlist, heap, meta, vs.src[j],
+                           vs.dst[j], vs.row_bytes[j], vs.units_log2[j], n, cap);
+        break;
+      case 2:
+        hipLaunchKernelGGL(k_scatter_values<uint16_t>, dim3(grid), dim3(kBlock), 0, st, wlist, heap, meta, vs.src[j],
+                           vs.dst[j], vs.row_bytes[j], vs.units_log2[j], n, cap);
+        break;
+      default:
+        hipLaunchKernelGGL(k_scatter_values<uint8_t>, dim3(grid), dim3(kBlock), 0, st, wlist, heap, meta, vs.src[j],
+                           vs.dst[j], vs.row_bytes[j], vs.units_log2[j], n, cap);
+        break;
+    }
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 hipError_t launch_commit(int kd, const TableRef& tb, const int32_t* keys, uint32_t n, const uint32_t* slot_of,
                          uint8_t* lost, int32_t* kB, const int32_t* heap, uint32_t cap, const ValueSet& vs,
                          int32_t* out_idx, uint8_t* out_mask, Meta* meta, uint64_t* status, int check,
-                         hipStream_t st) {
+                         uint32_t* wlist, hipStream_t st) {
   switch (kd) {
-    case 1: return commit_k<1>(tb, keys, n, slot_of, lost, kB, heap, cap, vs, out_idx, out_mask, meta, status, check, st);
-    case 2: return commit_k<2>(tb, keys, n, slot_of, lost, kB, heap, cap, vs, out_idx, out_mask, meta, status, check, st);
-    case 3: return commit_k<3>(tb, keys, n, slot_of, lost, kB, heap, cap, vs, out_idx, out_mask, meta, status, check, st);
-    case 4: return commit_k<4>(tb, keys, n, slot_of, lost, kB, heap, cap, vs, out_idx, out_mask, meta, status, check, st);
+    case 1: return commit_k<1>(tb, keys, n, slot_of, lost, kB, heap, cap, vs, out_idx, out_mask, meta, status, check, wlist, st);
+    case 2: return commit_k<2>(tb, keys, n, slot_of, lost, kB, heap, cap, vs, out_idx, out_mask, meta, status, check, wlist, st);
+    case 3: return commit_k<3>(tb, keys, n, slot_of, lost, kB, heap, cap, vs, out_idx, out_mask, meta, status, check, wlist, st);
+    case 4: return commit_k<4>(tb, keys, n, slot_of, lost, kB, heap, cap, vs, out_idx, out_mask, meta, status, check, wlist, st);
     default: return hipErrorInvalidValue;
   }
 }

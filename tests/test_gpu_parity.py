@@ -196,30 +196,35 @@ def test_edge_cases(ash):
     pair.check_state()
 
 
-def test_capacity_overflow_rolls_back(ash):
+@pytest.mark.parametrize("channels", [2, 32])  # rows copied inside the commit / in a pass of their own
+def test_capacity_overflow_rolls_back(ash, channels):
     rng = np.random.default_rng(9)
-    pair = Pair(ash, 1000, 3, [(np.float32, 2)])
+    pair = Pair(ash, 1000, 3, [(np.float32, channels)])
     k1 = rng.integers(0, 100, size=(900, 3), dtype=np.int32)
-    pair.insert(k1, [rng.standard_normal((900, 2)).astype(np.float32)])
-    before = host(pair.gpu.heap_buffer()).copy(), host(pair.gpu.key_buffer()).copy()
+    pair.insert(k1, [rng.standard_normal((900, channels)).astype(np.float32)])
+    before = (host(pair.gpu.heap_buffer()).copy(), host(pair.gpu.key_buffer()).copy(),
+              host(pair.gpu.value_buffer(0)).copy())
     k2 = rng.integers(100, 200, size=(300, 3), dtype=np.int32)
-    gi, gm = pair.gpu.insert(dev(k2), [dev(rng.standard_normal((300, 2)).astype(np.float32))])
-    st, oi, om = pair.orc.insert(k2, [np.zeros((300, 2), np.float32)])
+    gi, gm = pair.gpu.insert(dev(k2), [dev(rng.standard_normal((300, channels)).astype(np.float32))])
+    st, oi, om = pair.orc.insert(k2, [np.zeros((300, channels), np.float32)])
     assert st == ORACLE_E_CAPACITY
     assert np.all(host(gi) == -1) and not host(gm).any()
     assert pair.gpu.device_status() == 2  # ASH_E_CAPACITY, then cleared
     assert np.array_equal(host(pair.gpu.heap_buffer()), before[0])
+    # no value row moved, the free rows included
+    assert np.array_equal(bits(host(pair.gpu.value_buffer(0))), bits(before[2]))
     pair.check_state()
     pair.find(np.concatenate([k1, k2]))
 
 
-def test_autogrow(ash):
+@pytest.mark.parametrize("channels", [1, 32])  # rows copied inside the commit / in a pass of their own
+def test_autogrow(ash, channels):
     rng = np.random.default_rng(13)
-    pair = Pair(ash, 100, 3, [(np.float32, 1)], autogrow=True)
+    pair = Pair(ash, 100, 3, [(np.float32, channels)], autogrow=True)
     pair.autogrow = True
     for step in range(6):
         k = rng.integers(0, 40, size=(700, 3), dtype=np.int32)
-        pair.insert(k, [rng.standard_normal((700, 1)).astype(np.float32)])
+        pair.insert(k, [rng.standard_normal((700, channels)).astype(np.float32)])
         pair.erase(k[:100])
     pair.check_state()
     assert pair.gpu.capacity == pair.orc.capacity
