@@ -63,7 +63,8 @@ def traffic_applies(args):
         with open(os.path.join(csrc, name), "rb") as f:
             if hashlib.sha256(f.read()).hexdigest() != digest:
                 return False
-    return (args.rho, args.channels, args.probe_group, args.bucket_width, args.max_load) == (0.5, 8, 4, 4, 0.5)
+    return ((args.rho, args.channels, args.probe_group, args.bucket_width, args.max_load) == (0.5, 8, 4, 4, 0.5)
+            and not args.lds_dedup and not args.sorted_keys)
 
 
 def kernel_bytes(name, n, u, d, e, channels):
@@ -107,6 +108,9 @@ def main():
     ap.add_argument("--probe-group", type=int, default=4)
     ap.add_argument("--bucket-width", type=int, default=4)
     ap.add_argument("--max-load", type=float, default=0.5)
+    ap.add_argument("--lds-dedup", action="store_true", help="drop block-local duplicates in LDS before probing")
+    ap.add_argument("--sorted-keys", action="store_true",
+                    help="insert the keys sorted (equal keys adjacent) instead of in random order")
     ap.add_argument("--cpu-sample", type=int, default=2_000_000,
                     help="positions of the workload the oracle runs for cpu_baseline (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -135,6 +139,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     d = synth.plain_large(rho=args.rho, channels=args.channels)
+    if args.sorted_keys:
+        order = np.lexsort(d["keys"].T[::-1])
+        d["keys"], d["values"] = d["keys"][order], d["values"][order]
     n, nf, ne = len(d["keys"]), len(d["find_keys"]), len(d["erase_keys"])
     keys = torch.from_numpy(d["keys"]).cuda()
     vals = torch.from_numpy(d["values"]).cuda()
@@ -146,7 +153,7 @@ def main():
     fmask = torch.empty(nf, dtype=torch.uint8, device="cuda")
     emask = torch.empty(ne, dtype=torch.uint8, device="cuda")
     m = ash.HashMap(d["capacity"], 3, [(torch.float32, args.channels)], probe_group=args.probe_group,
-                    bucket_width=args.bucket_width, max_load=args.max_load)
+                    bucket_width=args.bucket_width, max_load=args.max_load, lds_dedup=args.lds_dedup)
     lib = L.load()
     stream = torch.cuda.current_stream()
     sp = ctypes.c_void_p(stream.cuda_stream)
@@ -276,7 +283,8 @@ def main():
         "config": {"workload": f"plain map at scale: insert {n} int32x3 keys (distinct ratio {args.rho}, "
                                f"f32x{args.channels} values), find {nf} (50% hits), erase {ne}",
                    "capacity": d["capacity"], "ops_per_step": ops, "probe_group": args.probe_group,
-                   "bucket_width": args.bucket_width, "max_load": args.max_load,
+                   "bucket_width": args.bucket_width, "max_load": args.max_load, "lds_dedup": args.lds_dedup,
+                   "sorted_keys": args.sorted_keys,
                    "measured": {"new_key_fraction": round(u, 4), "find_hit_rate": round(eta, 4),
                                 "erase_win_fraction": round(e, 4)}},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,

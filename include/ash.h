@@ -82,6 +82,10 @@ typedef struct {
 } ash_allocator_t;
 
 #define ASH_F_AUTOGROW 1u
+/* Claims first drop duplicates within each block of 256 positions in LDS, so
+ * only one copy of a key per block probes the table.  Results are the same;
+ * it pays off when equal keys sit close together in a batch. */
+#define ASH_F_LDS_DEDUP 2u
 
 /* Table tuning.  bucket_width W (1..64, power of two) aligns a key's home slot;
  * probe_group g is the number of wavefront lanes that probe one key together:

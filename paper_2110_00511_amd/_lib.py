@@ -20,6 +20,7 @@ ASH_E_NOMEM = 3
 ASH_E_DEVICE = 4
 ASH_E_UNSUPPORTED = 5
 ASH_F_AUTOGROW = 1
+ASH_F_LDS_DEDUP = 2
 
 ASH_U8, ASH_I32, ASH_F32, ASH_I64, ASH_F64, ASH_F16, ASH_BF16 = range(7)
 

@@ -349,6 +349,7 @@ ash_status_t ash_create(int64_t capacity, int32_t key_dim, int32_t n_values, con
   if (G != 1 && G != 4 && G != 8 && G != 16 && G != 32 && G != 64) return ASH_E_INVALID;
   if (G == 1 && W != 2 && W != 4 && W != 8) return ASH_E_INVALID;  // one lane reads a bucket
   if (!(lf >= 0.1f && lf <= 0.9f)) return ASH_E_INVALID;
+  if (flags & ~(ASH_F_AUTOGROW | ASH_F_LDS_DEDUP)) return ASH_E_INVALID;
   hipStream_t st = (hipStream_t)stream;
 
   ash_map* m = new ash_map;
@@ -627,6 +628,7 @@ ash_status_t ash_voxelize(const float* points, int64_t n, float voxel, int32_t* 
     tb.nbuckets = nslots / kW;
     tb.window = kG == 1 ? kW : kG;
     tb.max_windows = nslots / tb.window + 1;
+    tb.dedup = kVoxelDedup;
     Meta h;
     std::memset(&h, 0, sizeof(h));
     h.epoch = 1;

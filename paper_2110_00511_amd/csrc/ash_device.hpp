@@ -65,6 +65,7 @@ struct TableRef {
   uint32_t bucket_width;  // W: a key's home slot is a multiple of W
   uint32_t window;        // slots examined per probe step (G, or W when G == 1)
   uint32_t max_windows;   // probe steps that cover the whole table
+  uint32_t dedup;         // 1: claims drop block-local duplicates in LDS first
 };
 
 // ---------------------------------------------------------------------------

@@ -22,6 +22,10 @@ namespace ash_host {
 // faster inside, 128 B rows 10-15% faster on their own).
 constexpr uint32_t kSplitRowBytes = 64;
 
+// Voxelization drops duplicate voxels within each block of points in LDS
+// before probing (ASH_F_LDS_DEDUP for its internal set).
+constexpr uint32_t kVoxelDedup = 1;
+
 constexpr int64_t kMaxCount = (1ll << 31) - 3;  // positions and indices must fit PENDING(p)
 constexpr uint64_t kMaxSlots = (1ull << 32) - 128;
 
@@ -150,6 +154,7 @@ struct ash_map {
     r.nbuckets = nslots / (uint32_t)W;
     r.window = (uint32_t)(G == 1 ? W : G);
     r.max_windows = nslots / r.window + 1;
+    r.dedup = (flags & ASH_F_LDS_DEDUP) ? 1u : 0u;
     return r;
   }
 };

@@ -86,8 +86,22 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 // Block-shared scratch of the tile functions.  Every kernel declares one and
 // passes it down, so a persistent kernel that dispatches several probe shapes
 // holds a single copy.
+// Block-local duplicate removal of a claim: the block's keys, an LDS hash
+// table of 2 * kBlock entries (owner thread, lowest thread with that key) and
+// each thread's representative and claim result.
+struct DedupLds {
+  int32_t keys[kBlock][4];
+  uint32_t own[2 * kBlock];
+  uint32_t low[2 * kBlock];
+  uint32_t rep[kBlock];
+  uint32_t out[kBlock];
+};
+
 struct TileLds {
-  uint2 pairs[kScanTile];          // (source row, destination row) of value copies
+  union {
+    uint2 pairs[kScanTile];  // (source row, destination row) of value copies
+    DedupLds dd;
+  };
   uint64_t scan[kBlock / 64 + 1];  // block_rank_rows
   uint32_t count[16];              // per-wavefront partial sums (up to 1024 threads)
   uint32_t prefix;                 // look-back result
@@ -223,6 +237,47 @@ __device__ __forceinline__ uint64_t leader_bcast64(uint64_t x) {
 // point and mark candidates with kCandidate (the table has < 2^31 slots).
 constexpr uint32_t kCandidate = 0x80000000u;
 
+// Block-local duplicate removal (one thread per position of the block's 256
+// positions): every valid key enters an LDS hash table, where the first
+// thread to reach an entry owns it and every thread with that key lowers the
+// entry's minimum.  dd.rep[t] is then the lowest thread holding t's key, or
+// kNoSlot when position t has no valid key; dd.keys holds the keys.  Only
+// representatives probe the table: a later copy of a key in the same block
+// cannot be the batch's first occurrence.
+template <int KD, typename Src>
+__device__ __forceinline__ void block_dedup(const Src& src, uint32_t n, uint32_t tile_base, DedupLds& dd) {
+  constexpr uint32_t kEntries = 2 * kBlock;
+  const uint32_t t = threadIdx.x;
+  const uint32_t p = tile_base + t;
+  int32_t k[KD];
+  bool valid = false;
+  if (p < n) valid = src.load(p, k);
+#pragma unroll
+  for (int d = 0; d < KD; ++d) dd.keys[t][d] = valid ? k[d] : 0;
+  dd.own[t] = kNoSlot;
+  dd.own[t + kBlock] = kNoSlot;
+  dd.low[t] = kNoSlot;
+  dd.low[t + kBlock] = kNoSlot;
+  __syncthreads();
+  uint32_t j = 0;
+  if (valid) {
+    j = (uint32_t)(key_hash<KD>(k) >> 20) & (kEntries - 1);
+    while (true) {  // at most kBlock owners in kEntries entries: ends at a free or matching entry
+      const uint32_t o = atomicCAS(&dd.own[j], kNoSlot, t);
+      if (o == kNoSlot) break;
+      bool eq = true;
+#pragma unroll
+      for (int d = 0; d < KD; ++d) eq = eq && dd.keys[o][d] == k[d];
+      if (eq) break;
+      j = (j + 1) & (kEntries - 1);
+    }
+    atomicMin(&dd.low[j], t);
+  }
+  __syncthreads();
+  dd.rep[t] = valid ? dd.low[j] : kNoSlot;
+  __syncthreads();
+}
+
 template <int KD, int G, int WL, typename Src, bool kVoxel>
 __device__ __forceinline__ void claim_tile(const TableRef& tb, const Src& src, uint32_t n, uint32_t tile,
                                            uint32_t rounds, uint32_t* __restrict__ slot_of,
@@ -233,16 +288,27 @@ __device__ __forceinline__ void claim_tile(const TableRef& tb, const Src& src, u
   constexpr uint32_t kGroups = kBlock / G;
   const uint32_t sub = G == 1 ? 0u : (threadIdx.x & (G - 1));
   const uint32_t grp = threadIdx.x / G;
-  const uint32_t tile_base = tile * kGroups * rounds;
+  const uint32_t tile_base = tile * kGroups * rounds;  // 256 positions per tile
+  const bool dedup = tb.dedup != 0;
+  if (dedup) block_dedup<KD>(src, n, tile_base, lds.dd);
   uint32_t claimed = 0;
   uint32_t unresolved = 0;
   for (uint32_t r = 0; r < rounds; ++r) {
     const uint32_t p = tile_base + r * kGroups + grp;
     if (p >= n) break;
     int32_t k[KD];
-    const bool valid = src.load(p, k);
+    bool valid, copy = false;
+    if (dedup) {  // keys staged in LDS; block-local copies skip the probe
+      const uint32_t rp = lds.dd.rep[p - tile_base];
+      valid = rp != kNoSlot;
+      copy = valid && rp != p - tile_base;
+#pragma unroll
+      for (int d = 0; d < KD; ++d) k[d] = lds.dd.keys[p - tile_base][d];
+    } else {
+      valid = src.load(p, k);
+    }
     uint32_t out = kNoSlot;
-    if (valid) {
+    if (valid && !copy) {
       const uint64_t h = key_hash<KD>(k);
       const uint32_t tag = pending_tag<KD>(k, h);
       const uint64_t desired = ((uint64_t)(kPending + p) << 32) | tag;
@@ -314,7 +380,19 @@ __device__ __forceinline__ void claim_tile(const TableRef& tb, const Src& src, u
       }
       if (!resolved) unresolved = 1;
     }
-    if (sub == 0) slot_of[p] = out;
+    if (sub == 0) {
+      if (kVoxel && dedup) lds.dd.out[p - tile_base] = out;
+      if (!(kVoxel && copy)) slot_of[p] = out;
+    }
+  }
+  if (kVoxel && dedup) {  // a voxel's later points in the block resolve through their representative's slot
+    __syncthreads();
+    const uint32_t t = threadIdx.x;
+    const uint32_t rp = lds.dd.rep[t];
+    if (tile_base + t < n && rp != kNoSlot && rp != t) {
+      const uint32_t o = lds.dd.out[rp];
+      slot_of[tile_base + t] = o == kNoSlot ? kNoSlot : (o & ~kCandidate);
+    }
   }
   // Per-block count of new keys (a single shared counter would serialize
   // one atomic per wavefront); k_sum_partials adds them up when needed.

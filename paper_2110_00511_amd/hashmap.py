@@ -41,7 +41,7 @@ class HashMap:
     bucket_width W, probe_group g (lanes per key), max_load, autogrow."""
 
     def __init__(self, capacity, key_dim=3, value_specs=(), device="cuda", bucket_width=4, probe_group=4,
-                 max_load=0.5, autogrow=False):
+                 max_load=0.5, autogrow=False, lds_dedup=False):
         self._lib = L.load()
         self.device = torch.device(device)
         if self.device.index is None:
@@ -52,7 +52,8 @@ class HashMap:
         dts = (ctypes.c_int * max(n, 1))(*[_DTYPES[dt] for dt, _ in self.value_specs])
         els = (ctypes.c_int64 * max(n, 1))(*[e for _, e in self.value_specs])
         self._alloc = L.TorchAllocator(self.device)
-        tun = L.AshTuning(bucket_width, probe_group, max_load, L.ASH_F_AUTOGROW if autogrow else 0)
+        flags = (L.ASH_F_AUTOGROW if autogrow else 0) | (L.ASH_F_LDS_DEDUP if lds_dedup else 0)
+        tun = L.AshTuning(bucket_width, probe_group, max_load, flags)
         self._m = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             L.check(self._lib.ash_create(int(capacity), self.key_dim, n, ctypes.cast(dts, ctypes.c_void_p),

@@ -66,8 +66,9 @@ def test_batched_maps_match_oracle(ash, fused):
     rng = np.random.default_rng(40)
     sizes = [1000, 3000, 20000, 70000, 5000, 150000, 40000, 2000]
     maps, oracles, cases = [], [], []
-    for u, (g, w, lf) in zip(sizes, SHAPES):
-        maps.append(ash.HashMap(2 * u, 3, [(torch.float32, 8)], probe_group=g, bucket_width=w, max_load=lf))
+    for i, (u, (g, w, lf)) in enumerate(zip(sizes, SHAPES)):
+        maps.append(ash.HashMap(2 * u, 3, [(torch.float32, 8)], probe_group=g, bucket_width=w, max_load=lf,
+                                lds_dedup=i % 2 == 1))
         oracles.append(OracleMap(2 * u, 3, [(np.float32, 8)]))
         cases.append(make_case(rng, u))
     run_round(ash, maps, oracles, cases, fused)

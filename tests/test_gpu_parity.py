@@ -135,12 +135,32 @@ def test_plain_small_sequence(ash):
     plain_small_sequence(pair, d)
 
 
-@pytest.mark.parametrize("g,w,lf", [(1, 2, 0.5), (1, 4, 0.7), (1, 8, 0.9), (4, 4, 0.5), (8, 8, 0.7),
-                                     (16, 4, 0.85), (32, 32, 0.5), (64, 16, 0.9)])
-def test_tuning_grid_same_results(ash, g, w, lf):
+@pytest.mark.parametrize("g,w,lf,dd", [(1, 2, 0.5, 0), (1, 4, 0.7, 0), (1, 8, 0.9, 0), (4, 4, 0.5, 0),
+                                        (8, 8, 0.7, 0), (16, 4, 0.85, 0), (32, 32, 0.5, 0), (64, 16, 0.9, 0),
+                                        (4, 4, 0.5, 1), (1, 4, 0.7, 1), (16, 4, 0.85, 1)])
+def test_tuning_grid_same_results(ash, g, w, lf, dd):
     d = synth.plain_small(seed=11)
-    pair = Pair(ash, d["capacity"], 3, [(np.float32, 1)], probe_group=g, bucket_width=w, max_load=lf)
+    pair = Pair(ash, d["capacity"], 3, [(np.float32, 1)], probe_group=g, bucket_width=w, max_load=lf,
+                lds_dedup=bool(dd))
     plain_small_sequence(pair, d)
+
+
+@pytest.mark.parametrize("g", [1, 4, 64])
+def test_lds_dedup_with_local_duplicates(ash, g):
+    """Batches where equal keys sit close together (runs of a key, sorted
+    keys): most duplicates are removed inside a block, some straddle block
+    boundaries, and keys already in the map recur."""
+    rng = np.random.default_rng(19)
+    base = rng.integers(-50, 50, size=(20_000, 3), dtype=np.int32)
+    runs = np.repeat(base, rng.integers(1, 12, size=len(base)), axis=0)  # runs of equal keys
+    srt = runs[np.lexsort(runs.T[::-1])]  # sorted: long runs per key
+    pair = Pair(ash, 150_000, 3, [(np.float32, 8)], probe_group=g, bucket_width=4, lds_dedup=True)
+    for batch in (runs, srt[: len(srt) // 2], srt):
+        pair.insert(batch, [rng.standard_normal((len(batch), 8)).astype(np.float32)])
+        pair.find(np.concatenate([batch[::7], rng.integers(60, 90, size=(5000, 3), dtype=np.int32)]))
+    pair.erase(srt[::3])
+    pair.insert(runs, [rng.standard_normal((len(runs), 8)).astype(np.float32)])
+    pair.check_state()
 
 
 @pytest.mark.parametrize("key_dim", [1, 2, 3, 4])
@@ -295,6 +315,15 @@ def check_voxelize(ash, pts, voxel):
 @pytest.mark.parametrize("voxel", [0.005, 0.01, 0.02, 0.05])
 def test_voxelize_surface_points(ash, voxel):
     check_voxelize(ash, synth.points(n=300_000, seed=31), voxel)
+
+
+@pytest.mark.parametrize("voxel", [0.01, 0.1])
+def test_voxelize_ordered_points(ash, voxel):
+    """Points in scan order (sorted along x), so many points of a voxel fall
+    in the same block: the block-local duplicate removal resolves them through
+    their representative's slot."""
+    pts = synth.points(n=200_000, seed=32)
+    check_voxelize(ash, pts[np.argsort(pts[:, 0], kind="stable")], voxel)
 
 
 def test_voxelize_boundaries_and_rejects(ash):
