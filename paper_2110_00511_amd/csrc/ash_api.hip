@@ -585,7 +585,7 @@ ash_status_t ash_device_status(ash_map_t m, void* stream) {
   const uint32_t zero = 0;
   ASH_HIP(hipMemcpyAsync(&m->meta->status, &zero, sizeof(zero), hipMemcpyHostToDevice, st));
   ASH_HIP(hipStreamSynchronize(st));
-  return (h.status & ash::kStatusScanStall) ? ASH_E_DEVICE : ASH_E_CAPACITY;
+  return (h.status & (ash::kStatusScanStall | ash::kStatusGridStall)) ? ASH_E_DEVICE : ASH_E_CAPACITY;
 }
 
 ash_status_t ash_voxelize(const float* points, int64_t n, float voxel, int32_t* out_point_voxel,
@@ -653,6 +653,52 @@ ash_status_t ash_voxelize(const float* points, int64_t n, float voxel, int32_t* 
   mem.put(lost, st);
   mem.put(status, st);
   return rc;
+}
+
+// Blocks of the persistent batched kernel that the device runs all at once,
+// found once per (key_dim, device): an empty launch at the occupancy the
+// runtime reports, lowered one block per CU at a time until every block
+// passes the kernel's arrival check.  A failed try costs the barrier's
+// bounded wait and touches no map.
+std::mutex g_resident_mu;
+std::map<std::pair<int, int>, uint32_t> g_resident;
+
+ash_status_t batched_resident(int kd, DevMem& mem, hipStream_t st, uint32_t* out) {
+  int dev = 0, cus = 0, per_cu = 0;
+  ASH_HIP(hipGetDevice(&dev));
+  {
+    std::lock_guard<std::mutex> lock(g_resident_mu);
+    auto it = g_resident.find({kd, dev});
+    if (it != g_resident.end()) {
+      *out = it->second;
+      return ASH_OK;
+    }
+  }
+  ASH_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  ASH_HIP(ash::batched_occupancy(kd, &per_cu));
+  if (cus < 1 || per_cu < 1) return ASH_E_DEVICE;
+  ash::GridSync* gs = (ash::GridSync*)mem.get(sizeof(ash::GridSync), st);
+  if (!gs) return ASH_E_NOMEM;
+  uint32_t found = 0;
+  ash_status_t rc = ASH_OK;
+  for (int b = per_cu; b >= 1 && found == 0 && rc == ASH_OK; --b) {
+    ash::GridSync h;
+    if (ash::launch_fill_u32((uint32_t*)gs, 0u, sizeof(ash::GridSync) / 4, st) != hipSuccess ||
+        ash::launch_batched(kd, nullptr, 0, 0, 0, 0, 0, gs, (uint32_t)(cus * b), st) != hipSuccess ||
+        hipMemcpyAsync(&h, gs, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      rc = ASH_E_DEVICE;
+    } else if (h.abort == 0u) {  // every block passed every barrier
+      found = (uint32_t)(cus * b);
+    }
+  }
+  mem.put(gs, st);
+  if (rc != ASH_OK) return rc;
+  if (found == 0) return ASH_E_DEVICE;
+  std::lock_guard<std::mutex> lock(g_resident_mu);
+  g_resident[{kd, dev}] = found;
+  *out = found;
+  return ASH_OK;
 }
 
 ash_status_t ash_batched(const ash_batch_op_t* ops, int32_t n_ops, int32_t fused, void* stream) {
@@ -729,13 +775,21 @@ ash_status_t ash_batched(const ash_batch_op_t* ops, int32_t n_ops, int32_t fused
     if (m->n_values > 0 && op.find_values) it.vout = make_values(m, nullptr, op.find_values, false);
   }
   ash_map* m0 = ops[0].map;
-  const size_t bytes = sizeof(ash::BatchItem) * (size_t)n_ops;
-  ash::BatchItem* dev = (ash::BatchItem*)m0->mem.get(bytes, st);
+  uint32_t resident = 0;
+  ASH_TRY(batched_resident(kd, m0->mem, st, &resident));
+  const size_t item_bytes = (sizeof(ash::BatchItem) * (size_t)n_ops + 255) / 256 * 256;
+  const size_t bytes = item_bytes + sizeof(ash::GridSync);
+  uint8_t* dev = (uint8_t*)m0->mem.get(bytes, st);
   if (!dev) return ASH_E_NOMEM;
+  ash::BatchItem* dev_items = (ash::BatchItem*)dev;
+  ash::GridSync* gs = (ash::GridSync*)(dev + item_bytes);
   ash_status_t rc = ASH_OK;
-  if (hipMemcpyAsync(dev, items.data(), bytes, hipMemcpyHostToDevice, st) != hipSuccess ||
+  if (hipMemcpyAsync(dev_items, items.data(), sizeof(ash::BatchItem) * (size_t)n_ops, hipMemcpyHostToDevice, st) !=
+          hipSuccess ||
+      ash::launch_fill_u32((uint32_t*)gs, 0u, sizeof(ash::GridSync) / 4, st) != hipSuccess ||
       timed(m0, "batched", st, [&] {
-        return ash::launch_batched(kd, dev, n_ops, claim_tiles, commit_tiles, find_tiles, any_check, st);
+        return ash::launch_batched(kd, dev_items, n_ops, claim_tiles, commit_tiles, find_tiles, any_check, gs,
+                                   resident, st);
       }) != hipSuccess)
     rc = ASH_E_DEVICE;
   m0->mem.put(dev, st);

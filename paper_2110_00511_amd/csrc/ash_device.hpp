@@ -34,6 +34,8 @@ constexpr int kScanTile = kBlock * kScanItems;
 constexpr uint32_t kStatusCapacity = 1u;    // not enough free buffer indices
 constexpr uint32_t kStatusTableFull = 2u;   // probe found no empty slot
 constexpr uint32_t kStatusScanStall = 4u;   // a look-back wait hit its bound
+constexpr uint32_t kStatusGridStall = 8u;   // a persistent launch's blocks did not all run at once
+constexpr uint32_t kBarrierSpinLimit = 1u << 20;  // polls of a grid barrier before a launch gives up
 constexpr uint32_t kLookbackSpinLimit = 1u << 24;
 
 template <int KD>
@@ -56,6 +58,14 @@ struct Meta {
   uint32_t result;  // total of the last scanning kernel
   uint32_t fail;    // groups whose probe found no empty slot (claim/rebuild)
   uint32_t pad[7];
+};
+
+// Barrier words of a persistent launch (zeroed before the launch): blocks
+// that have passed a barrier so far, and the abort flag.
+struct GridSync {
+  uint32_t count;
+  uint32_t abort;
+  uint32_t pad[14];
 };
 
 struct TableRef {

@@ -26,7 +26,6 @@
 // table: positions displaced during the claim are marked in a per-position
 // `lost` byte array by whoever displaced them, using the value returned by
 // the atomic.
-#include <hip/hip_cooperative_groups.h>
 
 #include "ash_device.hpp"
 #include "ash_launch.hpp"
@@ -1000,36 +999,76 @@ __device__ __forceinline__ void batched_find(const BatchItem& it, uint32_t tile,
   }
 }
 
+// Grid barrier of the persistent launch, with a bounded wait.  Every block
+// adds itself to gs->count (a release: its earlier writes become visible at
+// agent scope) and waits until all gridDim.x blocks have passed the same
+// number of barriers (then an acquire).  The first barrier is an arrival
+// check before any table is touched: if the blocks of the launch cannot all
+// be resident at once, the resident ones stop waiting after the bound, raise
+// gs->abort and mark every map, and blocks that start later see the flag and
+// leave, so the launch always ends.  Returns false when the launch aborts.
+__device__ __forceinline__ bool grid_barrier(GridSync* gs, uint32_t& passed, const BatchItem* __restrict__ items, int32_t n_items,
+                             uint32_t* s_ok) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    bool ok = __hip_atomic_load(&gs->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u;
+    passed += 1;
+    if (ok) {
+      __hip_atomic_fetch_add(&gs->count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      const uint32_t target = passed * gridDim.x;
+      uint32_t spins = 0;
+      while (true) {
+        if (__hip_atomic_load(&gs->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
+        if (__hip_atomic_load(&gs->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u || ++spins == kBarrierSpinLimit) {
+          ok = false;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    if (!ok && __hip_atomic_exchange(&gs->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+      for (int32_t m = 0; m < n_items; ++m)  // the first block to give up marks every map
+        __hip_atomic_fetch_or(&items[m].meta->status, kStatusGridStall, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    *s_ok = ok ? 1u : 0u;
+  }
+  __syncthreads();
+  return *s_ok != 0u;
+}
+
 template <int KD>
 __global__ __launch_bounds__(kBlock) void k_batched(const BatchItem* __restrict__ items, int32_t n_items,
                                                     uint32_t claim_tiles, uint32_t commit_tiles, uint32_t find_tiles,
-                                                    int32_t any_check) {
+                                                    int32_t any_check, GridSync* gs) {
   __shared__ TileLds lds;
-  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  __shared__ uint32_t s_ok;
+  uint32_t passed = 0;
+  if (!grid_barrier(gs, passed, items, n_items, &s_ok)) return;  // all blocks resident, or none works
   for (uint32_t t = blockIdx.x; t < claim_tiles; t += gridDim.x) {
     const BatchItem& it = items[item_of<&BatchItem::claim0>(items, n_items, t)];
     batched_claim<KD>(it, t - it.claim0, lds);
   }
-  grid.sync();
+  if (!grid_barrier(gs, passed, items, n_items, &s_ok)) return;
   if (any_check) {
     for (int m = blockIdx.x; m < n_items; m += gridDim.x) {
       const BatchItem& it = items[m];
       if (it.check && it.n_insert) sum_partials_block<kBlock>(it.partial, (it.n_insert + 255u) / 256u, it.meta, lds);
     }
-    grid.sync();
+    if (!grid_barrier(gs, passed, items, n_items, &s_ok)) return;
   }
   for (uint32_t t = blockIdx.x; t < commit_tiles; t += gridDim.x) {
     const BatchItem& it = items[item_of<&BatchItem::commit0>(items, n_items, t)];
     commit_tile<KD, true>(it.tb, it.ikeys, it.n_insert, t - it.commit0, it.slot_of, it.lost, it.kB, it.heap, it.cap,
                           it.vin, it.iidx, it.imask, it.meta, it.status, it.check, nullptr, lds);
   }
-  grid.sync();
+  if (!grid_barrier(gs, passed, items, n_items, &s_ok)) return;
   for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < n_items; m += gridDim.x * blockDim.x) {
     const BatchItem& it = items[m];
     if (it.n_insert)
       finalize_map(it.meta, it.cap, kFinalizeInsert, 0, it.check, it.status, (it.n_insert + kScanTile - 1) / kScanTile - 1);
   }
-  grid.sync();
+  if (!grid_barrier(gs, passed, items, n_items, &s_ok)) return;
   for (uint32_t t = blockIdx.x; t < find_tiles; t += gridDim.x) {
     const BatchItem& it = items[item_of<&BatchItem::find0>(items, n_items, t)];
     batched_find<KD>(it, t - it.find0, lds);
@@ -1383,30 +1422,32 @@ hipError_t launch_voxel_resolve(const TableRef& tb, uint32_t n, const uint32_t* 
 
 template <int KD>
 static hipError_t batched_k(const BatchItem* items, int32_t n_items, uint32_t claim_tiles, uint32_t commit_tiles,
-                            uint32_t find_tiles, int32_t any_check, hipStream_t st) {
-  int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return e;
-  int cus = 0, per_cu = 0;
-  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e != hipSuccess) return e;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batched<KD>, kBlock, 0);
-  if (e != hipSuccess) return e;
-  if (per_cu < 1) return hipErrorInvalidConfiguration;
+                            uint32_t find_tiles, int32_t any_check, GridSync* gs, uint32_t resident, hipStream_t st) {
+  // n_items == 0 launches all `resident` blocks with no work: a residency probe
   const uint32_t work = std::max(std::max(claim_tiles, commit_tiles), std::max(find_tiles, (uint32_t)n_items));
-  const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>((uint32_t)(cus * per_cu), work));
-  void* args[] = {(void*)&items, (void*)&n_items, (void*)&claim_tiles, (void*)&commit_tiles, (void*)&find_tiles,
-                  (void*)&any_check};
-  return hipLaunchCooperativeKernel((const void*)k_batched<KD>, dim3(grid), dim3(kBlock), args, 0, st);
+  const uint32_t grid = n_items == 0 ? resident : std::max<uint32_t>(1, std::min<uint32_t>(resident, work));
+  hipLaunchKernelGGL((k_batched<KD>), dim3(grid), dim3(kBlock), 0, st, items, n_items, claim_tiles, commit_tiles,
+                     find_tiles, any_check, gs);
+  return hipGetLastError();
+}
+
+hipError_t batched_occupancy(int kd, int* per_cu) {
+  switch (kd) {
+    case 1: return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batched<1>, kBlock, 0);
+    case 2: return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batched<2>, kBlock, 0);
+    case 3: return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batched<3>, kBlock, 0);
+    case 4: return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batched<4>, kBlock, 0);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_batched(int kd, const BatchItem* items, int32_t n_items, uint32_t claim_tiles, uint32_t commit_tiles,
-                          uint32_t find_tiles, int32_t any_check, hipStream_t st) {
+                          uint32_t find_tiles, int32_t any_check, GridSync* gs, uint32_t resident, hipStream_t st) {
   switch (kd) {
-    case 1: return batched_k<1>(items, n_items, claim_tiles, commit_tiles, find_tiles, any_check, st);
-    case 2: return batched_k<2>(items, n_items, claim_tiles, commit_tiles, find_tiles, any_check, st);
-    case 3: return batched_k<3>(items, n_items, claim_tiles, commit_tiles, find_tiles, any_check, st);
-    case 4: return batched_k<4>(items, n_items, claim_tiles, commit_tiles, find_tiles, any_check, st);
+    case 1: return batched_k<1>(items, n_items, claim_tiles, commit_tiles, find_tiles, any_check, gs, resident, st);
+    case 2: return batched_k<2>(items, n_items, claim_tiles, commit_tiles, find_tiles, any_check, gs, resident, st);
+    case 3: return batched_k<3>(items, n_items, claim_tiles, commit_tiles, find_tiles, any_check, gs, resident, st);
+    case 4: return batched_k<4>(items, n_items, claim_tiles, commit_tiles, find_tiles, any_check, gs, resident, st);
     default: return hipErrorInvalidValue;
   }
 }

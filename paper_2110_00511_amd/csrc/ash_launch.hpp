@@ -56,8 +56,12 @@ hipError_t launch_voxel_resolve(const TableRef& tb, uint32_t n, const uint32_t* 
 
 // Inserts then finds of n_items independent maps in one cooperative launch.
 // items is a device array; tile counts are the flat totals of each phase.
+// One persistent launch over the items (grid = min(resident, work) blocks).
+// gs must be zero; resident is a block count the device runs all at once
+// (batched_occupancy gives the upper bound per CU).
 hipError_t launch_batched(int kd, const BatchItem* items, int32_t n_items, uint32_t claim_tiles, uint32_t commit_tiles,
-                          uint32_t find_tiles, int32_t any_check, hipStream_t st);
+                          uint32_t find_tiles, int32_t any_check, GridSync* gs, uint32_t resident, hipStream_t st);
+hipError_t batched_occupancy(int kd, int* per_cu);
 
 // Synthetic keys of the autotuner (uniform in [0, side)^kd; finds half hits).
 hipError_t launch_synth_keys(int32_t* keys, uint32_t n, int kd, uint32_t side, uint64_t seed, int32_t* fkeys,

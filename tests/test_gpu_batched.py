@@ -126,3 +126,29 @@ def test_autotune_picks_a_valid_shape(ash):
     k, v, f = make_case(rng, 20_000)
     run_round(ash, [m], [o], [(k, v, f)], True)
     check_maps([m], [o])
+
+
+@pytest.mark.parametrize("key_dim", [1, 2, 4])
+def test_batched_other_key_dims(ash, key_dim):
+    """The persistent kernel of each key width (their register use, and so
+    the number of blocks that run at once, differ)."""
+    rng = np.random.default_rng(44 + key_dim)
+    sizes = [3000, 20000, 500]
+    maps = [ash.HashMap(2 * u, key_dim, [(torch.float32, 4)]) for u in sizes]
+    oracles = [OracleMap(2 * u, key_dim, [(np.float32, 4)]) for u in sizes]
+    ops, cases = [], []
+    for u in sizes:
+        k = rng.integers(-30, 30, size=(2 * u, key_dim), dtype=np.int32)
+        v = rng.standard_normal((2 * u, 4)).astype(np.float32)
+        f = np.concatenate([k[: u], rng.integers(40, 60, size=(u, key_dim), dtype=np.int32)])
+        cases.append((k, v, f))
+        ops.append(dict(insert_keys=dev(k), insert_values=[dev(v)], find_keys=dev(f), gather=True))
+    res = ash.batched([dict(map=m, **op) for m, op in zip(maps, ops)], fused=True)
+    for r, o, (k, v, f) in zip(res, oracles, cases):
+        st, oi, om = o.insert(k, [v])
+        assert np.array_equal(host(r["insert_idx"]), oi)
+        st, fi, fm, (fv,) = o.find(f, gather=True, fill=0)
+        assert np.array_equal(host(r["find_idx"]), fi)
+        assert np.array_equal(bits(host(r["find_values"][0])), bits(fv))
+    check_maps(maps, oracles)
+    assert [m.device_status() for m in maps] == [0, 0, 0]
