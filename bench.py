@@ -120,6 +120,7 @@ def main():
                     help="plain: the headline 10M-key map; batched: 64 maps in one launch; voxelize: 5M points; "
                          "served: a Poisson request stream on a 2^25-capacity map")
     ap.add_argument("--requests", type=int, default=100_000, help="served: requests per run")
+    ap.add_argument("--served-max-load", type=float, default=0.5, help="served: max_load of the served map's table")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU sharding is a design note only"}))
@@ -450,7 +451,7 @@ def bench_served(args):
 
     torch.cuda.set_device(0)
     w = synth.served(n_requests=args.requests)
-    m = ash.HashMap(w["capacity"], 3, [(torch.float32, 8)])
+    m = ash.HashMap(w["capacity"], 3, [(torch.float32, 8)], max_load=args.served_max_load)
     m.insert(torch.from_numpy(w["preload_keys"]).cuda(), [torch.from_numpy(w["preload_values"]).cuda()])
     torch.cuda.synchronize()
     pool = 1 << 24
@@ -505,7 +506,8 @@ def bench_served(args):
         "p50_ms": round(head["p50_ms"], 3), "p99_ms": round(head["p99_ms"], 3),
         "config": {"workload": f"capacity 2^25, 20M preloaded keys, f32x8 values, {len(reqs)} Poisson requests "
                                "(60% find / 30% insert / 10% erase, sizes log-uniform in [256, 2^20])",
-                   "burst_capacity_Mops": round(cap / 1e6, 1), "mean_request_ops": round(mean_ops)},
+                   "burst_capacity_Mops": round(cap / 1e6, 1), "mean_request_ops": round(mean_ops),
+                   "max_load": args.served_max_load},
         "runs": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                  for k, v in out.items()}}), flush=True)
 

@@ -260,7 +260,7 @@ typedef struct {
 } ash_request_t;
 
 typedef struct {
-  int32_t max_fused;  /* requests per device batch (default 256) */
+  int32_t max_fused;  /* requests per device batch, 1..256 (default 256) */
   int64_t max_batch;  /* positions per fused device batch (default 2^22) */
   int32_t in_flight;  /* device batches queued at once (default 4) */
   int32_t fuse;       /* 0: every request is its own device batch */

@@ -60,6 +60,27 @@ struct Meta {
   uint32_t pad[7];
 };
 
+// One request of a fused served batch: its positions [off, off + n) of the
+// batch, its own key/value inputs and its own outputs (any may be null).
+struct ReqDesc {
+  int64_t off;
+  int64_t n;
+  const int32_t* keys;
+  const uint8_t* vals[kMaxValues];
+  int32_t* out_idx;
+  uint8_t* out_mask;
+  uint8_t* outv[kMaxValues];
+};
+
+// Most requests one fused served batch may carry.
+constexpr int kMaxFusedRequestsHost = 256;
+
+// Row layout of the value buffers of a map (bytes per row, j < n).
+struct RowSet {
+  int32_t n;
+  uint32_t bytes[kMaxValues];
+};
+
 // Barrier words of a persistent launch (zeroed before the launch): blocks
 // that have passed a barrier so far, and the abort flag.
 struct GridSync {

@@ -1151,6 +1151,87 @@ hipError_t launch_copy_masked_rows(const uint8_t* mask, const void* src, void* d
   return hipGetLastError();
 }
 
+// Fused served batches.  A block stages the requests' offsets in LDS and
+// finds each position's request by binary search (at most kMaxFusedRequests
+// requests per batch).  Rows move in 4-byte words when the row size allows,
+// else byte by byte.
+constexpr int kMaxFusedRequests = kMaxFusedRequestsHost;
+
+__device__ __forceinline__ int request_of(const int64_t* s_off, int nreq, int64_t e) {
+  int lo = 0, hi = nreq - 1;  // last request whose first position <= e
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (s_off[mid] <= e) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ void copy_row(const uint8_t* __restrict__ src, uint8_t* __restrict__ dst, uint32_t bytes) {
+  if ((bytes & 3u) == 0 && (((uintptr_t)src | (uintptr_t)dst) & 3u) == 0) {
+    for (uint32_t w = 0; w < bytes / 4; ++w)
+      reinterpret_cast<uint32_t*>(dst)[w] = reinterpret_cast<const uint32_t*>(src)[w];
+  } else {
+    for (uint32_t b = 0; b < bytes; ++b) dst[b] = src[b];
+  }
+}
+
+// Concatenates the requests' keys (and insert values) into the batch buffers.
+__global__ __launch_bounds__(kBlock) void k_gather_requests(const ReqDesc* __restrict__ d, int nreq, int64_t total,
+                                                            int kd, RowSet rows, int32_t* __restrict__ keys,
+                                                            uint8_t* const* __restrict__ vals) {
+  __shared__ int64_t s_off[kMaxFusedRequests];
+  for (int r = threadIdx.x; r < nreq; r += kBlock) s_off[r] = d[r].off;
+  __syncthreads();
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < total; e += (int64_t)gridDim.x * kBlock) {
+    const int r = request_of(s_off, nreq, e);
+    const int64_t q = e - s_off[r];
+    const int32_t* src = d[r].keys + q * kd;
+    for (int w = 0; w < kd; ++w) keys[e * kd + w] = src[w];
+    for (int j = 0; j < rows.n; ++j)
+      if (vals && d[r].vals[j]) copy_row(d[r].vals[j] + q * rows.bytes[j], vals[j] + e * rows.bytes[j], rows.bytes[j]);
+  }
+}
+
+// Hands each request its part of the batch results: indices, masks, and for
+// finds the gathered rows of hits (rows of misses stay untouched).
+__global__ __launch_bounds__(kBlock) void k_scatter_requests(const ReqDesc* __restrict__ d, int nreq, int64_t total,
+                                                             RowSet rows, const int32_t* __restrict__ idx,
+                                                             const uint8_t* __restrict__ mask,
+                                                             const uint8_t* const* __restrict__ outv) {
+  __shared__ int64_t s_off[kMaxFusedRequests];
+  for (int r = threadIdx.x; r < nreq; r += kBlock) s_off[r] = d[r].off;
+  __syncthreads();
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < total; e += (int64_t)gridDim.x * kBlock) {
+    const int r = request_of(s_off, nreq, e);
+    const int64_t q = e - s_off[r];
+    if (idx && d[r].out_idx) d[r].out_idx[q] = idx[e];
+    const uint8_t hit = mask[e];
+    if (d[r].out_mask) d[r].out_mask[q] = hit;
+    if (outv && hit)
+      for (int j = 0; j < rows.n; ++j)
+        if (d[r].outv[j]) copy_row(outv[j] + e * rows.bytes[j], d[r].outv[j] + q * rows.bytes[j], rows.bytes[j]);
+  }
+}
+
+hipError_t launch_gather_requests(const ReqDesc* d, int nreq, int64_t total, int kd, const RowSet& rows,
+                                  int32_t* keys, uint8_t* const* vals, hipStream_t st) {
+  if (nreq < 1 || nreq > kMaxFusedRequests) return hipErrorInvalidValue;
+  if (total == 0) return hipSuccess;
+  const uint32_t grid = (uint32_t)std::min<int64_t>((total + kBlock - 1) / kBlock, 4096);
+  hipLaunchKernelGGL(k_gather_requests, dim3(grid), dim3(kBlock), 0, st, d, nreq, total, kd, rows, keys, vals);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_requests(const ReqDesc* d, int nreq, int64_t total, const RowSet& rows, const int32_t* idx,
+                                   const uint8_t* mask, const uint8_t* const* outv, hipStream_t st) {
+  if (nreq < 1 || nreq > kMaxFusedRequests) return hipErrorInvalidValue;
+  if (total == 0) return hipSuccess;
+  const uint32_t grid = (uint32_t)std::min<int64_t>((total + kBlock - 1) / kBlock, 4096);
+  hipLaunchKernelGGL(k_scatter_requests, dim3(grid), dim3(kBlock), 0, st, d, nreq, total, rows, idx, mask, outv);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Launchers.
 static inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }

@@ -12,6 +12,15 @@ namespace ash {
 enum FinalizeMode { kFinalizeInsert = 0, kFinalizeErase = 1, kFinalizeCount = 2, kFinalizeRebuild = 3 };
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t st);
+// Fused served batches (1 <= nreq <= 256 requests, offsets ascending from 0,
+// total = sum of n): gather the requests' keys and (vals non-null) values into
+// batch buffers; scatter batch indices (idx nullable), masks and, with outv,
+// the value rows of hits to the requests' outputs.  vals / outv are device
+// arrays of rows.n device pointers.
+hipError_t launch_gather_requests(const ReqDesc* d, int nreq, int64_t total, int kd, const RowSet& rows,
+                                  int32_t* keys, uint8_t* const* vals, hipStream_t st);
+hipError_t launch_scatter_requests(const ReqDesc* d, int nreq, int64_t total, const RowSet& rows, const int32_t* idx,
+                                   const uint8_t* mask, const uint8_t* const* outv, hipStream_t st);
 // dst row r = src row r where mask[r] == 1 (rows of row_bytes, copied in vec-byte units).
 hipError_t launch_copy_masked_rows(const uint8_t* mask, const void* src, void* dst, uint64_t rows,
                                    uint32_t row_bytes, uint32_t vec, hipStream_t st);

@@ -23,6 +23,7 @@
 
 #include <chrono>
 #include <condition_variable>
+#include <cstring>
 #include <deque>
 #include <memory>
 #include <mutex>
@@ -57,6 +58,10 @@ struct Stage {
   std::vector<uint8_t*> outv;
   int32_t* idx = nullptr;
   uint8_t* mask = nullptr;
+  ash::ReqDesc* hdesc = nullptr;  // pinned host descriptors of the batch's requests
+  ash::ReqDesc* ddesc = nullptr;  // their device copy
+  uint8_t** dvals = nullptr;      // device arrays of the staging value / output row pointers
+  uint8_t** doutv = nullptr;
 };
 
 struct Batch {
@@ -65,6 +70,7 @@ struct Batch {
   int stage = -1;
   int64_t add_live = 0;  // upper bound on what the batch adds to t
   int64_t add_used = 0;  // ... and to the occupied slots
+  bool snap = false;     // the batch copied the map's counters to its stage's snapshot
 };
 
 }  // namespace
@@ -109,6 +115,18 @@ ash_status_t stage_alloc(ash_server* s, Stage& g) {
     if (hipMalloc(&g.vals[j], (size_t)n * m->row_bytes[j]) != hipSuccess) return ASH_E_NOMEM;
     if (hipMalloc(&g.outv[j], (size_t)n * m->row_bytes[j]) != hipSuccess) return ASH_E_NOMEM;
   }
+  const size_t dbytes = sizeof(ash::ReqDesc) * ash::kMaxFusedRequestsHost;
+  if (hipHostMalloc((void**)&g.hdesc, dbytes, hipHostMallocDefault) != hipSuccess) {
+    g.hdesc = nullptr;
+    return ASH_E_NOMEM;
+  }
+  if (hipMalloc(&g.ddesc, dbytes) != hipSuccess) return ASH_E_NOMEM;
+  const size_t pbytes = sizeof(uint8_t*) * std::max(m->n_values, 1);
+  if (hipMalloc(&g.dvals, pbytes) != hipSuccess || hipMalloc(&g.doutv, pbytes) != hipSuccess) return ASH_E_NOMEM;
+  if (m->n_values > 0 &&
+      (hipMemcpy(g.dvals, g.vals.data(), sizeof(uint8_t*) * m->n_values, hipMemcpyHostToDevice) != hipSuccess ||
+       hipMemcpy(g.doutv, g.outv.data(), sizeof(uint8_t*) * m->n_values, hipMemcpyHostToDevice) != hipSuccess))
+    return ASH_E_DEVICE;
   return ASH_OK;
 }
 
@@ -118,6 +136,10 @@ void stage_free(Stage& g) {
   (void)hipFree(g.mask);
   for (uint8_t* p : g.vals) (void)hipFree(p);
   for (uint8_t* p : g.outv) (void)hipFree(p);
+  if (g.hdesc) (void)hipHostFree(g.hdesc);
+  (void)hipFree(g.ddesc);
+  (void)hipFree(g.dvals);
+  (void)hipFree(g.doutv);
 }
 
 // Runs one request directly on its own buffers.
@@ -138,24 +160,40 @@ ash_status_t run_one(ash_server* s, Req* q) {
   }
 }
 
-// Runs requests of one kind as one device batch through staging buffers.
+// Runs requests of one kind as one device batch through staging buffers: one
+// descriptor upload and a gather kernel in, the operation, a scatter kernel
+// out.
 ash_status_t run_fused(ash_server* s, const std::vector<Req*>& run, Stage& g) {
   ash_map* m = s->map;
   hipStream_t st = s->stream;
   const int kind = run[0]->r.kind;
-  const size_t kbytes = (size_t)m->key_dim * 4;
+  const int nreq = (int)run.size();
+  bool gather = false;
   int64_t off = 0;
-  for (Req* q : run) {  // gather in arrival order
-    ASH_HIP(hipMemcpyAsync(g.keys + off * m->key_dim, q->r.keys, (size_t)q->r.n * kbytes, hipMemcpyDeviceToDevice,
-                           st));
+  for (int k = 0; k < nreq; ++k) {  // descriptors in arrival order
+    const Req* q = run[k];
+    ash::ReqDesc& d = g.hdesc[k];
+    std::memset(&d, 0, sizeof(d));
+    d.off = off;
+    d.n = q->r.n;
+    d.keys = q->r.keys;
     if (kind == ASH_REQ_INSERT)
-      for (int j = 0; j < m->n_values; ++j)
-        ASH_HIP(hipMemcpyAsync(g.vals[j] + off * m->row_bytes[j], q->values[j], (size_t)q->r.n * m->row_bytes[j],
-                               hipMemcpyDeviceToDevice, st));
+      for (int j = 0; j < m->n_values; ++j) d.vals[j] = (const uint8_t*)q->values[j];
+    d.out_idx = kind != ASH_REQ_ERASE ? q->r.out_idx : nullptr;
+    d.out_mask = q->r.out_mask;
+    if (kind == ASH_REQ_FIND && !q->out_values.empty()) {
+      gather = true;
+      for (int j = 0; j < m->n_values; ++j) d.outv[j] = (uint8_t*)q->out_values[j];
+    }
     off += q->r.n;
   }
-  bool gather = false;
-  for (Req* q : run) gather = gather || !q->out_values.empty();
+  ash::RowSet rows;
+  std::memset(&rows, 0, sizeof(rows));
+  rows.n = m->n_values;
+  for (int j = 0; j < m->n_values; ++j) rows.bytes[j] = m->row_bytes[j];
+  ASH_HIP(hipMemcpyAsync(g.ddesc, g.hdesc, sizeof(ash::ReqDesc) * nreq, hipMemcpyHostToDevice, st));
+  ASH_HIP(ash::launch_gather_requests(g.ddesc, nreq, off, m->key_dim, rows, g.keys,
+                                      kind == ASH_REQ_INSERT && m->n_values > 0 ? g.dvals : nullptr, st));
   std::vector<const void*> vin(g.vals.begin(), g.vals.end());
   std::vector<void*> vout(g.outv.begin(), g.outv.end());
   switch (kind) {
@@ -171,20 +209,8 @@ ash_status_t run_fused(ash_server* s, const std::vector<Req*>& run, Stage& g) {
     default:
       return ASH_E_INVALID;
   }
-  off = 0;
-  for (Req* q : run) {  // scatter the per-position results back
-    const ash_request_t& r = q->r;
-    if (r.out_idx && kind != ASH_REQ_ERASE)
-      ASH_HIP(hipMemcpyAsync(r.out_idx, g.idx + off, (size_t)r.n * 4, hipMemcpyDeviceToDevice, st));
-    if (r.out_mask) ASH_HIP(hipMemcpyAsync(r.out_mask, g.mask + off, (size_t)r.n, hipMemcpyDeviceToDevice, st));
-    if (kind == ASH_REQ_FIND && !q->out_values.empty())
-      for (int j = 0; j < m->n_values; ++j) {  // hits only: a find leaves the rows of misses untouched
-        const uint8_t* src = g.outv[j] + off * m->row_bytes[j];
-        ASH_HIP(ash::launch_copy_masked_rows(g.mask + off, src, q->out_values[j], (uint64_t)r.n, m->row_bytes[j],
-                                        copy_unit(m->row_bytes[j], src, q->out_values[j]), st));
-      }
-    off += r.n;
-  }
+  ASH_HIP(ash::launch_scatter_requests(g.ddesc, nreq, off, rows, kind != ASH_REQ_ERASE ? g.idx : nullptr, g.mask,
+                                       gather && m->n_values > 0 ? g.doutv : nullptr, st));
   return ASH_OK;
 }
 
@@ -247,7 +273,10 @@ void worker_loop(ash_server* s) {
     int64_t total = 0;
     for (Req* q : run) total += q->r.n;
     ash_status_t rc = run.size() == 1 ? run_one(s, run[0]) : run_fused(s, run, s->stages[stage]);
-    if (hipMemcpyAsync(&s->snaps[stage], m->meta, sizeof(Meta), hipMemcpyDeviceToHost, s->stream) != hipSuccess &&
+    // counters after the batch (a find changes neither t nor the occupied slots)
+    const bool snap = kind != ASH_REQ_FIND;
+    if (snap && hipMemcpyAsync(&s->snaps[stage], m->meta, sizeof(Meta), hipMemcpyDeviceToHost, s->stream) !=
+                    hipSuccess &&
         rc == ASH_OK)
       rc = ASH_E_DEVICE;
     if (hipEventRecord(ev, s->stream) != hipSuccess && rc == ASH_OK) rc = ASH_E_DEVICE;
@@ -258,6 +287,7 @@ void worker_loop(ash_server* s) {
       b.reqs = run;
       b.done = ev;
       b.stage = stage;
+      b.snap = snap;
       if (kind == ASH_REQ_INSERT) {
         b.add_live = total;
         b.add_used = std::min(total, m->c);
@@ -289,7 +319,7 @@ void completer_loop(ash_server* s) {
       s->flight.pop_front();
       s->add_live -= b.add_live;
       s->add_used -= b.add_used;
-      if (e == hipSuccess) {  // the batch's counter copy has landed
+      if (e == hipSuccess && b.snap) {  // the batch's counter copy has landed
         s->conf_t = s->snaps[b.stage].t;
         s->conf_used = s->snaps[b.stage].used;
       }
@@ -349,7 +379,8 @@ ash_status_t ash_server_create(ash_map_t map, const ash_server_config_t* cfg, as
   if (map->flags & ASH_F_AUTOGROW) return ASH_E_UNSUPPORTED;  // admission needs a fixed capacity
   ash_server_config_t c = {256, 1 << 22, 4, 1};
   if (cfg) c = *cfg;
-  if (c.max_fused < 1 || c.max_batch < 1 || c.max_batch > (1ll << 30) || c.in_flight < 1 || c.in_flight > 64)
+  if (c.max_fused < 1 || c.max_fused > ash::kMaxFusedRequestsHost || c.max_batch < 1 || c.max_batch > (1ll << 30) ||
+      c.in_flight < 1 || c.in_flight > 64)
     return ASH_E_INVALID;
   std::unique_ptr<ash_server> s(new ash_server);
   s->map = map;
