@@ -232,7 +232,6 @@ ash_status_t insert_impl(ash_map* m, const int32_t* keys, int64_t n, const void*
   ASH_TRY(ensure_scratch(m, n, st));
   ASH_TRY(maybe_clean(m, n, st));
   const uint32_t un = (uint32_t)n;
-  const uint32_t last_tile = (un + ash::kScanTile - 1) / ash::kScanTile - 1;
   const uint32_t blocks = ash::claim_blocks(m->G, un);
   auto claim = [&]() -> ash_status_t {
     ASH_HIP(timed(m, "claim", st, [&] {
@@ -252,13 +251,9 @@ ash_status_t insert_impl(ash_map* m, const int32_t* keys, int64_t n, const void*
     uint32_t row_total = 0;
     for (int j = 0; j < vs.n; ++j) row_total += vs.row_bytes[j];
     uint32_t* wlist = row_total >= kSplitRowBytes ? reinterpret_cast<uint32_t*>(m->aux) : nullptr;
-    ASH_HIP(timed(m, "commit", st, [&] {
+    ASH_HIP(timed(m, "commit", st, [&] {  // its last tile also finalizes the insert
       return ash::launch_commit(m->key_dim, m->ref(), keys, un, m->slot_of, m->lost, m->kB, m->heap,
-                                (uint32_t)m->c, vs, oi, om, m->meta, m->scan_status, check, wlist, st);
-    }));
-    ASH_HIP(timed(m, "finalize", st, [&] {
-      return ash::launch_finalize(m->meta, (uint32_t)m->c, ash::kFinalizeInsert, silent, check, m->scan_status,
-                                  last_tile, st);
+                                (uint32_t)m->c, vs, oi, om, m->meta, m->scan_status, check, wlist, silent, st);
     }));
     if (wlist)
       ASH_HIP(timed(m, "values", st, [&] {
@@ -476,7 +471,6 @@ ash_status_t ash_erase(ash_map_t m, const int32_t* keys, int64_t n, uint8_t* out
   hipStream_t st = (hipStream_t)stream;
   ASH_TRY(ensure_scratch(m, n, st));
   const uint32_t un = (uint32_t)n;
-  const uint32_t last_tile = (un + ash::kScanTile - 1) / ash::kScanTile - 1;
   if (++m->erase_epoch == 0) {  // epochs wrapped: start the owner entries afresh
     ASH_HIP(ash::launch_fill_u32((uint32_t*)m->owner, 0u, (size_t)m->c * 2, st));
     m->erase_epoch = 1;
@@ -486,11 +480,10 @@ ash_status_t ash_erase(ash_map_t m, const int32_t* keys, int64_t n, uint8_t* out
     return ash::launch_erase_mark(m->key_dim, m->G, m->W, m->ref(), keys, un, epoch, m->slot_of, m->aux, m->owner,
                                   m->lost, st);
   }));
-  ASH_HIP(timed(m, "erase_commit", st, [&] {
+  ASH_HIP(timed(m, "erase_commit", st, [&] {  // its last tile also finalizes the erase
     return ash::launch_erase_commit(m->key_dim, m->ref(), un, m->slot_of, m->aux, m->lost, m->heap, out_mask, m->meta,
                                     m->scan_status, st);
   }));
-  ASH_HIP(timed(m, "finalize", st, [&] { return ash::launch_finalize(m->meta, (uint32_t)m->c, ash::kFinalizeErase, 0, 0, m->scan_status, last_tile, st); }));
   return ASH_OK;
 }
 

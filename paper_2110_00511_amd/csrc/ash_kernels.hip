@@ -443,6 +443,47 @@ __global__ __launch_bounds__(1024) void k_sum_partials(const uint32_t* __restric
   sum_partials_block<1024>(partial, count, meta, lds);
 }
 
+// Moves the heap top and resets per-launch counters.  Runs after the
+// scanning kernel, so every block of that kernel has read t / epoch.  The
+// number of keys an insert added is the scan total of its commit (0 when the
+// batch was rolled back).
+// total: the scan total of the launch being finalized (winners of an insert
+// or erase, the count of a compaction).
+__device__ __forceinline__ void finalize_total(Meta* m, uint32_t cap, int mode, int silent, int check,
+                                               uint32_t total) {
+  if (mode == kFinalizeInsert) {
+    const bool overflow = m->fail != 0 || (check && m->claims > cap - m->t);
+    if (!overflow) {
+      m->t += total;
+      m->used += total;
+      m->result = total;
+    } else {
+      m->result = 0;
+      if (!silent)
+        __hip_atomic_fetch_or(&m->status, m->fail ? kStatusTableFull : kStatusCapacity, __ATOMIC_RELAXED,
+                              __HIP_MEMORY_SCOPE_AGENT);
+    }
+    m->claims = 0;
+    m->fail = 0;
+  } else if (mode == kFinalizeErase) {
+    m->t -= total;
+    m->tombs += total;
+    m->result = total;
+  } else if (mode == kFinalizeCount) {
+    m->result = total;
+  } else if (mode == kFinalizeRebuild) {
+    if (m->fail) __hip_atomic_fetch_or(&m->status, kStatusTableFull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    m->fail = 0;
+  }
+  m->epoch = m->epoch + 1u == 0u ? 1u : m->epoch + 1u;
+}
+
+__device__ __forceinline__ void finalize_map(Meta* m, uint32_t cap, int mode, int silent, int check,
+                                             const uint64_t* status, uint32_t last_tile) {
+  const uint32_t total = mode == kFinalizeRebuild ? 0u : (uint32_t)status[last_tile] & 0x7FFFFFFFu;
+  finalize_total(m, cap, mode, silent, check, total);
+}
+
 // ---------------------------------------------------------------------------
 // Commit (insert / activate pass 2).  Winners are the candidates not marked
 // lost; they are ranked in batch order and take i = h[t + rank].  The lost
@@ -460,7 +501,7 @@ __device__ __forceinline__ void commit_tile(const TableRef& tb, const int32_t* _
                                             const int32_t* __restrict__ heap, uint32_t cap, const ValueSet& vs,
                                             int32_t* __restrict__ out_idx, uint8_t* __restrict__ out_mask,
                                             Meta* meta, uint64_t* __restrict__ status, int check,
-                                            uint32_t* __restrict__ wlist, TileLds& lds) {
+                                            uint32_t* __restrict__ wlist, int fin, TileLds& lds) {
   constexpr int S = SlotWords<KD>::value;
   uint2* s_pairs = lds.pairs;
   const uint32_t t0 = meta->t;
@@ -493,6 +534,12 @@ __device__ __forceinline__ void commit_tile(const TableRef& tb, const int32_t* _
   uint32_t total;
   block_rank_rows(win, rank, total, lds.scan);
   const uint32_t prefix = block_lookback(status, tile, meta->epoch, total, &meta->status, &lds.prefix);
+  // fin >= 0: the last tile finalizes the insert (fin = silent flag).  Its
+  // look-back saw every other tile publish, and each tile publishes only
+  // after reading t, the epoch and the claim counters, so none reads them
+  // after this point; the next kernel sees the update at the launch boundary.
+  if (fin >= 0 && threadIdx.x == 0 && tile == (n - 1) / kScanTile)
+    finalize_total(meta, cap, kFinalizeInsert, fin, check, prefix + total);
   bool bad = false;
 #pragma unroll
   for (int r = 0; r < kScanItems; ++r) {
@@ -564,43 +611,10 @@ __global__ __launch_bounds__(kBlock) void k_commit(TableRef tb, const int32_t* _
                                                    uint32_t cap, ValueSet vs, int32_t* __restrict__ out_idx,
                                                    uint8_t* __restrict__ out_mask, Meta* meta,
                                                    uint64_t* __restrict__ status, int check,
-                                                   uint32_t* __restrict__ wlist) {
+                                                   uint32_t* __restrict__ wlist, int silent) {
   __shared__ TileLds lds;
   commit_tile<KD, kInline>(tb, keys, n, blockIdx.x, slot_of, lost, kB, heap, cap, vs, out_idx, out_mask, meta,
-                           status, check, wlist, lds);
-}
-
-// Moves the heap top and resets per-launch counters.  Runs after the
-// scanning kernel, so every block of that kernel has read t / epoch.  The
-// number of keys an insert added is the scan total of its commit (0 when the
-// batch was rolled back).
-__device__ __forceinline__ void finalize_map(Meta* m, uint32_t cap, int mode, int silent, int check,
-                                             const uint64_t* status, uint32_t last_tile) {
-  if (mode == kFinalizeInsert) {
-    const bool overflow = m->fail != 0 || (check && m->claims > cap - m->t);
-    if (!overflow) {
-      const uint32_t total = (uint32_t)status[last_tile] & 0x7FFFFFFFu;
-      m->t += total;
-      m->used += total;
-      m->result = total;
-    } else {
-      m->result = 0;
-      if (!silent) m->status |= m->fail ? kStatusTableFull : kStatusCapacity;
-    }
-    m->claims = 0;
-    m->fail = 0;
-  } else if (mode == kFinalizeErase) {
-    const uint32_t total = (uint32_t)status[last_tile] & 0x7FFFFFFFu;
-    m->t -= total;
-    m->tombs += total;
-    m->result = total;
-  } else if (mode == kFinalizeCount) {
-    m->result = (uint32_t)status[last_tile] & 0x7FFFFFFFu;
-  } else if (mode == kFinalizeRebuild) {
-    if (m->fail) m->status |= kStatusTableFull;
-    m->fail = 0;
-  }
-  m->epoch = m->epoch + 1u == 0u ? 1u : m->epoch + 1u;
+                           status, check, wlist, silent, lds);
 }
 
 __global__ void k_finalize(Meta* m, uint32_t cap, int mode, int silent, int check, const uint64_t* status,
@@ -773,6 +787,9 @@ __global__ __launch_bounds__(kBlock) void k_erase_commit(TableRef tb, uint32_t n
   block_rank_rows(win, rank, total, s_scan);
   block_lookback(status, tile, meta->epoch, total, &meta->status, &s_prefix);
   const uint32_t prefix = s_prefix;
+  // the last tile finalizes the erase (every tile read t and the epoch before
+  // publishing, see commit_tile)
+  if (threadIdx.x == 0 && tile == (n - 1) / kScanTile) finalize_total(meta, 0u, kFinalizeErase, 0, 0, prefix + total);
 #pragma unroll
   for (int r = 0; r < kScanItems; ++r) {
     const uint32_t p = base + r * kBlock + threadIdx.x;
@@ -1060,7 +1077,7 @@ __global__ __launch_bounds__(kBlock) void k_batched(const BatchItem* __restrict_
   for (uint32_t t = blockIdx.x; t < commit_tiles; t += gridDim.x) {
     const BatchItem& it = items[item_of<&BatchItem::commit0>(items, n_items, t)];
     commit_tile<KD, true>(it.tb, it.ikeys, it.n_insert, t - it.commit0, it.slot_of, it.lost, it.kB, it.heap, it.cap,
-                          it.vin, it.iidx, it.imask, it.meta, it.status, it.check, nullptr, lds);
+                          it.vin, it.iidx, it.imask, it.meta, it.status, it.check, nullptr, -1, lds);
   }
   if (!grid_barrier(gs, passed, items, n_items, &s_ok)) return;
   for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < n_items; m += gridDim.x * blockDim.x) {
@@ -1370,13 +1387,13 @@ template <int KD>
 static hipError_t commit_k(const TableRef& tb, const int32_t* keys, uint32_t n, const uint32_t* slot_of,
                            uint8_t* lost, int32_t* kB, const int32_t* heap, uint32_t cap, const ValueSet& vs,
                            int32_t* out_idx, uint8_t* out_mask, Meta* meta, uint64_t* status, int check,
-                           uint32_t* wlist, hipStream_t st) {
+                           uint32_t* wlist, int silent, hipStream_t st) {
   if (wlist)
     hipLaunchKernelGGL((k_commit<KD, false>), dim3(cdiv(n, kScanTile)), dim3(kBlock), 0, st, tb, keys, n, slot_of,
-                       lost, kB, heap, cap, vs, out_idx, out_mask, meta, status, check, wlist);
+                       lost, kB, heap, cap, vs, out_idx, out_mask, meta, status, check, wlist, silent);
   else
     hipLaunchKernelGGL((k_commit<KD, true>), dim3(cdiv(n, kScanTile)), dim3(kBlock), 0, st, tb, keys, n, slot_of,
-                       lost, kB, heap, cap, vs, out_idx, out_mask, meta, status, check, wlist);
+                       lost, kB, heap, cap, vs, out_idx, out_mask, meta, status, check, wlist, silent);
   return hipGetLastError();
 }
 
@@ -1418,12 +1435,12 @@ hipError_t launch_scatter_values(const ValueSet& vs, const uint32_t* wlist, cons
 hipError_t launch_commit(int kd, const TableRef& tb, const int32_t* keys, uint32_t n, const uint32_t* slot_of,
                          uint8_t* lost, int32_t* kB, const int32_t* heap, uint32_t cap, const ValueSet& vs,
                          int32_t* out_idx, uint8_t* out_mask, Meta* meta, uint64_t* status, int check,
-                         uint32_t* wlist, hipStream_t st) {
+                         uint32_t* wlist, int silent, hipStream_t st) {
   switch (kd) {
-    case 1: return commit_k<1>(tb, keys, n, slot_of, lost, kB, heap, cap, vs, out_idx, out_mask, meta, status, check, wlist, st);
-    case 2: return commit_k<2>(tb, keys, n, slot_of, lost, kB, heap, cap, vs, out_idx, out_mask, meta, status, check, wlist, st);
-    case 3: return commit_k<3>(tb, keys, n, slot_of, lost, kB, heap, cap, vs, out_idx, out_mask, meta, status, check, wlist, st);
-    case 4: return commit_k<4>(tb, keys, n, slot_of, lost, kB, heap, cap, vs, out_idx, out_mask, meta, status, check, wlist, st);
+    case 1: return commit_k<1>(tb, keys, n, slot_of, lost, kB, heap, cap, vs, out_idx, out_mask, meta, status, check, wlist, silent, st);
+    case 2: return commit_k<2>(tb, keys, n, slot_of, lost, kB, heap, cap, vs, out_idx, out_mask, meta, status, check, wlist, silent, st);
+    case 3: return commit_k<3>(tb, keys, n, slot_of, lost, kB, heap, cap, vs, out_idx, out_mask, meta, status, check, wlist, silent, st);
+    case 4: return commit_k<4>(tb, keys, n, slot_of, lost, kB, heap, cap, vs, out_idx, out_mask, meta, status, check, wlist, silent, st);
     default: return hipErrorInvalidValue;
   }
 }

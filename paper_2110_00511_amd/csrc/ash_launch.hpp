@@ -33,14 +33,16 @@ hipError_t launch_sum_partials(const uint32_t* partial, uint32_t count, Meta* me
 uint32_t claim_blocks(int g, uint32_t n);
 hipError_t launch_claim(int kd, int g, int w, const TableRef& tb, const int32_t* keys, uint32_t n, uint32_t* slot_of,
                         uint8_t* lost, uint32_t* partial, Meta* meta, hipStream_t st);
+// The commit's last tile also finalizes the insert (t, counters, epoch;
+// silent = no sticky status on overflow), so no separate finalize follows.
 // wlist NULL: value rows are copied inside the commit.  Otherwise n uint32 of
 // scratch that receive the winners' positions in rank order, and
-// launch_scatter_values must follow the finalize to copy the rows.
+// launch_scatter_values must follow to copy the rows.
 hipError_t launch_commit(int kd, const TableRef& tb, const int32_t* keys, uint32_t n, const uint32_t* slot_of,
                          uint8_t* lost, int32_t* kB, const int32_t* heap, uint32_t cap, const ValueSet& vs,
                          int32_t* out_idx, uint8_t* out_mask, Meta* meta, uint64_t* status, int check,
-                         uint32_t* wlist, hipStream_t st);
-// Value rows of the insert that was just finalized (n = its batch size).
+                         uint32_t* wlist, int silent, hipStream_t st);
+// Value rows of the insert whose commit just finished (n = its batch size).
 hipError_t launch_scatter_values(const ValueSet& vs, const uint32_t* wlist, const int32_t* heap, const Meta* meta,
                                  uint32_t n, uint32_t cap, hipStream_t st);
 hipError_t launch_find(int kd, int g, int w, const TableRef& tb, const int32_t* keys, uint32_t n, int32_t* out_idx,
@@ -48,6 +50,7 @@ hipError_t launch_find(int kd, int g, int w, const TableRef& tb, const int32_t* 
 hipError_t launch_erase_mark(int kd, int g, int w, const TableRef& tb, const int32_t* keys, uint32_t n,
                              uint32_t epoch, uint32_t* slot_of, int32_t* found, uint64_t* owner, uint8_t* lost,
                              hipStream_t st);
+// The last tile also finalizes the erase (t, tombstones, epoch).
 hipError_t launch_erase_commit(int kd, const TableRef& tb, uint32_t n, const uint32_t* slot_of, const int32_t* found,
                                uint8_t* lost, int32_t* heap, uint8_t* out_mask, Meta* meta, uint64_t* status,
                                hipStream_t st);
