@@ -316,11 +316,12 @@ def _timed(fn, steps, warmup):
 def bench_batched(args):
     """64 independent maps (distinct counts log-uniform in [1e3, 1e6], f32x8
     values): the inserts and finds of all maps in one persistent launch,
-    called through the C ABI with descriptors and outputs built once; the
-    same work op by op through the single-map path is timed beside it.  Every
-    map is cleared before each trial, outside the timed call (the figures
-    with the clears inside are reported too).  Each map's table shape comes
-    from the autotuner."""
+    called through the C ABI with descriptors and outputs built once, beside
+    the same work op by op through the single-map path.  Each path gets the
+    table shapes its own autotuner picks (ash_autotune_batched for the fused
+    launch, ash_autotune for the single-map path).  Every map is cleared
+    before each trial, outside the timed call (the figures with the clears
+    inside are reported too)."""
     import torch
 
     import paper_2110_00511_amd as ash
@@ -329,60 +330,68 @@ def bench_batched(args):
 
     torch.cuda.set_device(0)
     work = synth.batched()
-    t_tune = time.perf_counter()
-    maps = []
-    for w in work:
-        tun, _ = ash.autotune(w["capacity"], len(w["keys"]), 0.5, 3, [(torch.float32, 8)])
-        maps.append((ash.HashMap(w["capacity"], 3, [(torch.float32, 8)], **tun), tun))
-    t_tune = time.perf_counter() - t_tune
     lib = L.load()
     sp = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
     P = ctypes.c_void_p
     keep = []
-    arr = (L.AshBatchOp * len(work))()
-    for i, (w, (m, _)) in enumerate(zip(work, maps)):
-        ik = torch.from_numpy(w["keys"]).cuda()
-        iv = torch.from_numpy(w["values"]).cuda()
-        fk = torch.from_numpy(w["find_keys"]).cuda()
-        ni, nf = ik.shape[0], fk.shape[0]
-        outs = [torch.empty(ni, dtype=torch.int32, device="cuda"), torch.empty(ni, dtype=torch.uint8, device="cuda"),
-                torch.empty(nf, dtype=torch.int32, device="cuda"), torch.empty(nf, dtype=torch.uint8, device="cuda")]
-        vin = (P * 1)(iv.data_ptr())
-        keep.extend([ik, iv, fk, outs, vin])
-        arr[i] = L.AshBatchOp(m._m, ik.data_ptr(), ni, ctypes.cast(vin, P), outs[0].data_ptr(), outs[1].data_ptr(),
-                              fk.data_ptr(), nf, None, outs[2].data_ptr(), outs[3].data_ptr())
+
+    def build(batched_tuning):
+        t0 = time.perf_counter()
+        maps = []
+        for w in work:
+            tun, _ = ash.autotune(w["capacity"], len(w["keys"]), 0.5, 3, [(torch.float32, 8)], batched=batched_tuning)
+            maps.append((ash.HashMap(w["capacity"], 3, [(torch.float32, 8)], **tun), tun))
+        tune_s = time.perf_counter() - t0
+        arr = (L.AshBatchOp * len(work))()
+        for i, (w, (m, _)) in enumerate(zip(work, maps)):
+            ik = torch.from_numpy(w["keys"]).cuda()
+            iv = torch.from_numpy(w["values"]).cuda()
+            fk = torch.from_numpy(w["find_keys"]).cuda()
+            ni, nf = ik.shape[0], fk.shape[0]
+            outs = [torch.empty(ni, dtype=torch.int32, device="cuda"),
+                    torch.empty(ni, dtype=torch.uint8, device="cuda"),
+                    torch.empty(nf, dtype=torch.int32, device="cuda"),
+                    torch.empty(nf, dtype=torch.uint8, device="cuda")]
+            vin = (P * 1)(iv.data_ptr())
+            keep.extend([ik, iv, fk, outs, vin])
+            arr[i] = L.AshBatchOp(m._m, ik.data_ptr(), ni, ctypes.cast(vin, P), outs[0].data_ptr(),
+                                  outs[1].data_ptr(), fk.data_ptr(), nf, None, outs[2].data_ptr(), outs[3].data_ptr())
+        shapes = {}
+        for _, t in maps:
+            k = f"g{t['probe_group']}_w{t['bucket_width']}_lf{t['max_load']:.2f}"
+            shapes[k] = shapes.get(k, 0) + 1
+        return maps, arr, shapes, tune_s
+
+    maps_f, arr_f, shapes_f, tune_f = build(True)
+    maps_p, arr_p, shapes_p, tune_p = build(False)
     n_ops = sum(len(w["keys"]) + len(w["find_keys"]) for w in work)
 
-    def clear_all():
+    def clear_all(maps):
         for m, _ in maps:
             L.check(lib.ash_clear(m._m, sp), "clear")
 
-    def run(fused):
+    def run(arr, fused):
         L.check(lib.ash_batched(arr, len(work), 1 if fused else 0, sp), "ash_batched")
 
-    def timed_hot(fused):
+    def timed_hot(maps, arr, fused):
         """Mean ms of the batched call alone; the clears run untimed before each trial."""
         for _ in range(args.warmup):
-            clear_all()
-            run(fused)
+            clear_all(maps)
+            run(arr, fused)
         total = 0.0
         for _ in range(args.steps):
-            clear_all()
+            clear_all(maps)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            run(fused)
+            run(arr, fused)
             torch.cuda.synchronize()
             total += time.perf_counter() - t0
         return total * 1e3 / args.steps
 
-    ms_f = timed_hot(True)
-    ms_p = timed_hot(False)
-    ms_fc = _timed(lambda: (clear_all(), run(True)), args.steps, args.warmup)
-    ms_pc = _timed(lambda: (clear_all(), run(False)), args.steps, args.warmup)
-    shapes = {}
-    for _, t in maps:
-        k = f"g{t['probe_group']}_w{t['bucket_width']}_lf{t['max_load']:.2f}"
-        shapes[k] = shapes.get(k, 0) + 1
+    ms_f = timed_hot(maps_f, arr_f, True)
+    ms_p = timed_hot(maps_p, arr_p, False)
+    ms_fc = _timed(lambda: (clear_all(maps_f), run(arr_f, True)), args.steps, args.warmup)
+    ms_pc = _timed(lambda: (clear_all(maps_p), run(arr_p, False)), args.steps, args.warmup)
     print(json.dumps({
         "metric": "Mops/s insert+find, 64 batched maps in one persistent launch", "value": round(n_ops / ms_f / 1e3, 1),
         "unit": "Mops/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_f, 4),
@@ -390,8 +399,9 @@ def bench_batched(args):
         "config": {"workload": f"64 maps, distinct counts log-uniform in [1e3, 1e6], {n_ops} key ops per step "
                                "(insert 2u then find 2u per map), f32x8 values; maps cleared untimed before "
                                "each step",
-                   "tuned_shapes": shapes, "autotune_s": round(t_tune, 2)},
-        "plain_path": {"ms_per_step": round(ms_p, 4), "value": round(n_ops / ms_p / 1e3, 1), "unit": "Mops/s"},
+                   "tuned_shapes": shapes_f, "autotune_s": round(tune_f, 2)},
+        "plain_path": {"ms_per_step": round(ms_p, 4), "value": round(n_ops / ms_p / 1e3, 1), "unit": "Mops/s",
+                       "tuned_shapes": shapes_p, "autotune_s": round(tune_p, 2)},
         "speedup_vs_plain": round(ms_p / ms_f, 3),
         "with_clears": {"fused_ms": round(ms_fc, 4), "plain_ms": round(ms_pc, 4),
                         "fused_Mops": round(n_ops / ms_fc / 1e3, 1), "plain_Mops": round(n_ops / ms_pc / 1e3, 1)}}),

@@ -191,6 +191,14 @@ ash_status_t ash_voxelize(const float* points, int64_t n, float voxel,
                           int32_t* out_voxel_counts, int64_t* out_n_voxels,
                           const ash_allocator_t* allocator, void* stream);
 
+/* Blocks of the persistent batched launch for maps of this key_dim on the
+ * current device: the occupancy the runtime reports (*out_reported, blocks per
+ * CU times CUs) and the count the device was seen to run all at once
+ * (*out_blocks), which ash_batched uses.  The first call per key_dim and
+ * device makes an empty launch (touching no map) and synchronizes; later
+ * calls return the cached count. */
+ash_status_t ash_batched_grid(int32_t key_dim, int64_t* out_blocks, int64_t* out_reported, void* stream);
+
 /* Batched maps (many independent maps of uneven sizes at once).  One op is
  * one map's work: an insert batch, then a find batch, with the meaning of
  * ash_insert followed by ash_find on that map (insert_values / find_values
@@ -231,6 +239,18 @@ ash_status_t ash_autotune(int64_t capacity, int32_t key_dim, int32_t n_values,
                           int64_t n_insert, double distinct_ratio,
                           const ash_allocator_t* allocator, void* stream,
                           ash_tuning_t* out, double* out_ms);
+
+/* The sweep for maps meant for ash_batched: each candidate is timed as the
+ * insert and find of one map in the persistent batched launch.  That kernel
+ * keeps a fixed number of blocks resident, each taking its tiles one after
+ * another, so the sweep keeps the shapes that probe all keys of a tile at
+ * once: g = 1 with W in {2, 4, 8}, max_load in {0.5, 0.7, 0.85}.  Cached
+ * separately from ash_autotune.  Synchronizes. */
+ash_status_t ash_autotune_batched(int64_t capacity, int32_t key_dim, int32_t n_values,
+                                  const ash_dtype_t* value_dtypes, const int64_t* value_elems,
+                                  int64_t n_insert, double distinct_ratio,
+                                  const ash_allocator_t* allocator, void* stream,
+                                  ash_tuning_t* out, double* out_ms);
 
 /* Served map (continuous batching).  A server owns one map (the caller must
  * not use the map while it is served) and a worker thread with its own HIP

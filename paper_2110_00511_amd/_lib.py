@@ -85,7 +85,10 @@ SIGNATURES = {
     "ash_batched": (ST, [ctypes.POINTER(AshBatchOp), I32, I32, P]),
     "ash_autotune": (ST, [I64, I32, I32, P, P, I64, ctypes.c_double, P, P, ctypes.POINTER(AshTuning),
                           ctypes.POINTER(ctypes.c_double)]),
+    "ash_autotune_batched": (ST, [I64, I32, I32, P, P, I64, ctypes.c_double, P, P, ctypes.POINTER(AshTuning),
+                                  ctypes.POINTER(ctypes.c_double)]),
     "ash_server_create": (ST, [P, P, ctypes.POINTER(P)]),
+    "ash_batched_grid": (ST, [I32, ctypes.POINTER(I64), ctypes.POINTER(I64), P]),
     "ash_server_submit": (ST, [P, ctypes.POINTER(AshRequest), ctypes.POINTER(I64)]),
     "ash_server_wait": (ST, [P, I64, ctypes.POINTER(ctypes.c_double)]),
     "ash_server_replay": (ST, [P, ctypes.POINTER(AshRequest), I64, P, P, P, ctypes.POINTER(ctypes.c_double)]),

@@ -656,7 +656,7 @@ ash_status_t ash_voxelize(const float* points, int64_t n, float voxel, int32_t* 
 std::mutex g_resident_mu;
 std::map<std::pair<int, int>, uint32_t> g_resident;
 
-ash_status_t batched_resident(int kd, DevMem& mem, hipStream_t st, uint32_t* out) {
+static ash_status_t batched_resident(int kd, DevMem& mem, hipStream_t st, uint32_t* out) {
   int dev = 0, cus = 0, per_cu = 0;
   ASH_HIP(hipGetDevice(&dev));
   {
@@ -691,6 +691,21 @@ ash_status_t batched_resident(int kd, DevMem& mem, hipStream_t st, uint32_t* out
   std::lock_guard<std::mutex> lock(g_resident_mu);
   g_resident[{kd, dev}] = found;
   *out = found;
+  return ASH_OK;
+}
+
+ash_status_t ash_batched_grid(int32_t key_dim, int64_t* out_blocks, int64_t* out_reported, void* stream) {
+  if (key_dim < 1 || key_dim > 4 || !out_blocks) return ASH_E_INVALID;
+  hipStream_t st = (hipStream_t)stream;
+  int dev = 0, cus = 0, per_cu = 0;
+  ASH_HIP(hipGetDevice(&dev));
+  ASH_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  ASH_HIP(ash::batched_occupancy(key_dim, &per_cu));
+  DevMem mem;
+  uint32_t resident = 0;
+  ASH_TRY(batched_resident(key_dim, mem, st, &resident));
+  *out_blocks = resident;
+  if (out_reported) *out_reported = (int64_t)cus * per_cu;
   return ASH_OK;
 }
 
@@ -797,7 +812,7 @@ ash_status_t ash_batched(const ash_batch_op_t* ops, int32_t n_ops, int32_t fused
 
 namespace {
 
-typedef std::tuple<int, int64_t, int, int, int> TuneKey;
+typedef std::tuple<int, int64_t, int, int, int, int> TuneKey;  // ..., fused
 std::mutex g_tune_mu;
 std::map<TuneKey, std::pair<ash_tuning_t, double>> g_tune_cache;
 
@@ -826,16 +841,20 @@ uint32_t cube_side(int64_t n, int kd, double ratio) {
 
 }  // namespace
 
-ash_status_t ash_autotune(int64_t capacity, int32_t key_dim, int32_t n_values, const ash_dtype_t* value_dtypes,
-                          const int64_t* value_elems, int64_t n_insert, double distinct_ratio,
-                          const ash_allocator_t* allocator, void* stream, ash_tuning_t* out, double* out_ms) {
+// The sweep of ash_autotune; fused times each candidate as one map of the
+// persistent batched launch instead of the single-map insert and find.
+static ash_status_t autotune_impl(int64_t capacity, int32_t key_dim, int32_t n_values,
+                                  const ash_dtype_t* value_dtypes, const int64_t* value_elems, int64_t n_insert,
+                                  double distinct_ratio, const ash_allocator_t* allocator, void* stream,
+                                  ash_tuning_t* out, double* out_ms, bool fused) {
   if (!out || capacity <= 0 || capacity > kMaxCount || key_dim < 1 || key_dim > 4) return ASH_E_INVALID;
   if (n_insert <= 0 || n_insert > kMaxCount || !(distinct_ratio > 0.0) || distinct_ratio > 1.0) return ASH_E_INVALID;
   if (n_values < 0 || n_values > ash::kMaxValues || (n_values > 0 && (!value_dtypes || !value_elems)))
     return ASH_E_INVALID;
   int64_t row = 0;
   for (int j = 0; j < n_values; ++j) row += (int64_t)dtype_size(value_dtypes[j]) * value_elems[j];
-  const TuneKey key(key_dim, row, log2_floor(capacity), log2_floor(n_insert), (int)std::lround(distinct_ratio * 10));
+  const TuneKey key(key_dim, row, log2_floor(capacity), log2_floor(n_insert), (int)std::lround(distinct_ratio * 10),
+                    fused ? 1 : 0);
   {
     std::lock_guard<std::mutex> lock(g_tune_mu);
     auto it = g_tune_cache.find(key);
@@ -868,8 +887,15 @@ ash_status_t ash_autotune(int64_t capacity, int32_t key_dim, int32_t n_values, c
   const int widths[] = {4, 8, 16, 32};
   const int groups[] = {1, 4, 8, 16, 64};
   const float loads[] = {0.5f, 0.7f, 0.85f};
+  // In the persistent batched launch every resident block takes its tiles
+  // one after another, so a tile's latency is not hidden by other blocks: a
+  // lane per key probes all 256 keys of a tile at once, while g >= 4 runs
+  // g rounds in sequence.  The batched sweep therefore keeps g = 1.
+  const int lane_widths[] = {2, 4, 8};
   for (int g : groups) {
-    for (int w : widths) {
+    if (fused && g != 1) continue;
+    for (int w : (fused ? std::vector<int>(std::begin(lane_widths), std::end(lane_widths))
+                        : std::vector<int>(std::begin(widths), std::end(widths)))) {
       if (g == 1 && w > 8) continue;
       for (float lf : loads) {
         if (!ok) break;
@@ -879,9 +905,13 @@ ash_status_t ash_autotune(int64_t capacity, int32_t key_dim, int32_t n_values, c
           continue;  // e.g. not enough memory for this load factor
         double ms = 1e30;
         for (int rep = 0; rep < 4 && ok; ++rep) {
+          ash_batch_op_t op = {m, keys, n_insert, n_values ? vals.data() : nullptr, nullptr, nullptr,
+                               fkeys, n_insert, nullptr, nullptr, nullptr};
           ok = ash_clear(m, stream) == ASH_OK && hipEventRecord(e0, st) == hipSuccess &&
-               insert_impl(m, keys, n_insert, n_values ? vals.data() : nullptr, nullptr, nullptr, st) == ASH_OK &&
-               ash_find(m, fkeys, n_insert, nullptr, nullptr, nullptr, stream) == ASH_OK &&
+               (fused ? ash_batched(&op, 1, 1, stream) == ASH_OK
+                      : insert_impl(m, keys, n_insert, n_values ? vals.data() : nullptr, nullptr, nullptr, st) ==
+                                ASH_OK &&
+                            ash_find(m, fkeys, n_insert, nullptr, nullptr, nullptr, stream) == ASH_OK) &&
                hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
           float f = 0.0f;
           if (ok && rep > 0 && hipEventElapsedTime(&f, e0, e1) == hipSuccess) ms = std::min(ms, (double)f);
@@ -908,6 +938,21 @@ ash_status_t ash_autotune(int64_t capacity, int32_t key_dim, int32_t n_values, c
   *out = best;
   if (out_ms) *out_ms = best_ms;
   return ASH_OK;
+}
+
+ash_status_t ash_autotune(int64_t capacity, int32_t key_dim, int32_t n_values, const ash_dtype_t* value_dtypes,
+                          const int64_t* value_elems, int64_t n_insert, double distinct_ratio,
+                          const ash_allocator_t* allocator, void* stream, ash_tuning_t* out, double* out_ms) {
+  return autotune_impl(capacity, key_dim, n_values, value_dtypes, value_elems, n_insert, distinct_ratio, allocator,
+                       stream, out, out_ms, false);
+}
+
+ash_status_t ash_autotune_batched(int64_t capacity, int32_t key_dim, int32_t n_values,
+                                  const ash_dtype_t* value_dtypes, const int64_t* value_elems, int64_t n_insert,
+                                  double distinct_ratio, const ash_allocator_t* allocator, void* stream,
+                                  ash_tuning_t* out, double* out_ms) {
+  return autotune_impl(capacity, key_dim, n_values, value_dtypes, value_elems, n_insert, distinct_ratio, allocator,
+                       stream, out, out_ms, true);
 }
 
 const char* ash_status_string(ash_status_t s) {

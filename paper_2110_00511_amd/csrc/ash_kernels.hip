@@ -974,15 +974,13 @@ __global__ __launch_bounds__(kBlock) void k_voxel_resolve(TableRef tb, uint32_t 
 // takes its tiles in increasing order and all blocks are co-resident, so the
 // per-map look-back of the commit phase (which only waits on lower tiles of
 // the same map) always completes.  Each item keeps its own probe shape.
+// The item that holds tile t of a phase: the last item whose first tile is
+// <= t.  A block visits its tiles in increasing order, so it moves its
+// current item forward instead of searching (usually one check per tile).
 template <uint32_t BatchItem::*kFirst>
-__device__ __forceinline__ int item_of(const BatchItem* __restrict__ items, int n_items, uint32_t t) {
-  int lo = 0, hi = n_items - 1;  // last item whose first tile <= t
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (items[mid].*kFirst <= t) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
+__device__ __forceinline__ int advance_item(const BatchItem* __restrict__ items, int n_items, int cur, uint32_t t) {
+  while (cur + 1 < n_items && items[cur + 1].*kFirst <= t) ++cur;
+  return cur;
 }
 
 template <int KD>
@@ -1062,8 +1060,10 @@ __global__ __launch_bounds__(kBlock) void k_batched(const BatchItem* __restrict_
   __shared__ uint32_t s_ok;
   uint32_t passed = 0;
   if (!grid_barrier(gs, passed, items, n_items, &s_ok)) return;  // all blocks resident, or none works
+  int cur = 0;
   for (uint32_t t = blockIdx.x; t < claim_tiles; t += gridDim.x) {
-    const BatchItem& it = items[item_of<&BatchItem::claim0>(items, n_items, t)];
+    cur = advance_item<&BatchItem::claim0>(items, n_items, cur, t);
+    const BatchItem& it = items[cur];
     batched_claim<KD>(it, t - it.claim0, lds);
   }
   if (!grid_barrier(gs, passed, items, n_items, &s_ok)) return;
@@ -1074,8 +1074,10 @@ __global__ __launch_bounds__(kBlock) void k_batched(const BatchItem* __restrict_
     }
     if (!grid_barrier(gs, passed, items, n_items, &s_ok)) return;
   }
+  cur = 0;
   for (uint32_t t = blockIdx.x; t < commit_tiles; t += gridDim.x) {
-    const BatchItem& it = items[item_of<&BatchItem::commit0>(items, n_items, t)];
+    cur = advance_item<&BatchItem::commit0>(items, n_items, cur, t);
+    const BatchItem& it = items[cur];
     commit_tile<KD, true>(it.tb, it.ikeys, it.n_insert, t - it.commit0, it.slot_of, it.lost, it.kB, it.heap, it.cap,
                           it.vin, it.iidx, it.imask, it.meta, it.status, it.check, nullptr, -1, lds);
   }
@@ -1086,8 +1088,10 @@ __global__ __launch_bounds__(kBlock) void k_batched(const BatchItem* __restrict_
       finalize_map(it.meta, it.cap, kFinalizeInsert, 0, it.check, it.status, (it.n_insert + kScanTile - 1) / kScanTile - 1);
   }
   if (!grid_barrier(gs, passed, items, n_items, &s_ok)) return;
+  cur = 0;
   for (uint32_t t = blockIdx.x; t < find_tiles; t += gridDim.x) {
-    const BatchItem& it = items[item_of<&BatchItem::find0>(items, n_items, t)];
+    cur = advance_item<&BatchItem::find0>(items, n_items, cur, t);
+    const BatchItem& it = items[cur];
     batched_find<KD>(it, t - it.find0, lds);
   }
 }

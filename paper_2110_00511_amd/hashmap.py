@@ -212,10 +212,11 @@ def voxelize(points, voxel_size):
     return pv, vk[:u], cnt[:u]
 
 
-def autotune(capacity, n_insert, distinct_ratio, key_dim=3, value_specs=(), device="cuda"):
+def autotune(capacity, n_insert, distinct_ratio, key_dim=3, value_specs=(), device="cuda", batched=False):
     """Table shape for a map of `capacity` receiving batches of `n_insert`
     keys with the given distinct ratio: times insert + find of a synthetic
-    batch for every point of the sweep on this GPU.  Returns
+    batch for every point of the sweep on this GPU (through the persistent
+    batched launch when batched=True).  Returns
     (dict(bucket_width, probe_group, max_load), milliseconds)."""
     lib = L.load()
     specs = [(dt, int(e)) for dt, e in value_specs]
@@ -225,10 +226,10 @@ def autotune(capacity, n_insert, distinct_ratio, key_dim=3, value_specs=(), devi
     alloc = L.TorchAllocator(device)
     out = L.AshTuning()
     ms = ctypes.c_double()
-    L.check(lib.ash_autotune(int(capacity), int(key_dim), n, ctypes.cast(dts, ctypes.c_void_p),
-                             ctypes.cast(els, ctypes.c_void_p), int(n_insert), float(distinct_ratio),
-                             ctypes.byref(alloc.struct), _stream(), ctypes.byref(out), ctypes.byref(ms)),
-            "ash_autotune")
+    fn = lib.ash_autotune_batched if batched else lib.ash_autotune
+    L.check(fn(int(capacity), int(key_dim), n, ctypes.cast(dts, ctypes.c_void_p), ctypes.cast(els, ctypes.c_void_p),
+               int(n_insert), float(distinct_ratio), ctypes.byref(alloc.struct), _stream(), ctypes.byref(out),
+               ctypes.byref(ms)), "ash_autotune")
     return dict(bucket_width=out.bucket_width, probe_group=out.probe_group, max_load=out.max_load), ms.value
 
 

@@ -111,14 +111,18 @@ def test_batched_empty_ops_and_hash_sets(ash):
     assert a.size() == oa.size and b.size() == 0
 
 
-def test_autotune_picks_a_valid_shape(ash):
-    tun, ms = ash.autotune(40_000, 20_000, 0.5, key_dim=3, value_specs=[(torch.float32, 8)])
-    assert tun["probe_group"] in (1, 4, 8, 16, 64)
-    assert tun["bucket_width"] in (4, 8, 16, 32)
+@pytest.mark.parametrize("batched", [False, True])
+def test_autotune_picks_a_valid_shape(ash, batched):
+    tun, ms = ash.autotune(40_000, 20_000, 0.5, key_dim=3, value_specs=[(torch.float32, 8)], batched=batched)
+    if batched:  # the batched sweep keeps one lane per key
+        assert tun["probe_group"] == 1 and tun["bucket_width"] in (2, 4, 8)
+    else:
+        assert tun["probe_group"] in (1, 4, 8, 16, 64)
+        assert tun["bucket_width"] in (4, 8, 16, 32)
     assert min(abs(tun["max_load"] - x) for x in (0.5, 0.7, 0.85)) < 1e-6
     assert ms > 0
     # cached: the second call returns the same answer at once
-    tun2, ms2 = ash.autotune(40_000, 20_000, 0.5, key_dim=3, value_specs=[(torch.float32, 8)])
+    tun2, ms2 = ash.autotune(40_000, 20_000, 0.5, key_dim=3, value_specs=[(torch.float32, 8)], batched=batched)
     assert tun2 == tun and ms2 == ms
     rng = np.random.default_rng(43)
     m = ash.HashMap(40_000, 3, [(torch.float32, 8)], **tun)
