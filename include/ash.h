@@ -72,9 +72,11 @@ typedef enum {
   ASH_U8 = 0, ASH_I32 = 1, ASH_F32 = 2, ASH_I64 = 3, ASH_F64 = 4, ASH_F16 = 5, ASH_BF16 = 6
 } ash_dtype_t;
 
-/* Device-memory provider.  alloc returns a device pointer of at least `bytes`
- * bytes usable on `stream` (NULL on failure); free releases it after the work
- * already queued on `stream`. */
+/* Device-memory provider.  alloc returns a 256-byte aligned device pointer
+ * of at least `bytes` bytes usable on `stream` (NULL on failure; a block that
+ * is not 256-byte aligned is freed again and the call fails with
+ * ASH_E_NOMEM); free releases it after the work already queued on
+ * `stream`. */
 typedef struct {
   void* (*alloc)(void* ctx, size_t bytes, void* stream);
   void (*free)(void* ctx, void* ptr, void* stream);

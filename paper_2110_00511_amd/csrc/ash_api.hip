@@ -379,7 +379,7 @@ ash_status_t ash_create(int64_t capacity, int32_t key_dim, int32_t n_values, con
     ash_destroy(m);
     return ASH_E_NOMEM;
   }
-  if (hipMemsetAsync(m->meta, 0, sizeof(Meta), st) != hipSuccess ||
+  if (ash::launch_fill_u32((uint32_t*)m->meta, 0u, sizeof(Meta) / 4, st) != hipSuccess ||
       ash::launch_fill_u32((uint32_t*)m->owner, 0u, (size_t)capacity * 2, st) != hipSuccess ||
       reset_state(m, st) != ASH_OK || hipStreamSynchronize(st) != hipSuccess) {
     ash_destroy(m);

@@ -55,9 +55,19 @@ inline bool pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
 struct DevMem {
   ash_allocator_t a;
   bool custom;
+  // Kernels load 16-byte slots, CAS 8-byte pairs and fill 16 bytes at a
+  // time from the start of each block, so a block that is not 256-byte
+  // aligned is handed back and reported as an allocation failure.
   void* get(size_t bytes, hipStream_t st) {
     bytes = std::max<size_t>(bytes, 256);
-    if (custom) return a.alloc(a.ctx, bytes, st);
+    if (custom) {
+      void* p = a.alloc(a.ctx, bytes, st);
+      if (p && ((uintptr_t)p & 255u) != 0) {
+        a.free(a.ctx, p, st);
+        return nullptr;
+      }
+      return p;
+    }
     void* p = nullptr;
     if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
     return p;

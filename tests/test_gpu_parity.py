@@ -394,3 +394,27 @@ def test_plain_large_properties(ash, rho, channels):
     erased = np.isin(_pack(fk), _pack(ek))
     assert np.array_equal(host(fm2), hit & ~erased)
     assert m.device_status() == 0
+
+
+def test_misaligned_allocator_is_refused(ash):
+    """A provider whose blocks are not 256-byte aligned gets each block back
+    and the call fails with ASH_E_NOMEM; nothing is launched on such memory."""
+    import ctypes
+    from paper_2110_00511_amd import _lib as L
+
+    class Shifted(L.TorchAllocator):
+        def _do_alloc(self, ctx, nbytes, stream):
+            t = torch.empty(int(nbytes) + 64, dtype=torch.uint8, device=self.device)
+            ptr = t.data_ptr() + 16  # 16-byte aligned only
+            self.blocks[ptr] = t
+            return ptr
+
+    alloc = Shifted("cuda")
+    dts = (ctypes.c_int * 1)(L.ASH_F32)
+    els = (ctypes.c_int64 * 1)(4)
+    out = ctypes.c_void_p()
+    lib = L.load()
+    st = lib.ash_create(1000, 3, 1, ctypes.cast(dts, ctypes.c_void_p), ctypes.cast(els, ctypes.c_void_p),
+                        ctypes.byref(alloc.struct), None, None, ctypes.byref(out))
+    assert st == L.ASH_E_NOMEM
+    assert not alloc.blocks  # every block was handed back
