@@ -126,6 +126,8 @@ def main():
     # operations/s of burst capacity for g = 4, W = 4).
     ap.add_argument("--served-probe-group", type=int, default=1, help="served: probe group of the served map")
     ap.add_argument("--served-bucket-width", type=int, default=4, help="served: bucket width of the served map")
+    ap.add_argument("--served-in-flight", type=int, default=4, help="served: device batches queued at once")
+    ap.add_argument("--served-max-batch", type=int, default=1 << 22, help="served: positions per fused batch")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU sharding is a design note only"}))
@@ -498,7 +500,7 @@ def bench_served(args):
     mean_ops = total_ops / len(sizes)
 
     def run(load_ops_per_s, fuse, count):
-        srv = ash.Server(m, fuse=fuse)
+        srv = ash.Server(m, fuse=fuse, in_flight=args.served_in_flight, max_batch=args.served_max_batch)
         gaps = w["gaps"][:count] * (mean_ops / load_ops_per_s) if load_ops_per_s else np.zeros(count)
         lat, sts, span = srv.replay(reqs[:count], np.cumsum(gaps) - gaps[0])
         st = srv.stats()
@@ -524,7 +526,8 @@ def bench_served(args):
                                "(60% find / 30% insert / 10% erase, sizes log-uniform in [256, 2^20])",
                    "burst_capacity_Mops": round(cap / 1e6, 1), "mean_request_ops": round(mean_ops),
                    "max_load": args.served_max_load, "probe_group": args.served_probe_group,
-                   "bucket_width": args.served_bucket_width},
+                   "bucket_width": args.served_bucket_width, "in_flight": args.served_in_flight,
+                   "max_batch": args.served_max_batch},
         "runs": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                  for k, v in out.items()}}), flush=True)
 
