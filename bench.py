@@ -44,14 +44,14 @@ STORE = 32        # a small random store writes a 32-byte sector
 # only: traffic is reported as null for any other sources or workload.
 MEASURED_TRAFFIC = {
     "claim": 2.4238e9,
-    "commit": 0.9229e9,
+    "commit": 0.9223e9,
     "find": 1.4429e9,
     "erase_mark": 0.8949e9,
-    "erase_commit": 0.1802e9,
+    "erase_commit": 0.1803e9,
 }
 MEASURED_SOURCES = {
-    "ash_kernels.hip": "3773e8f3acef417bf2cae9cfed9c430ce301fc933d0b4892123e667865e6fde8",
-    "ash_device.hpp": "c9b17bff7730d02f0602c0954062bc0920a60e1e4770f817066b7231c930e8e3",
+    "ash_kernels.hip": "76c064ac31e3a7310fc69e2cbf9a161ce3fa327a71c291b435a4f0b2bc0c4ec6",
+    "ash_device.hpp": "886a22c94dee72ddee3138b2a128b1162050f5b06a179ade80cca67c4ef41535",
 }
 
 
