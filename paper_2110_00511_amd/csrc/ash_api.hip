@@ -125,7 +125,8 @@ ash_status_t rebuild_table(ash_map* m, int64_t live, hipStream_t st, int64_t roo
   ASH_HIP(hipMemcpyAsync(m->meta, &h, sizeof(Meta), hipMemcpyHostToDevice, st));
   ASH_HIP(hipStreamSynchronize(st));
   m->used_ub = live;
-  return (h.status & ash::kStatusTableFull) ? ASH_E_CAPACITY : ASH_OK;
+  m->tombs_possible = false;
+  return h.result ? ASH_E_CAPACITY : ASH_OK;  // this rebuild found no slot for some key
 }
 
 ash_status_t grow(ash_map* m, int64_t new_c, hipStream_t st) {
@@ -190,6 +191,10 @@ ash_status_t maybe_clean(ash_map* m, int64_t n, hipStream_t st) {
   const int64_t limit = m->c + ((int64_t)m->nslots - m->c) / 4;
   if (m->used_ub + std::min(n, m->c) <= limit) return ASH_OK;
   Meta h;
+  ASH_TRY(read_meta(m, &h, st));
+  if ((int64_t)h.used + std::min<int64_t>(n, m->c - h.t) <= limit) return ASH_OK;
+  // the device's count is a bound too (inserts reuse tombstones): count exactly
+  ASH_HIP(ash::launch_count_slots(m->key_dim, m->ref(), m->meta, st));
   ASH_TRY(read_meta(m, &h, st));
   if ((int64_t)h.used + std::min<int64_t>(n, m->c - h.t) <= limit) return ASH_OK;
   return rebuild_table(m, h.t, st);
@@ -309,6 +314,7 @@ ash_status_t reset_state(ash_map* m, hipStream_t st) {
   ASH_HIP(ash::launch_reset_meta(m->meta, st));
   m->live_ub = 0;
   m->used_ub = 0;
+  m->tombs_possible = false;
   return ASH_OK;
 }
 
@@ -480,6 +486,7 @@ ash_status_t ash_erase(ash_map_t m, const int32_t* keys, int64_t n, uint8_t* out
     return ash::launch_erase_mark(m->key_dim, m->G, m->W, m->ref(), keys, un, epoch, m->slot_of, m->aux, m->owner,
                                   m->lost, st);
   }));
+  m->tombs_possible = true;
   ASH_HIP(timed(m, "erase_commit", st, [&] {  // its last tile also finalizes the erase
     return ash::launch_erase_commit(m->key_dim, m->ref(), un, m->slot_of, m->aux, m->lost, m->heap, out_mask, m->meta,
                                     m->scan_status, st);
@@ -542,6 +549,7 @@ ash_status_t ash_capacity(ash_map_t m, int64_t* out) {
 ash_status_t ash_stats(ash_map_t m, ash_stats_t* out, void* stream) {
   if (!m || !out) return ASH_E_INVALID;
   Meta h;
+  ASH_HIP(ash::launch_count_slots(m->key_dim, m->ref(), m->meta, (hipStream_t)stream));
   ASH_TRY(read_meta(m, &h, (hipStream_t)stream));
   out->size = h.t;
   out->capacity = m->c;

@@ -50,8 +50,8 @@ struct SlotWords {
 struct Meta {
   uint32_t t;       // heap top = number of live keys
   uint32_t claims;  // summed new-key count of the insert in flight (when needed)
-  uint32_t used;    // non-empty slots (live + tombstones)
-  uint32_t tombs;   // tombstones
+  uint32_t used;    // bound on the non-empty slots (live + tombstones); exact after a count
+  uint32_t tombs;   // bound on the tombstones; exact after a count
   uint32_t status;  // sticky error bits
   uint32_t epoch;   // tag of the scan status words of the current launch
   uint32_t spare;
@@ -97,6 +97,7 @@ struct TableRef {
   uint32_t window;        // slots examined per probe step (G, or W when G == 1)
   uint32_t max_windows;   // probe steps that cover the whole table
   uint32_t dedup;         // 1: claims drop block-local duplicates in LDS first
+  uint32_t reuse;         // 1: the table may hold tombstones, which claims may take
 };
 
 // ---------------------------------------------------------------------------

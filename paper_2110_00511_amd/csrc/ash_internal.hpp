@@ -153,6 +153,9 @@ struct ash_map {
   // host-side upper bounds (exact after any synchronizing call)
   int64_t live_ub = 0;
   int64_t used_ub = 0;
+  // An erase ran since the table was last empty or rebuilt, so it may hold
+  // tombstones for claims to reuse (skipping them is always correct).
+  bool tombs_possible = false;
 
   int slot_words() const { return key_dim == 1 ? 2 : (key_dim <= 3 ? 4 : 8); }
 
@@ -165,6 +168,7 @@ struct ash_map {
     r.window = (uint32_t)(G == 1 ? W : G);
     r.max_windows = nslots / r.window + 1;
     r.dedup = (flags & ASH_F_LDS_DEDUP) ? 1u : 0u;
+    r.reuse = tombs_possible ? 1u : 0u;
     return r;
   }
 };

@@ -277,7 +277,7 @@ __device__ __forceinline__ void block_dedup(const Src& src, uint32_t n, uint32_t
   __syncthreads();
 }
 
-template <int KD, int G, int WL, typename Src, bool kVoxel>
+template <int KD, int G, int WL, typename Src, bool kVoxel, bool kReuse = false>
 __device__ __forceinline__ void claim_tile(const TableRef& tb, const Src& src, uint32_t n, uint32_t tile,
                                            uint32_t rounds, uint32_t* __restrict__ slot_of,
                                            uint8_t* __restrict__ lost, uint32_t* __restrict__ partial, Meta* meta,
@@ -313,9 +313,15 @@ __device__ __forceinline__ void claim_tile(const TableRef& tb, const Src& src, u
       const uint64_t desired = ((uint64_t)(kPending + p) << 32) | tag;
       uint32_t base = home_slot(tb, h);
       bool resolved = false;
+      // The first reusable slot of the sequence: a tombstone seen before the
+      // first EMPTY slot (which confirms the key is absent), with the window
+      // it was seen in, for a rescan when its CAS fails.
+      uint32_t r_slot = kNoSlot, r_base = 0, r_w = 0;
+      uint64_t r_pair = 0;
       for (uint32_t w = 0; w < tb.max_windows && !resolved; ++w) {
         Win win;
         win.load(tb, base, sub);
+        bool rescan = false;
         while (true) {
           // key committed by an earlier call: not new
           const uint64_t mc = win.mask([&](const Slot<S> sl) {
@@ -359,21 +365,50 @@ __device__ __forceinline__ void claim_tile(const TableRef& tb, const Src& src, u
             break;
           }
           const uint64_t me = win.mask([&](const Slot<S> sl) { return sl.w[S - 1] == kEmpty; });
+          if (kReuse && r_slot == kNoSlot) {
+            const uint64_t mt = win.mask([&](const Slot<S> sl) { return sl.w[S - 1] == kTomb; });
+            if (mt && (!me || first_lane(mt) < first_lane(me))) {
+              const uint32_t L = first_lane(mt);
+              r_slot = win.slot(L);
+              r_pair = ((uint64_t)win.word(L, S - 1) << 32) | win.word(L, S - 2);
+              r_base = base;
+              r_w = w;
+            }
+          }
           if (!me) break;  // no empty slot in this window: next window
+          // The key is absent: claim the first reusable slot, a tombstone
+          // seen on the way or else this EMPTY slot.  Every claimer of a key
+          // targets the first slot it sees reusable, and slots only stop
+          // being reusable during a claim, so claimers of one key meet there.
+          const bool tomb = kReuse && r_slot != kNoSlot;
           const uint32_t L = first_lane(me);
-          const uint32_t s = win.slot(L);
+          const uint32_t s = tomb ? r_slot : win.slot(L);
+          const uint64_t expect = tomb ? r_pair : kEmptyPair;
           uint64_t found = 0;
-          if (sub == 0) found = cas_pair(tb.words + (size_t)s * S + S - 2, kEmptyPair, desired);
+          if (sub == 0) found = cas_pair(tb.words + (size_t)s * S + S - 2, expect, desired);
           found = leader_bcast64<G>(found);
-          if (found == kEmptyPair) {
+          if (found == expect) {
             out = kVoxel ? (s | kCandidate) : s;
             claimed += sub == 0 ? 1u : 0u;
             resolved = true;
             break;
           }
-          // someone filled it first: look at what is there now
+          if (tomb) {
+            if ((uint32_t)(found >> 32) == kTomb) {  // still a tombstone (an older tag word was seen)
+              r_pair = found;
+              continue;
+            }
+            // the tombstone was taken: look again from its window
+            r_slot = kNoSlot;
+            base = r_base;
+            w = r_w - 1u;  // the loop's increment brings it back to r_w
+            rescan = true;
+            break;
+          }
+          // someone filled the EMPTY slot first: look at what is there now
           win.set_pair(L, sub, (uint32_t)found, (uint32_t)(found >> 32));
         }
+        if (rescan) continue;
         base += tb.window;
         if (base >= tb.nslots) base -= tb.nslots;
       }
@@ -411,12 +446,12 @@ __device__ __forceinline__ void claim_tile(const TableRef& tb, const Src& src, u
   __syncthreads();  // the scratch is reused by the next tile of a persistent block
 }
 
-template <int KD, int G, int WL, typename Src, bool kVoxel>
+template <int KD, int G, int WL, typename Src, bool kVoxel, bool kReuse>
 __global__ __launch_bounds__(kBlock) void k_claim(TableRef tb, Src src, uint32_t n, uint32_t rounds,
                                                   uint32_t* __restrict__ slot_of, uint8_t* __restrict__ lost,
                                                   uint32_t* __restrict__ partial, Meta* meta) {
   __shared__ TileLds lds;
-  claim_tile<KD, G, WL, Src, kVoxel>(tb, src, n, blockIdx.x, rounds, slot_of, lost, partial, meta, lds);
+  claim_tile<KD, G, WL, Src, kVoxel, kReuse>(tb, src, n, blockIdx.x, rounds, slot_of, lost, partial, meta, lds);
 }
 
 // meta->claims = sum of the claim kernel's per-block counts (one block).
@@ -448,9 +483,11 @@ __global__ __launch_bounds__(1024) void k_sum_partials(const uint32_t* __restric
 // number of keys an insert added is the scan total of its commit (0 when the
 // batch was rolled back).
 // total: the scan total of the launch being finalized (winners of an insert
-// or erase, the count of a compaction).
+// or erase, the count of a compaction); n: the insert's batch size.
+// used and tombs are upper bounds (an insert may reuse tombstones, a rolled
+// back insert leaves tombstones); k_count_slots makes them exact.
 __device__ __forceinline__ void finalize_total(Meta* m, uint32_t cap, int mode, int silent, int check,
-                                               uint32_t total) {
+                                               uint32_t total, uint32_t n = 0) {
   if (mode == kFinalizeInsert) {
     const bool overflow = m->fail != 0 || (check && m->claims > cap - m->t);
     if (!overflow) {
@@ -459,6 +496,8 @@ __device__ __forceinline__ void finalize_total(Meta* m, uint32_t cap, int mode, 
       m->result = total;
     } else {
       m->result = 0;
+      m->used += n;  // claimed slots were rolled back to tombstones
+      m->tombs += n;
       if (!silent)
         __hip_atomic_fetch_or(&m->status, m->fail ? kStatusTableFull : kStatusCapacity, __ATOMIC_RELAXED,
                               __HIP_MEMORY_SCOPE_AGENT);
@@ -472,6 +511,7 @@ __device__ __forceinline__ void finalize_total(Meta* m, uint32_t cap, int mode, 
   } else if (mode == kFinalizeCount) {
     m->result = total;
   } else if (mode == kFinalizeRebuild) {
+    m->result = m->fail ? 1u : 0u;  // this rebuild's own outcome (status is sticky across calls)
     if (m->fail) __hip_atomic_fetch_or(&m->status, kStatusTableFull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     m->fail = 0;
   }
@@ -479,9 +519,9 @@ __device__ __forceinline__ void finalize_total(Meta* m, uint32_t cap, int mode, 
 }
 
 __device__ __forceinline__ void finalize_map(Meta* m, uint32_t cap, int mode, int silent, int check,
-                                             const uint64_t* status, uint32_t last_tile) {
+                                             const uint64_t* status, uint32_t last_tile, uint32_t n = 0) {
   const uint32_t total = mode == kFinalizeRebuild ? 0u : (uint32_t)status[last_tile] & 0x7FFFFFFFu;
-  finalize_total(m, cap, mode, silent, check, total);
+  finalize_total(m, cap, mode, silent, check, total, n);
 }
 
 // ---------------------------------------------------------------------------
@@ -523,10 +563,14 @@ __device__ __forceinline__ void commit_tile(const TableRef& tb, const int32_t* _
       win[r] = slot[r] != kNoSlot && l == 0;
     }
   }
-  if (overflow) {  // roll the claims back: the table is as before the call
+  if (overflow) {
+    // Roll the claims back to tombstones: a claimed slot may have been a
+    // tombstone that other keys' probe sequences run through, and a
+    // tombstone is correct in either case (the occupied-slot count stays an
+    // upper bound).
 #pragma unroll
     for (int r = 0; r < kScanItems; ++r) {
-      if (win[r]) *reinterpret_cast<uint2*>(tb.words + (size_t)slot[r] * S + S - 2) = make_uint2(kEmpty, kEmpty);
+      if (win[r]) *reinterpret_cast<uint2*>(tb.words + (size_t)slot[r] * S + S - 2) = make_uint2(kEmpty, kTomb);
       win[r] = false;  // every position reports a miss; tiles still publish
     }
   }
@@ -539,7 +583,7 @@ __device__ __forceinline__ void commit_tile(const TableRef& tb, const int32_t* _
   // after reading t, the epoch and the claim counters, so none reads them
   // after this point; the next kernel sees the update at the launch boundary.
   if (fin >= 0 && threadIdx.x == 0 && tile == (n - 1) / kScanTile)
-    finalize_total(meta, cap, kFinalizeInsert, fin, check, prefix + total);
+    finalize_total(meta, cap, kFinalizeInsert, fin, check, prefix + total, n);
   bool bad = false;
 #pragma unroll
   for (int r = 0; r < kScanItems; ++r) {
@@ -800,6 +844,50 @@ __global__ __launch_bounds__(kBlock) void k_erase_commit(TableRef tb, uint32_t n
     }
     if (out_mask) out_mask[p] = win[r] ? 1 : 0;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Exact occupancy: meta->used += non-EMPTY slots and meta->tombs += tombstones
+// (both zeroed before the launch), one atomic pair per block.
+template <int S>
+__global__ __launch_bounds__(kBlock) void k_count_slots(TableRef tb, Meta* meta) {
+  __shared__ uint32_t s_used[kBlock / 64], s_tomb[kBlock / 64];
+  uint32_t used = 0, tomb = 0;
+  for (uint32_t s = blockIdx.x * kBlock + threadIdx.x; s < tb.nslots; s += gridDim.x * kBlock) {
+    const uint32_t st = tb.words[(size_t)s * S + S - 1];
+    used += st != kEmpty ? 1u : 0u;
+    tomb += st == kTomb ? 1u : 0u;
+  }
+  used = wave_sum(used);
+  tomb = wave_sum(tomb);
+  if (lane_id() == 0) {
+    s_used[threadIdx.x >> 6] = used;
+    s_tomb[threadIdx.x >> 6] = tomb;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t u = 0, t = 0;
+    for (int w = 0; w < kBlock / 64; ++w) {
+      u += s_used[w];
+      t += s_tomb[w];
+    }
+    atomic_add_u32(&meta->used, u);
+    atomic_add_u32(&meta->tombs, t);
+  }
+}
+
+hipError_t launch_count_slots(int kd, const TableRef& tb, Meta* meta, hipStream_t st) {
+  hipError_t e = launch_fill_u32(&meta->used, 0u, 2, st);  // used and tombs are adjacent
+  if (e != hipSuccess) return e;
+  const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>((tb.nslots + kBlock - 1) / kBlock, 1024));
+  switch (kd) {
+    case 1: hipLaunchKernelGGL(k_count_slots<2>, dim3(grid), dim3(kBlock), 0, st, tb, meta); break;
+    case 2:
+    case 3: hipLaunchKernelGGL(k_count_slots<4>, dim3(grid), dim3(kBlock), 0, st, tb, meta); break;
+    case 4: hipLaunchKernelGGL(k_count_slots<8>, dim3(grid), dim3(kBlock), 0, st, tb, meta); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -1085,7 +1173,8 @@ __global__ __launch_bounds__(kBlock) void k_batched(const BatchItem* __restrict_
   for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < n_items; m += gridDim.x * blockDim.x) {
     const BatchItem& it = items[m];
     if (it.n_insert)
-      finalize_map(it.meta, it.cap, kFinalizeInsert, 0, it.check, it.status, (it.n_insert + kScanTile - 1) / kScanTile - 1);
+      finalize_map(it.meta, it.cap, kFinalizeInsert, 0, it.check, it.status, (it.n_insert + kScanTile - 1) / kScanTile - 1,
+                   it.n_insert);
   }
   if (!grid_barrier(gs, passed, items, n_items, &s_ok)) return;
   cur = 0;
@@ -1299,8 +1388,13 @@ struct ClaimK {
   static hipError_t run(const TableRef& tb, const int32_t* keys, uint32_t n, uint32_t* slot_of, uint8_t* lost,
                         uint32_t* partial, Meta* meta, hipStream_t st) {
     const uint32_t rounds = rounds_for<G>();
-    hipLaunchKernelGGL((k_claim<KD, G, WL, BatchKeys<KD>, false>), dim3(cdiv(n, (kBlock / G) * rounds)),
-                       dim3(kBlock), 0, st, tb, BatchKeys<KD>{keys}, n, rounds, slot_of, lost, partial, meta);
+    // tombstones are reused only where an erase may have left some
+    if (tb.reuse)
+      hipLaunchKernelGGL((k_claim<KD, G, WL, BatchKeys<KD>, false, true>), dim3(cdiv(n, (kBlock / G) * rounds)),
+                         dim3(kBlock), 0, st, tb, BatchKeys<KD>{keys}, n, rounds, slot_of, lost, partial, meta);
+    else
+      hipLaunchKernelGGL((k_claim<KD, G, WL, BatchKeys<KD>, false, false>), dim3(cdiv(n, (kBlock / G) * rounds)),
+                         dim3(kBlock), 0, st, tb, BatchKeys<KD>{keys}, n, rounds, slot_of, lost, partial, meta);
     return hipGetLastError();
   }
 };
@@ -1343,7 +1437,7 @@ struct VoxelClaimK {
   static hipError_t run(const TableRef& tb, const float* pts, float voxel, uint32_t n, uint32_t* slot_of,
                         uint8_t* lost, uint32_t* partial, Meta* meta, hipStream_t st) {
     const uint32_t rounds = rounds_for<G>();
-    hipLaunchKernelGGL((k_claim<3, G, WL, VoxelKeys, true>), dim3(cdiv(n, (kBlock / G) * rounds)), dim3(kBlock), 0,
+    hipLaunchKernelGGL((k_claim<3, G, WL, VoxelKeys, true, false>), dim3(cdiv(n, (kBlock / G) * rounds)), dim3(kBlock), 0,
                        st, tb, VoxelKeys{pts, voxel}, n, rounds, slot_of, lost, partial, meta);
     return hipGetLastError();
   }

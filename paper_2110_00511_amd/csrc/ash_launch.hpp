@@ -12,6 +12,8 @@ namespace ash {
 enum FinalizeMode { kFinalizeInsert = 0, kFinalizeErase = 1, kFinalizeCount = 2, kFinalizeRebuild = 3 };
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t st);
+// meta->used / meta->tombs = exact counts of non-EMPTY slots / tombstones.
+hipError_t launch_count_slots(int kd, const TableRef& tb, Meta* meta, hipStream_t st);
 // Fused served batches (1 <= nreq <= 256 requests, offsets ascending from 0,
 // total = sum of n): gather the requests' keys and (vals non-null) values into
 // batch buffers; scatter batch indices (idx nullable), masks and, with outv,

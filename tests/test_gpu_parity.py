@@ -114,6 +114,9 @@ class Pair:
                 f"value buffer {j} differs on live written indices"
         stats = g.stats()
         assert stats["size"] == o.size
+        # exact counts: every occupied slot is a live key or a tombstone (no
+        # claim left pending, none lost)
+        assert stats["used_slots"] - stats["tombstones"] == o.size
         assert g.device_status() == (2 if self.overflowed else 0), "sticky status differs from the oracle's"
         self.overflowed = False
 
@@ -266,24 +269,27 @@ def test_rehash_keeps_indices(ash):
 
 @pytest.mark.parametrize("capacity", [27_000, 4096])
 def test_erase_insert_churn(ash, capacity):
-    """Tombstones pile up under churn and are cleaned by table rebuilds; the
-    smaller capacity also overflows on some batches (map unchanged, CAPACITY)."""
+    """Erases leave tombstones; inserts reuse those they pass before the first
+    EMPTY slot, and table rebuilds drop the rest.  Occupancy stays bounded;
+    the smaller capacity also overflows on some batches (CAPACITY, claims
+    rolled back to tombstones)."""
     rng = np.random.default_rng(21)
     pair = Pair(ash, capacity, 3, [(np.int32, 1)], max_load=0.5)
-    cleaned = False
-    prev_tombs = 0
+    consumed = False
     for step in range(40):
         k = rng.integers(0, 30, size=(3000, 3), dtype=np.int32)
+        before = pair.gpu.stats()
         pair.insert(k, [rng.integers(0, 1000, (3000, 1), dtype=np.int32)])
+        after = pair.gpu.stats()
+        consumed |= after["tombstones"] < before["tombstones"]  # reused by the insert, or a rebuild
         pair.erase(rng.integers(0, 30, size=(3000, 3), dtype=np.int32))
         pair.find(k, gather=False)
         s = pair.gpu.stats()
-        assert s["used_slots"] <= s["capacity"] + (s["slots"] - s["capacity"]) // 2 + 3000
-        cleaned |= s["tombstones"] < prev_tombs  # a rebuild dropped the tombstones
-        prev_tombs = s["tombstones"]
+        assert s["used_slots"] <= s["capacity"] + (s["slots"] - s["capacity"]) // 4 + 3000
+        assert s["used_slots"] - s["tombstones"] == s["size"]
         if step % 10 == 9:
             pair.check_state()
-    assert cleaned
+    assert consumed
 
 
 @pytest.mark.parametrize("g", [1, 4])
@@ -418,3 +424,42 @@ def test_misaligned_allocator_is_refused(ash):
                         ctypes.byref(alloc.struct), None, None, ctypes.byref(out))
     assert st == L.ASH_E_NOMEM
     assert not alloc.blocks  # every block was handed back
+
+
+@pytest.mark.parametrize("g,w", [(4, 4), (1, 4), (16, 4)])
+def test_tombstones_are_reused_under_churn(ash, g, w):
+    """Erase-heavy churn on a small table: inserts take tombstones seen before
+    the first EMPTY slot of their sequence, so occupancy stays near the live
+    count, and every result still equals the oracle's (duplicates in the
+    batch, keys erased and re-inserted in the same region, rollbacks)."""
+    rng = np.random.default_rng(60 + g)
+    cap = 3000
+    pair = Pair(ash, cap, 3, [(np.float32, 2)], probe_group=g, bucket_width=w, max_load=0.5)
+    universe = rng.integers(-40, 40, size=(9000, 3), dtype=np.int32)
+    for step in range(12):
+        k = universe[rng.integers(0, len(universe), size=2500)]
+        pair.insert(k, [rng.standard_normal((len(k), 2)).astype(np.float32)])
+        pair.find(universe[rng.integers(0, len(universe), size=3000)])
+        pair.erase(k[rng.permutation(len(k))[:1800]])
+        pair.check_state()
+    st = pair.gpu.stats()
+    # without reuse every insert after an erase would take a fresh slot
+    assert st["used_slots"] <= st["size"] + st["tombstones"]
+    assert st["used_slots"] - st["tombstones"] == st["size"]
+    assert st["used_slots"] < 2 * cap
+
+
+def test_tombstones_and_overflow_rollback(ash):
+    """An insert that overflows the heap after tombstones exist rolls its
+    claims back to tombstones; the map stays equal to the oracle's."""
+    rng = np.random.default_rng(63)
+    pair = Pair(ash, 1200, 3, [(np.float32, 1)])
+    k1 = rng.integers(0, 30, size=(1500, 3), dtype=np.int32)
+    pair.insert(k1, [rng.standard_normal((1500, 1)).astype(np.float32)])
+    pair.erase(k1[:600])
+    big = rng.integers(30, 60, size=(2000, 3), dtype=np.int32)  # more new keys than free indices
+    pair.insert(big, [rng.standard_normal((2000, 1)).astype(np.float32)])
+    pair.check_state()
+    pair.insert(k1[:700], [rng.standard_normal((700, 1)).astype(np.float32)])
+    pair.find(np.concatenate([k1, big]))
+    pair.check_state()
