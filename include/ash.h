@@ -38,7 +38,9 @@
  *     failure) return immediately; nothing is launched and outputs are
  *     untouched.
  *   - A batch whose new keys exceed the free indices c - t is detected on the
- *     device: the map is left bit-for-bit unchanged, outputs are idx -1 /
+ *     device: nothing is inserted (size, heap, index-addressed buffers and
+ *     every stored key are as before; slots the batch had claimed become
+ *     tombstones, which later inserts reuse), outputs are idx -1 /
  *     mask 0, and ash_device_status() reports ASH_E_CAPACITY.  With
  *     ASH_F_AUTOGROW the map instead grows to the smallest c * 2^k that fits
  *     (this path synchronizes).
