@@ -44,14 +44,14 @@ STORE = 32        # a small random store writes a 32-byte sector
 # only: traffic is reported as null for any other sources or workload.
 MEASURED_TRAFFIC = {
     "claim": 2.4238e9,
-    "commit": 0.9223e9,
+    "commit": 0.9224e9,
     "find": 1.4429e9,
     "erase_mark": 0.8949e9,
     "erase_commit": 0.1803e9,
 }
 MEASURED_SOURCES = {
-    "ash_kernels.hip": "76c064ac31e3a7310fc69e2cbf9a161ce3fa327a71c291b435a4f0b2bc0c4ec6",
-    "ash_device.hpp": "886a22c94dee72ddee3138b2a128b1162050f5b06a179ade80cca67c4ef41535",
+    "ash_kernels.hip": "9ee5e0017cd8c00658d6758f9f1a2527604d12c611346f136ba9d9e383addd90",
+    "ash_device.hpp": "98d566e65faa8c582630eb193e8162b8dd818730df1046ae6868bd81c89866f6",
 }
 
 
