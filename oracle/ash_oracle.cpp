@@ -23,7 +23,13 @@
 //   * rehash grows c to c' >= c and keeps every live index (h' = h[0..c)
 //     followed by c..c'-1); c' = c only rebuilds the table;
 //   * voxelize divides in binary32 and floors toward -infinity (Listing 1 of
-//     Sec. 6.1 computes floor(xyz / voxel_size) in float32).
+//     Sec. 6.1 computes floor(xyz / voxel_size) in float32);
+//   * a neighbor key is the query plus the offset word by word, wrapping
+//     modulo 2^32 (any int32 is a legal key, so no sum is rejected), and the
+//     results are laid out query-major, n rows of n_offsets (Listing 3
+//     reshapes its results to one row per point);
+//   * intersection keeps the queries' order and their duplicates: it is the
+//     masked selection of the second set by the find mask (Sec. 6.4).
 #include "ash_oracle.h"
 
 #include <array>
@@ -226,6 +232,45 @@ const int32_t* oracle_heap(const oracle_map* m) { return m->h.data(); }
 int64_t oracle_heap_top(const oracle_map* m) { return m->t; }
 const uint8_t* oracle_active_flags(const oracle_map* m) {
   return m->active.data();
+}
+
+int oracle_find_offsets(oracle_map* m, const int32_t* keys, int64_t n,
+                        const int32_t* offsets, int64_t n_offsets,
+                        int32_t* out_idx, uint8_t* out_mask) {
+  if (n < 0 || n_offsets < 0 || (n > 0 && !keys) ||
+      (n_offsets > 0 && !offsets))
+    return ORACLE_E_INVALID;
+  for (int64_t q = 0; q < n; ++q) {
+    for (int64_t o = 0; o < n_offsets; ++o) {
+      Key k = {0, 0, 0, 0};
+      for (int d = 0; d < m->key_dim; ++d) {
+        uint32_t a = (uint32_t)keys[q * m->key_dim + d];
+        uint32_t b = (uint32_t)offsets[o * m->key_dim + d];
+        k[d] = (int32_t)(a + b);  // unsigned sum wraps modulo 2^32
+      }
+      int64_t out = q * n_offsets + o;
+      std::map<Key, int32_t>::const_iterator it = m->M.find(k);
+      bool hit = it != m->M.end();
+      if (out_idx) out_idx[out] = hit ? it->second : -1;
+      if (out_mask) out_mask[out] = hit ? 1 : 0;
+    }
+  }
+  return ORACLE_OK;
+}
+
+int64_t oracle_intersect(oracle_map* m, const int32_t* keys, int64_t n,
+                         int32_t* out_keys) {
+  if (n < 0 || (n > 0 && !keys)) return -1;
+  int64_t count = 0;
+  for (int64_t p = 0; p < n; ++p) {
+    Key k = read_key(keys, p, m->key_dim);
+    if (m->M.find(k) == m->M.end()) continue;
+    if (out_keys)
+      for (int d = 0; d < m->key_dim; ++d)
+        out_keys[count * m->key_dim + d] = k[d];
+    ++count;
+  }
+  return count;
 }
 
 int64_t oracle_voxelize(const float* points, int64_t n, float voxel,

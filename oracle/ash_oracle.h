@@ -17,6 +17,9 @@
  *   - erase frees the index back to the heap: t -= 1, h[t] = i (Sec. 4.3)
  *   - rehash grows the buffers (x2 policy for auto-growth, Sec. 4.5)
  *   - voxelize: keys floor(p / voxel) inserted into a hash set (Sec. 6.1)
+ *   - neighbor lookups: finds of every query key shifted by every offset of
+ *     a neighborhood (Listing 3, Sec. 6.2.4; Sec. 6.3); set intersection as a find mask
+ *     selecting the queries (Sec. 6.4)
  *
  * Batches are processed strictly in position order, which is the
  * "lowest batch position wins" rule for in-batch duplicates.  Readings of the
@@ -80,6 +83,20 @@ const void* oracle_value_buffer(const oracle_map* m, int32_t j);
 const int32_t* oracle_heap(const oracle_map* m);
 int64_t oracle_heap_top(const oracle_map* m);
 const uint8_t* oracle_active_flags(const oracle_map* m);
+
+/* Neighbor lookup (the radius search of Listing 3, Sec. 6.2.4, and the 1-cube
+ * and 1-ring lookups of Sec. 6.3): for every query q and offset o, the find of
+ * the key keys[q] + offsets[o] (per word, int32 addition wrapping modulo
+ * 2^32) goes to out_idx[q * n_offsets + o] / out_mask[...], query-major.
+ * offsets: n_offsets * key_dim int32, row-major.  Outputs may be NULL. */
+int oracle_find_offsets(oracle_map* m, const int32_t* keys, int64_t n,
+                        const int32_t* offsets, int64_t n_offsets,
+                        int32_t* out_idx, uint8_t* out_mask);
+/* Set intersection (Sec. 6.4): the query keys that the map holds, in batch
+ * order, duplicates kept (a masked selection of the queries by the find
+ * mask).  out_keys may be NULL; returns the number of selected rows. */
+int64_t oracle_intersect(oracle_map* m, const int32_t* keys, int64_t n,
+                         int32_t* out_keys);
 
 /* Voxelization (Sec. 6.1).  points: n * 3 float32.  For every point p and
  * axis d, q = p[d] / voxel in IEEE binary32 (round to nearest even), key =

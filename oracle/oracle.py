@@ -65,6 +65,10 @@ def _load(path=_LIB):
         getattr(lib, name).restype = P
     lib.oracle_value_buffer.argtypes = [P, i32]
     lib.oracle_value_buffer.restype = P
+    lib.oracle_find_offsets.argtypes = [P, P, i64, P, i64, P, P]
+    lib.oracle_find_offsets.restype = ctypes.c_int
+    lib.oracle_intersect.argtypes = [P, P, i64, P]
+    lib.oracle_intersect.restype = i64
     lib.oracle_voxelize.argtypes = [P, i64, ctypes.c_float, P, P, P]
     lib.oracle_voxelize.restype = i64
     _lib_cache[path] = lib
@@ -142,6 +146,26 @@ class OracleMap:
         mask = np.empty(n, np.uint8)
         st = self._lib.oracle_erase(self._m, _ptr(keys), n, _ptr(mask))
         return st, mask
+
+    def find_offsets(self, keys, offsets):
+        """Finds of keys[q] + offsets[o] (int32 words, wrapping); returns
+        (status, idx[n, K], mask[n, K])."""
+        keys, n = self._keys(keys)
+        offs = np.ascontiguousarray(offsets, dtype=np.int32).reshape(-1, self.key_dim)
+        k = offs.shape[0]
+        idx = np.empty((n, k), np.int32)
+        mask = np.empty((n, k), np.uint8)
+        st = self._lib.oracle_find_offsets(self._m, _ptr(keys), n, _ptr(offs), k, _ptr(idx), _ptr(mask))
+        return st, idx, mask
+
+    def intersect(self, keys):
+        """The query rows the map holds, in batch order (duplicates kept)."""
+        keys, n = self._keys(keys)
+        out = np.empty((max(n, 1), self.key_dim), np.int32)
+        cnt = self._lib.oracle_intersect(self._m, _ptr(keys), n, _ptr(out))
+        if cnt < 0:
+            raise ValueError("oracle_intersect rejected its arguments")
+        return out[:cnt].copy()
 
     def active_indices(self):
         out = np.empty(max(self.capacity, 1), np.int32)

@@ -38,6 +38,11 @@ MUTANTS = {
     "voxel_count_reset": ("    counts[id] += 1;\n", "    counts[id] = 1;\n"),
     "voxel_rank_off_by_one": ("      id = (int32_t)n_voxels++;",
                               "      id = (int32_t)(n_voxels <= 1 ? 0 : n_voxels - 1);\n      n_voxels++;"),
+    "neighbor_offset_subtracted": ("k[d] = (int32_t)(a + b);", "k[d] = (int32_t)(a - b);"),
+    "neighbor_offset_major": ("int64_t out = q * n_offsets + o;", "int64_t out = o * n + q;"),
+    "neighbor_drops_last_word": ("      for (int d = 0; d < m->key_dim; ++d) {\n        uint32_t a",
+                                 "      for (int d = 0; d + 1 < m->key_dim; ++d) {\n        uint32_t a"),
+    "intersect_keeps_misses": ("if (m->M.find(k) == m->M.end()) continue;", "if (m->M.find(k) != m->M.end()) continue;"),
 }
 
 
@@ -54,6 +59,7 @@ def test_pins_catch_mutant(name, tmp_path):
     env = dict(os.environ, ASH_ORACLE_LIB=lib)
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_pins.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_voxelize.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_voxelize.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_neighbors.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"mutant {name} survived the pins:\n{r.stdout[-2000:]}"
