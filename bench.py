@@ -116,7 +116,7 @@ def main():
                     help="positions of the workload the oracle runs for cpu_baseline (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, copy 256 MiB once (reference kernel for byte counters)")
-    ap.add_argument("--workload", default="plain", choices=["plain", "batched", "voxelize", "served"],
+    ap.add_argument("--workload", default="plain", choices=["plain", "batched", "voxelize", "served", "neighbors"],
                     help="plain: the headline 10M-key map; batched: 64 maps in one launch; voxelize: 5M points; "
                          "served: a Poisson request stream on a 2^25-capacity map")
     ap.add_argument("--requests", type=int, default=100_000, help="served: requests per run")
@@ -136,6 +136,8 @@ def main():
         return bench_batched(args)
     if args.workload == "voxelize":
         return bench_voxelize(args)
+    if args.workload == "neighbors":
+        return bench_neighbors(args)
     if args.workload == "served":
         return bench_served(args)
 
@@ -451,6 +453,98 @@ def bench_voxelize(args):
         "unit": "Mpoints/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms0,
         "higher_is_better": True, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{n} points on 20 random spheres/planes in a 10 m box, sigma 1 cm", "sweep": out},
+        "cpu_baseline": cpu}), flush=True)
+
+
+def bench_neighbors(args):
+    """Neighbor search (Listing 3 of Sec. 6.2.4): the 27 radius-1 neighbors of
+    every distinct 5 mm lattice cell of the 5M-point surface cloud (4.8M
+    cells, the key set and the query set), one ash_find_offsets call per step.
+    Beside it: the 1-ring (6) and 1-cube (8) neighborhoods of Sec. 6.3 and the
+    intersection of the cells with a copy shifted by one cell (Sec. 6.4)."""
+    import torch
+
+    import paper_2110_00511_amd as ash
+    import synth
+    from paper_2110_00511_amd import _lib as L
+
+    torch.cuda.set_device(0)
+    keys_np = synth.surface_keys()
+    n = len(keys_np)
+    keys = torch.from_numpy(keys_np).cuda()
+    m = ash.HashMap(n, 3, probe_group=args.probe_group, bucket_width=args.bucket_width, max_load=args.max_load)
+    m.insert(keys)
+    lib = L.load()
+    sp = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    P = ctypes.c_void_p
+    outs = {}
+
+    def run(kind, radius, steps, warmup, profile=False):
+        off = ash.neighbor_offsets(kind, radius)
+        k = off.shape[0]
+        idx = torch.empty((n, k), dtype=torch.int32, device="cuda")
+        mask = torch.empty((n, k), dtype=torch.uint8, device="cuda")
+
+        def step():
+            L.check(lib.ash_find_offsets(m._m, P(keys.data_ptr()), n, P(off.data_ptr()), k, P(idx.data_ptr()),
+                                         P(mask.data_ptr()), sp), "find_offsets")
+        if profile:
+            for _ in range(warmup):
+                step()
+            m.profile(True)
+            m.profile_collect()
+            ms = _timed(step, steps, 0)
+            launches, total = m.profile_collect()["find_offsets"]
+            m.profile(False)
+            outs["kernel_ms"] = total / launches
+        else:
+            ms = _timed(step, steps, warmup)
+        return k, ms, float(mask.float().mean().item())
+
+    k, ms, hit = run("radius", 1, args.steps, args.warmup, profile=True)
+    sweep = {"radius1": {"offsets": k, "ms": round(ms, 4), "Mlookups_per_s": round(n * k / ms / 1e3, 1),
+                         "hit_rate": round(hit, 4)}}
+    for kind, r in (("ring", 1), ("cube", 1), ("radius", 2)):
+        kk, mss, h = run(kind, r, max(args.steps // 2, 1), 1)
+        sweep[f"{kind}{r}"] = {"offsets": kk, "ms": round(mss, 4), "Mlookups_per_s": round(n * kk / mss / 1e3, 1),
+                               "hit_rate": round(h, 4)}
+    shifted = keys + torch.tensor([1, 0, 0], dtype=torch.int32, device="cuda")
+    res = {}
+
+    def inter():
+        res["r"] = m.intersect(shifted)
+    ims = _timed(inter, max(args.steps // 2, 1), 1)
+    sweep["intersect"] = {"ms": round(ims, 4), "Mkeys_per_s": round(n / ims / 1e3, 1), "rows": int(res["r"].shape[0])}
+    assert m.device_status() == 0
+
+    # roofline of the lookup kernel: per lookup one random window line, the
+    # index and mask outputs, and the query key read once per query
+    per_lookup = READ_LINE + 4 + 1 + 12.0 / k
+    kern_s = outs["kernel_ms"] / 1e3
+    achieved = per_lookup * n * k / kern_s / 1e9
+    cpu = None
+    if args.cpu_sample > 0:
+        from oracle import OracleMap
+        s = min(max(args.cpu_sample // 10, 1), n)
+        om = OracleMap(n, 3)
+        om.insert(keys_np)
+        off_np = ash.neighbor_offsets("radius", 1, device=None).numpy()
+        c0 = time.perf_counter()
+        om.find_offsets(keys_np[:s], off_np)
+        c1 = time.perf_counter()
+        cpu = {"value": round(s * k / (c1 - c0) / 1e6, 3), "unit": "Mlookups/s", "cores": 1, "kind": "oracle",
+               "sample": f"27-neighborhoods of the first {s} cells ({c1 - c0:.1f} s; map of all {n} cells built untimed)"}
+    print(json.dumps({
+        "metric": "Mlookups/s neighbor search (27 radius-1 neighbors of every cell)",
+        "value": round(n * k / ms / 1e3, 1), "unit": "Mlookups/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"{n} distinct 5 mm lattice cells of 5M surface points; queries = the cells",
+                   "probe_group": args.probe_group, "bucket_width": args.bucket_width, "max_load": args.max_load,
+                   "sweep": sweep},
+        "roofline": {"bound": "hbm", "kernel": "find_offsets", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "algorithmic_bytes_per_lookup": round(per_lookup, 2), "kernel_ms": round(outs["kernel_ms"], 4)},
         "cpu_baseline": cpu}), flush=True)
 
 

@@ -16,7 +16,10 @@
  *   - multi-value maps and hash sets (n_values = 0) (Sec. 4.7);
  *   - rehash grows the buffers, x2 for auto-growth (Sec. 4.5);
  *   - voxelize turns points into floor(p / voxel) keys and keeps one entry per
- *     voxel with a hash-set insertion (Sec. 6.1, Listing 1).
+ *     voxel with a hash-set insertion (Sec. 6.1, Listing 1);
+ *   - neighbor lookups are finds of keys shifted by a neighborhood's offsets
+ *     (Listing 3, Sec. 6.2.4; Sec. 6.3), and set intersection keeps the
+ *     queries a map holds (Sec. 6.4).
  *
  * Conventions shared by every entry point:
  *   - Pointers to keys, values, points and per-position outputs are DEVICE
@@ -148,6 +151,48 @@ ash_status_t ash_find(ash_map_t map, const int32_t* keys, int64_t n,
  * order; out_mask[p] = 1 for those positions, 0 otherwise. */
 ash_status_t ash_erase(ash_map_t map, const int32_t* keys, int64_t n,
                        uint8_t* out_mask, void* stream);
+
+/* Neighbor lookups (Listing 3 of Sec. 6.2.4 finds every point's neighbors as
+ * finds of the point shifted by each offset; Sec. 6.3 uses 1-cube and 1-ring
+ * neighborhoods the same way).  keys: n * key_dim int32 (device);
+ * offsets: n_offsets * key_dim int32 (device), row-major.  For query q and
+ * offset o, the key keys[q] + offsets[o] (word by word, int32 addition
+ * wrapping modulo 2^32) is looked up as by ash_find, and out_idx[q * n_offsets
+ * + o] / out_mask[q * n_offsets + o] receive its index and mask (query-major
+ * n x n_offsets; either output may be NULL).  n * n_offsets must stay below
+ * 2^31 - 3, else ASH_E_INVALID.  Asynchronous. */
+ash_status_t ash_find_offsets(ash_map_t map, const int32_t* keys, int64_t n,
+                              const int32_t* offsets, int32_t n_offsets,
+                              int32_t* out_idx, uint8_t* out_mask,
+                              void* stream);
+
+/* Standard neighborhoods for ash_find_offsets, written to host memory as rows
+ * of key_dim int32, enumerated with the first word slowest:
+ *   ASH_NB_RADIUS: every offset with all words in [-radius, radius],
+ *                  (2 radius + 1)^key_dim rows, the zero offset included
+ *                  (radius 1 in 3-D: the 27 entries of Listing 3);
+ *   ASH_NB_CUBE:   every offset with all words in [0, radius]
+ *                  (radius 1: the 2^key_dim corners of the 1-cube, Sec. 6.3);
+ *   ASH_NB_RING:   every nonzero offset whose word magnitudes sum to at most
+ *                  radius (radius 1: the 2 key_dim face neighbors of the
+ *                  1-ring, Sec. 6.3).
+ * radius in [1, 64]; at most 2^16 rows from at most 2^24 candidates, else
+ * ASH_E_INVALID.  out_offsets NULL: only *out_count is written; otherwise it
+ * must hold *out_count rows (ask for the count first).  Host only. */
+#define ASH_NB_RADIUS 0
+#define ASH_NB_CUBE 1
+#define ASH_NB_RING 2
+ash_status_t ash_neighbor_offsets(int32_t kind, int32_t radius,
+                                  int32_t key_dim, int32_t* out_offsets,
+                                  int64_t* out_count);
+
+/* Set intersection (Sec. 6.4: build a set from the first keys, query the
+ * second and keep the hits): out_keys (device, room for n rows) receives the
+ * rows of keys the map holds, in batch order with duplicates kept, and
+ * *out_count (host) their number.  Synchronizes. */
+ash_status_t ash_intersect(ash_map_t map, const int32_t* keys, int64_t n,
+                           int32_t* out_keys, int64_t* out_count,
+                           void* stream);
 
 /* Live buffer indices in ascending order (the active set gathered for
  * rehashing, Sec. 4.5).  out_idx is a device array of at least `size`

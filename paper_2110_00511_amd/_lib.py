@@ -21,6 +21,7 @@ ASH_E_DEVICE = 4
 ASH_E_UNSUPPORTED = 5
 ASH_F_AUTOGROW = 1
 ASH_F_LDS_DEDUP = 2
+ASH_NB_RADIUS, ASH_NB_CUBE, ASH_NB_RING = 0, 1, 2
 
 ASH_U8, ASH_I32, ASH_F32, ASH_I64, ASH_F64, ASH_F16, ASH_BF16 = range(7)
 
@@ -71,6 +72,9 @@ SIGNATURES = {
     "ash_activate": (ST, [P, P, I64, P, P, P]),
     "ash_find": (ST, [P, P, I64, P, P, P, P]),
     "ash_erase": (ST, [P, P, I64, P, P]),
+    "ash_find_offsets": (ST, [P, P, I64, P, I32, P, P, P]),
+    "ash_neighbor_offsets": (ST, [I32, I32, I32, P, ctypes.POINTER(I64)]),
+    "ash_intersect": (ST, [P, P, I64, P, ctypes.POINTER(I64), P]),
     "ash_active_indices": (ST, [P, P, ctypes.POINTER(I64), P]),
     "ash_rehash": (ST, [P, I64, P]),
     "ash_clear": (ST, [P, P]),

@@ -494,6 +494,79 @@ ash_status_t ash_erase(ash_map_t m, const int32_t* keys, int64_t n, uint8_t* out
   return ASH_OK;
 }
 
+ash_status_t ash_find_offsets(ash_map_t m, const int32_t* keys, int64_t n, const int32_t* offsets, int32_t n_offsets,
+                              int32_t* out_idx, uint8_t* out_mask, void* stream) {
+  ASH_TRY(check_keys(m, keys, n));
+  if (n_offsets < 0 || (n_offsets > 0 && !offsets)) return ASH_E_INVALID;
+  if (n_offsets > 0 && n > kMaxCount / n_offsets) return ASH_E_INVALID;
+  const int64_t total = n * n_offsets;
+  if (total == 0) return ASH_OK;
+  hipStream_t st = (hipStream_t)stream;
+  ASH_HIP(timed(m, "find_offsets", st, [&] {
+    return ash::launch_find_offsets(m->key_dim, m->G, m->W, m->ref(), keys, offsets, (uint32_t)n_offsets,
+                                    (uint32_t)total, out_idx, out_mask, st);
+  }));
+  return ASH_OK;
+}
+
+ash_status_t ash_intersect(ash_map_t m, const int32_t* keys, int64_t n, int32_t* out_keys, int64_t* out_count,
+                           void* stream) {
+  ASH_TRY(check_keys(m, keys, n));
+  if (!out_count || (n > 0 && !out_keys)) return ASH_E_INVALID;
+  if (n == 0) {
+    *out_count = 0;
+    return ASH_OK;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  ASH_TRY(ensure_scratch(m, n, st));  // look-back status words for n positions
+  uint8_t* mask = (uint8_t*)m->mem.get((size_t)n, st);
+  if (!mask) return ASH_E_NOMEM;
+  ValueSet none;
+  std::memset(&none, 0, sizeof(none));
+  ash_status_t rc = ASH_OK;
+  if (timed(m, "find", st, [&] {
+        return ash::launch_find(m->key_dim, m->G, m->W, m->ref(), keys, (uint32_t)n, nullptr, mask, none, st);
+      }) != hipSuccess ||
+      timed(m, "compact_rows", st, [&] {  // its last tile writes the count
+        return ash::launch_compact_rows(m->key_dim, mask, (uint32_t)n, keys, out_keys, m->meta, m->scan_status, st);
+      }) != hipSuccess)
+    rc = ASH_E_DEVICE;
+  Meta h;
+  if (rc == ASH_OK) rc = read_meta(m, &h, st);
+  m->mem.put(mask, st);
+  if (rc == ASH_OK) *out_count = h.result;
+  return rc;
+}
+
+ash_status_t ash_neighbor_offsets(int32_t kind, int32_t radius, int32_t key_dim, int32_t* out_offsets,
+                                  int64_t* out_count) {
+  if (!out_count || key_dim < 1 || key_dim > 4 || radius < 1 || radius > 64) return ASH_E_INVALID;
+  if (kind != ASH_NB_RADIUS && kind != ASH_NB_CUBE && kind != ASH_NB_RING) return ASH_E_INVALID;
+  // candidates: every word in [lo, radius], enumerated with the first word slowest
+  const int64_t lo = kind == ASH_NB_CUBE ? 0 : -radius;
+  const int64_t side = radius - lo + 1;
+  int64_t cand = 1;
+  for (int d = 0; d < key_dim; ++d) cand *= side;  // <= 129^4
+  if (cand > kMaxNeighborCandidates) return ASH_E_INVALID;
+  int64_t count = 0;
+  int32_t w[4];
+  for (int64_t c = 0; c < cand; ++c) {
+    int64_t r = c, l1 = 0;
+    for (int d = key_dim - 1; d >= 0; --d) {
+      w[d] = (int32_t)(lo + r % side);
+      r /= side;
+      l1 += w[d] < 0 ? -w[d] : w[d];
+    }
+    if (kind == ASH_NB_RING && (l1 == 0 || l1 > radius)) continue;
+    if (count >= kMaxNeighborOffsets) return ASH_E_INVALID;
+    if (out_offsets)
+      for (int d = 0; d < key_dim; ++d) out_offsets[count * key_dim + d] = w[d];
+    ++count;
+  }
+  *out_count = count;
+  return ASH_OK;
+}
+
 ash_status_t ash_active_indices(ash_map_t m, int32_t* out_idx, int64_t* out_count, void* stream) {
   if (!m || !out_count || (m->c > 0 && !out_idx)) return ASH_E_INVALID;
   hipStream_t st = (hipStream_t)stream;

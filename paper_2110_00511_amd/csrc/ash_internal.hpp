@@ -27,6 +27,10 @@ constexpr uint32_t kSplitRowBytes = 64;
 constexpr uint32_t kVoxelDedup = 1;
 
 constexpr int64_t kMaxCount = (1ll << 31) - 3;  // positions and indices must fit PENDING(p)
+// Standard neighborhoods: at most this many offsets, enumerated from at most
+// this many candidates.
+constexpr int64_t kMaxNeighborOffsets = 1ll << 16;
+constexpr int64_t kMaxNeighborCandidates = 1ll << 24;
 constexpr uint64_t kMaxSlots = (1ull << 32) - 128;
 
 #define ASH_HIP(call)                           \

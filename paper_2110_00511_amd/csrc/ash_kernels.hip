@@ -68,6 +68,25 @@ struct VoxelKeys {
   }
 };
 
+// Neighbor keys (Listing 3 of Sec. 6.2.4; the 1-cube and 1-ring lookups of
+// Sec. 6.3): position p is query p / k shifted by offset p % k, word by word
+// with int32 addition wrapping modulo 2^32.  Positions of one query are
+// adjacent, so its key is read once per wavefront from one cache line.
+template <int KD>
+struct OffsetKeys {
+  const int32_t* __restrict__ keys;
+  const int32_t* __restrict__ offsets;
+  uint32_t k;
+  __device__ __forceinline__ bool load(uint32_t p, int32_t (&out)[KD]) const {
+    const uint32_t q = p / k;
+    const uint32_t o = p - q * k;
+#pragma unroll
+    for (int d = 0; d < KD; ++d)
+      out[d] = (int32_t)((uint32_t)keys[(size_t)q * KD + d] + (uint32_t)offsets[(size_t)o * KD + d]);
+    return true;
+  }
+};
+
 template <int KD>
 __device__ __forceinline__ bool keys_equal(const int32_t (&a)[KD], const int32_t (&b)[KD]) {
   bool eq = true;
@@ -671,8 +690,8 @@ __global__ void k_finalize(Meta* m, uint32_t cap, int mode, int silent, int chec
 // the first window that holds an EMPTY slot: a key is always claimed at the
 // first EMPTY slot of its sequence and slots never return to EMPTY outside a
 // rebuild.
-template <int KD, int G, int WL>
-__device__ __forceinline__ void find_tile(const TableRef& tb, const int32_t* __restrict__ keys, uint32_t n,
+template <int KD, int G, int WL, typename Src>
+__device__ __forceinline__ void find_tile(const TableRef& tb, const Src& src, uint32_t n,
                                           uint32_t tile, uint32_t rounds, int32_t* __restrict__ out_idx,
                                           uint8_t* __restrict__ out_mask, const ValueSet& vs, TileLds& lds) {
   using Win = Window<KD, G, WL>;
@@ -691,8 +710,7 @@ __device__ __forceinline__ void find_tile(const TableRef& tb, const int32_t* __r
     const uint32_t p = tile_base + r * kGroups + grp;
     if (p >= n) break;
     int32_t k[KD];
-#pragma unroll
-    for (int d = 0; d < KD; ++d) k[d] = keys[(size_t)p * KD + d];
+    src.load(p, k);
     const uint64_t h = key_hash<KD>(k);
     uint32_t base = home_slot(tb, h);
     uint32_t idx = kNoSlot;
@@ -730,7 +748,18 @@ __global__ __launch_bounds__(kBlock) void k_find(TableRef tb, const int32_t* __r
                                                  uint32_t rounds, int32_t* __restrict__ out_idx,
                                                  uint8_t* __restrict__ out_mask, ValueSet vs) {
   __shared__ TileLds lds;
-  find_tile<KD, G, WL>(tb, keys, n, blockIdx.x, rounds, out_idx, out_mask, vs, lds);
+  find_tile<KD, G, WL>(tb, BatchKeys<KD>{keys}, n, blockIdx.x, rounds, out_idx, out_mask, vs, lds);
+}
+
+// Neighbor lookups: a find over n * k shifted keys, results query-major.
+template <int KD, int G, int WL>
+__global__ __launch_bounds__(kBlock) void k_find_offsets(TableRef tb, OffsetKeys<KD> src, uint32_t n,
+                                                         uint32_t rounds, int32_t* __restrict__ out_idx,
+                                                         uint8_t* __restrict__ out_mask) {
+  __shared__ TileLds lds;
+  ValueSet none;
+  none.n = 0;
+  find_tile<KD, G, WL>(tb, src, n, blockIdx.x, rounds, out_idx, out_mask, none, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -924,6 +953,39 @@ __global__ __launch_bounds__(kBlock) void k_compact_flags(const uint8_t* __restr
     if (on[r]) out[s_prefix + rank[r]] = (int32_t)(base + r * kBlock + threadIdx.x);
 }
 
+// Set intersection (Sec. 6.4): the rows of the queries whose find mask is 1,
+// compacted in batch order.  The last tile's look-back sees every tile's
+// count, so it also finalizes (meta->result = number of rows).
+template <int KD>
+__global__ __launch_bounds__(kBlock) void k_compact_rows(const uint8_t* __restrict__ mask, uint32_t n,
+                                                         const int32_t* __restrict__ keys,
+                                                         int32_t* __restrict__ out, Meta* meta,
+                                                         uint64_t* __restrict__ status) {
+  __shared__ uint32_t s_prefix;
+  __shared__ uint64_t s_scan[kBlock / 64 + 1];
+  const uint32_t tile = blockIdx.x;
+  const uint32_t base = tile * kScanTile;
+  bool on[kScanItems];
+#pragma unroll
+  for (int r = 0; r < kScanItems; ++r) {
+    const uint32_t i = base + r * kBlock + threadIdx.x;
+    on[r] = i < n && mask[i] != 0;
+  }
+  uint32_t rank[kScanItems];
+  uint32_t total;
+  block_rank_rows(on, rank, total, s_scan);
+  const uint32_t prefix = block_lookback(status, tile, meta->epoch, total, &meta->status, &s_prefix);
+#pragma unroll
+  for (int r = 0; r < kScanItems; ++r) {
+    if (!on[r]) continue;
+    const size_t i = base + r * kBlock + threadIdx.x;
+    const size_t o = prefix + rank[r];
+#pragma unroll
+    for (int d = 0; d < KD; ++d) out[o * KD + d] = keys[i * KD + d];
+  }
+  if (threadIdx.x == 0 && tile == (n - 1) / kScanTile) finalize_total(meta, 0u, kFinalizeCount, 0, 0, prefix + total);
+}
+
 // ---------------------------------------------------------------------------
 // Rebuild (rehash, Sec. 4.5): every committed slot of the old table is
 // inserted into a fresh table as (key, COMMITTED(i)); tombstones are dropped.
@@ -1090,14 +1152,14 @@ __device__ __forceinline__ void batched_claim(const BatchItem& it, uint32_t tile
 template <int KD>
 __device__ __forceinline__ void batched_find(const BatchItem& it, uint32_t tile, TileLds& lds) {
   switch (it.g == 1 ? it.w : 100 + it.g) {
-    case 2: find_tile<KD, 1, 2>(it.tb, it.fkeys, it.n_find, tile, rounds_for_dev<1>(), it.fidx, it.fmask, it.vout, lds); break;
-    case 4: find_tile<KD, 1, 4>(it.tb, it.fkeys, it.n_find, tile, rounds_for_dev<1>(), it.fidx, it.fmask, it.vout, lds); break;
-    case 8: find_tile<KD, 1, 8>(it.tb, it.fkeys, it.n_find, tile, rounds_for_dev<1>(), it.fidx, it.fmask, it.vout, lds); break;
-    case 104: find_tile<KD, 4, 1>(it.tb, it.fkeys, it.n_find, tile, rounds_for_dev<4>(), it.fidx, it.fmask, it.vout, lds); break;
-    case 108: find_tile<KD, 8, 1>(it.tb, it.fkeys, it.n_find, tile, rounds_for_dev<8>(), it.fidx, it.fmask, it.vout, lds); break;
-    case 116: find_tile<KD, 16, 1>(it.tb, it.fkeys, it.n_find, tile, rounds_for_dev<16>(), it.fidx, it.fmask, it.vout, lds); break;
-    case 132: find_tile<KD, 32, 1>(it.tb, it.fkeys, it.n_find, tile, rounds_for_dev<32>(), it.fidx, it.fmask, it.vout, lds); break;
-    case 164: find_tile<KD, 64, 1>(it.tb, it.fkeys, it.n_find, tile, rounds_for_dev<64>(), it.fidx, it.fmask, it.vout, lds); break;
+    case 2: find_tile<KD, 1, 2>(it.tb, BatchKeys<KD>{it.fkeys}, it.n_find, tile, rounds_for_dev<1>(), it.fidx, it.fmask, it.vout, lds); break;
+    case 4: find_tile<KD, 1, 4>(it.tb, BatchKeys<KD>{it.fkeys}, it.n_find, tile, rounds_for_dev<1>(), it.fidx, it.fmask, it.vout, lds); break;
+    case 8: find_tile<KD, 1, 8>(it.tb, BatchKeys<KD>{it.fkeys}, it.n_find, tile, rounds_for_dev<1>(), it.fidx, it.fmask, it.vout, lds); break;
+    case 104: find_tile<KD, 4, 1>(it.tb, BatchKeys<KD>{it.fkeys}, it.n_find, tile, rounds_for_dev<4>(), it.fidx, it.fmask, it.vout, lds); break;
+    case 108: find_tile<KD, 8, 1>(it.tb, BatchKeys<KD>{it.fkeys}, it.n_find, tile, rounds_for_dev<8>(), it.fidx, it.fmask, it.vout, lds); break;
+    case 116: find_tile<KD, 16, 1>(it.tb, BatchKeys<KD>{it.fkeys}, it.n_find, tile, rounds_for_dev<16>(), it.fidx, it.fmask, it.vout, lds); break;
+    case 132: find_tile<KD, 32, 1>(it.tb, BatchKeys<KD>{it.fkeys}, it.n_find, tile, rounds_for_dev<32>(), it.fidx, it.fmask, it.vout, lds); break;
+    case 164: find_tile<KD, 64, 1>(it.tb, BatchKeys<KD>{it.fkeys}, it.n_find, tile, rounds_for_dev<64>(), it.fidx, it.fmask, it.vout, lds); break;
     default: break;
   }
 }
@@ -1411,6 +1473,17 @@ struct FindK {
 };
 
 template <int KD, int G, int WL>
+struct FindOffsetsK {
+  static hipError_t run(const TableRef& tb, const int32_t* keys, const int32_t* offsets, uint32_t k, uint32_t n,
+                        int32_t* out_idx, uint8_t* out_mask, hipStream_t st) {
+    const uint32_t rounds = rounds_for<G>();
+    hipLaunchKernelGGL((k_find_offsets<KD, G, WL>), dim3(cdiv(n, (kBlock / G) * rounds)), dim3(kBlock), 0, st, tb,
+                       OffsetKeys<KD>{keys, offsets, k}, n, rounds, out_idx, out_mask);
+    return hipGetLastError();
+  }
+};
+
+template <int KD, int G, int WL>
 struct EraseMarkK {
   static hipError_t run(const TableRef& tb, const int32_t* keys, uint32_t n, uint32_t epoch, uint32_t* slot_of,
                         int32_t* found, uint64_t* owner, uint8_t* lost, hipStream_t st) {
@@ -1546,6 +1619,24 @@ hipError_t launch_commit(int kd, const TableRef& tb, const int32_t* keys, uint32
 hipError_t launch_find(int kd, int g, int w, const TableRef& tb, const int32_t* keys, uint32_t n, int32_t* out_idx,
                        uint8_t* out_mask, const ValueSet& vs, hipStream_t st) {
   return with_kd_probe<FindK>(kd, g, w, tb, keys, n, out_idx, out_mask, vs, st);
+}
+
+hipError_t launch_find_offsets(int kd, int g, int w, const TableRef& tb, const int32_t* keys, const int32_t* offsets,
+                               uint32_t k, uint32_t n, int32_t* out_idx, uint8_t* out_mask, hipStream_t st) {
+  return with_kd_probe<FindOffsetsK>(kd, g, w, tb, keys, offsets, k, n, out_idx, out_mask, st);
+}
+
+hipError_t launch_compact_rows(int kd, const uint8_t* mask, uint32_t n, const int32_t* keys, int32_t* out, Meta* meta,
+                               uint64_t* status, hipStream_t st) {
+  const dim3 grid(cdiv(n, kScanTile));
+  switch (kd) {
+    case 1: hipLaunchKernelGGL(k_compact_rows<1>, grid, dim3(kBlock), 0, st, mask, n, keys, out, meta, status); break;
+    case 2: hipLaunchKernelGGL(k_compact_rows<2>, grid, dim3(kBlock), 0, st, mask, n, keys, out, meta, status); break;
+    case 3: hipLaunchKernelGGL(k_compact_rows<3>, grid, dim3(kBlock), 0, st, mask, n, keys, out, meta, status); break;
+    case 4: hipLaunchKernelGGL(k_compact_rows<4>, grid, dim3(kBlock), 0, st, mask, n, keys, out, meta, status); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_erase_mark(int kd, int g, int w, const TableRef& tb, const int32_t* keys, uint32_t n,

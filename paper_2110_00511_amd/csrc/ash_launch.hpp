@@ -49,6 +49,14 @@ hipError_t launch_scatter_values(const ValueSet& vs, const uint32_t* wlist, cons
                                  uint32_t n, uint32_t cap, hipStream_t st);
 hipError_t launch_find(int kd, int g, int w, const TableRef& tb, const int32_t* keys, uint32_t n, int32_t* out_idx,
                        uint8_t* out_mask, const ValueSet& vs, hipStream_t st);
+// Finds of keys[q] + offsets[o] for q < n / k, o < k (n = queries * k
+// positions, < 2^31 - 3); outputs query-major, either may be NULL.
+hipError_t launch_find_offsets(int kd, int g, int w, const TableRef& tb, const int32_t* keys, const int32_t* offsets,
+                               uint32_t k, uint32_t n, int32_t* out_idx, uint8_t* out_mask, hipStream_t st);
+// Rows of keys with mask 1, compacted in order (n >= 1); the count lands in
+// meta->result (the last tile finalizes with kFinalizeCount).
+hipError_t launch_compact_rows(int kd, const uint8_t* mask, uint32_t n, const int32_t* keys, int32_t* out, Meta* meta,
+                               uint64_t* status, hipStream_t st);
 hipError_t launch_erase_mark(int kd, int g, int w, const TableRef& tb, const int32_t* keys, uint32_t n,
                              uint32_t epoch, uint32_t* slot_of, int32_t* found, uint64_t* owner, uint8_t* lost,
                              hipStream_t st);

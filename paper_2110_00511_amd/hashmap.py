@@ -113,6 +113,29 @@ class HashMap:
         L.check(self._lib.ash_erase(self._m, _ptr(keys), n, _ptr(mask), _stream()), "ash_erase")
         return mask.bool()
 
+    def find_offsets(self, keys, offsets):
+        """Neighbor lookups: finds of keys[q] + offsets[o] (int32, wrapping),
+        returned as (idx[n, K], mask[n, K]) (Listing 3, Sec. 6.2.4)."""
+        keys = _keys(keys, self.key_dim, self.device)
+        offsets = _keys(offsets, self.key_dim, self.device)
+        n, k = keys.shape[0], offsets.shape[0]
+        idx = torch.empty((n, k), dtype=torch.int32, device=self.device)
+        mask = torch.empty((n, k), dtype=torch.uint8, device=self.device)
+        L.check(self._lib.ash_find_offsets(self._m, _ptr(keys), n, _ptr(offsets), k, _ptr(idx), _ptr(mask),
+                                           _stream()), "ash_find_offsets")
+        return idx, mask.bool()
+
+    def intersect(self, keys):
+        """The rows of keys that the map holds, in order, duplicates kept
+        (Sec. 6.4)."""
+        keys = _keys(keys, self.key_dim, self.device)
+        n = keys.shape[0]
+        out = torch.empty((max(n, 1), self.key_dim), dtype=torch.int32, device=self.device)
+        cnt = ctypes.c_int64()
+        L.check(self._lib.ash_intersect(self._m, _ptr(keys), n, _ptr(out), ctypes.byref(cnt), _stream()),
+                "ash_intersect")
+        return out[: cnt.value]
+
     def active_indices(self):
         out = torch.empty(max(self.capacity, 1), dtype=torch.int32, device=self.device)
         cnt = ctypes.c_int64()
@@ -189,6 +212,23 @@ class HashSet(HashMap):
 
     def __init__(self, capacity, key_dim=3, **kw):
         super().__init__(capacity, key_dim=key_dim, value_specs=(), **kw)
+
+
+NEIGHBORHOODS = {"radius": L.ASH_NB_RADIUS, "cube": L.ASH_NB_CUBE, "ring": L.ASH_NB_RING}
+
+
+def neighbor_offsets(kind="radius", radius=1, key_dim=3, device="cuda"):
+    """Offset table of a standard neighborhood ("radius": every word in
+    [-r, r]; "cube": every word in [0, r]; "ring": nonzero offsets with L1
+    norm <= r) as an int32 [K, key_dim] tensor."""
+    lib = L.load()
+    code = NEIGHBORHOODS[kind]
+    cnt = ctypes.c_int64()
+    L.check(lib.ash_neighbor_offsets(code, int(radius), int(key_dim), None, ctypes.byref(cnt)), "ash_neighbor_offsets")
+    host = (ctypes.c_int32 * max(cnt.value * key_dim, 1))()
+    L.check(lib.ash_neighbor_offsets(code, int(radius), int(key_dim), host, ctypes.byref(cnt)), "ash_neighbor_offsets")
+    out = torch.tensor(list(host)[: cnt.value * key_dim], dtype=torch.int32).reshape(cnt.value, key_dim)
+    return out.to(device) if device is not None else out
 
 
 def voxelize(points, voxel_size):

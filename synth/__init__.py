@@ -13,6 +13,9 @@ model, extended to 10M keys):
                 10M finds at 50% hit, 5M erases
   points        5M float32 xyz points on 20 random spheres/planes in a 10 m
                 box with N(0, 1 cm) noise (stand-in for the paper's scans)
+  surface_keys  the distinct lattice cells (int32x3) of those points on a
+                5 mm grid, in order of first appearance: the key set of a
+                neighbor search (Listing 3 of Sec. 6.2.4)
   batched       64 maps with log-uniform distinct counts in [1e3, 1e6]
   served        request stream over a 318^3 key universe
 """
@@ -97,6 +100,16 @@ def points(n=5_000_000, n_surfaces=20, box=10.0, sigma=0.01, seed=5):
             p = c + s * u + t * v
         out.append(p + rng.normal(0.0, sigma, size=(m, 3)))
     return np.ascontiguousarray(np.concatenate(out).astype(np.float32))
+
+
+def surface_keys(n=5_000_000, cell=0.005, seed=5):
+    """Distinct lattice cells of the surface points (nearest lattice point of
+    a cell-unit grid, in float64), in order of first appearance: integer keys
+    with the structure of a scanned surface."""
+    pts = points(n=n, seed=seed).astype(np.float64)
+    cells = np.rint(pts / cell).astype(np.int32)
+    _, first = np.unique(cells, axis=0, return_index=True)
+    return np.ascontiguousarray(cells[np.sort(first)])
 
 
 def batched(n_maps=64, channels=8, lo=1e3, hi=1e6, seed=6):

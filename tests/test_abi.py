@@ -83,3 +83,41 @@ def test_server_and_batched_reject_bad_arguments_on_the_host(lib):
     assert L.ash_server_stats(None, None, None) == _lib.ASH_E_INVALID
     assert L.ash_server_destroy(None) == _lib.ASH_E_INVALID
     assert L.ash_server_replay(None, None, 0, None, None, None, None) == _lib.ASH_E_INVALID
+
+
+def _offsets(L, kind, radius, kd):
+    cnt = ctypes.c_int64()
+    assert L.ash_neighbor_offsets(kind, radius, kd, None, ctypes.byref(cnt)) == 0
+    buf = (ctypes.c_int32 * max(cnt.value * kd, 1))()
+    assert L.ash_neighbor_offsets(kind, radius, kd, buf, ctypes.byref(cnt)) == 0
+    return [tuple(buf[i * kd:(i + 1) * kd]) for i in range(cnt.value)]
+
+
+@pytest.mark.parametrize("kd", [1, 2, 3, 4])
+@pytest.mark.parametrize("radius", [1, 2])
+def test_neighbor_offsets_are_the_standard_neighborhoods(lib, kd, radius):
+    """Host-only helper: the neighborhoods by their definitions, enumerated
+    with itertools (first word slowest)."""
+    import itertools
+    from paper_2110_00511_amd import _lib
+    L = _lib.load()
+    full = list(itertools.product(range(-radius, radius + 1), repeat=kd))
+    assert _offsets(L, _lib.ASH_NB_RADIUS, radius, kd) == full
+    assert _offsets(L, _lib.ASH_NB_CUBE, radius, kd) == list(itertools.product(range(radius + 1), repeat=kd))
+    ring = [o for o in full if 0 < sum(map(abs, o)) <= radius]
+    assert _offsets(L, _lib.ASH_NB_RING, radius, kd) == ring
+    if radius == 1:
+        assert len(full) == 3 ** kd and len(ring) == 2 * kd  # 27 and 6 in 3-D
+
+
+def test_neighbor_and_intersect_argument_errors(lib):
+    from paper_2110_00511_amd import _lib
+    L = _lib.load()
+    cnt = ctypes.c_int64()
+    assert L.ash_neighbor_offsets(7, 1, 3, None, ctypes.byref(cnt)) == _lib.ASH_E_INVALID
+    assert L.ash_neighbor_offsets(0, 0, 3, None, ctypes.byref(cnt)) == _lib.ASH_E_INVALID
+    assert L.ash_neighbor_offsets(0, 1, 5, None, ctypes.byref(cnt)) == _lib.ASH_E_INVALID
+    assert L.ash_neighbor_offsets(0, 64, 4, None, ctypes.byref(cnt)) == _lib.ASH_E_INVALID  # 129^4 candidates
+    assert L.ash_neighbor_offsets(0, 1, 3, None, None) == _lib.ASH_E_INVALID
+    assert L.ash_find_offsets(None, None, 0, None, 0, None, None, None) == _lib.ASH_E_INVALID
+    assert L.ash_intersect(None, None, 0, None, ctypes.byref(cnt), None) == _lib.ASH_E_INVALID
