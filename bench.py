@@ -120,6 +120,10 @@ def main():
                     help="plain: the headline 10M-key map; batched: 64 maps in one launch; voxelize: 5M points; "
                          "served: a Poisson request stream on a 2^25-capacity map")
     ap.add_argument("--requests", type=int, default=100_000, help="served: requests per run")
+    ap.add_argument("--query-order", default="given", choices=["given", "morton"],
+                    help="neighbors: query order (first appearance, or sorted by Z-order code)")
+    ap.add_argument("--neighbors-probe-group", type=int, default=1, help="neighbors: probe group of the map")
+    ap.add_argument("--neighbors-bucket-width", type=int, default=4, help="neighbors: bucket width of the map")
     ap.add_argument("--served-max-load", type=float, default=0.5, help="served: max_load of the served map's table")
     # A served map sees many small batches whose kernels are latency-bound: one
     # lane per key probes all keys of a block at once (5.5 against 4.5 G
@@ -456,6 +460,18 @@ def bench_voxelize(args):
         "cpu_baseline": cpu}), flush=True)
 
 
+def morton3(keys):
+    """Z-order code of int32x3 keys (21 bits per word after a shift to
+    non-negative), for ordering queries so neighbors of nearby cells are
+    looked up close in time."""
+    k = (keys - keys.min(axis=0)).astype(np.uint64) & np.uint64((1 << 21) - 1)
+    code = np.zeros(len(keys), np.uint64)
+    for b in range(21):
+        for d in range(3):
+            code |= ((k[:, d] >> np.uint64(b)) & np.uint64(1)) << np.uint64(3 * b + d)
+    return code
+
+
 def bench_neighbors(args):
     """Neighbor search (Listing 3 of Sec. 6.2.4): the 27 radius-1 neighbors of
     every distinct 5 mm lattice cell of the 5M-point surface cloud (4.8M
@@ -470,9 +486,12 @@ def bench_neighbors(args):
 
     torch.cuda.set_device(0)
     keys_np = synth.surface_keys()
+    if args.query_order == "morton":
+        keys_np = keys_np[np.argsort(morton3(keys_np), kind="stable")]
     n = len(keys_np)
     keys = torch.from_numpy(keys_np).cuda()
-    m = ash.HashMap(n, 3, probe_group=args.probe_group, bucket_width=args.bucket_width, max_load=args.max_load)
+    m = ash.HashMap(n, 3, probe_group=args.neighbors_probe_group, bucket_width=args.neighbors_bucket_width,
+                    max_load=args.max_load)
     m.insert(keys)
     lib = L.load()
     sp = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
@@ -540,8 +559,8 @@ def bench_neighbors(args):
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": f"{n} distinct 5 mm lattice cells of 5M surface points; queries = the cells",
-                   "probe_group": args.probe_group, "bucket_width": args.bucket_width, "max_load": args.max_load,
-                   "sweep": sweep},
+                   "query_order": args.query_order, "probe_group": args.neighbors_probe_group,
+                   "bucket_width": args.neighbors_bucket_width, "max_load": args.max_load, "sweep": sweep},
         "roofline": {"bound": "hbm", "kernel": "find_offsets", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "algorithmic_bytes_per_lookup": round(per_lookup, 2), "kernel_ms": round(outs["kernel_ms"], 4)},
