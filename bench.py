@@ -116,7 +116,8 @@ def main():
                     help="positions of the workload the oracle runs for cpu_baseline (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, copy 256 MiB once (reference kernel for byte counters)")
-    ap.add_argument("--workload", default="plain", choices=["plain", "batched", "voxelize", "served", "neighbors"],
+    ap.add_argument("--workload", default="plain",
+                    choices=["plain", "batched", "voxelize", "served", "neighbors", "values"],
                     help="plain: the headline 10M-key map; batched: 64 maps in one launch; voxelize: 5M points; "
                          "served: a Poisson request stream on a 2^25-capacity map")
     ap.add_argument("--requests", type=int, default=100_000, help="served: requests per run")
@@ -142,6 +143,8 @@ def main():
         return bench_voxelize(args)
     if args.workload == "neighbors":
         return bench_neighbors(args)
+    if args.workload == "values":
+        return bench_values(args)
     if args.workload == "served":
         return bench_served(args)
 
@@ -458,6 +461,90 @@ def bench_voxelize(args):
         "higher_is_better": True, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{n} points on 20 random spheres/planes in a 10 m box, sigma 1 cm", "sweep": out},
         "cpu_baseline": cpu}), flush=True)
+
+
+def bench_values(args):
+    """Setup 1's value-size sweep (Sec. 5.1): 1M int32x3 keys (distinct ratio
+    0.99) with f32 x 2^j value rows, j = 0..12 (4 B to 16 KB), capacity = the
+    number of keys.  Per size: insert into a cleared map, then a 50%-hit find
+    that gathers the hits' rows.  Rows under 64 B are copied inside the commit
+    and the find; longer ones by the separate row pass after the commit.
+    Value rows are drawn on the device from a seeded generator."""
+    import torch
+
+    import paper_2110_00511_amd as ash
+    import synth
+    from paper_2110_00511_amd import _lib as L
+
+    torch.cuda.set_device(0)
+    d = synth.value_sweep()
+    n, nf = len(d["keys"]), len(d["find_keys"])
+    keys = torch.from_numpy(d["keys"]).cuda()
+    fkeys = torch.from_numpy(d["find_keys"]).cuda()
+    idx = torch.empty(n, dtype=torch.int32, device="cuda")
+    mask = torch.empty(n, dtype=torch.uint8, device="cuda")
+    fidx = torch.empty(nf, dtype=torch.int32, device="cuda")
+    fmask = torch.empty(nf, dtype=torch.uint8, device="cuda")
+    lib = L.load()
+    sp = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    P = ctypes.c_void_p
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(8)
+    sweep = {}
+    for j in range(0, 13):
+        ch = 1 << j
+        m = ash.HashMap(n, 3, [(torch.float32, ch)])
+        vals = torch.randn((n, ch), dtype=torch.float32, device="cuda", generator=gen)
+        outv = torch.empty((nf, ch), dtype=torch.float32, device="cuda")
+        vptr = (ctypes.c_void_p * 1)(vals.data_ptr())
+        optr = (ctypes.c_void_p * 1)(outv.data_ptr())
+
+        def ins():
+            L.check(lib.ash_clear(m._m, sp), "clear")
+            L.check(lib.ash_insert(m._m, P(keys.data_ptr()), n, ctypes.cast(vptr, P), P(idx.data_ptr()),
+                                   P(mask.data_ptr()), sp), "insert")
+
+        def fnd():
+            L.check(lib.ash_find(m._m, P(fkeys.data_ptr()), nf, P(fidx.data_ptr()), P(fmask.data_ptr()),
+                                 ctypes.cast(optr, P), sp), "find")
+        steps = max(1, args.steps // (1 if j < 10 else 2))
+        ins()
+        m.profile(True)
+        m.profile_collect()
+        t_ins = _timed(ins, steps, 1)
+        kern = {k: v[1] / v[0] for k, v in m.profile_collect().items()}
+        t_fnd = _timed(fnd, steps, 1)
+        kern_f = {k: v[1] / v[0] for k, v in m.profile_collect().items()}
+        m.profile(False)
+        assert m.device_status() == 0
+        u = int(mask.sum().item())
+        hits = int(fmask.sum().item())
+        row = 4 * ch
+        # value bytes moved: each inserted row read from the batch and written to v^B, each hit row read and written
+        ins_gb = 2.0 * u * row / 1e9
+        fnd_gb = 2.0 * hits * row / 1e9
+        sweep[f"f32x{ch}"] = {
+            "row_bytes": row, "insert_ms": round(t_ins, 4), "find_ms": round(t_fnd, 4),
+            "insert_Mops": round(n / t_ins / 1e3, 1), "find_Mops": round(nf / t_fnd / 1e3, 1),
+            "insert_value_GBps": round(ins_gb / t_ins * 1e3, 1), "find_value_GBps": round(fnd_gb / t_fnd * 1e3, 1),
+            "kernel_ms": {k: round(v, 4) for k, v in {**kern, **{"find": kern_f.get("find", 0.0)}}.items()},
+            "new_keys": u, "hits": hits}
+        del m, vals, outv
+        torch.cuda.empty_cache()
+    top = sweep["f32x4096"]
+    # roofline of the dominant kernel at 16 KB rows: the separate row pass reads and writes every inserted row
+    vk = top["kernel_ms"]["values"]
+    achieved = (top["new_keys"] * (2 * top["row_bytes"] + 8)) / (vk / 1e3) / 1e9
+    print(json.dumps({
+        "metric": "value-row GB/s moved by insert (1M keys, f32x4096 rows); Setup 1 sweep f32x1..4096",
+        "value": top["insert_value_GBps"], "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": top["insert_ms"], "higher_is_better": True, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": f"{n} int32x3 keys (distinct ratio 0.99), capacity {n}, f32 x 2^j rows; "
+                               f"{nf} finds (half hits) gathering rows", "sweep": sweep},
+        "roofline": {"bound": "hbm", "kernel": "values", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "algorithmic_bytes_per_row": 2 * top["row_bytes"] + 8, "kernel_ms": vk},
+        "cpu_baseline": None}), flush=True)
 
 
 def morton3(keys):

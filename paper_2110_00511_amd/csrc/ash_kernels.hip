@@ -639,8 +639,13 @@ __device__ __forceinline__ void commit_tile(const TableRef& tb, const int32_t* _
 // the number of winners in meta->result and moved t past their indices, so
 // winner w (in batch order) went to i = h[t - total + w] from position
 // wlist[w].  dst row i = src row p, in units of V; threads past the winners
-// only read the two counters.
-template <typename V>
+// only read the two counters.  Each thread takes U units a grid stride
+// apart and issues all their loads before any store, so U (wlist, heap, row)
+// chains are in flight per thread; that pays for rows of 1 KB and more
+// (16 KB rows: 7.25 -> 6.55 ms for 1M rows) and costs up to 40% below.
+constexpr uint32_t kUnrollRowBytes = 1024;
+
+template <typename V, int U>
 __global__ __launch_bounds__(kBlock) void k_scatter_values(const uint32_t* __restrict__ wlist,
                                                            const int32_t* __restrict__ heap, const Meta* meta,
                                                            const uint8_t* __restrict__ src, uint8_t* __restrict__ dst,
@@ -650,20 +655,32 @@ __global__ __launch_bounds__(kBlock) void k_scatter_values(const uint32_t* __res
   const uint32_t base = meta->t - total;
   const uint32_t units = row_bytes / (uint32_t)sizeof(V);
   const uint64_t items = (uint64_t)total * units;
-  for (uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x; e < items; e += (uint64_t)gridDim.x * kBlock) {
-    uint32_t w, c;
-    if (units_log2 != 0xFFu) {
-      w = (uint32_t)(e >> units_log2);
-      c = (uint32_t)e & (units - 1u);
-    } else {
-      w = (uint32_t)(e / units);
-      c = (uint32_t)(e - (uint64_t)w * units);
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  for (uint64_t e0 = (uint64_t)blockIdx.x * kBlock + threadIdx.x; e0 < items; e0 += stride * U) {
+    V v[U];
+    V* to[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      to[k] = nullptr;
+      const uint64_t e = e0 + (uint64_t)k * stride;
+      if (e >= items) continue;
+      uint32_t w, c;
+      if (units_log2 != 0xFFu) {
+        w = (uint32_t)(e >> units_log2);
+        c = (uint32_t)e & (units - 1u);
+      } else {
+        w = (uint32_t)(e / units);
+        c = (uint32_t)(e - (uint64_t)w * units);
+      }
+      const uint32_t p = wlist[w];
+      const uint32_t i = (uint32_t)heap[base + w];
+      if (p >= n || i >= cap) continue;  // cannot happen: every winner listed itself
+      v[k] = reinterpret_cast<const V*>(src + (size_t)p * row_bytes)[c];
+      to[k] = reinterpret_cast<V*>(dst + (size_t)i * row_bytes) + c;
     }
-    const uint32_t p = wlist[w];
-    const uint32_t i = (uint32_t)heap[base + w];
-    if (p >= n || i >= cap) continue;  // cannot happen: every winner listed itself
-    const V v = reinterpret_cast<const V*>(src + (size_t)p * row_bytes)[c];
-    reinterpret_cast<V*>(dst + (size_t)i * row_bytes)[c] = v;
+#pragma unroll
+    for (int k = 0; k < U; ++k)
+      if (to[k]) *to[k] = v[k];
   }
 }
 
@@ -1568,6 +1585,22 @@ static hipError_t commit_k(const TableRef& tb, const int32_t* keys, uint32_t n, 
   return hipGetLastError();
 }
 
+template <typename V, int U>
+static void scatter_values_k(const ValueSet& vs, int j, const uint32_t* wlist, const int32_t* heap, const Meta* meta,
+                             uint32_t n, uint32_t cap, uint32_t grid, hipStream_t st) {
+  hipLaunchKernelGGL((k_scatter_values<V, U>), dim3(grid), dim3(kBlock), 0, st, wlist, heap, meta, vs.src[j],
+                     vs.dst[j], vs.row_bytes[j], vs.units_log2[j], n, cap);
+}
+
+template <typename V>
+static void scatter_values_v(const ValueSet& vs, int j, const uint32_t* wlist, const int32_t* heap, const Meta* meta,
+                             uint32_t n, uint32_t cap, uint32_t grid, hipStream_t st) {
+  if (vs.row_bytes[j] >= kUnrollRowBytes)
+    scatter_values_k<V, 4>(vs, j, wlist, heap, meta, n, cap, grid, st);
+  else
+    scatter_values_k<V, 1>(vs, j, wlist, heap, meta, n, cap, grid, st);
+}
+
 hipError_t launch_scatter_values(const ValueSet& vs, const uint32_t* wlist, const int32_t* heap, const Meta* meta,
                                  uint32_t n, uint32_t cap, hipStream_t st) {
   hipError_t e = hipSuccess;
@@ -1577,26 +1610,11 @@ hipError_t launch_scatter_values(const ValueSet& vs, const uint32_t* wlist, cons
     const uint32_t grid =
         (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(((uint64_t)n * units + kBlock - 1) / kBlock, 16384));
     switch (vs.vec[j]) {
-      case 16:
-        hipLaunchKernelGGL(k_scatter_values<uint4>, dim3(grid), dim3(kBlock), 0, st, wlist, heap, meta, vs.src[j],
-                           vs.dst[j], vs.row_bytes[j], vs.units_log2[j], n, cap);
-        break;
-      case 8:
-        hipLaunchKernelGGL(k_scatter_values<uint2>, dim3(grid), dim3(kBlock), 0, st, wlist, heap, meta, vs.src[j],
-                           vs.dst[j], vs.row_bytes[j], vs.units_log2[j], n, cap);
-        break;
-      case 4:
-        hipLaunchKernelGGL(k_scatter_values<uint32_t>, dim3(grid), dim3(kBlock), 0, st, wlist, heap, meta, vs.src[j],
-                           vs.dst[j], vs.row_bytes[j], vs.units_log2[j], n, cap);
-        break;
-      case 2:
-        hipLaunchKernelGGL(k_scatter_values<uint16_t>, dim3(grid), dim3(kBlock), 0, st, wlist, heap, meta, vs.src[j],
-                           vs.dst[j], vs.row_bytes[j], vs.units_log2[j], n, cap);
-        break;
-      default:
-        hipLaunchKernelGGL(k_scatter_values<uint8_t>, dim3(grid), dim3(kBlock), 0, st, wlist, heap, meta, vs.src[j],
-                           vs.dst[j], vs.row_bytes[j], vs.units_log2[j], n, cap);
-        break;
+      case 16: scatter_values_v<uint4>(vs, j, wlist, heap, meta, n, cap, grid, st); break;
+      case 8: scatter_values_v<uint2>(vs, j, wlist, heap, meta, n, cap, grid, st); break;
+      case 4: scatter_values_v<uint32_t>(vs, j, wlist, heap, meta, n, cap, grid, st); break;
+      case 2: scatter_values_v<uint16_t>(vs, j, wlist, heap, meta, n, cap, grid, st); break;
+      default: scatter_values_v<uint8_t>(vs, j, wlist, heap, meta, n, cap, grid, st); break;
     }
     e = hipGetLastError();
   }

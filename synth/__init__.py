@@ -16,6 +16,8 @@ model, extended to 10M keys):
   surface_keys  the distinct lattice cells (int32x3) of those points on a
                 5 mm grid, in order of first appearance: the key set of a
                 neighbor search (Listing 3 of Sec. 6.2.4)
+  value_sweep   1M int32x3 keys (distinct ratio ~0.99) and a 50%-hit find
+                batch for value rows of 2^j floats (Setup 1's sweep)
   batched       64 maps with log-uniform distinct counts in [1e3, 1e6]
   served        request stream over a 318^3 key universe
 """
@@ -110,6 +112,20 @@ def surface_keys(n=5_000_000, cell=0.005, seed=5):
     cells = np.rint(pts / cell).astype(np.int32)
     _, first = np.unique(cells, axis=0, return_index=True)
     return np.ascontiguousarray(cells[np.sort(first)])
+
+
+def value_sweep(n=1_000_000, side=368, seed=8):
+    """Keys of the value-size sweep (Setup 1 of Sec. 5.1 at its largest c):
+    n int32x3 keys uniform in [0, side)^3 (distinct ratio ~0.99 for the
+    defaults) and an n-key find batch, half drawn from the inserted keys and
+    half from [side, 2 side)^3.  Value rows are drawn by the caller."""
+    rng = np.random.default_rng(seed)
+    keys = rng.integers(0, side, size=(n, 3), dtype=np.int32)
+    half = n // 2
+    present = keys[rng.integers(0, n, size=half)]
+    absent = rng.integers(side, 2 * side, size=(n - half, 3), dtype=np.int32)
+    find_keys = np.concatenate([present, absent])[rng.permutation(n)]
+    return dict(keys=keys, find_keys=np.ascontiguousarray(find_keys))
 
 
 def batched(n_maps=64, channels=8, lo=1e3, hi=1e6, seed=6):
