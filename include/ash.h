@@ -194,6 +194,36 @@ ash_status_t ash_intersect(ash_map_t map, const int32_t* keys, int64_t n,
                            int32_t* out_keys, int64_t* out_count,
                            void* stream);
 
+/* Saving and loading (the paper stores a map on disk between processing
+ * stages, Sec. 6.3).  ash_save writes the map's logical state to a file and
+ * synchronizes; ash_load creates a new map (allocator and tuning as for
+ * ash_create) holding exactly that state: the same capacity, heap h and top
+ * t, live indices, keys and value rows, so it hands out the indices the saved
+ * map would have.  Value rows of free indices are not kept (they read as
+ * zero).  The file is little-endian:
+ *   char magic[8] = "ASHMAP", 0, 1;
+ *   int32 key_dim, n_values; int64 capacity c, size t;
+ *   n_values x { int32 dtype, int32 0, int64 elems };
+ *   int32 heap[c]; int32 live[t] (ascending); int32 keys[t][key_dim];
+ *   for each value buffer j: rows[t][row_bytes_j] (in the order of live).
+ * ash_load checks the whole file before any device work (magic, sizes,
+ * ascending live indices below c, a free region h[t..c) that holds every
+ * other index exactly once, heap entries below t in range, distinct keys, no
+ * trailing bytes) and returns ASH_E_INVALID for a
+ * file that fails, or that cannot be opened, read or written.  Both
+ * synchronize `stream`. */
+ash_status_t ash_save(ash_map_t map, const char* path, void* stream);
+ash_status_t ash_load(const char* path, const ash_allocator_t* allocator,
+                      const ash_tuning_t* tuning, void* stream,
+                      ash_map_t* out);
+
+/* Key width, number of value buffers and, when the arrays are given (n_values
+ * entries each), the value dtypes and elements per row given at creation.
+ * Host only. */
+ash_status_t ash_describe(ash_map_t map, int32_t* out_key_dim,
+                          int32_t* out_n_values, ash_dtype_t* out_dtypes,
+                          int64_t* out_elems);
+
 /* Live buffer indices in ascending order (the active set gathered for
  * rehashing, Sec. 4.5).  out_idx is a device array of at least `size`
  * entries; *out_count (host) receives the count.  Synchronizes. */

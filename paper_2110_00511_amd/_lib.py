@@ -75,6 +75,9 @@ SIGNATURES = {
     "ash_find_offsets": (ST, [P, P, I64, P, I32, P, P, P]),
     "ash_neighbor_offsets": (ST, [I32, I32, I32, P, ctypes.POINTER(I64)]),
     "ash_intersect": (ST, [P, P, I64, P, ctypes.POINTER(I64), P]),
+    "ash_save": (ST, [P, ctypes.c_char_p, P]),
+    "ash_load": (ST, [ctypes.c_char_p, P, P, P, ctypes.POINTER(P)]),
+    "ash_describe": (ST, [P, ctypes.POINTER(I32), ctypes.POINTER(I32), P, P]),
     "ash_active_indices": (ST, [P, P, ctypes.POINTER(I64), P]),
     "ash_rehash": (ST, [P, I64, P]),
     "ash_clear": (ST, [P, P]),

@@ -102,7 +102,7 @@ void free_buffers(ash_map* m, hipStream_t st) {
 
 // Rebuilds the slot table of `m` (new slot array, tombstones dropped) from the
 // committed slots of the old table, sized for max(c, room_for) keys.
-ash_status_t rebuild_table(ash_map* m, int64_t live, hipStream_t st, int64_t room_for = 0) {
+ash_status_t rebuild_table(ash_map* m, int64_t live, hipStream_t st, int64_t room_for) {
   uint32_t nslots;
   ASH_TRY(slots_for(std::max(m->c, room_for), m->max_load, m->W, m->G, &nslots));
   uint32_t* fresh = (uint32_t*)m->mem.get((size_t)nslots * m->slot_words() * 4, st);
@@ -360,6 +360,8 @@ ash_status_t ash_create(int64_t capacity, int32_t key_dim, int32_t n_values, con
   m->key_dim = key_dim;
   m->n_values = n_values;
   m->row_bytes = rb;
+  m->dtypes.assign(value_dtypes, value_dtypes + n_values);
+  m->elems.assign(value_elems, value_elems + n_values);
   m->W = W;
   m->G = G;
   m->max_load = lf;

@@ -134,6 +134,8 @@ struct ash_map {
   int key_dim = 3;
   int n_values = 0;
   std::vector<uint32_t> row_bytes;
+  std::vector<ash_dtype_t> dtypes;  // as given at creation
+  std::vector<int64_t> elems;
   int W = 4, G = 4;
   float max_load = 0.5f;
   uint32_t flags = 0;
@@ -183,6 +185,9 @@ namespace ash_host {
 // Implemented in ash_api.hip.
 ash_status_t read_meta(ash_map* m, Meta* out, hipStream_t st);
 ash_status_t ensure_scratch(ash_map* m, int64_t n, hipStream_t st);
+// Rebuilds the slot table from the committed slots of m->table (m->nslots of
+// them), which it frees; live = number of committed slots.  Synchronizes.
+ash_status_t rebuild_table(ash_map* m, int64_t live, hipStream_t st, int64_t room_for = 0);
 ash_status_t insert_impl(ash_map* m, const int32_t* keys, int64_t n, const void* const* values, int32_t* out_idx,
                          uint8_t* out_mask, hipStream_t st);
 

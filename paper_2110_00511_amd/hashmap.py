@@ -60,6 +60,38 @@ class HashMap:
                                          ctypes.cast(els, ctypes.c_void_p), ctypes.byref(self._alloc.struct),
                                          ctypes.byref(tun), _stream(), ctypes.byref(self._m)), "ash_create")
 
+    def save(self, path):
+        """Writes the map's state (capacity, heap, live indices, keys, value
+        rows) to a file; synchronizes."""
+        L.check(self._lib.ash_save(self._m, str(path).encode(), _stream()), "ash_save")
+
+    @classmethod
+    def load(cls, path, device="cuda", bucket_width=4, probe_group=4, max_load=0.5, autogrow=False, lds_dedup=False):
+        """A map holding exactly the state a file was saved with (same
+        indices, heap and rows), with the given table tuning."""
+        self = cls.__new__(cls)
+        self._lib = L.load()
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self._alloc = L.TorchAllocator(self.device)
+        flags = (L.ASH_F_AUTOGROW if autogrow else 0) | (L.ASH_F_LDS_DEDUP if lds_dedup else 0)
+        tun = L.AshTuning(bucket_width, probe_group, max_load, flags)
+        self._m = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            L.check(self._lib.ash_load(str(path).encode(), ctypes.byref(self._alloc.struct), ctypes.byref(tun),
+                                       _stream(), ctypes.byref(self._m)), "ash_load")
+        kd, nv = ctypes.c_int32(), ctypes.c_int32()
+        L.check(self._lib.ash_describe(self._m, ctypes.byref(kd), ctypes.byref(nv), None, None), "ash_describe")
+        dts = (ctypes.c_int * max(nv.value, 1))()
+        els = (ctypes.c_int64 * max(nv.value, 1))()
+        L.check(self._lib.ash_describe(self._m, ctypes.byref(kd), ctypes.byref(nv), ctypes.cast(dts, ctypes.c_void_p),
+                                       ctypes.cast(els, ctypes.c_void_p)), "ash_describe")
+        codes = {v: k for k, v in _DTYPES.items()}
+        self.key_dim = kd.value
+        self.value_specs = [(codes[dts[j]], int(els[j])) for j in range(nv.value)]
+        return self
+
     def __del__(self):
         m = getattr(self, "_m", None)
         if m is not None and m.value:

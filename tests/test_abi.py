@@ -121,3 +121,39 @@ def test_neighbor_and_intersect_argument_errors(lib):
     assert L.ash_neighbor_offsets(0, 1, 3, None, None) == _lib.ASH_E_INVALID
     assert L.ash_find_offsets(None, None, 0, None, 0, None, None, None) == _lib.ASH_E_INVALID
     assert L.ash_intersect(None, None, 0, None, ctypes.byref(cnt), None) == _lib.ASH_E_INVALID
+
+
+def _map_file(kd=2, c=4, live=(1, 3), keys=((1, 2), (3, 4)), heap=None, extra=b"", magic=b"ASHMAP\x00\x01"):
+    import struct
+    heap = list(heap) if heap is not None else list(live) + [i for i in range(c) if i not in live]
+    out = magic + struct.pack("<iiqq", kd, 1, c, len(live)) + struct.pack("<iiq", 2, 0, 1)
+    out += struct.pack(f"<{c}i", *heap) + struct.pack(f"<{len(live)}i", *live)
+    out += b"".join(struct.pack(f"<{kd}i", *k) for k in keys) + b"\0" * 4 * len(live)
+    return out + extra
+
+
+@pytest.mark.parametrize("case", ["missing", "magic", "truncated", "trailing", "free_index_twice",
+                                  "live_index_free", "stale_entry_out_of_range", "live_unsorted",
+                                  "duplicate_keys", "bad_dtype"])
+def test_load_rejects_bad_files_before_device_work(lib, tmp_path, case):
+    """Every check of ash_load runs on the host before a map is created, so a
+    bad file fails here without a GPU."""
+    from paper_2110_00511_amd import _lib
+    L = _lib.load()
+    files = {
+        "magic": _map_file(magic=b"ASHMAP\x00\x02"),
+        "truncated": _map_file()[:-3],
+        "trailing": _map_file(extra=b"\0"),
+        "free_index_twice": _map_file(heap=[1, 3, 0, 0]),
+        "live_index_free": _map_file(heap=[0, 2, 3, 2]),
+        "stale_entry_out_of_range": _map_file(heap=[7, 3, 0, 2]),
+        "live_unsorted": _map_file(live=(3, 1), heap=[3, 1, 0, 2]),
+        "duplicate_keys": _map_file(keys=((1, 2), (1, 2))),
+        "bad_dtype": _map_file().replace(b"\x02\x00\x00\x00\x00\x00\x00\x00\x01\x00", b"\x09\x00\x00\x00\x00\x00\x00\x00\x01\x00", 1),
+    }
+    path = tmp_path / "m.ash"
+    if case != "missing":
+        path.write_bytes(files[case])
+    out = ctypes.c_void_p()
+    assert L.ash_load(str(path).encode(), None, None, None, ctypes.byref(out)) == _lib.ASH_E_INVALID
+    assert not out.value
