@@ -43,27 +43,35 @@ STORE = 32        # a small random store writes a 32-byte sector
 # write x1.0000).  They hold for the kernel sources with these SHA-256 digests
 # only: traffic is reported as null for any other sources or workload.
 MEASURED_TRAFFIC = {
-    "claim": 2.4238e9,
-    "commit": 0.9224e9,
-    "find": 1.4429e9,
+    "claim": 2.4239e9,
+    "commit": 0.9233e9,
+    "find": 1.4430e9,
     "erase_mark": 0.8949e9,
     "erase_commit": 0.1803e9,
 }
+# The same for the neighbor search (radius 1 over the 4.8M surface cells,
+# one lane per key, W = 4, max load 0.5, queries in first-appearance order).
+MEASURED_TRAFFIC_NEIGHBORS = 18.53e9
 MEASURED_SOURCES = {
-    "ash_kernels.hip": "9ee5e0017cd8c00658d6758f9f1a2527604d12c611346f136ba9d9e383addd90",
+    "ash_kernels.hip": "4e62123670148013259f2cbd06a5f65e8c889ffbafcdd671fd81f27b72abbf6e",
     "ash_device.hpp": "98d566e65faa8c582630eb193e8162b8dd818730df1046ae6868bd81c89866f6",
 }
 
 
-def traffic_applies(args):
-    """True when the kernels and the workload are the ones the counters were taken on."""
+def sources_measured():
+    """True when the kernel sources are the ones the counters were taken on."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_2110_00511_amd", "csrc")
     for name, digest in MEASURED_SOURCES.items():
         with open(os.path.join(csrc, name), "rb") as f:
             if hashlib.sha256(f.read()).hexdigest() != digest:
                 return False
-    return ((args.rho, args.channels, args.probe_group, args.bucket_width, args.max_load) == (0.5, 8, 4, 4, 0.5)
+    return True
+
+
+def traffic_applies(args):
+    """True when the kernels and the workload are the ones the counters were taken on."""
+    return sources_measured() and ((args.rho, args.channels, args.probe_group, args.bucket_width, args.max_load) == (0.5, 8, 4, 4, 0.5)
             and not args.lds_dedup and not args.sorted_keys)
 
 
@@ -627,6 +635,10 @@ def bench_neighbors(args):
     # index and mask outputs, and the query key read once per query
     per_lookup = READ_LINE + 4 + 1 + 12.0 / k
     kern_s = outs["kernel_ms"] / 1e3
+    nb_traffic = None
+    if (sources_measured() and args.query_order == "given" and args.max_load == 0.5
+            and (args.neighbors_probe_group, args.neighbors_bucket_width) == (1, 4)):
+        nb_traffic = round(MEASURED_TRAFFIC_NEIGHBORS / 1e9, 2)
     achieved = per_lookup * n * k / kern_s / 1e9
     cpu = None
     if args.cpu_sample > 0:
@@ -649,7 +661,8 @@ def bench_neighbors(args):
                    "query_order": args.query_order, "probe_group": args.neighbors_probe_group,
                    "bucket_width": args.neighbors_bucket_width, "max_load": args.max_load, "sweep": sweep},
         "roofline": {"bound": "hbm", "kernel": "find_offsets", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": nb_traffic,
+                     "traffic_unit": "GB per launch",
                      "algorithmic_bytes_per_lookup": round(per_lookup, 2), "kernel_ms": round(outs["kernel_ms"], 4)},
         "cpu_baseline": cpu}), flush=True)
 
