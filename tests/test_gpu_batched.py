@@ -156,3 +156,46 @@ def test_batched_other_key_dims(ash, key_dim):
         assert np.array_equal(bits(host(r["find_values"][0])), bits(fv))
     check_maps(maps, oracles)
     assert [m.device_status() for m in maps] == [0, 0, 0]
+
+
+def test_batched_full_size(ash):
+    """The benchmark's 64 maps (distinct counts log-uniform in [1e3, 1e6],
+    f32x8 values) in one persistent launch with the batched tuner's shapes.
+    Every map is fresh, so results follow from numpy alone: the insert mask
+    marks first occurrences, their indices are ranks, a find returns the rank
+    of its key and the first occurrence's row."""
+    import synth
+    maps_d = synth.batched()
+    maps, ops = [], []
+    for d in maps_d:
+        n = len(d["keys"])
+        tun, _ = ash.autotune(d["capacity"], n, 0.5, value_specs=[(torch.float32, 8)], batched=True)
+        m = ash.HashMap(d["capacity"], 3, [(torch.float32, 8)], **tun)
+        maps.append(m)
+        ops.append(dict(map=m, insert_keys=dev(d["keys"]), insert_values=[dev(d["values"])],
+                        find_keys=dev(d["find_keys"]), gather=True))
+    res = ash.batched(ops, fused=True)
+    torch.cuda.synchronize()
+    for d, r, m in zip(maps_d, res, maps):
+        keys, vals, fk = d["keys"], d["values"], d["find_keys"]
+        packed = np.ascontiguousarray(keys).view(np.dtype((np.void, 12))).ravel()
+        _, first, inv = np.unique(packed, return_index=True, return_inverse=True)
+        rank = np.empty(len(first), np.int64)
+        rank[np.argsort(first)] = np.arange(len(first))  # rank of each distinct key in batch order
+        want_mask = np.zeros(len(keys), bool)
+        want_mask[first] = True
+        assert np.array_equal(host(r["insert_mask"]), want_mask)
+        gi = host(r["insert_idx"])
+        assert np.array_equal(gi[want_mask], rank[inv[want_mask]].astype(np.int32))
+        assert np.all(gi[~want_mask] == -1)
+        fpacked = np.ascontiguousarray(fk).view(np.dtype((np.void, 12))).ravel()
+        uniq = np.unique(packed)
+        pos = np.searchsorted(uniq, fpacked)
+        hit = (pos < len(uniq)) & (uniq[np.minimum(pos, len(uniq) - 1)] == fpacked)
+        assert np.array_equal(host(r["find_mask"]), hit)
+        fi = host(r["find_idx"])
+        assert np.array_equal(fi[hit], rank[pos[hit]].astype(np.int32))
+        assert np.all(fi[~hit] == -1)
+        src = first[pos[hit]]  # the first occurrence's row was stored
+        assert np.array_equal(bits(host(r["find_values"][0])[hit]), bits(vals[src]))
+        assert m.size() == len(first) and m.device_status() == 0

@@ -332,6 +332,11 @@ def test_voxelize_ordered_points(ash, voxel):
     check_voxelize(ash, pts[np.argsort(pts[:, 0], kind="stable")], voxel)
 
 
+def test_voxelize_full_size(ash):
+    """The benchmark's 5M surface points at 5 mm against the oracle, whole."""
+    check_voxelize(ash, synth.points(), 0.005)
+
+
 def test_voxelize_boundaries_and_rejects(ash):
     s = np.float32(0.1)
     k = np.arange(-3000, 3000, dtype=np.float32)

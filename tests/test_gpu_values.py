@@ -97,3 +97,40 @@ def test_double_hash_map_frames(ash):
         assert np.array_equal(host(loc_g.key_buffer())[i_local], uniq)
         gl.check_state()
     assert gl.gpu.size() > 0 and gl.gpu.size() == gl.orc.size
+
+
+def test_value_sweep_full_size_16k_rows(ash):
+    """The value sweep's largest shape: 1M keys with 16 KB rows.  A fresh
+    map's insert mask marks first occurrences and their indices are ranks;
+    sampled rows of v^B and of a gathering find must equal the first
+    occurrence's input row bit for bit."""
+    d = synth.value_sweep()
+    keys, fk = d["keys"], d["find_keys"]
+    n = len(keys)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(81)
+    vals = torch.randn((n, 4096), dtype=torch.float32, device="cuda", generator=gen)
+    m = ash.HashMap(n, 3, [(torch.float32, 4096)])
+    gi, gm = m.insert(dev(keys), [vals])
+    packed = np.ascontiguousarray(keys).view(np.dtype((np.void, 12))).ravel()
+    uniq, first, inv = np.unique(packed, return_index=True, return_inverse=True)
+    rank = np.empty(len(first), np.int64)
+    rank[np.argsort(first)] = np.arange(len(first))
+    want = np.zeros(n, bool)
+    want[first] = True
+    assert np.array_equal(host(gm), want)
+    assert np.array_equal(host(gi)[want], rank[inv[want]].astype(np.int32))
+    rng = np.random.default_rng(82)
+    s = np.sort(rng.choice(len(first), size=2000, replace=False))  # sampled distinct keys
+    rows = torch.from_numpy(rank[s]).cuda()
+    assert torch.equal(m.value_buffer(0)[rows].view(torch.int32), vals[torch.from_numpy(first[s]).cuda()].view(torch.int32))
+    fi, fmask, (fv,) = m.find(dev(fk), gather=True)
+    fpacked = np.ascontiguousarray(fk).view(np.dtype((np.void, 12))).ravel()
+    pos = np.searchsorted(uniq, fpacked)
+    hit = (pos < len(uniq)) & (uniq[np.minimum(pos, len(uniq) - 1)] == fpacked)
+    assert np.array_equal(host(fmask), hit)
+    hp = np.flatnonzero(hit)[:: max(1, hit.sum() // 2000)]
+    got = fv[torch.from_numpy(hp).cuda()].view(torch.int32)
+    src = vals[torch.from_numpy(first[pos[hp]]).cuda()].view(torch.int32)
+    assert torch.equal(got, src)
+    assert m.device_status() == 0
