@@ -714,8 +714,8 @@ ash_status_t ash_voxelize(const float* points, int64_t n, float voxel, int32_t* 
               hipMemcpyAsync(meta, &h, sizeof(Meta), hipMemcpyHostToDevice, st) == hipSuccess &&
               ash::launch_voxel_claim(kG, kW, tb, points, voxel, un, slot_of, lost, partial, meta, st) == hipSuccess &&
               ash::launch_sum_partials(partial, blocks, meta, st) == hipSuccess &&
-              ash::launch_voxel_commit(tb, points, voxel, un, slot_of, lost, out_voxel_keys, out_voxel_counts, meta,
-                                       status, st) == hipSuccess &&
+              ash::launch_voxel_commit(tb, points, voxel, un, slot_of, lost, out_voxel_keys, out_voxel_counts,
+                                       out_point_voxel, meta, status, st) == hipSuccess &&
               ash::launch_voxel_resolve(tb, un, slot_of, out_point_voxel, out_voxel_counts, st) == hipSuccess &&
               hipMemcpyAsync(&h, meta, sizeof(Meta), hipMemcpyDeviceToHost, st) == hipSuccess &&
               hipStreamSynchronize(st) == hipSuccess;

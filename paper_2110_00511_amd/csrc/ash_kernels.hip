@@ -1068,10 +1068,11 @@ __global__ __launch_bounds__(kBlock) void k_rebuild(TableRef tb, const uint32_t*
 // Voxelization pass 2: the first occurrence of each voxel (its winner) gets
 // the id rank-of-first-occurrence; its slot becomes COMMITTED(id).
 __global__ __launch_bounds__(kBlock) void k_voxel_commit(TableRef tb, VoxelKeys src, uint32_t n,
-                                                         const uint32_t* __restrict__ slot_of,
+                                                         uint32_t* __restrict__ slot_of,
                                                          uint8_t* __restrict__ lost,
                                                          int32_t* __restrict__ voxel_keys,
-                                                         int32_t* __restrict__ counts, Meta* meta,
+                                                         int32_t* __restrict__ counts,
+                                                         int32_t* __restrict__ point_voxel, Meta* meta,
                                                          uint64_t* __restrict__ status) {
   constexpr int S = SlotWords<3>::value;
   __shared__ uint32_t s_prefix;
@@ -1091,6 +1092,7 @@ __global__ __launch_bounds__(kBlock) void k_voxel_commit(TableRef tb, VoxelKeys 
       if (l) lost[p] = 0;
       win[r] = so != kNoSlot && (so & kCandidate) && l == 0;
       slot[r] = so & ~kCandidate;
+      if (so == kNoSlot) point_voxel[p] = -1;  // rejected point
     }
   }
   uint32_t rank[kScanItems];
@@ -1107,12 +1109,18 @@ __global__ __launch_bounds__(kBlock) void k_voxel_commit(TableRef tb, VoxelKeys 
     voxel_keys[(size_t)id * 3 + 0] = k[0];
     voxel_keys[(size_t)id * 3 + 1] = k[1];
     voxel_keys[(size_t)id * 3 + 2] = k[2];
-    counts[id] = 0;
+    // a voxel's first point is resolved here: it counts itself, and the
+    // resolve pass skips it
+    counts[id] = 1;
+    point_voxel[p] = (int32_t)id;
+    slot_of[p] = kNoSlot;
     tb.words[(size_t)slot[r] * S + S - 1] = id;
   }
 }
 
-// Voxelization pass 3: per-point voxel id and per-voxel counts.
+// Voxelization pass 3: voxel ids and counts of the points the commit left:
+// every accepted point that is not its voxel's first (the commit resolved
+// first points and rejected ones, and set their slot_of to kNoSlot).
 __global__ __launch_bounds__(kBlock) void k_voxel_resolve(TableRef tb, uint32_t n, const uint32_t* __restrict__ slot_of,
                                                           int32_t* __restrict__ point_voxel,
                                                           int32_t* __restrict__ counts) {
@@ -1120,10 +1128,7 @@ __global__ __launch_bounds__(kBlock) void k_voxel_resolve(TableRef tb, uint32_t 
   const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
   const uint32_t so = slot_of[p];
-  if (so == kNoSlot) {
-    point_voxel[p] = -1;
-    return;
-  }
+  if (so == kNoSlot) return;
   const uint32_t id = tb.words[(size_t)(so & ~kCandidate) * S + S - 1];
   if (id >= n) {  // cannot happen once every claimed slot is committed
     point_voxel[p] = -1;
@@ -1710,11 +1715,11 @@ hipError_t launch_voxel_claim(int g, int w, const TableRef& tb, const float* pts
   return with_probe<3, VoxelClaimK>(g, w, tb, pts, voxel, n, slot_of, lost, partial, meta, st);
 }
 
-hipError_t launch_voxel_commit(const TableRef& tb, const float* pts, float voxel, uint32_t n, const uint32_t* slot_of,
-                               uint8_t* lost, int32_t* voxel_keys, int32_t* counts, Meta* meta, uint64_t* status,
-                               hipStream_t st) {
+hipError_t launch_voxel_commit(const TableRef& tb, const float* pts, float voxel, uint32_t n, uint32_t* slot_of,
+                               uint8_t* lost, int32_t* voxel_keys, int32_t* counts, int32_t* point_voxel, Meta* meta,
+                               uint64_t* status, hipStream_t st) {
   hipLaunchKernelGGL(k_voxel_commit, dim3(cdiv(n, kScanTile)), dim3(kBlock), 0, st, tb, VoxelKeys{pts, voxel}, n,
-                     slot_of, lost, voxel_keys, counts, meta, status);
+                     slot_of, lost, voxel_keys, counts, point_voxel, meta, status);
   return hipGetLastError();
 }
 

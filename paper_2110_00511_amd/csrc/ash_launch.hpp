@@ -70,9 +70,12 @@ hipError_t launch_rebuild(int kd, int g, int w, const TableRef& tb, const uint32
                           Meta* meta, hipStream_t st);
 hipError_t launch_voxel_claim(int g, int w, const TableRef& tb, const float* pts, float voxel, uint32_t n,
                               uint32_t* slot_of, uint8_t* lost, uint32_t* partial, Meta* meta, hipStream_t st);
-hipError_t launch_voxel_commit(const TableRef& tb, const float* pts, float voxel, uint32_t n, const uint32_t* slot_of,
-                               uint8_t* lost, int32_t* voxel_keys, int32_t* counts, Meta* meta, uint64_t* status,
-                               hipStream_t st);
+// Ranks first points into voxel ids, writes voxel keys, the first points'
+// ids and counts of 1, and -1 for rejected points; both kinds get slot_of =
+// kNoSlot, so launch_voxel_resolve only handles the remaining points.
+hipError_t launch_voxel_commit(const TableRef& tb, const float* pts, float voxel, uint32_t n, uint32_t* slot_of,
+                               uint8_t* lost, int32_t* voxel_keys, int32_t* counts, int32_t* point_voxel, Meta* meta,
+                               uint64_t* status, hipStream_t st);
 hipError_t launch_voxel_resolve(const TableRef& tb, uint32_t n, const uint32_t* slot_of, int32_t* point_voxel,
                                 int32_t* counts, hipStream_t st);
 
