@@ -35,6 +35,23 @@
 namespace ash {
 
 // ---------------------------------------------------------------------------
+// Fused served batches: the requests of a batch occupy consecutive position
+// ranges in arrival order.  A block stages the ranges' first positions in LDS
+// and finds a position's request by binary search (at most
+// kMaxFusedRequests requests per batch).
+constexpr int kMaxFusedRequests = kMaxFusedRequestsHost;
+
+__device__ __forceinline__ int request_of(const int64_t* s_off, int nreq, int64_t e) {
+  int lo = 0, hi = nreq - 1;  // last request whose first position <= e
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (s_off[mid] <= e) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// ---------------------------------------------------------------------------
 // Key sources: map keys read from the batch, or voxel keys computed from
 // points.  load() returns false for a point that is rejected.
 template <int KD>
@@ -83,6 +100,21 @@ struct OffsetKeys {
 #pragma unroll
     for (int d = 0; d < KD; ++d)
       out[d] = (int32_t)((uint32_t)keys[(size_t)q * KD + d] + (uint32_t)offsets[(size_t)o * KD + d]);
+    return true;
+  }
+};
+
+// Keys of a fused served batch, read from the requests' own buffers.
+template <int KD>
+struct ReqKeys {
+  const ReqDesc* __restrict__ d;
+  const int64_t* s_off;  // LDS
+  int nreq;
+  __device__ __forceinline__ bool load(uint32_t p, int32_t (&out)[KD]) const {
+    const int r = request_of(s_off, nreq, p);
+    const int32_t* k = d[r].keys + (size_t)(p - s_off[r]) * KD;
+#pragma unroll
+    for (int w = 0; w < KD; ++w) out[w] = k[w];
     return true;
   }
 };
@@ -707,10 +739,64 @@ __global__ void k_finalize(Meta* m, uint32_t cap, int mode, int silent, int chec
 // the first window that holds an EMPTY slot: a key is always claimed at the
 // first EMPTY slot of its sequence and slots never return to EMPTY outside a
 // rebuild.
-template <int KD, int G, int WL, typename Src>
+// Where a find's results go: batch-indexed outputs (DirectOut), or the
+// requests of a fused served batch (ReqOut).  put() writes a position's index
+// (kNoSlot for a miss) and mask; rows() copies the value rows of the tile's
+// hits, given as (buffer index, position) pairs.
+struct DirectOut {
+  int32_t* __restrict__ idx;
+  uint8_t* __restrict__ mask;
+  __device__ __forceinline__ void put(uint32_t p, uint32_t i) const {
+    const bool hit = i != kNoSlot;
+    if (idx) idx[p] = hit ? (int32_t)i : -1;
+    if (mask) mask[p] = hit ? 1 : 0;
+  }
+  __device__ __forceinline__ void rows(const ValueSet& vs, int j, const uint2* pairs, uint32_t count) const {
+    copy_rows(vs, j, pairs, count);
+  }
+};
+
+struct ReqOut {
+  const ReqDesc* __restrict__ d;
+  const int64_t* s_off;  // LDS
+  int nreq;
+  __device__ __forceinline__ void put(uint32_t p, uint32_t i) const {
+    const int r = request_of(s_off, nreq, p);
+    const size_t q = p - s_off[r];
+    const bool hit = i != kNoSlot;
+    if (d[r].out_idx) d[r].out_idx[q] = hit ? (int32_t)i : -1;
+    if (d[r].out_mask) d[r].out_mask[q] = hit ? 1 : 0;
+  }
+  template <typename V>
+  __device__ __forceinline__ void rows_t(const ValueSet& vs, int j, const uint2* pairs, uint32_t count) const {
+    const uint32_t row = vs.row_bytes[j];
+    const uint32_t units = row / (uint32_t)sizeof(V);
+    for (uint32_t e = threadIdx.x; e < count * units; e += blockDim.x) {
+      const uint32_t w = e / units;
+      const uint32_t c = e - w * units;
+      const uint2 pr = pairs[w];  // (buffer index, position)
+      const int r = request_of(s_off, nreq, pr.y);
+      uint8_t* dst = d[r].outv[j];
+      if (!dst) continue;
+      const V v = reinterpret_cast<const V*>(vs.src[j] + (size_t)pr.x * row)[c];
+      reinterpret_cast<V*>(dst + (size_t)(pr.y - s_off[r]) * row)[c] = v;
+    }
+  }
+  __device__ __forceinline__ void rows(const ValueSet& vs, int j, const uint2* pairs, uint32_t count) const {
+    switch (vs.vec[j]) {
+      case 16: rows_t<uint4>(vs, j, pairs, count); break;
+      case 8: rows_t<uint2>(vs, j, pairs, count); break;
+      case 4: rows_t<uint32_t>(vs, j, pairs, count); break;
+      case 2: rows_t<uint16_t>(vs, j, pairs, count); break;
+      default: rows_t<uint8_t>(vs, j, pairs, count); break;
+    }
+  }
+};
+
+template <int KD, int G, int WL, typename Src, typename Out = DirectOut>
 __device__ __forceinline__ void find_tile(const TableRef& tb, const Src& src, uint32_t n,
-                                          uint32_t tile, uint32_t rounds, int32_t* __restrict__ out_idx,
-                                          uint8_t* __restrict__ out_mask, const ValueSet& vs, TileLds& lds) {
+                                          uint32_t tile, uint32_t rounds, const Out& out, const ValueSet& vs,
+                                          TileLds& lds) {
   using Win = Window<KD, G, WL>;
   constexpr int S = Win::S;
   constexpr uint32_t kGroups = kBlock / G;
@@ -746,16 +832,14 @@ __device__ __forceinline__ void find_tile(const TableRef& tb, const Src& src, ui
       if (base >= tb.nslots) base -= tb.nslots;
     }
     if (sub == 0) {
-      const bool hit = idx != kNoSlot;
-      if (out_idx) out_idx[p] = hit ? (int32_t)idx : -1;
-      if (out_mask) out_mask[p] = hit ? 1 : 0;
-      if (hit && vs.n > 0) s_pairs[atomicAdd(&s_hits, 1u)] = make_uint2(idx, p);
+      out.put(p, idx);
+      if (idx != kNoSlot && vs.n > 0) s_pairs[atomicAdd(&s_hits, 1u)] = make_uint2(idx, p);
     }
   }
   if (vs.n > 0) {
     __syncthreads();
     const uint32_t hits = s_hits;
-    for (int j = 0; j < vs.n; ++j) copy_rows(vs, j, s_pairs, hits);
+    for (int j = 0; j < vs.n; ++j) out.rows(vs, j, s_pairs, hits);
     __syncthreads();  // LDS is reused by the next tile of a persistent block
   }
 }
@@ -765,7 +849,20 @@ __global__ __launch_bounds__(kBlock) void k_find(TableRef tb, const int32_t* __r
                                                  uint32_t rounds, int32_t* __restrict__ out_idx,
                                                  uint8_t* __restrict__ out_mask, ValueSet vs) {
   __shared__ TileLds lds;
-  find_tile<KD, G, WL>(tb, BatchKeys<KD>{keys}, n, blockIdx.x, rounds, out_idx, out_mask, vs, lds);
+  find_tile<KD, G, WL>(tb, BatchKeys<KD>{keys}, n, blockIdx.x, rounds, DirectOut{out_idx, out_mask}, vs, lds);
+}
+
+// A fused served find: keys come from the requests' buffers and every
+// result goes straight to its request (vs: the map's rows as sources; rows
+// are copied for requests that asked for them).
+template <int KD, int G, int WL>
+__global__ __launch_bounds__(kBlock) void k_find_requests(TableRef tb, const ReqDesc* __restrict__ d, int nreq,
+                                                          uint32_t n, uint32_t rounds, ValueSet vs) {
+  __shared__ TileLds lds;
+  __shared__ int64_t s_off[kMaxFusedRequests];
+  for (int r = threadIdx.x; r < nreq; r += kBlock) s_off[r] = d[r].off;
+  __syncthreads();
+  find_tile<KD, G, WL>(tb, ReqKeys<KD>{d, s_off, nreq}, n, blockIdx.x, rounds, ReqOut{d, s_off, nreq}, vs, lds);
 }
 
 // Neighbor lookups: a find over n * k shifted keys, results query-major.
@@ -776,7 +873,7 @@ __global__ __launch_bounds__(kBlock) void k_find_offsets(TableRef tb, OffsetKeys
   __shared__ TileLds lds;
   ValueSet none;
   none.n = 0;
-  find_tile<KD, G, WL>(tb, src, n, blockIdx.x, rounds, out_idx, out_mask, none, lds);
+  find_tile<KD, G, WL>(tb, src, n, blockIdx.x, rounds, DirectOut{out_idx, out_mask}, none, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1174,14 +1271,14 @@ __device__ __forceinline__ void batched_claim(const BatchItem& it, uint32_t tile
 template <int KD>
 __device__ __forceinline__ void batched_find(const BatchItem& it, uint32_t tile, TileLds& lds) {
   switch (it.g == 1 ? it.w : 100 + it.g) {
-    case 2: find_tile<KD, 1, 2>(it.tb, BatchKeys<KD>{it.fkeys}, it.n_find, tile, rounds_for_dev<1>(), it.fidx, it.fmask, it.vout, lds); break;
-    case 4: find_tile<KD, 1, 4>(it.tb, BatchKeys<KD>{it.fkeys}, it.n_find, tile, rounds_for_dev<1>(), it.fidx, it.fmask, it.vout, lds); break;
-    case 8: find_tile<KD, 1, 8>(it.tb, BatchKeys<KD>{it.fkeys}, it.n_find, tile, rounds_for_dev<1>(), it.fidx, it.fmask, it.vout, lds); break;
-    case 104: find_tile<KD, 4, 1>(it.tb, BatchKeys<KD>{it.fkeys}, it.n_find, tile, rounds_for_dev<4>(), it.fidx, it.fmask, it.vout, lds); break;
-    case 108: find_tile<KD, 8, 1>(it.tb, BatchKeys<KD>{it.fkeys}, it.n_find, tile, rounds_for_dev<8>(), it.fidx, it.fmask, it.vout, lds); break;
-    case 116: find_tile<KD, 16, 1>(it.tb, BatchKeys<KD>{it.fkeys}, it.n_find, tile, rounds_for_dev<16>(), it.fidx, it.fmask, it.vout, lds); break;
-    case 132: find_tile<KD, 32, 1>(it.tb, BatchKeys<KD>{it.fkeys}, it.n_find, tile, rounds_for_dev<32>(), it.fidx, it.fmask, it.vout, lds); break;
-    case 164: find_tile<KD, 64, 1>(it.tb, BatchKeys<KD>{it.fkeys}, it.n_find, tile, rounds_for_dev<64>(), it.fidx, it.fmask, it.vout, lds); break;
+    case 2: find_tile<KD, 1, 2>(it.tb, BatchKeys<KD>{it.fkeys}, it.n_find, tile, rounds_for_dev<1>(), DirectOut{it.fidx, it.fmask}, it.vout, lds); break;
+    case 4: find_tile<KD, 1, 4>(it.tb, BatchKeys<KD>{it.fkeys}, it.n_find, tile, rounds_for_dev<1>(), DirectOut{it.fidx, it.fmask}, it.vout, lds); break;
+    case 8: find_tile<KD, 1, 8>(it.tb, BatchKeys<KD>{it.fkeys}, it.n_find, tile, rounds_for_dev<1>(), DirectOut{it.fidx, it.fmask}, it.vout, lds); break;
+    case 104: find_tile<KD, 4, 1>(it.tb, BatchKeys<KD>{it.fkeys}, it.n_find, tile, rounds_for_dev<4>(), DirectOut{it.fidx, it.fmask}, it.vout, lds); break;
+    case 108: find_tile<KD, 8, 1>(it.tb, BatchKeys<KD>{it.fkeys}, it.n_find, tile, rounds_for_dev<8>(), DirectOut{it.fidx, it.fmask}, it.vout, lds); break;
+    case 116: find_tile<KD, 16, 1>(it.tb, BatchKeys<KD>{it.fkeys}, it.n_find, tile, rounds_for_dev<16>(), DirectOut{it.fidx, it.fmask}, it.vout, lds); break;
+    case 132: find_tile<KD, 32, 1>(it.tb, BatchKeys<KD>{it.fkeys}, it.n_find, tile, rounds_for_dev<32>(), DirectOut{it.fidx, it.fmask}, it.vout, lds); break;
+    case 164: find_tile<KD, 64, 1>(it.tb, BatchKeys<KD>{it.fkeys}, it.n_find, tile, rounds_for_dev<64>(), DirectOut{it.fidx, it.fmask}, it.vout, lds); break;
     default: break;
   }
 }
@@ -1345,22 +1442,9 @@ hipError_t launch_copy_masked_rows(const uint8_t* mask, const void* src, void* d
   return hipGetLastError();
 }
 
-// Fused served batches.  A block stages the requests' offsets in LDS and
-// finds each position's request by binary search (at most kMaxFusedRequests
-// requests per batch).  Rows move in 4-byte words when the row size allows,
-// else byte by byte.
-constexpr int kMaxFusedRequests = kMaxFusedRequestsHost;
-
-__device__ __forceinline__ int request_of(const int64_t* s_off, int nreq, int64_t e) {
-  int lo = 0, hi = nreq - 1;  // last request whose first position <= e
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (s_off[mid] <= e) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
-
+// Fused served batches (gather and scatter for inserts and erases; fused
+// finds read and write the requests' buffers directly, see k_find_requests).
+// Rows move in 4-byte words when the row size allows, else byte by byte.
 __device__ __forceinline__ void copy_row(const uint8_t* __restrict__ src, uint8_t* __restrict__ dst, uint32_t bytes) {
   if ((bytes & 3u) == 0 && (((uintptr_t)src | (uintptr_t)dst) & 3u) == 0) {
     for (uint32_t w = 0; w < bytes / 4; ++w)
@@ -1490,6 +1574,17 @@ struct FindK {
     const uint32_t rounds = rounds_for<G>();
     hipLaunchKernelGGL((k_find<KD, G, WL>), dim3(cdiv(n, (kBlock / G) * rounds)), dim3(kBlock), 0, st, tb, keys, n,
                        rounds, out_idx, out_mask, vs);
+    return hipGetLastError();
+  }
+};
+
+template <int KD, int G, int WL>
+struct FindRequestsK {
+  static hipError_t run(const TableRef& tb, const ReqDesc* d, int nreq, uint32_t n, const ValueSet& vs,
+                        hipStream_t st) {
+    const uint32_t rounds = rounds_for<G>();
+    hipLaunchKernelGGL((k_find_requests<KD, G, WL>), dim3(cdiv(n, (kBlock / G) * rounds)), dim3(kBlock), 0, st, tb, d,
+                       nreq, n, rounds, vs);
     return hipGetLastError();
   }
 };
@@ -1642,6 +1737,13 @@ hipError_t launch_commit(int kd, const TableRef& tb, const int32_t* keys, uint32
 hipError_t launch_find(int kd, int g, int w, const TableRef& tb, const int32_t* keys, uint32_t n, int32_t* out_idx,
                        uint8_t* out_mask, const ValueSet& vs, hipStream_t st) {
   return with_kd_probe<FindK>(kd, g, w, tb, keys, n, out_idx, out_mask, vs, st);
+}
+
+hipError_t launch_find_requests(int kd, int g, int w, const TableRef& tb, const ReqDesc* d, int nreq, uint32_t n,
+                                const ValueSet& vs, hipStream_t st) {
+  if (nreq < 1 || nreq > kMaxFusedRequests) return hipErrorInvalidValue;
+  if (n == 0) return hipSuccess;
+  return with_kd_probe<FindRequestsK>(kd, g, w, tb, d, nreq, n, vs, st);
 }
 
 hipError_t launch_find_offsets(int kd, int g, int w, const TableRef& tb, const int32_t* keys, const int32_t* offsets,

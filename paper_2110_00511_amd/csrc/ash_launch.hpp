@@ -23,6 +23,13 @@ hipError_t launch_gather_requests(const ReqDesc* d, int nreq, int64_t total, int
                                   int32_t* keys, uint8_t* const* vals, hipStream_t st);
 hipError_t launch_scatter_requests(const ReqDesc* d, int nreq, int64_t total, const RowSet& rows, const int32_t* idx,
                                    const uint8_t* mask, const uint8_t* const* outv, hipStream_t st);
+// A fused served find over n positions of nreq requests (device
+// descriptors, offsets ascending from 0): keys are read from, and indices,
+// masks and (vs.n > 0) the value rows of hits written to, each request's own
+// buffers; vs.src are the map's rows, vs.vec must divide every request's
+// output address.
+hipError_t launch_find_requests(int kd, int g, int w, const TableRef& tb, const ReqDesc* d, int nreq, uint32_t n,
+                                const ValueSet& vs, hipStream_t st);
 // dst row r = src row r where mask[r] == 1 (rows of row_bytes, copied in vec-byte units).
 hipError_t launch_copy_masked_rows(const uint8_t* mask, const void* src, void* dst, uint64_t rows,
                                    uint32_t row_bytes, uint32_t vec, hipStream_t st);

@@ -55,13 +55,11 @@ struct Stage {
   int64_t cap = 0;
   int32_t* keys = nullptr;
   std::vector<uint8_t*> vals;
-  std::vector<uint8_t*> outv;
   int32_t* idx = nullptr;
   uint8_t* mask = nullptr;
   ash::ReqDesc* hdesc = nullptr;  // pinned host descriptors of the batch's requests
   ash::ReqDesc* ddesc = nullptr;  // their device copy
-  uint8_t** dvals = nullptr;      // device arrays of the staging value / output row pointers
-  uint8_t** doutv = nullptr;
+  uint8_t** dvals = nullptr;      // device array of the staging value row pointers
 };
 
 struct Batch {
@@ -110,11 +108,8 @@ ash_status_t stage_alloc(ash_server* s, Stage& g) {
   if (hipMalloc(&g.idx, (size_t)n * 4) != hipSuccess) return ASH_E_NOMEM;
   if (hipMalloc(&g.mask, (size_t)n) != hipSuccess) return ASH_E_NOMEM;
   g.vals.assign(m->n_values, nullptr);
-  g.outv.assign(m->n_values, nullptr);
-  for (int j = 0; j < m->n_values; ++j) {
+  for (int j = 0; j < m->n_values; ++j)
     if (hipMalloc(&g.vals[j], (size_t)n * m->row_bytes[j]) != hipSuccess) return ASH_E_NOMEM;
-    if (hipMalloc(&g.outv[j], (size_t)n * m->row_bytes[j]) != hipSuccess) return ASH_E_NOMEM;
-  }
   const size_t dbytes = sizeof(ash::ReqDesc) * ash::kMaxFusedRequestsHost;
   if (hipHostMalloc((void**)&g.hdesc, dbytes, hipHostMallocDefault) != hipSuccess) {
     g.hdesc = nullptr;
@@ -122,10 +117,9 @@ ash_status_t stage_alloc(ash_server* s, Stage& g) {
   }
   if (hipMalloc(&g.ddesc, dbytes) != hipSuccess) return ASH_E_NOMEM;
   const size_t pbytes = sizeof(uint8_t*) * std::max(m->n_values, 1);
-  if (hipMalloc(&g.dvals, pbytes) != hipSuccess || hipMalloc(&g.doutv, pbytes) != hipSuccess) return ASH_E_NOMEM;
+  if (hipMalloc(&g.dvals, pbytes) != hipSuccess) return ASH_E_NOMEM;
   if (m->n_values > 0 &&
-      (hipMemcpy(g.dvals, g.vals.data(), sizeof(uint8_t*) * m->n_values, hipMemcpyHostToDevice) != hipSuccess ||
-       hipMemcpy(g.doutv, g.outv.data(), sizeof(uint8_t*) * m->n_values, hipMemcpyHostToDevice) != hipSuccess))
+      hipMemcpy(g.dvals, g.vals.data(), sizeof(uint8_t*) * m->n_values, hipMemcpyHostToDevice) != hipSuccess)
     return ASH_E_DEVICE;
   return ASH_OK;
 }
@@ -135,11 +129,9 @@ void stage_free(Stage& g) {
   (void)hipFree(g.idx);
   (void)hipFree(g.mask);
   for (uint8_t* p : g.vals) (void)hipFree(p);
-  for (uint8_t* p : g.outv) (void)hipFree(p);
   if (g.hdesc) (void)hipHostFree(g.hdesc);
   (void)hipFree(g.ddesc);
   (void)hipFree(g.dvals);
-  (void)hipFree(g.doutv);
 }
 
 // Runs one request directly on its own buffers.
@@ -160,9 +152,10 @@ ash_status_t run_one(ash_server* s, Req* q) {
   }
 }
 
-// Runs requests of one kind as one device batch through staging buffers: one
-// descriptor upload and a gather kernel in, the operation, a scatter kernel
-// out.
+// Runs requests of one kind as one device batch.  A find is one kernel that
+// reads the keys from, and writes the results to, the requests' own buffers
+// (after one descriptor upload); inserts and erases go through staging
+// buffers: a gather kernel in, the operation, a scatter kernel out.
 ash_status_t run_fused(ash_server* s, const std::vector<Req*>& run, Stage& g) {
   ash_map* m = s->map;
   hipStream_t st = s->stream;
@@ -192,16 +185,31 @@ ash_status_t run_fused(ash_server* s, const std::vector<Req*>& run, Stage& g) {
   rows.n = m->n_values;
   for (int j = 0; j < m->n_values; ++j) rows.bytes[j] = m->row_bytes[j];
   ASH_HIP(hipMemcpyAsync(g.ddesc, g.hdesc, sizeof(ash::ReqDesc) * nreq, hipMemcpyHostToDevice, st));
+  if (kind == ASH_REQ_FIND) {
+    // one kernel: keys read from the requests, results written to them
+    ValueSet vs;
+    std::memset(&vs, 0, sizeof(vs));
+    if (gather && m->n_values > 0) {
+      vs.n = m->n_values;
+      for (int j = 0; j < m->n_values; ++j) {
+        vs.src[j] = m->vB[j];
+        vs.row_bytes[j] = m->row_bytes[j];
+        uint32_t vec = 16;
+        for (int k = 0; k < nreq; ++k)
+          if (g.hdesc[k].outv[j]) vec = std::min(vec, copy_unit(m->row_bytes[j], m->vB[j], g.hdesc[k].outv[j]));
+        vs.vec[j] = vec;
+        vs.units_log2[j] = units_log2(m->row_bytes[j], vec);
+      }
+    }
+    ASH_HIP(ash::launch_find_requests(m->key_dim, m->G, m->W, m->ref(), g.ddesc, nreq, (uint32_t)off, vs, st));
+    return ASH_OK;
+  }
   ASH_HIP(ash::launch_gather_requests(g.ddesc, nreq, off, m->key_dim, rows, g.keys,
                                       kind == ASH_REQ_INSERT && m->n_values > 0 ? g.dvals : nullptr, st));
   std::vector<const void*> vin(g.vals.begin(), g.vals.end());
-  std::vector<void*> vout(g.outv.begin(), g.outv.end());
   switch (kind) {
     case ASH_REQ_INSERT:
       ASH_TRY(insert_impl(m, g.keys, off, m->n_values > 0 ? vin.data() : nullptr, g.idx, g.mask, st));
-      break;
-    case ASH_REQ_FIND:
-      ASH_TRY(ash_find(m, g.keys, off, g.idx, g.mask, gather && m->n_values > 0 ? vout.data() : nullptr, st));
       break;
     case ASH_REQ_ERASE:
       ASH_TRY(ash_erase(m, g.keys, off, g.mask, st));
@@ -209,8 +217,8 @@ ash_status_t run_fused(ash_server* s, const std::vector<Req*>& run, Stage& g) {
     default:
       return ASH_E_INVALID;
   }
-  ASH_HIP(ash::launch_scatter_requests(g.ddesc, nreq, off, rows, kind != ASH_REQ_ERASE ? g.idx : nullptr, g.mask,
-                                       gather && m->n_values > 0 ? g.doutv : nullptr, st));
+  ASH_HIP(ash::launch_scatter_requests(g.ddesc, nreq, off, rows, kind == ASH_REQ_INSERT ? g.idx : nullptr, g.mask,
+                                       nullptr, st));
   return ASH_OK;
 }
 
