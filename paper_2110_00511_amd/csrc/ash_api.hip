@@ -705,6 +705,8 @@ ash_status_t ash_voxelize(const float* points, int64_t n, float voxel, int32_t* 
     tb.window = kG == 1 ? kW : kG;
     tb.max_windows = nslots / tb.window + 1;
     tb.dedup = kVoxelDedup;
+    tb.reuse = 0;
+    tb.mirror = nullptr;
     Meta h;
     std::memset(&h, 0, sizeof(h));
     h.epoch = 1;

@@ -98,6 +98,7 @@ struct TableRef {
   uint32_t max_windows;   // probe steps that cover the whole table
   uint32_t dedup;         // 1: claims drop block-local duplicates in LDS first
   uint32_t reuse;         // 1: the table may hold tombstones, which claims may take
+  Meta* mirror;           // nullable host-mapped copy of t / used / tombs, written by every finalize
 };
 
 // ---------------------------------------------------------------------------

@@ -162,6 +162,9 @@ struct ash_map {
   // An erase ran since the table was last empty or rebuilt, so it may hold
   // tombstones for claims to reuse (skipping them is always correct).
   bool tombs_possible = false;
+  // Host-mapped memory that every insert and erase finalize copies t, used
+  // and tombs to (a server reads it once a batch is done), or null.
+  Meta* mirror = nullptr;
 
   int slot_words() const { return key_dim == 1 ? 2 : (key_dim <= 3 ? 4 : 8); }
 
@@ -175,6 +178,7 @@ struct ash_map {
     r.max_windows = nslots / r.window + 1;
     r.dedup = (flags & ASH_F_LDS_DEDUP) ? 1u : 0u;
     r.reuse = tombs_possible ? 1u : 0u;
+    r.mirror = mirror;
     return r;
   }
 };

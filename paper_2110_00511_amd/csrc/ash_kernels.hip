@@ -569,6 +569,16 @@ __device__ __forceinline__ void finalize_total(Meta* m, uint32_t cap, int mode, 
   m->epoch = m->epoch + 1u == 0u ? 1u : m->epoch + 1u;
 }
 
+// Copies the counters a host reader tracks to the table's mirror, if any
+// (vector stores to host-mapped memory, visible once the kernel is done).
+__device__ __forceinline__ void publish_counts(const TableRef& tb, const Meta* m) {
+  if (!tb.mirror) return;
+  tb.mirror->t = m->t;
+  tb.mirror->used = m->used;
+  tb.mirror->tombs = m->tombs;
+  __threadfence_system();
+}
+
 __device__ __forceinline__ void finalize_map(Meta* m, uint32_t cap, int mode, int silent, int check,
                                              const uint64_t* status, uint32_t last_tile, uint32_t n = 0) {
   const uint32_t total = mode == kFinalizeRebuild ? 0u : (uint32_t)status[last_tile] & 0x7FFFFFFFu;
@@ -633,8 +643,10 @@ __device__ __forceinline__ void commit_tile(const TableRef& tb, const int32_t* _
   // look-back saw every other tile publish, and each tile publishes only
   // after reading t, the epoch and the claim counters, so none reads them
   // after this point; the next kernel sees the update at the launch boundary.
-  if (fin >= 0 && threadIdx.x == 0 && tile == (n - 1) / kScanTile)
+  if (fin >= 0 && threadIdx.x == 0 && tile == (n - 1) / kScanTile) {
     finalize_total(meta, cap, kFinalizeInsert, fin, check, prefix + total, n);
+    publish_counts(tb, meta);
+  }
   bool bad = false;
 #pragma unroll
   for (int r = 0; r < kScanItems; ++r) {
@@ -976,7 +988,10 @@ __global__ __launch_bounds__(kBlock) void k_erase_commit(TableRef tb, uint32_t n
   const uint32_t prefix = s_prefix;
   // the last tile finalizes the erase (every tile read t and the epoch before
   // publishing, see commit_tile)
-  if (threadIdx.x == 0 && tile == (n - 1) / kScanTile) finalize_total(meta, 0u, kFinalizeErase, 0, 0, prefix + total);
+  if (threadIdx.x == 0 && tile == (n - 1) / kScanTile) {
+    finalize_total(meta, 0u, kFinalizeErase, 0, 0, prefix + total);
+    publish_counts(tb, meta);
+  }
 #pragma unroll
   for (int r = 0; r < kScanItems; ++r) {
     const uint32_t p = base + r * kBlock + threadIdx.x;

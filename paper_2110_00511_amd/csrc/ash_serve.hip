@@ -68,7 +68,7 @@ struct Batch {
   int stage = -1;
   int64_t add_live = 0;  // upper bound on what the batch adds to t
   int64_t add_used = 0;  // ... and to the occupied slots
-  bool snap = false;     // the batch copied the map's counters to its stage's snapshot
+  bool snap = false;     // an insert or erase: its finalize updated the counter mirror
 };
 
 }  // namespace
@@ -86,8 +86,9 @@ struct ash_server {
   std::vector<Stage> stages;
   std::vector<int> free_stages;
   std::vector<hipEvent_t> free_events;
-  Meta* snaps = nullptr;  // pinned: the map's counters after each stage's batch
-  int64_t conf_t = 0, conf_used = 0;    // exact, after the last retired batch
+  Meta* mirror_h = nullptr;  // pinned, host-mapped: the map's counters after its latest finalize
+  Meta* mirror_d = nullptr;  // the same memory as the device addresses it
+  int64_t conf_t = 0, conf_used = 0;    // read from the mirror when a batch retires
   int64_t add_live = 0, add_used = 0;  // summed over the batches in flight
   bool stop = false;
   bool worker_done = false;
@@ -283,10 +284,6 @@ void worker_loop(ash_server* s) {
     ash_status_t rc = run.size() == 1 ? run_one(s, run[0]) : run_fused(s, run, s->stages[stage]);
     // counters after the batch (a find changes neither t nor the occupied slots)
     const bool snap = kind != ASH_REQ_FIND;
-    if (snap && hipMemcpyAsync(&s->snaps[stage], m->meta, sizeof(Meta), hipMemcpyDeviceToHost, s->stream) !=
-                    hipSuccess &&
-        rc == ASH_OK)
-      rc = ASH_E_DEVICE;
     if (hipEventRecord(ev, s->stream) != hipSuccess && rc == ASH_OK) rc = ASH_E_DEVICE;
     {
       std::lock_guard<std::mutex> lk(s->mu);
@@ -327,9 +324,13 @@ void completer_loop(ash_server* s) {
       s->flight.pop_front();
       s->add_live -= b.add_live;
       s->add_used -= b.add_used;
-      if (e == hipSuccess && b.snap) {  // the batch's counter copy has landed
-        s->conf_t = s->snaps[b.stage].t;
-        s->conf_used = s->snaps[b.stage].used;
+      if (e == hipSuccess && b.snap) {
+        // The mirror holds this batch's counters or those of a later batch
+        // (still in flight, so its additions are also in add_live): either
+        // way conf + add stays an upper bound.
+        const volatile Meta* mr = s->mirror_h;
+        s->conf_t = mr->t;
+        s->conf_used = mr->used;
       }
       for (Req* q : b.reqs) {
         if (e != hipSuccess && q->status == ASH_OK) q->status = ASH_E_DEVICE;
@@ -343,8 +344,9 @@ void completer_loop(ash_server* s) {
   }
 }
 
-// Device resources of a server: stream, staging, events, counter snapshots,
-// the map's scratch sized for a full batch, and the exact starting counters.
+// Device resources of a server: stream, staging, events, the counter mirror
+// (attached to the map while the server lives), the map's scratch sized for
+// a full batch, and the exact starting counters.
 ash_status_t setup(ash_server* s) {
   const ash_server_config_t& c = s->cfg;
   if (hipGetDevice(&s->device) != hipSuccess) return ASH_E_DEVICE;
@@ -357,15 +359,18 @@ ash_status_t setup(ash_server* s) {
     if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return ASH_E_DEVICE;
     s->free_events.push_back(e);
   }
-  if (hipHostMalloc((void**)&s->snaps, sizeof(Meta) * c.in_flight, hipHostMallocDefault) != hipSuccess) {
-    s->snaps = nullptr;
+  if (hipHostMalloc((void**)&s->mirror_h, sizeof(Meta), hipHostMallocDefault) != hipSuccess) {
+    s->mirror_h = nullptr;
     return ASH_E_NOMEM;
   }
+  if (hipHostGetDevicePointer((void**)&s->mirror_d, s->mirror_h, 0) != hipSuccess) return ASH_E_DEVICE;
   Meta h;
   ASH_TRY(ensure_scratch(s->map, c.fuse ? c.max_batch : 1, s->stream));
   ASH_TRY(read_meta(s->map, &h, s->stream));
+  *s->mirror_h = h;
   s->conf_t = h.t;
   s->conf_used = h.used;
+  s->map->mirror = s->mirror_d;
   return ASH_OK;
 }
 
@@ -374,7 +379,8 @@ void release(ash_server* s) {
   if (s->stream) (void)hipStreamSynchronize(s->stream);
   for (Stage& g : s->stages) stage_free(g);
   for (hipEvent_t e : s->free_events) (void)hipEventDestroy(e);
-  if (s->snaps) (void)hipHostFree(s->snaps);
+  s->map->mirror = nullptr;
+  if (s->mirror_h) (void)hipHostFree(s->mirror_h);
   if (s->stream) (void)hipStreamDestroy(s->stream);
 }
 
