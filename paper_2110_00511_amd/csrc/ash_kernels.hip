@@ -1486,12 +1486,11 @@ __global__ __launch_bounds__(kBlock) void k_gather_requests(const ReqDesc* __res
   }
 }
 
-// Hands each request its part of the batch results: indices, masks, and for
-// finds the gathered rows of hits (rows of misses stay untouched).
+// Hands each request of a fused insert or erase its part of the batch
+// results: indices and masks.
 __global__ __launch_bounds__(kBlock) void k_scatter_requests(const ReqDesc* __restrict__ d, int nreq, int64_t total,
-                                                             RowSet rows, const int32_t* __restrict__ idx,
-                                                             const uint8_t* __restrict__ mask,
-                                                             const uint8_t* const* __restrict__ outv) {
+                                                             const int32_t* __restrict__ idx,
+                                                             const uint8_t* __restrict__ mask) {
   __shared__ int64_t s_off[kMaxFusedRequests];
   for (int r = threadIdx.x; r < nreq; r += kBlock) s_off[r] = d[r].off;
   __syncthreads();
@@ -1499,11 +1498,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter_requests(const ReqDesc* __re
     const int r = request_of(s_off, nreq, e);
     const int64_t q = e - s_off[r];
     if (idx && d[r].out_idx) d[r].out_idx[q] = idx[e];
-    const uint8_t hit = mask[e];
-    if (d[r].out_mask) d[r].out_mask[q] = hit;
-    if (outv && hit)
-      for (int j = 0; j < rows.n; ++j)
-        if (d[r].outv[j]) copy_row(outv[j] + e * rows.bytes[j], d[r].outv[j] + q * rows.bytes[j], rows.bytes[j]);
+    if (d[r].out_mask) d[r].out_mask[q] = mask[e];
   }
 }
 
@@ -1516,12 +1511,12 @@ hipError_t launch_gather_requests(const ReqDesc* d, int nreq, int64_t total, int
   return hipGetLastError();
 }
 
-hipError_t launch_scatter_requests(const ReqDesc* d, int nreq, int64_t total, const RowSet& rows, const int32_t* idx,
-                                   const uint8_t* mask, const uint8_t* const* outv, hipStream_t st) {
+hipError_t launch_scatter_requests(const ReqDesc* d, int nreq, int64_t total, const int32_t* idx, const uint8_t* mask,
+                                   hipStream_t st) {
   if (nreq < 1 || nreq > kMaxFusedRequests) return hipErrorInvalidValue;
   if (total == 0) return hipSuccess;
   const uint32_t grid = (uint32_t)std::min<int64_t>((total + kBlock - 1) / kBlock, 4096);
-  hipLaunchKernelGGL(k_scatter_requests, dim3(grid), dim3(kBlock), 0, st, d, nreq, total, rows, idx, mask, outv);
+  hipLaunchKernelGGL(k_scatter_requests, dim3(grid), dim3(kBlock), 0, st, d, nreq, total, idx, mask);
   return hipGetLastError();
 }
 

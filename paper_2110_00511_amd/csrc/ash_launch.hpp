@@ -14,15 +14,15 @@ enum FinalizeMode { kFinalizeInsert = 0, kFinalizeErase = 1, kFinalizeCount = 2,
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t st);
 // meta->used / meta->tombs = exact counts of non-EMPTY slots / tombstones.
 hipError_t launch_count_slots(int kd, const TableRef& tb, Meta* meta, hipStream_t st);
-// Fused served batches (1 <= nreq <= 256 requests, offsets ascending from 0,
-// total = sum of n): gather the requests' keys and (vals non-null) values into
-// batch buffers; scatter batch indices (idx nullable), masks and, with outv,
-// the value rows of hits to the requests' outputs.  vals / outv are device
-// arrays of rows.n device pointers.
+// Fused served inserts and erases (1 <= nreq <= 256 requests, offsets
+// ascending from 0, total = sum of n): gather the requests' keys and (vals
+// non-null) values into batch buffers; scatter batch indices (idx nullable)
+// and masks to the requests' outputs.  vals is a device array of rows.n
+// device pointers.
 hipError_t launch_gather_requests(const ReqDesc* d, int nreq, int64_t total, int kd, const RowSet& rows,
                                   int32_t* keys, uint8_t* const* vals, hipStream_t st);
-hipError_t launch_scatter_requests(const ReqDesc* d, int nreq, int64_t total, const RowSet& rows, const int32_t* idx,
-                                   const uint8_t* mask, const uint8_t* const* outv, hipStream_t st);
+hipError_t launch_scatter_requests(const ReqDesc* d, int nreq, int64_t total, const int32_t* idx, const uint8_t* mask,
+                                   hipStream_t st);
 // A fused served find over n positions of nreq requests (device
 // descriptors, offsets ascending from 0): keys are read from, and indices,
 // masks and (vs.n > 0) the value rows of hits written to, each request's own

@@ -218,8 +218,7 @@ ash_status_t run_fused(ash_server* s, const std::vector<Req*>& run, Stage& g) {
     default:
       return ASH_E_INVALID;
   }
-  ASH_HIP(ash::launch_scatter_requests(g.ddesc, nreq, off, rows, kind == ASH_REQ_INSERT ? g.idx : nullptr, g.mask,
-                                       nullptr, st));
+  ASH_HIP(ash::launch_scatter_requests(g.ddesc, nreq, off, kind == ASH_REQ_INSERT ? g.idx : nullptr, g.mask, st));
   return ASH_OK;
 }
 
