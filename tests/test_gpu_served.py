@@ -121,3 +121,51 @@ def test_served_tight_capacity_matches_serial(ash):
     m, outs, lat, sts, stats = run_served(ash, capacity, (pk, pv), reqs, np.zeros(len(reqs)), fuse=True,
                                           max_fused=32, max_batch=1 << 15, in_flight=2)
     check_against_oracle(capacity, (pk, pv), reqs, m, outs)
+
+
+def test_fused_finds_mixed_outputs(ash):
+    """Finds fused into one batch where some requests gather rows and some do
+    not, some skip the index output, and one writes its rows to a view that
+    starts 4 bytes into its buffer (the batch then copies in 4-byte units):
+    every request still gets exactly the oracle's results and misses' rows
+    stay untouched."""
+    rng = np.random.default_rng(72)
+    side, capacity, ch = 30, 40_000, 8
+    pre = rng.choice(side ** 3, size=15_000, replace=False)
+    pk = np.stack([pre // (side * side), (pre // side) % side, pre % side], axis=1).astype(np.int32)
+    pv = rng.standard_normal((len(pk), ch)).astype(np.float32)
+    m = ash.HashMap(capacity, 3, [(torch.float32, ch)])
+    m.insert(dev(pk), [dev(pv)])
+    o = OracleMap(capacity, 3, [(np.float32, ch)])
+    o.insert(pk, [pv])
+    torch.cuda.synchronize()
+    srv = ash.Server(m, fuse=True, max_fused=64, max_batch=1 << 16, in_flight=2)
+    built, outs, keep = [], [], []
+    for i in range(40):
+        n = int(rng.integers(1, 3000))
+        keys = rng.integers(0, side + 5, size=(n, 3), dtype=np.int32)
+        gather = i % 3 != 0
+        base = torch.full((n * ch + 1,), 7.0, dtype=torch.float32, device="cuda")
+        vals = base[1:].view(n, ch) if i == 5 else base[: n * ch].view(n, ch)  # request 5: 4-byte aligned rows
+        idx = torch.full((n,), -7, dtype=torch.int32, device="cuda") if i % 4 != 1 else None
+        mask = torch.full((n,), 7, dtype=torch.uint8, device="cuda")
+        kd = dev(keys)
+        r, k = srv.request(FIND, kd, [], out_idx=idx, out_mask=mask, out_values=[vals] if gather else None)
+        built.append(r)
+        keep.append((kd, k, base))
+        outs.append((keys, gather, vals, idx, mask))
+    lat, sts, span = srv.replay(built, np.zeros(len(built)))
+    stats = srv.stats()
+    srv.close()
+    torch.cuda.synchronize()
+    assert np.all(sts == 0) and stats["batches"] < len(built)
+    for keys, gather, vals, idx, mask in outs:
+        st, oi, om, (ov,) = o.find(keys, gather=True, fill=7.0)
+        assert np.array_equal(host(mask), om)
+        if idx is not None:
+            assert np.array_equal(host(idx), oi)
+        got = host(vals)
+        if gather:
+            assert np.array_equal(bits(got), bits(ov))
+        else:
+            assert np.all(got == 7.0)
