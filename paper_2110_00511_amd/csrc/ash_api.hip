@@ -236,6 +236,17 @@ ash_status_t insert_impl(ash_map* m, const int32_t* keys, int64_t n, const void*
   if (values && m->n_values > 0) vs = make_values(m, values, nullptr, true);
   ASH_TRY(ensure_scratch(m, n, st));
   ASH_TRY(maybe_clean(m, n, st));
+  // Keeping pending keys in their slots pays when most positions repeat a
+  // key (the later copies compare against the slot instead of reading the
+  // batch) and costs a store per repeated key otherwise: measured on 10M
+  // keys, the claim takes 277 against 379 us with 90% repeats, 497 against
+  // 466 us with 50%.  The last finalized insert's new-key fraction (possibly
+  // an earlier call's) decides; results do not depend on the choice.
+  {
+    const volatile Meta* mr = m->mirror_h;
+    const uint64_t last_n = mr->last_n, last_new = mr->result;
+    m->keyed = last_n > 0 && last_new * 10 <= last_n * 4;
+  }
   const uint32_t un = (uint32_t)n;
   const uint32_t blocks = ash::claim_blocks(m->G, un);
   auto claim = [&]() -> ash_status_t {
@@ -383,6 +394,14 @@ ash_status_t ash_create(int64_t capacity, int32_t key_dim, int32_t n_values, con
     ok = m->vB[j] != nullptr;
   }
   if (ok) ok = ensure_scratch(m, 0, st) == ASH_OK;
+  if (ok) {
+    ok = hipHostMalloc((void**)&m->mirror_h, sizeof(Meta), hipHostMallocDefault) == hipSuccess;
+    if (!ok) m->mirror_h = nullptr;
+    if (ok) {
+      std::memset(m->mirror_h, 0, sizeof(Meta));
+      ok = hipHostGetDevicePointer((void**)&m->mirror, m->mirror_h, 0) == hipSuccess;
+    }
+  }
   if (!ok) {
     ash_destroy(m);
     return ASH_E_NOMEM;
@@ -408,6 +427,10 @@ ash_status_t ash_destroy(ash_map_t m) {
   m->mem.put(m->lost, st);
   m->mem.put(m->scan_status, st);
   for (hipEvent_t e : m->prof.pool) (void)hipEventDestroy(e);
+  if (m->mirror_h) {
+    (void)hipDeviceSynchronize();  // no finalize may still write the mirror
+    (void)hipHostFree(m->mirror_h);
+  }
   delete m;
   return ASH_OK;
 }
@@ -706,6 +729,7 @@ ash_status_t ash_voxelize(const float* points, int64_t n, float voxel, int32_t* 
     tb.max_windows = nslots / tb.window + 1;
     tb.dedup = kVoxelDedup;
     tb.reuse = 0;
+    tb.keyed = 1;  // (the voxel claim always keeps pending keys in their slots)
     tb.mirror = nullptr;
     Meta h;
     std::memset(&h, 0, sizeof(h));

@@ -57,7 +57,8 @@ struct Meta {
   uint32_t spare;
   uint32_t result;  // total of the last scanning kernel
   uint32_t fail;    // groups whose probe found no empty slot (claim/rebuild)
-  uint32_t pad[7];
+  uint32_t last_n;  // mirror only: batch size of the last finalized insert (its result: new keys)
+  uint32_t pad[6];
 };
 
 // One request of a fused served batch: its positions [off, off + n) of the
@@ -98,7 +99,8 @@ struct TableRef {
   uint32_t max_windows;   // probe steps that cover the whole table
   uint32_t dedup;         // 1: claims drop block-local duplicates in LDS first
   uint32_t reuse;         // 1: the table may hold tombstones, which claims may take
-  Meta* mirror;           // nullable host-mapped copy of t / used / tombs, written by every finalize
+  uint32_t keyed;         // 1: claims keep pending keys in their slots (no tombstone reuse then)
+  Meta* mirror;           // nullable host-mapped copy of the counters, written by every finalize
 };
 
 // ---------------------------------------------------------------------------

@@ -162,9 +162,15 @@ struct ash_map {
   // An erase ran since the table was last empty or rebuilt, so it may hold
   // tombstones for claims to reuse (skipping them is always correct).
   bool tombs_possible = false;
-  // Host-mapped memory that every insert and erase finalize copies t, used
-  // and tombs to (a server reads it once a batch is done), or null.
+  // Pinned host memory that every insert and erase finalize copies t, used,
+  // tombs and (inserts) the new-key count and batch size to: mirror_h as
+  // the host reads it, mirror as the device writes it.  A server reads the
+  // counters once a batch is done; inserts read the last new-key fraction.
+  Meta* mirror_h = nullptr;
   Meta* mirror = nullptr;
+  // The next claim keeps pending keys in their slots (chosen per insert from
+  // the last insert's new-key fraction; results are the same either way).
+  bool keyed = false;
 
   int slot_words() const { return key_dim == 1 ? 2 : (key_dim <= 3 ? 4 : 8); }
 
@@ -178,6 +184,7 @@ struct ash_map {
     r.max_windows = nslots / r.window + 1;
     r.dedup = (flags & ASH_F_LDS_DEDUP) ? 1u : 0u;
     r.reuse = tombs_possible ? 1u : 0u;
+    r.keyed = keyed ? 1u : 0u;
     r.mirror = mirror;
     return r;
   }

@@ -224,6 +224,19 @@ struct Window {
     }
   }
 
+  // The same, with each member's slot number passed to the predicate.
+  template <typename F>
+  __device__ __forceinline__ uint64_t mask_at(F&& pred) const {
+    if constexpr (G == 1) {
+      uint64_t m = 0;
+#pragma unroll
+      for (int j = 0; j < kPer; ++j) m |= pred(v[j], at[j]) ? (1ull << j) : 0ull;
+      return m;
+    } else {
+      return group_ballot<G>(pred(v[0], at[0]));
+    }
+  }
+
   // (member selection in lane mode is an OR of masked words, which keeps the
   // window in registers; a select chain would be folded into an indexed
   // load from a stack copy)
@@ -328,7 +341,28 @@ __device__ __forceinline__ void block_dedup(const Src& src, uint32_t n, uint32_t
   __syncthreads();
 }
 
-template <int KD, int G, int WL, typename Src, bool kVoxel, bool kReuse = false>
+// Claims on a table without reusable tombstones keep a pending slot's key
+// in the slot once someone has read it: the pending tag word is the key's
+// last word, and a position that compares against a pending slot whose other
+// key words still read 0xFFFFFFFF (a slot claimed from EMPTY keeps those
+// until written; EMPTY slots are never written otherwise) reads the pending
+// position's key from the batch and writes its other words into the slot
+// with one write-through store.  Later positions of that key then compare
+// against the slot alone.  Every such store writes the slot's own key (all
+// positions pending on a slot share it), so concurrent stores agree.  Keys
+// seen only once cost nothing extra.  With key_dim 4 the three words would
+// need two stores, so that case keeps a hash tag.
+template <int KD, int S>
+__device__ __forceinline__ void publish_key_words(uint32_t* slot, const int32_t (&k)[KD]) {
+  if constexpr (KD == 2) {
+    __hip_atomic_store(slot, (uint32_t)k[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } else if constexpr (KD == 3) {
+    const uint64_t w = (uint64_t)(uint32_t)k[0] | ((uint64_t)(uint32_t)k[1] << 32);
+    __hip_atomic_store(reinterpret_cast<uint64_t*>(slot), w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+template <int KD, int G, int WL, typename Src, bool kVoxel, bool kReuse = false, bool kKeep = false>
 __device__ __forceinline__ void claim_tile(const TableRef& tb, const Src& src, uint32_t n, uint32_t tile,
                                            uint32_t rounds, uint32_t* __restrict__ slot_of,
                                            uint8_t* __restrict__ lost, uint32_t* __restrict__ partial, Meta* meta,
@@ -336,6 +370,7 @@ __device__ __forceinline__ void claim_tile(const TableRef& tb, const Src& src, u
   using Win = Window<KD, G, WL>;
   constexpr int S = Win::S;
   constexpr uint32_t kGroups = kBlock / G;
+  constexpr bool kKeyed = kKeep && !kReuse && (KD == 2 || KD == 3);  // pending keys kept in their slots
   const uint32_t sub = G == 1 ? 0u : (threadIdx.x & (G - 1));
   const uint32_t grp = threadIdx.x / G;
   const uint32_t tile_base = tile * kGroups * rounds;  // 256 positions per tile
@@ -360,7 +395,7 @@ __device__ __forceinline__ void claim_tile(const TableRef& tb, const Src& src, u
     uint32_t out = kNoSlot;
     if (valid && !copy) {
       const uint64_t h = key_hash<KD>(k);
-      const uint32_t tag = pending_tag<KD>(k, h);
+      const uint32_t tag = kKeyed ? (uint32_t)k[KD - 1] : pending_tag<KD>(k, h);
       const uint64_t desired = ((uint64_t)(kPending + p) << 32) | tag;
       uint32_t base = home_slot(tb, h);
       bool resolved = false;
@@ -384,14 +419,24 @@ __device__ __forceinline__ void claim_tile(const TableRef& tb, const Src& src, u
             break;
           }
           // same key pending in this batch (compared against the read-only batch)
-          const uint64_t mp = win.mask([&](const Slot<S> sl) {
+          const uint64_t mp = win.mask_at([&](const Slot<S> sl, uint32_t slot_no) {
             const uint32_t st = sl.w[S - 1];
             if (!(st >= kPending && st < kTomb && sl.w[S - 2] == tag && st - kPending < n)) return false;
             if constexpr (KD == 1) {
               return true;  // the tag word of a 1-word key is the key
             } else {
+              if constexpr (kKeyed) {  // the tag word is the last key word
+                bool unset = true, eq = true;
+#pragma unroll
+                for (int d = 0; d < KD - 1; ++d) {
+                  unset = unset && sl.w[d] == kEmpty;
+                  eq = eq && sl.w[d] == (uint32_t)k[d];
+                }
+                if (!unset) return eq;
+              }
               int32_t kq[KD];
               src.load(st - kPending, kq);
+              if constexpr (kKeyed) publish_key_words<KD, S>(tb.words + (size_t)slot_no * S, kq);
               return keys_equal<KD>(kq, k);
             }
           });
@@ -497,12 +542,13 @@ __device__ __forceinline__ void claim_tile(const TableRef& tb, const Src& src, u
   __syncthreads();  // the scratch is reused by the next tile of a persistent block
 }
 
-template <int KD, int G, int WL, typename Src, bool kVoxel, bool kReuse>
+template <int KD, int G, int WL, typename Src, bool kVoxel, bool kReuse, bool kKeep>
 __global__ __launch_bounds__(kBlock) void k_claim(TableRef tb, Src src, uint32_t n, uint32_t rounds,
                                                   uint32_t* __restrict__ slot_of, uint8_t* __restrict__ lost,
                                                   uint32_t* __restrict__ partial, Meta* meta) {
   __shared__ TileLds lds;
-  claim_tile<KD, G, WL, Src, kVoxel, kReuse>(tb, src, n, blockIdx.x, rounds, slot_of, lost, partial, meta, lds);
+  claim_tile<KD, G, WL, Src, kVoxel, kReuse, kKeep>(tb, src, n, blockIdx.x, rounds, slot_of, lost, partial, meta,
+                                                     lds);
 }
 
 // meta->claims = sum of the claim kernel's per-block counts (one block).
@@ -570,12 +616,18 @@ __device__ __forceinline__ void finalize_total(Meta* m, uint32_t cap, int mode, 
 }
 
 // Copies the counters a host reader tracks to the table's mirror, if any
-// (vector stores to host-mapped memory, visible once the kernel is done).
-__device__ __forceinline__ void publish_counts(const TableRef& tb, const Meta* m) {
+// (vector stores to host-mapped memory, visible once the kernel is done):
+// t and the slot counts, and after an insert of n positions its new-key
+// count, which the host uses to choose the next insert's claim variant.
+__device__ __forceinline__ void publish_counts(const TableRef& tb, const Meta* m, uint32_t insert_n = 0) {
   if (!tb.mirror) return;
   tb.mirror->t = m->t;
   tb.mirror->used = m->used;
   tb.mirror->tombs = m->tombs;
+  if (insert_n) {
+    tb.mirror->result = m->result;
+    tb.mirror->last_n = insert_n;
+  }
   __threadfence_system();
 }
 
@@ -645,7 +697,7 @@ __device__ __forceinline__ void commit_tile(const TableRef& tb, const int32_t* _
   // after this point; the next kernel sees the update at the launch boundary.
   if (fin >= 0 && threadIdx.x == 0 && tile == (n - 1) / kScanTile) {
     finalize_total(meta, cap, kFinalizeInsert, fin, check, prefix + total, n);
-    publish_counts(tb, meta);
+    publish_counts(tb, meta, n);
   }
   bool bad = false;
 #pragma unroll
@@ -1566,13 +1618,17 @@ struct ClaimK {
   static hipError_t run(const TableRef& tb, const int32_t* keys, uint32_t n, uint32_t* slot_of, uint8_t* lost,
                         uint32_t* partial, Meta* meta, hipStream_t st) {
     const uint32_t rounds = rounds_for<G>();
+    const dim3 grid(cdiv(n, (kBlock / G) * rounds));
     // tombstones are reused only where an erase may have left some
     if (tb.reuse)
-      hipLaunchKernelGGL((k_claim<KD, G, WL, BatchKeys<KD>, false, true>), dim3(cdiv(n, (kBlock / G) * rounds)),
-                         dim3(kBlock), 0, st, tb, BatchKeys<KD>{keys}, n, rounds, slot_of, lost, partial, meta);
+      hipLaunchKernelGGL((k_claim<KD, G, WL, BatchKeys<KD>, false, true, false>), grid, dim3(kBlock), 0, st, tb,
+                         BatchKeys<KD>{keys}, n, rounds, slot_of, lost, partial, meta);
+    else if (tb.keyed)
+      hipLaunchKernelGGL((k_claim<KD, G, WL, BatchKeys<KD>, false, false, true>), grid, dim3(kBlock), 0, st, tb,
+                         BatchKeys<KD>{keys}, n, rounds, slot_of, lost, partial, meta);
     else
-      hipLaunchKernelGGL((k_claim<KD, G, WL, BatchKeys<KD>, false, false>), dim3(cdiv(n, (kBlock / G) * rounds)),
-                         dim3(kBlock), 0, st, tb, BatchKeys<KD>{keys}, n, rounds, slot_of, lost, partial, meta);
+      hipLaunchKernelGGL((k_claim<KD, G, WL, BatchKeys<KD>, false, false, false>), grid, dim3(kBlock), 0, st, tb,
+                         BatchKeys<KD>{keys}, n, rounds, slot_of, lost, partial, meta);
     return hipGetLastError();
   }
 };
@@ -1637,7 +1693,7 @@ struct VoxelClaimK {
   static hipError_t run(const TableRef& tb, const float* pts, float voxel, uint32_t n, uint32_t* slot_of,
                         uint8_t* lost, uint32_t* partial, Meta* meta, hipStream_t st) {
     const uint32_t rounds = rounds_for<G>();
-    hipLaunchKernelGGL((k_claim<3, G, WL, VoxelKeys, true, false>), dim3(cdiv(n, (kBlock / G) * rounds)), dim3(kBlock), 0,
+    hipLaunchKernelGGL((k_claim<3, G, WL, VoxelKeys, true, false, true>), dim3(cdiv(n, (kBlock / G) * rounds)), dim3(kBlock), 0,
                        st, tb, VoxelKeys{pts, voxel}, n, rounds, slot_of, lost, partial, meta);
     return hipGetLastError();
   }

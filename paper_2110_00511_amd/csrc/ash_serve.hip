@@ -86,8 +86,6 @@ struct ash_server {
   std::vector<Stage> stages;
   std::vector<int> free_stages;
   std::vector<hipEvent_t> free_events;
-  Meta* mirror_h = nullptr;  // pinned, host-mapped: the map's counters after its latest finalize
-  Meta* mirror_d = nullptr;  // the same memory as the device addresses it
   int64_t conf_t = 0, conf_used = 0;    // read from the mirror when a batch retires
   int64_t add_live = 0, add_used = 0;  // summed over the batches in flight
   bool stop = false;
@@ -327,7 +325,7 @@ void completer_loop(ash_server* s) {
         // The mirror holds this batch's counters or those of a later batch
         // (still in flight, so its additions are also in add_live): either
         // way conf + add stays an upper bound.
-        const volatile Meta* mr = s->mirror_h;
+        const volatile Meta* mr = s->map->mirror_h;
         s->conf_t = mr->t;
         s->conf_used = mr->used;
       }
@@ -343,9 +341,9 @@ void completer_loop(ash_server* s) {
   }
 }
 
-// Device resources of a server: stream, staging, events, the counter mirror
-// (attached to the map while the server lives), the map's scratch sized for
-// a full batch, and the exact starting counters.
+// Device resources of a server: stream, staging, events, the map's scratch
+// sized for a full batch, and the exact starting counters (also written to
+// the map's counter mirror, which the completion thread reads).
 ash_status_t setup(ash_server* s) {
   const ash_server_config_t& c = s->cfg;
   if (hipGetDevice(&s->device) != hipSuccess) return ASH_E_DEVICE;
@@ -358,18 +356,14 @@ ash_status_t setup(ash_server* s) {
     if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return ASH_E_DEVICE;
     s->free_events.push_back(e);
   }
-  if (hipHostMalloc((void**)&s->mirror_h, sizeof(Meta), hipHostMallocDefault) != hipSuccess) {
-    s->mirror_h = nullptr;
-    return ASH_E_NOMEM;
-  }
-  if (hipHostGetDevicePointer((void**)&s->mirror_d, s->mirror_h, 0) != hipSuccess) return ASH_E_DEVICE;
   Meta h;
   ASH_TRY(ensure_scratch(s->map, c.fuse ? c.max_batch : 1, s->stream));
   ASH_TRY(read_meta(s->map, &h, s->stream));
-  *s->mirror_h = h;
+  s->map->mirror_h->t = h.t;  // nothing is in flight: the counters are exact
+  s->map->mirror_h->used = h.used;
+  s->map->mirror_h->tombs = h.tombs;
   s->conf_t = h.t;
   s->conf_used = h.used;
-  s->map->mirror = s->mirror_d;
   return ASH_OK;
 }
 
@@ -378,8 +372,7 @@ void release(ash_server* s) {
   if (s->stream) (void)hipStreamSynchronize(s->stream);
   for (Stage& g : s->stages) stage_free(g);
   for (hipEvent_t e : s->free_events) (void)hipEventDestroy(e);
-  s->map->mirror = nullptr;
-  if (s->mirror_h) (void)hipHostFree(s->mirror_h);
+
   if (s->stream) (void)hipStreamDestroy(s->stream);
 }
 

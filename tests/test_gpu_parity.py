@@ -468,3 +468,30 @@ def test_tombstones_and_overflow_rollback(ash):
     pair.insert(k1[:700], [rng.standard_normal((700, 1)).astype(np.float32)])
     pair.find(np.concatenate([k1, big]))
     pair.check_state()
+
+
+@pytest.mark.parametrize("key_dim", [2, 3])
+@pytest.mark.parametrize("g,w", [(1, 4), (4, 4), (16, 8)])
+def test_claims_that_keep_pending_keys(ash, key_dim, g, w):
+    """After an insert whose positions mostly repeat a key, the next claims
+    keep pending keys in their slots.  Their batches mix keys whose leading
+    words are all -1 (the value an unwritten slot word holds), many keys that
+    share their last word (the pending tag), repeats of earlier keys and new
+    ones; every result must still equal the oracle's."""
+    rng = np.random.default_rng(110 + key_dim * 10 + g)
+    pair = Pair(ash, 60_000, key_dim, [(np.float32, 2)], probe_group=g, bucket_width=w)
+
+    def batch(n, distinct):
+        base = rng.integers(-20, 20, size=(distinct, key_dim), dtype=np.int32)
+        base[: distinct // 8, : key_dim - 1] = -1           # leading words all -1
+        base[distinct // 8: distinct // 2, key_dim - 1] = 7  # one shared last word
+        keys = base[rng.integers(0, distinct, size=n)]
+        return keys, [rng.standard_normal((n, 2)).astype(np.float32)]
+
+    pair.insert(*batch(20_000, 2_000))  # 90% repeats: the next inserts keep pending keys
+    pair.check_state()
+    for _ in range(3):
+        pair.insert(*batch(30_000, 3_000))
+        pair.check_state()
+    keys, _ = batch(10_000, 4_000)
+    pair.find(keys)
