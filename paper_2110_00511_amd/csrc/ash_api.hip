@@ -239,7 +239,7 @@ ash_status_t insert_impl(ash_map* m, const int32_t* keys, int64_t n, const void*
   // Keeping pending keys in their slots pays when most positions repeat a
   // key (the later copies compare against the slot instead of reading the
   // batch) and costs a store per repeated key otherwise: measured on 10M
-  // keys, the claim takes 277 against 379 us with 90% repeats, 497 against
+  // keys, the claim takes 280 against 379 us with 90% repeats, 497 against
   // 466 us with 50%.  The last finalized insert's new-key fraction (possibly
   // an earlier call's) decides; results do not depend on the choice.
   {
