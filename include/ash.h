@@ -119,11 +119,16 @@ typedef struct {
 
 /* Creates an empty map (Sec. 4.3: h = 0..c-1, t = 0).  capacity in
  * [0, 2^31 - 3]; key_dim in [1, 4]; n_values in [0, 8]; value_elems[j] > 0.
- * Synchronizes `stream` once the buffers are initialised. */
+ * Besides the device buffers from the allocator, the map holds 64 bytes of
+ * pinned host memory (hipHostMalloc) that its kernels write the counters
+ * to.  Synchronizes `stream` once the buffers are initialised. */
 ash_status_t ash_create(int64_t capacity, int32_t key_dim, int32_t n_values,
                         const ash_dtype_t* value_dtypes, const int64_t* value_elems,
                         const ash_allocator_t* allocator, const ash_tuning_t* tuning,
                         void* stream, ash_map_t* out);
+/* Returns the device buffers to the allocator (after the work queued on the
+ * null stream) and frees the pinned counter memory once the whole device is
+ * idle (this waits for the device). */
 ash_status_t ash_destroy(ash_map_t map);
 
 /* Lazy insertion (Sec. 4.3.1): for each new key (first occurrence in batch
