@@ -702,7 +702,9 @@ ash_status_t ash_voxelize(const float* points, int64_t n, float voxel, int32_t* 
   DevMem mem;
   mem.custom = allocator != nullptr;
   if (allocator) mem.a = *allocator;
-  constexpr int kW = 4, kG = 1;  // one lane per point, 4-slot buckets
+  // four lanes per point, 4-slot buckets: against one lane per point, equal
+  // at 5 mm and 1 cm, 3% faster at 2 cm and 8% at 5 cm (5M points)
+  constexpr int kW = 4, kG = 4;
   constexpr float kLoad = 0.5f;
   uint32_t nslots;
   ASH_TRY(slots_for(n, kLoad, kW, kG, &nslots));
