@@ -310,4 +310,33 @@ int64_t oracle_voxelize(const float* points, int64_t n, float voxel,
   return n_voxels;
 }
 
+void oracle_block_coords(const float* points, int64_t n, float voxel,
+                         int32_t res, int32_t* block_keys,
+                         int32_t* local_coords, uint8_t* valid) {
+  for (int64_t p = 0; p < n; ++p) {
+    int64_t v[3];
+    bool ok = true;
+    for (int d = 0; d < 3; ++d) {
+      float q = points[p * 3 + d] / voxel;  // binary32 division, as voxelize
+      float f = std::floor(q);
+      if (!std::isfinite(f) || f < -2147483648.0f || f >= 2147483648.0f) {
+        ok = false;
+        break;
+      }
+      v[d] = (int64_t)f;
+    }
+    valid[p] = ok ? 1 : 0;
+    for (int d = 0; d < 3; ++d) {
+      int64_t b = 0, l = 0;
+      if (ok) {
+        b = v[d] / res;
+        if (v[d] % res != 0 && v[d] < 0) b -= 1;  // floor, not truncation
+        l = v[d] - b * res;
+      }
+      block_keys[p * 3 + d] = (int32_t)b;
+      local_coords[p * 3 + d] = (int32_t)l;
+    }
+  }
+}
+
 }  // extern "C"

@@ -108,6 +108,17 @@ int64_t oracle_voxelize(const float* points, int64_t n, float voxel,
                         int32_t* point_voxel, int32_t* voxel_keys,
                         int32_t* counts);
 
+/* Block and in-block voxel coordinates of points (the coupled lookup of
+ * Sec. 6.2.2: a voxel block of res^3 voxels of size `voxel`).  For each
+ * axis the voxel index v = floor(p[d] / voxel) is formed exactly as in
+ * oracle_voxelize; then block = floor(v / res) (rounding toward -infinity)
+ * and local = v - block * res, in [0, res).  Over the reals these equal the
+ * paper's floor(x / (s res)) and floor((x - block s res) / s).  A point
+ * voxelize rejects gets valid 0 and zero coordinates. */
+void oracle_block_coords(const float* points, int64_t n, float voxel,
+                         int32_t res, int32_t* block_keys,
+                         int32_t* local_coords, uint8_t* valid);
+
 #ifdef __cplusplus
 }
 #endif

@@ -69,6 +69,8 @@ def _load(path=_LIB):
     lib.oracle_find_offsets.restype = ctypes.c_int
     lib.oracle_intersect.argtypes = [P, P, i64, P]
     lib.oracle_intersect.restype = i64
+    lib.oracle_block_coords.argtypes = [P, i64, ctypes.c_float, i32, P, P, P]
+    lib.oracle_block_coords.restype = None
     lib.oracle_voxelize.argtypes = [P, i64, ctypes.c_float, P, P, P]
     lib.oracle_voxelize.restype = i64
     _lib_cache[path] = lib
@@ -219,3 +221,15 @@ def oracle_voxelize(points, voxel, lib_path=_LIB):
     cnt = np.empty(max(n, 1), np.int32)
     u = lib.oracle_voxelize(_ptr(pts), n, ctypes.c_float(np.float32(voxel)), _ptr(pv), _ptr(vk), _ptr(cnt))
     return pv, vk[:u].copy(), cnt[:u].copy()
+
+
+def oracle_block_coords(points, voxel, res, lib_path=_LIB):
+    """Returns (block_keys[n,3], local_coords[n,3], valid[n])."""
+    lib = _load(lib_path)
+    pts = np.ascontiguousarray(points, dtype=np.float32).reshape(-1, 3)
+    n = pts.shape[0]
+    bk = np.empty((n, 3), np.int32)
+    lc = np.empty((n, 3), np.int32)
+    ok = np.empty(n, np.uint8)
+    lib.oracle_block_coords(_ptr(pts), n, ctypes.c_float(np.float32(voxel)), int(res), _ptr(bk), _ptr(lc), _ptr(ok))
+    return bk, lc, ok

@@ -42,6 +42,8 @@ MUTANTS = {
     "neighbor_offset_major": ("int64_t out = q * n_offsets + o;", "int64_t out = o * n + q;"),
     "neighbor_drops_last_word": ("      for (int d = 0; d < m->key_dim; ++d) {\n        uint32_t a",
                                  "      for (int d = 0; d + 1 < m->key_dim; ++d) {\n        uint32_t a"),
+    "block_truncates": ("        if (v[d] % res != 0 && v[d] < 0) b -= 1;  // floor, not truncation\n", "\n"),
+    "block_local_remainder": ("        l = v[d] - b * res;", "        l = v[d] % res;"),
     "intersect_keeps_misses": ("if (m->M.find(k) == m->M.end()) continue;", "if (m->M.find(k) != m->M.end()) continue;"),
 }
 

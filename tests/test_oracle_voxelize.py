@@ -91,3 +91,43 @@ def test_empty_and_single():
     assert len(pv) == 0 and len(vk) == 0
     pv, vk, cnt = _compare(np.array([[0.5, 0.5, 0.5]], np.float32), 0.01)
     assert pv.tolist() == [0] and cnt.tolist() == [1]
+
+
+# ---------------------------------------------------------------------------
+# Block and in-block voxel coordinates (Sec. 6.2.2).
+def test_block_coords_hand_worked():
+    """x = -0.1 m, 0.0 m, 0.45 m with 5 cm voxels and 8^3 blocks: voxel
+    indices -2, 0, 9 (binary32 quotients -2, 0, 9), blocks -1, 0, 1, local
+    coordinates 6, 0, 1."""
+    from oracle import oracle_block_coords
+    bk, lc, ok = oracle_block_coords(np.array([[-0.1, 0.0, 0.45]], np.float32), 0.05, 8)
+    assert ok.tolist() == [1]
+    assert bk.tolist() == [[-1, 0, 1]] and lc.tolist() == [[6, 0, 1]]
+
+
+@pytest.mark.parametrize("voxel,res", [(0.05, 8), (0.004, 16), (0.1, 3)])
+def test_block_coords_recompose_voxel_keys(voxel, res):
+    """block * res + local is the point's voxelization key; local lies in
+    [0, res); away from block boundaries the block equals the paper's
+    floor(x / (s * res)) evaluated in float64."""
+    from oracle import oracle_block_coords, oracle_voxelize
+    rng = np.random.default_rng(7)
+    pts = (rng.standard_normal((20_000, 3)) * 3.0).astype(np.float32)
+    bk, lc, ok = oracle_block_coords(pts, voxel, res)
+    assert ok.all()
+    pv, vk, _ = oracle_voxelize(pts, voxel)
+    keys = vk[pv]
+    assert np.array_equal(bk.astype(np.int64) * res + lc, keys)
+    assert lc.min() >= 0 and lc.max() < res
+    r = pts.astype(np.float64) / (float(np.float32(voxel)) * res)
+    far = np.abs(r - np.round(r)) > 1e-4
+    assert far.mean() > 0.99
+    assert np.array_equal(bk[far], np.floor(r[far]).astype(np.int64))
+
+
+def test_block_coords_rejects():
+    from oracle import oracle_block_coords
+    pts = np.array([[np.nan, 0, 0], [0, np.inf, 0], [3e38, 0, 0], [0.5, 0.5, 0.5]], np.float32)
+    bk, lc, ok = oracle_block_coords(pts, 0.01, 8)
+    assert ok.tolist() == [0, 0, 0, 1]
+    assert not bk[:3].any() and not lc[:3].any()
