@@ -171,6 +171,21 @@ ash_status_t ash_find_offsets(ash_map_t map, const int32_t* keys, int64_t n,
                               int32_t* out_idx, uint8_t* out_mask,
                               void* stream);
 
+/* Block and in-block voxel coordinates (Sec. 6.2.2: a voxel is found by a
+ * lookup of its block, a res^3 grid of voxels, plus direct indexing inside
+ * it).  points: n x 3 float32 (device).  Per axis the voxel index v =
+ * floor(p / voxel_size) is formed exactly as in ash_voxelize; then
+ * out_block_keys = floor(v / block_res) (toward -infinity) and out_local =
+ * v - block * block_res, in [0, block_res) -- over the reals the paper's
+ * floor(x / (s l)) and floor((x - x_block s l) / s).  Points voxelize would
+ * reject get out_valid 0 and zero coordinates.  Outputs: n x 3 int32,
+ * n x 3 int32 and n uint8 (device).  voxel_size > 0 and finite, block_res
+ * >= 1, n < 2^31 - 3, else ASH_E_INVALID.  Asynchronous. */
+ash_status_t ash_block_coords(const float* points, int64_t n, float voxel_size,
+                              int32_t block_res, int32_t* out_block_keys,
+                              int32_t* out_local, uint8_t* out_valid,
+                              void* stream);
+
 /* Standard neighborhoods for ash_find_offsets, written to host memory as rows
  * of key_dim int32, enumerated with the first word slowest:
  *   ASH_NB_RADIUS: every offset with all words in [-radius, radius],

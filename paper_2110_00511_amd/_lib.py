@@ -74,6 +74,7 @@ SIGNATURES = {
     "ash_erase": (ST, [P, P, I64, P, P]),
     "ash_find_offsets": (ST, [P, P, I64, P, I32, P, P, P]),
     "ash_neighbor_offsets": (ST, [I32, I32, I32, P, ctypes.POINTER(I64)]),
+    "ash_block_coords": (ST, [P, I64, ctypes.c_float, I32, P, P, P, P]),
     "ash_intersect": (ST, [P, P, I64, P, ctypes.POINTER(I64), P]),
     "ash_save": (ST, [P, ctypes.c_char_p, P]),
     "ash_load": (ST, [ctypes.c_char_p, P, P, P, ctypes.POINTER(P)]),

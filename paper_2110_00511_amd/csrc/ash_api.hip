@@ -563,6 +563,17 @@ ash_status_t ash_intersect(ash_map_t m, const int32_t* keys, int64_t n, int32_t*
   return rc;
 }
 
+ash_status_t ash_block_coords(const float* points, int64_t n, float voxel_size, int32_t block_res,
+                              int32_t* out_block_keys, int32_t* out_local, uint8_t* out_valid, void* stream) {
+  if (n < 0 || n > kMaxCount || block_res < 1 || !(voxel_size > 0.0f) || !std::isfinite(voxel_size))
+    return ASH_E_INVALID;
+  if (n > 0 && (!points || !out_block_keys || !out_local || !out_valid)) return ASH_E_INVALID;
+  if (n == 0) return ASH_OK;
+  ASH_HIP(ash::launch_block_coords(points, (uint32_t)n, voxel_size, block_res, out_block_keys, out_local, out_valid,
+                                   (hipStream_t)stream));
+  return ASH_OK;
+}
+
 ash_status_t ash_neighbor_offsets(int32_t kind, int32_t radius, int32_t key_dim, int32_t* out_offsets,
                                   int64_t* out_count) {
   if (!out_count || key_dim < 1 || key_dim > 4 || radius < 1 || radius > 64) return ASH_E_INVALID;

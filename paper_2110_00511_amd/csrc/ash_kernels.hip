@@ -1282,6 +1282,33 @@ __global__ __launch_bounds__(kBlock) void k_voxel_commit(TableRef tb, VoxelKeys 
   }
 }
 
+// Block and in-block voxel coordinates (the coupled lookup of Sec. 6.2.2):
+// per axis the voxel index v = floor(p / voxel), formed as in voxelization,
+// then block = floor(v / res) and local = v - block * res in [0, res).
+// Equal over the reals to the paper's floor(x / (s res)) and
+// floor((x - block s res) / s), and exact in integers.  Rejected points get
+// valid 0 and zero coordinates.  One thread per point; an HBM-bound stream.
+__global__ __launch_bounds__(kBlock) void k_block_coords(const float* __restrict__ pts, uint32_t n, float voxel,
+                                                         int32_t res, int32_t* __restrict__ block_keys,
+                                                         int32_t* __restrict__ local, uint8_t* __restrict__ valid) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  int32_t v[3];
+  const bool ok = VoxelKeys{pts, voxel}.load(p, v);
+  valid[p] = ok ? 1 : 0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    int64_t b = 0, l = 0;  // 64-bit: b * res may leave int32 near its ends
+    if (ok) {
+      b = v[d] / res;
+      if (v[d] % res != 0 && v[d] < 0) b -= 1;
+      l = v[d] - b * res;
+    }
+    block_keys[(size_t)p * 3 + d] = (int32_t)b;
+    local[(size_t)p * 3 + d] = (int32_t)l;
+  }
+}
+
 // Voxelization pass 3: voxel ids and counts of the points the commit left:
 // every accepted point that is not its voxel's first (the commit resolved
 // first points and rejected ones, and set their slot_of to kNoSlot).
@@ -1888,6 +1915,14 @@ hipError_t launch_voxel_commit(const TableRef& tb, const float* pts, float voxel
                                uint64_t* status, hipStream_t st) {
   hipLaunchKernelGGL(k_voxel_commit, dim3(cdiv(n, kScanTile)), dim3(kBlock), 0, st, tb, VoxelKeys{pts, voxel}, n,
                      slot_of, lost, voxel_keys, counts, point_voxel, meta, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_block_coords(const float* pts, uint32_t n, float voxel, int32_t res, int32_t* block_keys,
+                               int32_t* local, uint8_t* valid, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_block_coords, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, pts, n, voxel, res, block_keys,
+                     local, valid);
   return hipGetLastError();
 }
 

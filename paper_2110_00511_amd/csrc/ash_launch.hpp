@@ -83,6 +83,9 @@ hipError_t launch_voxel_claim(int g, int w, const TableRef& tb, const float* pts
 hipError_t launch_voxel_commit(const TableRef& tb, const float* pts, float voxel, uint32_t n, uint32_t* slot_of,
                                uint8_t* lost, int32_t* voxel_keys, int32_t* counts, int32_t* point_voxel, Meta* meta,
                                uint64_t* status, hipStream_t st);
+// Per point: block keys, in-block voxel coordinates (res >= 1) and a valid flag.
+hipError_t launch_block_coords(const float* pts, uint32_t n, float voxel, int32_t res, int32_t* block_keys,
+                               int32_t* local, uint8_t* valid, hipStream_t st);
 hipError_t launch_voxel_resolve(const TableRef& tb, uint32_t n, const uint32_t* slot_of, int32_t* point_voxel,
                                 int32_t* counts, hipStream_t st);
 

@@ -263,6 +263,23 @@ def neighbor_offsets(kind="radius", radius=1, key_dim=3, device="cuda"):
     return out.to(device) if device is not None else out
 
 
+def block_coords(points, voxel_size, block_res):
+    """(block_keys [n, 3] int32, local [n, 3] int32, valid [n] bool) of
+    float32 [n, 3] points on the GPU: the voxel block of res^3 voxels each
+    point falls in and its voxel inside that block (Sec. 6.2.2)."""
+    if not (points.is_cuda and points.dtype == torch.float32):
+        raise TypeError("points must be a float32 tensor on the GPU")
+    pts = points.reshape(-1, 3).contiguous()
+    n = pts.shape[0]
+    bk = torch.empty((n, 3), dtype=torch.int32, device=pts.device)
+    lc = torch.empty((n, 3), dtype=torch.int32, device=pts.device)
+    ok = torch.empty(n, dtype=torch.uint8, device=pts.device)
+    lib = L.load()
+    L.check(lib.ash_block_coords(_ptr(pts), n, ctypes.c_float(voxel_size), int(block_res), _ptr(bk), _ptr(lc),
+                                 _ptr(ok), _stream()), "ash_block_coords")
+    return bk, lc, ok.bool()
+
+
 def voxelize(points, voxel_size):
     """Point-cloud voxelization (Sec. 6.1): returns (point_voxel [n] int32,
     voxel_keys [u, 3] int32, counts [u] int32), voxels in first-occurrence

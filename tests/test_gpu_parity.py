@@ -495,3 +495,26 @@ def test_claims_that_keep_pending_keys(ash, key_dim, g, w):
         pair.check_state()
     keys, _ = batch(10_000, 4_000)
     pair.find(keys)
+
+
+@pytest.mark.parametrize("voxel,res", [(0.05, 8), (0.005, 16), (0.1, 3), (1.0, 1)])
+def test_block_coords_match_oracle(ash, voxel, res):
+    """Block keys, in-block voxel coordinates and the valid flag of surface
+    points moved to straddle the origin, of points on voxel boundaries and of
+    rejected points, bit-exact against the oracle."""
+    from oracle import oracle_block_coords
+    pts = synth.points(n=100_001, seed=33) - np.float32(5.0)
+    s = np.float32(voxel)
+    k = np.arange(-500, 500, dtype=np.float32)
+    edge = (k * s).astype(np.float32)
+    edge = np.stack([edge, np.nextafter(edge, np.float32(-np.inf)), np.nextafter(edge, np.float32(np.inf))], axis=1)
+    rej = np.array([[np.nan, 0, 0], [0, np.inf, 0], [3e38, 0, 0], [-3e38, 1, 1],
+                    [np.float32(2.0 ** 31) * s, 0, 0]], np.float32)
+    pts = np.concatenate([pts, edge, rej]).astype(np.float32)
+    gb, gl, gv = ash.block_coords(dev(pts), float(s), res)
+    ob, ol, ov = oracle_block_coords(pts, s, res)
+    assert np.array_equal(host(gv).astype(np.uint8), ov)
+    assert np.array_equal(host(gb), ob) and np.array_equal(host(gl), ol)
+    assert ov[:100_001].all() and not ov[-5:-1].any()
+    e = ash.block_coords(dev(np.zeros((0, 3), np.float32)), float(s), res)
+    assert e[0].shape == (0, 3)
