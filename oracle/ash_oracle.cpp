@@ -42,6 +42,18 @@ namespace {
 
 typedef std::array<int32_t, 4> Key;  // unused trailing words are zero
 
+// Voxel index of one coordinate (Listing 1 of Sec. 6.1): floor(x / voxel)
+// with the binary32 quotient; false for a non-finite quotient or a floor
+// outside int32.
+bool voxel_index(float x, float voxel, int64_t* v) {
+  float q = x / voxel;  // binary32 division
+  float f = std::floor(q);
+  if (!std::isfinite(f) || f < -2147483648.0f || f >= 2147483648.0f)
+    return false;
+  *v = (int64_t)f;
+  return true;
+}
+
 Key read_key(const int32_t* keys, int64_t p, int key_dim) {
   Key k = {0, 0, 0, 0};
   for (int d = 0; d < key_dim; ++d) k[d] = keys[p * key_dim + d];
@@ -281,14 +293,10 @@ int64_t oracle_voxelize(const float* points, int64_t n, float voxel,
   for (int64_t p = 0; p < n; ++p) {
     std::array<int32_t, 3> k;
     bool ok = true;
-    for (int d = 0; d < 3; ++d) {
-      float q = points[p * 3 + d] / voxel;  // binary32 division
-      float f = std::floor(q);
-      if (!std::isfinite(f) || f < -2147483648.0f || f >= 2147483648.0f) {
-        ok = false;
-        break;
-      }
-      k[d] = (int32_t)f;
+    for (int d = 0; d < 3 && ok; ++d) {
+      int64_t v = 0;
+      ok = voxel_index(points[p * 3 + d], voxel, &v);
+      k[d] = (int32_t)v;
     }
     if (!ok) {
       point_voxel[p] = -1;
@@ -314,17 +322,9 @@ void oracle_block_coords(const float* points, int64_t n, float voxel,
                          int32_t res, int32_t* block_keys,
                          int32_t* local_coords, uint8_t* valid) {
   for (int64_t p = 0; p < n; ++p) {
-    int64_t v[3];
+    int64_t v[3] = {0, 0, 0};
     bool ok = true;
-    for (int d = 0; d < 3; ++d) {
-      float q = points[p * 3 + d] / voxel;  // binary32 division, as voxelize
-      float f = std::floor(q);
-      if (!std::isfinite(f) || f < -2147483648.0f || f >= 2147483648.0f) {
-        ok = false;
-        break;
-      }
-      v[d] = (int64_t)f;
-    }
+    for (int d = 0; d < 3 && ok; ++d) ok = voxel_index(points[p * 3 + d], voxel, &v[d]);
     valid[p] = ok ? 1 : 0;
     for (int d = 0; d < 3; ++d) {
       int64_t b = 0, l = 0;

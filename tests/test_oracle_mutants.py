@@ -32,7 +32,7 @@ MUTANTS = {
     "rehash_heap_reversed": ("for (int64_t i = old_c; i < new_capacity; ++i) m->h[i] = (int32_t)i;",
                              "for (int64_t i = old_c; i < new_capacity; ++i) m->h[i] = (int32_t)(new_capacity - 1 - (i - old_c));"),
     "autogrow_plus_one": ("while (grown - m->t < fresh) grown *= 2;", "while (grown - m->t < fresh) grown += 1;"),
-    "voxel_reciprocal": ("float q = points[p * 3 + d] / voxel;", "float q = points[p * 3 + d] * (1.0f / voxel);"),
+    "voxel_reciprocal": ("float q = x / voxel;", "float q = x * (1.0f / voxel);"),
     "voxel_trunc": ("float f = std::floor(q);", "float f = std::trunc(q);"),
     "voxel_range_edge": ("f >= 2147483648.0f", "f > 2147483648.0f"),
     "voxel_count_reset": ("    counts[id] += 1;\n", "    counts[id] = 1;\n"),
