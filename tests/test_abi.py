@@ -157,3 +157,28 @@ def test_load_rejects_bad_files_before_device_work(lib, tmp_path, case):
     out = ctypes.c_void_p()
     assert L.ash_load(str(path).encode(), None, None, None, ctypes.byref(out)) == _lib.ASH_E_INVALID
     assert not out.value
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """There is no fallback: without libash.so the binding raises."""
+    import subprocess
+    import sys
+    code = ("from paper_2110_00511_amd import _lib\n"
+            "try:\n"
+            f"    _lib.load({str(tmp_path / 'libash.so')!r})\n"
+            "except RuntimeError as e:\n"
+            "    print('raised:', e)\n")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=120)
+    assert "raised:" in r.stdout and "is missing" in r.stdout
+
+
+def test_block_coords_argument_errors(lib):
+    from paper_2110_00511_amd import _lib
+    L = _lib.load()
+    P = ctypes.c_void_p(16)  # never dereferenced: the host checks fail first
+    assert L.ash_block_coords(P, -1, ctypes.c_float(0.1), 8, P, P, P, None) == _lib.ASH_E_INVALID
+    assert L.ash_block_coords(P, 10, ctypes.c_float(0.0), 8, P, P, P, None) == _lib.ASH_E_INVALID
+    assert L.ash_block_coords(P, 10, ctypes.c_float(float("inf")), 8, P, P, P, None) == _lib.ASH_E_INVALID
+    assert L.ash_block_coords(P, 10, ctypes.c_float(0.1), 0, P, P, P, None) == _lib.ASH_E_INVALID
+    assert L.ash_block_coords(None, 10, ctypes.c_float(0.1), 8, P, P, P, None) == _lib.ASH_E_INVALID
+    assert L.ash_block_coords(None, 0, ctypes.c_float(0.1), 8, None, None, None, None) == _lib.ASH_OK
