@@ -463,11 +463,25 @@ def bench_voxelize(args):
         c1 = time.perf_counter()
         cpu = {"value": round(s / (c1 - c0) / 1e6, 3), "unit": "Mpoints/s", "cores": 1, "kind": "oracle",
                "sample": f"first {s} points at 5 mm ({c1 - c0:.1f} s)"}
+    # Roofline of one whole call (its kernels are launched back to back on one
+    # stream): algorithmic bytes per point with u = voxels / points --
+    # claim: point 12 + window line + u * CAS + slot 4; commit: slot 4 +
+    # lost 1 + point id 4 + u * (voxel key 12 + count 4 + slot store 32);
+    # resolve: slot 4 + (1 - u) * (slot line + count atomic + point id 4);
+    # fills: the 16 B slots of a table at load 0.5 (32 B per point) and 1 B
+    # per point of scratch.
+    u = out["0.5cm"]["voxels"] / n
+    per_point = (12 + READ_LINE + u * CAS64 + 4) + (4 + 1 + 4 + u * (12 + 4 + STORE)) \
+        + (4 + (1 - u) * (READ_LINE + ATOM32 + 4)) + (32 + 1)
+    achieved = per_point * n / (ms0 / 1e3) / 1e9
     print(json.dumps({
         "metric": "Mpoints/s voxelization (5M points, 5 mm voxels)", "value": round(n / ms0 / 1e3, 1),
         "unit": "Mpoints/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms0,
         "higher_is_better": True, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{n} points on 20 random spheres/planes in a 10 m box, sigma 1 cm", "sweep": out},
+        "roofline": {"bound": "hbm", "kernel": "voxelize (one whole call)", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "algorithmic_bytes_per_point": round(per_point, 1)},
         "cpu_baseline": cpu}), flush=True)
 
 
