@@ -125,12 +125,13 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, copy 256 MiB once (reference kernel for byte counters)")
     ap.add_argument("--workload", default="plain",
-                    choices=["plain", "batched", "voxelize", "served", "neighbors", "values"],
+                    choices=["plain", "batched", "voxelize", "served", "neighbors", "values", "large"],
                     help="plain: the headline 10M-key map; batched: 64 maps in one launch; voxelize: 5M points; "
                          "served: a Poisson request stream on a 2^25-capacity map")
     ap.add_argument("--requests", type=int, default=100_000, help="served: requests per run")
     ap.add_argument("--query-order", default="given", choices=["given", "morton"],
                     help="neighbors: query order (first appearance, or sorted by Z-order code)")
+    ap.add_argument("--large-n", type=int, default=1_000_000_000, help="large: keys per insert and per find")
     ap.add_argument("--neighbors-probe-group", type=int, default=1, help="neighbors: probe group of the map")
     ap.add_argument("--neighbors-bucket-width", type=int, default=4, help="neighbors: bucket width of the map")
     ap.add_argument("--served-max-load", type=float, default=0.5, help="served: max_load of the served map's table")
@@ -153,6 +154,8 @@ def main():
         return bench_neighbors(args)
     if args.workload == "values":
         return bench_values(args)
+    if args.workload == "large":
+        return bench_large(args)
     if args.workload == "served":
         return bench_served(args)
 
@@ -566,6 +569,54 @@ def bench_values(args):
         "roofline": {"bound": "hbm", "kernel": "values", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "algorithmic_bytes_per_row": 2 * top["row_bytes"] + 8, "kernel_ms": vk},
+        "cpu_baseline": None}), flush=True)
+
+
+def bench_large(args):
+    """A hash set far beyond the caches: n int32x3 keys (default 1e9, distinct
+    ratio ~0.5, drawn on the device from a seeded generator) inserted into a
+    cleared map of capacity 0.65 n (max load 0.5), then n finds, half hits.
+    Shows how insert and find rates hold up as the table grows to tens of GB."""
+    import torch
+
+    import paper_2110_00511_amd as ash
+
+    torch.cuda.set_device(0)
+    n = args.large_n
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(9)
+    side = int(round((n / 1.5936) ** (1 / 3)))  # n draws from side^3 cells: ~0.5 distinct
+    keys = torch.randint(0, side, (n, 3), dtype=torch.int32, device="cuda", generator=gen)
+    fk = keys[torch.randint(0, n, (n,), device="cuda", generator=gen)]
+    fk[n // 2:] += side  # the second half misses
+    m = ash.HashMap(int(n * 0.65), 3, [], probe_group=args.probe_group, bucket_width=args.bucket_width,
+                    max_load=args.max_load)
+    t_ins, t_fnd = [], []
+    for step in range(args.warmup + args.steps):
+        m.clear()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m.insert(keys)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, fm = m.find(fk)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if step >= args.warmup:
+            t_ins.append(t1 - t0)
+            t_fnd.append(t2 - t1)
+    ti, tf = sum(t_ins) / len(t_ins), sum(t_fnd) / len(t_fnd)
+    st = m.stats()
+    assert m.device_status() == 0
+    print(json.dumps({
+        "metric": "Mops/s insert+find on a large hash set", "value": round(2 * n / (ti + tf) / 1e6, 1),
+        "unit": "Mops/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round((ti + tf) * 1e3, 2), "higher_is_better": True, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": f"{n} int32x3 keys (distinct ratio ~0.5), hash set, then {n} finds (half hits)",
+                   "distinct": st["size"], "slots": st["slots"], "table_GB": round(st["slots"] * 16 / 1e9, 1),
+                   "insert_ms": round(ti * 1e3, 2), "insert_Mops": round(n / ti / 1e6, 1),
+                   "find_ms": round(tf * 1e3, 2), "find_Mops": round(n / tf / 1e6, 1),
+                   "hit_rate": round(float(fm.float().mean().item()), 4)},
         "cpu_baseline": None}), flush=True)
 
 
