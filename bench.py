@@ -591,15 +591,23 @@ def bench_large(args):
     fk[n // 2:] += side  # the second half misses
     m = ash.HashMap(int(n * 0.65), 3, [], probe_group=args.probe_group, bucket_width=args.bucket_width,
                     max_load=args.max_load)
+    from paper_2110_00511_amd import _lib as L
+    lib = L.load()
+    sp = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    P = ctypes.c_void_p
+    idx = torch.empty(n, dtype=torch.int32, device="cuda")
+    mask = torch.empty(n, dtype=torch.uint8, device="cuda")
+    fidx = torch.empty(n, dtype=torch.int32, device="cuda")
+    fm = torch.empty(n, dtype=torch.uint8, device="cuda")
     t_ins, t_fnd = [], []
     for step in range(args.warmup + args.steps):
-        m.clear()
+        L.check(lib.ash_clear(m._m, sp), "clear")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        m.insert(keys)
+        L.check(lib.ash_insert(m._m, P(keys.data_ptr()), n, None, P(idx.data_ptr()), P(mask.data_ptr()), sp), "insert")
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        _, fm = m.find(fk)
+        L.check(lib.ash_find(m._m, P(fk.data_ptr()), n, P(fidx.data_ptr()), P(fm.data_ptr()), None, sp), "find")
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         if step >= args.warmup:
