@@ -4,7 +4,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -799,11 +801,12 @@ static ash_status_t batched_resident(int kd, DevMem& mem, hipStream_t st, uint32
   for (int b = per_cu; b >= 1 && found == 0 && rc == ASH_OK; --b) {
     ash::GridSync h;
     if (ash::launch_fill_u32((uint32_t*)gs, 0u, sizeof(ash::GridSync) / 4, st) != hipSuccess ||
-        ash::launch_batched(kd, nullptr, 0, 0, 0, 0, 0, gs, (uint32_t)(cus * b), st) != hipSuccess ||
+        ash::launch_batched(kd, nullptr, 0, 0, 0, 0, 0, gs, (uint32_t)(cus * b), ash::kArrivalSpinLimit, st) !=
+            hipSuccess ||
         hipMemcpyAsync(&h, gs, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess) {
       rc = ASH_E_DEVICE;
-    } else if (h.abort == 0u) {  // every block passed every barrier
+    } else if ((h.count & ash::kArrivalFailed) == 0u && h.late == 0u) {  // every block passed every barrier
       found = (uint32_t)(cus * b);
     }
   }
@@ -831,6 +834,42 @@ ash_status_t ash_batched_grid(int32_t key_dim, int64_t* out_blocks, int64_t* out
   return ASH_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Launches of the persistent batched kernel that failed their arrival check
+// and ran op by op instead.
+std::atomic<int64_t> batched_fallbacks{0};
+
+// Bound of the arrival check: kArrivalSpinLimit polls, or the value of
+// ASH_BATCHED_ARRIVAL_SPINS.  The variable exists for tests: with 0 the
+// first block to arrive gives up at once, so the launch takes its fallback
+// while every kernel still exits normally.
+uint32_t arrival_spin_limit() {
+  const char* v = std::getenv("ASH_BATCHED_ARRIVAL_SPINS");
+  if (!v || !*v) return ash::kArrivalSpinLimit;
+  char* end = nullptr;
+  const unsigned long x = std::strtoul(v, &end, 10);
+  if (end == v || *end != '\0' || x > 0xFFFFFFFFul) return ash::kArrivalSpinLimit;
+  return (uint32_t)x;
+}
+
+// The single-map path, op by op: each op's insert, then its find.
+ash_status_t batched_op_by_op(const ash_batch_op_t* ops, int32_t n_ops, hipStream_t st) {
+  for (int32_t i = 0; i < n_ops; ++i) {
+    const ash_batch_op_t& op = ops[i];
+    ASH_TRY(insert_impl(op.map, op.insert_keys, op.n_insert, op.map->n_values > 0 ? op.insert_values : nullptr,
+                        op.insert_idx, op.insert_mask, st));
+    ASH_TRY(ash_find(op.map, op.find_keys, op.n_find, op.find_idx, op.find_mask, op.find_values, (void*)st));
+  }
+  return ASH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 ash_status_t ash_batched(const ash_batch_op_t* ops, int32_t n_ops, int32_t fused, void* stream) {
   if (n_ops < 0 || (n_ops > 0 && !ops)) return ASH_E_INVALID;
   if (n_ops == 0) return ASH_OK;
@@ -855,15 +894,7 @@ ash_status_t ash_batched(const ash_batch_op_t* ops, int32_t n_ops, int32_t fused
       for (int j = 0; j < m->n_values; ++j)
         if (!op.find_values[j]) return ASH_E_INVALID;
   }
-  if (!fused) {  // the plain single-map path, op by op
-    for (int32_t i = 0; i < n_ops; ++i) {
-      const ash_batch_op_t& op = ops[i];
-      ASH_TRY(insert_impl(op.map, op.insert_keys, op.n_insert, op.map->n_values > 0 ? op.insert_values : nullptr,
-                          op.insert_idx, op.insert_mask, st));
-      ASH_TRY(ash_find(op.map, op.find_keys, op.n_find, op.find_idx, op.find_mask, op.find_values, stream));
-    }
-    return ASH_OK;
-  }
+  if (!fused) return batched_op_by_op(ops, n_ops, st);
   std::vector<ash::BatchItem> items(n_ops);
   uint32_t claim_tiles = 0, commit_tiles = 0, find_tiles = 0;
   int32_t any_check = 0;
@@ -914,16 +945,28 @@ ash_status_t ash_batched(const ash_batch_op_t* ops, int32_t n_ops, int32_t fused
   ash::BatchItem* dev_items = (ash::BatchItem*)dev;
   ash::GridSync* gs = (ash::GridSync*)(dev + item_bytes);
   ash_status_t rc = ASH_OK;
+  ash::GridSync h;
+  std::memset(&h, 0, sizeof(h));
+  const uint32_t arrival_spins = arrival_spin_limit();
   if (hipMemcpyAsync(dev_items, items.data(), sizeof(ash::BatchItem) * (size_t)n_ops, hipMemcpyHostToDevice, st) !=
           hipSuccess ||
       ash::launch_fill_u32((uint32_t*)gs, 0u, sizeof(ash::GridSync) / 4, st) != hipSuccess ||
       timed(m0, "batched", st, [&] {
         return ash::launch_batched(kd, dev_items, n_ops, claim_tiles, commit_tiles, find_tiles, any_check, gs,
-                                   resident, st);
-      }) != hipSuccess)
+                                   resident, arrival_spins, st);
+      }) != hipSuccess ||
+      hipMemcpyAsync(&h, gs, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
     rc = ASH_E_DEVICE;
   m0->mem.put(dev, st);
   if (rc != ASH_OK) return rc;
+  if (h.count & ash::kArrivalFailed) {
+    // The blocks could not all run at once (other work holds CUs): the launch
+    // left before touching any map, so the same work runs op by op.
+    batched_fallbacks.fetch_add(1);
+    return batched_op_by_op(ops, n_ops, st);
+  }
+  if (h.late) return ASH_E_DEVICE;  // every map of the launch carries kStatusGridStall
   for (int32_t i = 0; i < n_ops; ++i) {
     ash_map* m = ops[i].map;
     m->live_ub = std::min(m->c, m->live_ub + ops[i].n_insert);
@@ -931,6 +974,8 @@ ash_status_t ash_batched(const ash_batch_op_t* ops, int32_t n_ops, int32_t fused
   }
   return ASH_OK;
 }
+
+int64_t ash_batched_fallbacks(void) { return batched_fallbacks.load(); }
 
 namespace {
 

@@ -35,7 +35,14 @@ constexpr uint32_t kStatusCapacity = 1u;    // not enough free buffer indices
 constexpr uint32_t kStatusTableFull = 2u;   // probe found no empty slot
 constexpr uint32_t kStatusScanStall = 4u;   // a look-back wait hit its bound
 constexpr uint32_t kStatusGridStall = 8u;   // a persistent launch's blocks did not all run at once
-constexpr uint32_t kBarrierSpinLimit = 1u << 20;  // polls of a grid barrier before a launch gives up
+// Polls of a persistent launch's arrival check before its blocks give up
+// (about 0.1 s): no table has been touched then.
+constexpr uint32_t kArrivalSpinLimit = 1u << 20;
+// Polls of its later phase barriers.  Once every block has arrived, all
+// blocks are resident and every phase ends, so these waits only end early
+// for a broken invariant; they must outlast the slowest phase of the
+// largest batch (seconds), and are bounded so a launch still always ends.
+constexpr uint32_t kPhaseSpinLimit = 1u << 30;
 constexpr uint32_t kLookbackSpinLimit = 1u << 24;
 
 template <int KD>
@@ -82,11 +89,16 @@ struct RowSet {
   uint32_t bytes[kMaxValues];
 };
 
-// Barrier words of a persistent launch (zeroed before the launch): blocks
-// that have passed a barrier so far, and the abort flag.
+// Barrier words of a persistent launch (zeroed before the launch).  count
+// holds the barrier arrivals so far in bits 0-30 and, in bit 31, the flag
+// that the arrival check failed (some block gave up before every block had
+// arrived; no block then proceeds and no table is touched).  late is set
+// when a later phase barrier hit its bound (tables may be half updated;
+// every map of the launch then carries kStatusGridStall).
+constexpr uint32_t kArrivalFailed = 0x80000000u;
 struct GridSync {
   uint32_t count;
-  uint32_t abort;
+  uint32_t late;
   uint32_t pad[14];
 };
 

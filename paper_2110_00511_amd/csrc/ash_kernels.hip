@@ -1377,19 +1377,61 @@ __device__ __forceinline__ void batched_find(const BatchItem& it, uint32_t tile,
   }
 }
 
-// Grid barrier of the persistent launch, with a bounded wait.  Every block
-// adds itself to gs->count (a release: its earlier writes become visible at
-// agent scope) and waits until all gridDim.x blocks have passed the same
-// number of barriers (then an acquire).  The first barrier is an arrival
-// check before any table is touched: if the blocks of the launch cannot all
-// be resident at once, the resident ones stop waiting after the bound, raise
-// gs->abort and mark every map, and blocks that start later see the flag and
-// leave, so the launch always ends.  Returns false when the launch aborts.
+// Grid barriers of the persistent launch.  Every block adds itself to
+// gs->count (a release: its earlier writes become visible at agent scope)
+// and waits until all gridDim.x blocks have passed the same number of
+// barriers (then an acquire).
+//
+// The first barrier is an arrival check before any table is touched, and it
+// either lets every block through or none: a block that has waited
+// arrival_spins polls gives up by setting kArrivalFailed with a
+// compare-and-swap that only succeeds while some block has not arrived, and
+// no block passes while the flag is set.  So once one block has seen every
+// arrival, no give-up can succeed, and once a give-up has succeeded, no block
+// passes (blocks that start later see the flag in the value their arrival
+// returns).  If the blocks cannot all be resident at once, the resident ones
+// give up and leave, the rest then start, see the flag and leave, and the
+// launch ends with no map changed.
+//
+// Later barriers wait on blocks that are all resident (each passed the
+// arrival check and stays until it exits), so they only end early after a
+// broken invariant: the bound then sets gs->late and marks every map.
+__device__ __forceinline__ bool arrival_check(GridSync* gs, uint32_t arrival_spins, uint32_t* s_ok) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t c = __hip_atomic_fetch_add(&gs->count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+    bool ok = false;
+    uint32_t spins = 0;
+    while (true) {
+      if (c & kArrivalFailed) break;
+      if (c >= gridDim.x) {
+        ok = true;
+        break;
+      }
+      if (spins >= arrival_spins) {
+        uint32_t expected = c;  // give up only while some block has not arrived
+        if (__hip_atomic_compare_exchange_strong(&gs->count, &expected, c | kArrivalFailed, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+          break;
+        c = expected;  // the count moved: look again
+        continue;
+      }
+      ++spins;
+      __builtin_amdgcn_s_sleep(2);
+      c = __hip_atomic_load(&gs->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    *s_ok = ok ? 1u : 0u;
+  }
+  __syncthreads();
+  return *s_ok != 0u;
+}
+
 __device__ __forceinline__ bool grid_barrier(GridSync* gs, uint32_t& passed, const BatchItem* __restrict__ items, int32_t n_items,
                              uint32_t* s_ok) {
   __syncthreads();
   if (threadIdx.x == 0) {
-    bool ok = __hip_atomic_load(&gs->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u;
+    bool ok = __hip_atomic_load(&gs->late, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u;
     passed += 1;
     if (ok) {
       __hip_atomic_fetch_add(&gs->count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -1397,7 +1439,7 @@ __device__ __forceinline__ bool grid_barrier(GridSync* gs, uint32_t& passed, con
       uint32_t spins = 0;
       while (true) {
         if (__hip_atomic_load(&gs->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
-        if (__hip_atomic_load(&gs->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u || ++spins == kBarrierSpinLimit) {
+        if (__hip_atomic_load(&gs->late, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u || ++spins == kPhaseSpinLimit) {
           ok = false;
           break;
         }
@@ -1405,7 +1447,7 @@ __device__ __forceinline__ bool grid_barrier(GridSync* gs, uint32_t& passed, con
       }
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
-    if (!ok && __hip_atomic_exchange(&gs->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+    if (!ok && __hip_atomic_exchange(&gs->late, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
       for (int32_t m = 0; m < n_items; ++m)  // the first block to give up marks every map
         __hip_atomic_fetch_or(&items[m].meta->status, kStatusGridStall, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -1418,11 +1460,11 @@ __device__ __forceinline__ bool grid_barrier(GridSync* gs, uint32_t& passed, con
 template <int KD>
 __global__ __launch_bounds__(kBlock) void k_batched(const BatchItem* __restrict__ items, int32_t n_items,
                                                     uint32_t claim_tiles, uint32_t commit_tiles, uint32_t find_tiles,
-                                                    int32_t any_check, GridSync* gs) {
+                                                    int32_t any_check, GridSync* gs, uint32_t arrival_spins) {
   __shared__ TileLds lds;
   __shared__ uint32_t s_ok;
-  uint32_t passed = 0;
-  if (!grid_barrier(gs, passed, items, n_items, &s_ok)) return;  // all blocks resident, or none works
+  if (!arrival_check(gs, arrival_spins, &s_ok)) return;  // all blocks resident, or none works
+  uint32_t passed = 1;
   int cur = 0;
   for (uint32_t t = blockIdx.x; t < claim_tiles; t += gridDim.x) {
     cur = advance_item<&BatchItem::claim0>(items, n_items, cur, t);
@@ -1935,12 +1977,13 @@ hipError_t launch_voxel_resolve(const TableRef& tb, uint32_t n, const uint32_t* 
 
 template <int KD>
 static hipError_t batched_k(const BatchItem* items, int32_t n_items, uint32_t claim_tiles, uint32_t commit_tiles,
-                            uint32_t find_tiles, int32_t any_check, GridSync* gs, uint32_t resident, hipStream_t st) {
+                            uint32_t find_tiles, int32_t any_check, GridSync* gs, uint32_t resident,
+                            uint32_t arrival_spins, hipStream_t st) {
   // n_items == 0 launches all `resident` blocks with no work: a residency probe
   const uint32_t work = std::max(std::max(claim_tiles, commit_tiles), std::max(find_tiles, (uint32_t)n_items));
   const uint32_t grid = n_items == 0 ? resident : std::max<uint32_t>(1, std::min<uint32_t>(resident, work));
   hipLaunchKernelGGL((k_batched<KD>), dim3(grid), dim3(kBlock), 0, st, items, n_items, claim_tiles, commit_tiles,
-                     find_tiles, any_check, gs);
+                     find_tiles, any_check, gs, arrival_spins);
   return hipGetLastError();
 }
 
@@ -1955,12 +1998,17 @@ hipError_t batched_occupancy(int kd, int* per_cu) {
 }
 
 hipError_t launch_batched(int kd, const BatchItem* items, int32_t n_items, uint32_t claim_tiles, uint32_t commit_tiles,
-                          uint32_t find_tiles, int32_t any_check, GridSync* gs, uint32_t resident, hipStream_t st) {
+                          uint32_t find_tiles, int32_t any_check, GridSync* gs, uint32_t resident,
+                          uint32_t arrival_spins, hipStream_t st) {
   switch (kd) {
-    case 1: return batched_k<1>(items, n_items, claim_tiles, commit_tiles, find_tiles, any_check, gs, resident, st);
-    case 2: return batched_k<2>(items, n_items, claim_tiles, commit_tiles, find_tiles, any_check, gs, resident, st);
-    case 3: return batched_k<3>(items, n_items, claim_tiles, commit_tiles, find_tiles, any_check, gs, resident, st);
-    case 4: return batched_k<4>(items, n_items, claim_tiles, commit_tiles, find_tiles, any_check, gs, resident, st);
+    case 1: return batched_k<1>(items, n_items, claim_tiles, commit_tiles, find_tiles, any_check, gs, resident,
+                                    arrival_spins, st);
+    case 2: return batched_k<2>(items, n_items, claim_tiles, commit_tiles, find_tiles, any_check, gs, resident,
+                                    arrival_spins, st);
+    case 3: return batched_k<3>(items, n_items, claim_tiles, commit_tiles, find_tiles, any_check, gs, resident,
+                                    arrival_spins, st);
+    case 4: return batched_k<4>(items, n_items, claim_tiles, commit_tiles, find_tiles, any_check, gs, resident,
+                                    arrival_spins, st);
     default: return hipErrorInvalidValue;
   }
 }

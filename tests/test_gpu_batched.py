@@ -199,3 +199,29 @@ def test_batched_full_size(ash):
         src = first[pos[hit]]  # the first occurrence's row was stored
         assert np.array_equal(bits(host(r["find_values"][0])[hit]), bits(vals[src]))
         assert m.size() == len(first) and m.device_status() == 0
+
+
+def test_batched_arrival_failure_runs_op_by_op(ash, monkeypatch):
+    """When the blocks of the persistent launch cannot all run at once, they
+    leave before touching any map and the call runs the same work op by op,
+    with the oracle's results.  The condition is forced from the host:
+    ASH_BATCHED_ARRIVAL_SPINS=0 makes the first block to arrive give up at
+    once, and every kernel still exits normally."""
+    from paper_2110_00511_amd import _lib as L
+    lib = L.load()
+    rng = np.random.default_rng(48)
+    sizes = [20000, 3000, 60000, 9000]
+    maps = [ash.HashMap(2 * u, 3, [(torch.float32, 8)], probe_group=1, bucket_width=4) for u in sizes]
+    oracles = [OracleMap(2 * u, 3, [(np.float32, 8)]) for u in sizes]
+    run_round(ash, maps, oracles, [make_case(rng, u) for u in sizes], True)  # fused, caches the grid
+    before = lib.ash_batched_fallbacks()
+    monkeypatch.setenv("ASH_BATCHED_ARRIVAL_SPINS", "0")
+    print("case: batched launch with a zero arrival bound", flush=True)
+    run_round(ash, maps, oracles, [make_case(rng, max(u // 3, 1)) for u in sizes], True)
+    assert lib.ash_batched_fallbacks() == before + 1
+    monkeypatch.delenv("ASH_BATCHED_ARRIVAL_SPINS")
+    check_maps(maps, oracles)
+    assert [m.device_status() for m in maps] == [0, 0, 0, 0]
+    run_round(ash, maps, oracles, [make_case(rng, max(u // 5, 1)) for u in sizes], True)  # fused again
+    assert lib.ash_batched_fallbacks() == before + 1
+    check_maps(maps, oracles)
