@@ -125,13 +125,18 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, copy 256 MiB once (reference kernel for byte counters)")
     ap.add_argument("--workload", default="plain",
-                    choices=["plain", "batched", "voxelize", "served", "neighbors", "values", "large"],
+                    choices=["plain", "batched", "voxelize", "served", "neighbors", "values", "large", "access",
+                             "setup1", "construct"],
                     help="plain: the headline 10M-key map; batched: 64 maps in one launch; voxelize: 5M points; "
                          "served: a Poisson request stream on a 2^25-capacity map")
     ap.add_argument("--requests", type=int, default=100_000, help="served: requests per run")
     ap.add_argument("--query-order", default="given", choices=["given", "morton"],
                     help="neighbors: query order (first appearance, or sorted by Z-order code)")
     ap.add_argument("--large-n", type=int, default=1_000_000_000, help="large: keys per insert and per find")
+    ap.add_argument("--access-table-gib", type=float, default=16.0,
+                    help="access: size of the large table (far beyond the 256 MB Infinity Cache)")
+    ap.add_argument("--access-quick", action="store_true",
+                    help="access: one launch per case (for counter runs under rocprofv3)")
     ap.add_argument("--neighbors-probe-group", type=int, default=1, help="neighbors: probe group of the map")
     ap.add_argument("--neighbors-bucket-width", type=int, default=4, help="neighbors: bucket width of the map")
     ap.add_argument("--served-max-load", type=float, default=0.5, help="served: max_load of the served map's table")
@@ -156,6 +161,12 @@ def main():
         return bench_values(args)
     if args.workload == "large":
         return bench_large(args)
+    if args.workload == "access":
+        return bench_access(args)
+    if args.workload == "setup1":
+        return bench_setup1(args)
+    if args.workload == "construct":
+        return bench_construct(args)
     if args.workload == "served":
         return bench_served(args)
 
@@ -572,6 +583,156 @@ def bench_values(args):
         "cpu_baseline": None}), flush=True)
 
 
+def _event_ms(fn, trials):
+    """Median GPU time of fn() between two events on torch's current stream
+    (the library launches on that stream), one untimed call first."""
+    import torch
+    fn()
+    ts = []
+    for _ in range(trials):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    return float(np.median(ts))
+
+
+def bench_setup1(args):
+    """Setup 1 of Sec. 5.1: int32x3 keys, f32 x 2^j values (j = 0..12),
+    capacities c = 10^3..10^6 with c input keys, distinct ratios 0.1 and
+    0.99.  Per point: insert into a cleared map, activate into a cleared
+    map (keys only: the paper reports its time flat in the value size), and
+    a 50%-hit find that gathers the hits' rows; each the median GPU time of
+    10 calls (the map is cleared before each insert or activate, outside the
+    timed call)."""
+    import torch
+
+    import paper_2110_00511_amd as ash
+    import synth
+    from paper_2110_00511_amd import _lib as L
+
+    torch.cuda.set_device(0)
+    lib = L.load()
+    sp = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    P = ctypes.c_void_p
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(10)
+    grid = {}
+    for c in (1_000, 10_000, 100_000, 1_000_000):
+        for rho in (0.1, 0.99):
+            d = synth.setup1(c, rho)
+            keys = torch.from_numpy(d["keys"]).cuda()
+            fkeys = torch.from_numpy(d["find_keys"]).cuda()
+            idx = torch.empty(c, dtype=torch.int32, device="cuda")
+            mask = torch.empty(c, dtype=torch.uint8, device="cuda")
+            fidx = torch.empty(c, dtype=torch.int32, device="cuda")
+            fmask = torch.empty(c, dtype=torch.uint8, device="cuda")
+            row = {}
+            for j in range(13):
+                ch = 1 << j
+                m = ash.HashMap(c, 3, [(torch.float32, ch)])
+                vals = torch.randn((c, ch), dtype=torch.float32, device="cuda", generator=gen)
+                outv = torch.empty((c, ch), dtype=torch.float32, device="cuda")
+                vptr = (ctypes.c_void_p * 1)(vals.data_ptr())
+                optr = (ctypes.c_void_p * 1)(outv.data_ptr())
+                times = {}
+                for op in ("insert", "activate"):
+                    def one(op=op):
+                        if op == "insert":
+                            L.check(lib.ash_insert(m._m, P(keys.data_ptr()), c, ctypes.cast(vptr, P),
+                                                   P(idx.data_ptr()), P(mask.data_ptr()), sp), "insert")
+                        else:
+                            L.check(lib.ash_activate(m._m, P(keys.data_ptr()), c, P(idx.data_ptr()),
+                                                     P(mask.data_ptr()), sp), "activate")
+                    ts = []
+                    for _ in range(11):
+                        L.check(lib.ash_clear(m._m, sp), "clear")
+                        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                        a.record()
+                        one()
+                        b.record()
+                        b.synchronize()
+                        ts.append(a.elapsed_time(b))
+                    times[op] = float(np.median(ts[1:]))
+                L.check(lib.ash_clear(m._m, sp), "clear")
+                L.check(lib.ash_insert(m._m, P(keys.data_ptr()), c, ctypes.cast(vptr, P), P(idx.data_ptr()),
+                                       P(mask.data_ptr()), sp), "insert")
+                times["find"] = _event_ms(lambda: L.check(lib.ash_find(
+                    m._m, P(fkeys.data_ptr()), c, P(fidx.data_ptr()), P(fmask.data_ptr()), ctypes.cast(optr, P),
+                    sp), "find"), 10)
+                assert m.device_status() == 0
+                row[str(4 * ch)] = {k: round(v * 1e3, 2) for k, v in times.items()}  # microseconds
+                m.close()
+                del vals, outv
+            u = int(mask.sum().item())
+            grid[f"c={c},rho={rho}"] = {"distinct": u, "us_by_row_bytes": row}
+            print(f"# setup1 c={c} rho={rho}: {row}", flush=True)
+            torch.cuda.empty_cache()
+    flat = {k: round(v["us_by_row_bytes"]["16384"]["activate"] / v["us_by_row_bytes"]["4"]["activate"], 3)
+            for k, v in grid.items()}
+    grow = {k: round(v["us_by_row_bytes"]["16384"]["insert"] / v["us_by_row_bytes"]["4"]["insert"], 3)
+            for k, v in grid.items()}
+    top = grid["c=1000000,rho=0.99"]["us_by_row_bytes"]["4"]
+    print(json.dumps({
+        "metric": "Setup 1 grid: insert / activate / find microseconds (int32x3 keys, f32 x 2^j values)",
+        "value": round(1_000_000 / top["insert"], 1), "unit": "Mops/s (insert, c = 10^6, rho 0.99, 4 B rows)",
+        "n_gpus": 1, "higher_is_better": True, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "c in {1e3, 1e4, 1e5, 1e6} keys (capacity c), rho in {0.1, 0.99}, f32 x 2^j "
+                               "values j = 0..12; median GPU time of 10 calls per point"},
+        "activate_16KB_over_4B": flat, "insert_16KB_over_4B": grow, "grid": grid, "cpu_baseline": None}),
+        flush=True)
+
+
+def bench_construct(args):
+    """Construction time (Sec. 5.2 reports under 1 ms for c = 10^3..10^6):
+    ash_create of an int32x3 -> f32 map of capacity c, which allocates the
+    table, key, value, heap and owner buffers, fills the table, writes the
+    heap 0..c-1 and synchronizes; then ash_destroy.  Host clock around each
+    call, median of 10 after one warm-up, with torch's caching allocator
+    (blocks reused after the first create) and with plain hipMalloc."""
+    import torch
+
+    from paper_2110_00511_amd import _lib as L
+
+    torch.cuda.set_device(0)
+    lib = L.load()
+    sp = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    alloc = L.TorchAllocator("cuda")
+    dts = (ctypes.c_int * 1)(L.ASH_F32)
+    els = (ctypes.c_int64 * 1)(1)
+    res = {}
+    for c in (1_000, 10_000, 100_000, 1_000_000, 10_000_000):
+        row = {}
+        for name, a in (("torch_allocator", ctypes.byref(alloc.struct)), ("hipMalloc", None)):
+            tc, td = [], []
+            for rep in range(11):
+                out = ctypes.c_void_p()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                L.check(lib.ash_create(c, 3, 1, ctypes.cast(dts, ctypes.c_void_p), ctypes.cast(els, ctypes.c_void_p),
+                                       a, None, sp, ctypes.byref(out)), "create")
+                t1 = time.perf_counter()
+                L.check(lib.ash_destroy(out), "destroy")
+                torch.cuda.synchronize()
+                t2 = time.perf_counter()
+                if rep:
+                    tc.append(t1 - t0)
+                    td.append(t2 - t1)
+            row[name] = {"create_ms": round(float(np.median(tc)) * 1e3, 3),
+                         "destroy_ms": round(float(np.median(td)) * 1e3, 3)}
+        res[str(c)] = row
+        print(f"# construct c={c}: {row}", flush=True)
+    top = res["1000000"]["torch_allocator"]["create_ms"]
+    print(json.dumps({
+        "metric": "map construction time (ash_create, synchronized)", "value": top,
+        "unit": "ms at c = 10^6 (torch caching allocator)", "n_gpus": 1, "higher_is_better": False,
+        "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "int32x3 -> f32 map, capacity 10^3..10^7, default tuning; median of 10"},
+        "results": res, "cpu_baseline": None}), flush=True)
+
+
 def bench_large(args):
     """A hash set far beyond the caches: n int32x3 keys (default 1e9, distinct
     ratio ~0.5, drawn on the device from a seeded generator) inserted into a
@@ -626,6 +787,73 @@ def bench_large(args):
                    "find_ms": round(tf * 1e3, 2), "find_Mops": round(n / tf / 1e6, 1),
                    "hit_rate": round(float(fm.float().mean().item()), 4)},
         "cpu_baseline": None}), flush=True)
+
+
+def bench_access(args):
+    """Cost of one random access to a table far beyond every cache (16 GiB by
+    default) and to a table of the 10M-key map's size (320 MiB, a little
+    beyond the 256 MB Infinity Cache): random reads of 4..256 B, random
+    stores, device-scope CAS and atomic min, and streaming read and copy of
+    the table for reference.  Reads of A >= 16 B are made by A / 16 adjacent
+    lanes (a probe group reading a window).
+
+    The DRAM granule g of a small random read follows from timing alone:
+    random reads of 256 B move whole lines and no byte they do not need, so
+    their byte rate B256 is the rate at which the memory system serves random
+    lines; a 16 B read that costs g bytes then runs at B256 / g reads/s, and
+    g16 = B256 / R16.  rocprofv3 FETCH_SIZE / WRITE_SIZE of the same kernels
+    (see the access profile summary) give the bytes directly."""
+    import torch
+
+    from paper_2110_00511_amd import _lib as L
+
+    torch.cuda.set_device(0)
+    lib = L.load()
+    sp = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    reps = 1 if args.access_quick else 3
+    tables = [("large", int(args.access_table_gib * (1 << 30)) // 256 * 256), ("map10M", 320 << 20)]
+    n_read = 1 << 27
+    n_store = 1 << 26
+    n_atomic = 1 << 26
+    cases = [("read", L.ASH_ACC_READ, a, n_read) for a in (4, 16, 32, 64, 128, 256)]
+    cases += [("store", L.ASH_ACC_STORE, a, n_store) for a in (8, 16, 64, 128)]
+    cases += [("cas64", L.ASH_ACC_CAS64, 8, n_atomic), ("min32", L.ASH_ACC_MIN32, 4, n_atomic),
+              ("stream_read", L.ASH_ACC_STREAM_READ, 16, 0), ("stream_copy", L.ASH_ACC_STREAM_COPY, 16, 0)]
+    results = {}
+    for tname, tbytes in tables:
+        buf = torch.zeros(tbytes, dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        res = {}
+        for kname, kind, abytes, n in cases:
+            ms_all = []
+            for r in range(reps + (0 if args.access_quick else 1)):
+                ms = ctypes.c_double()
+                L.check(lib.ash_access_bench(kind, ctypes.c_void_p(buf.data_ptr()), tbytes, abytes, n, 1234 + r,
+                                             ctypes.byref(ms), sp), f"access {kname} {abytes}")
+                ms_all.append(ms.value)
+            ms = min(ms_all[-reps:])
+            key = f"{kname}_{abytes}" if kname in ("read", "store") else kname
+            if kname == "stream_read":
+                res[key] = {"ms": round(ms, 4), "GBps": round(tbytes / (ms * 1e-3) / 1e9, 1)}
+            elif kname == "stream_copy":
+                res[key] = {"ms": round(ms, 4), "GBps_read_plus_write": round(tbytes / (ms * 1e-3) / 1e9, 1)}
+            else:
+                rate = n / (ms * 1e-3)
+                res[key] = {"ms": round(ms, 4), "n": n, "G_per_s": round(rate / 1e9, 2),
+                            "GBps_at_access_size": round(rate * abytes / 1e9, 1)}
+            print(f"# access {tname} {key}: {res[key]}", flush=True)
+        b256 = res["read_256"]["G_per_s"] * 256
+        res["granule_from_timing_B"] = {f"read_{a}": round(b256 / res[f"read_{a}"]["G_per_s"], 1)
+                                        for a in (4, 16, 32, 64, 128)}
+        results[tname] = {"table_bytes": tbytes, **res}
+        del buf
+        torch.cuda.empty_cache()
+    g16 = results["large"]["granule_from_timing_B"]["read_16"]
+    print(json.dumps({
+        "metric": "random access cost on MI355X (instrumentation)", "value": g16, "unit": "B per random 16 B read",
+        "n_gpus": 1, "higher_is_better": False, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": "random reads/stores/atomics at hashed addresses; streaming read and copy"},
+        "results": results}), flush=True)
 
 
 def morton3(keys):

@@ -302,13 +302,20 @@ ash_status_t ash_batched_grid(int32_t key_dim, int64_t* out_blocks, int64_t* out
  * one map's work: an insert batch, then a find batch, with the meaning of
  * ash_insert followed by ash_find on that map (insert_values / find_values
  * are host arrays of n_values device pointers; outputs may be NULL).  With
- * fused = 1 all ops run in one persistent cooperative launch whose phases
+ * fused = 1 all ops run in one persistent launch whose phases
  * (claims, commits, heap tops, finds) are separated by grid barriers and
  * whose tiles are spread over every resident block, each map keeping its own
  * probe shape; fused = 0 runs the same work op by op through the single-map
  * path.  Maps must be distinct, share key_dim and not use ASH_F_AUTOGROW
  * (ASH_E_UNSUPPORTED otherwise).  Capacity overflow of one map rolls back
- * that map's batch only, as in ash_insert. */
+ * that map's batch only, as in ash_insert.
+ * The fused launch needs all its blocks resident at once.  Its blocks first
+ * check in, and if they cannot all run together (other work holds compute
+ * units) they leave before touching any map and the call runs the same work
+ * op by op, with the same results.  A later phase barrier that gives up
+ * (a broken invariant, not expected) returns ASH_E_DEVICE and leaves
+ * every map of the call with a sticky device error.  With fused = 1 the
+ * call synchronizes `stream` to read the launch's outcome. */
 typedef struct {
   ash_map_t map;
   const int32_t* insert_keys;
@@ -324,6 +331,9 @@ typedef struct {
 } ash_batch_op_t;
 
 ash_status_t ash_batched(const ash_batch_op_t* ops, int32_t n_ops, int32_t fused, void* stream);
+/* Fused ash_batched calls of this process that failed the arrival check and
+ * ran op by op instead (instrumentation). */
+int64_t ash_batched_fallbacks(void);
 
 /* Autotuner for the table shape.  Times insert + find of a synthetic batch on
  * this device -- n_insert keys uniform in a cube sized for the expected ratio
@@ -400,8 +410,10 @@ ash_status_t ash_server_wait(ash_server_t server, int64_t ticket, double* out_la
 ash_status_t ash_server_replay(ash_server_t server, const ash_request_t* reqs, int64_t n,
                                const double* arrival_s, double* out_latency_s, int32_t* out_status,
                                double* out_span_s);
-/* Device batches launched and requests they carried so far. */
-ash_status_t ash_server_stats(ash_server_t server, int64_t* out_batches, int64_t* out_requests);
+/* Device batches launched, requests they carried and the most requests one
+ * batch carried, so far (each output nullable). */
+ash_status_t ash_server_stats(ash_server_t server, int64_t* out_batches, int64_t* out_requests,
+                              int64_t* out_largest);
 /* Runs the remaining requests, then stops the threads and frees the server
  * (not the map). */
 ash_status_t ash_server_destroy(ash_server_t server);
@@ -420,6 +432,35 @@ typedef struct {
 ash_status_t ash_profile_enable(ash_map_t map, int32_t enable);
 ash_status_t ash_profile_collect(ash_map_t map, ash_kernel_time_t* out, int32_t max_entries,
                                  int32_t* n_entries, void* stream);
+
+/* Access-cost microbenchmark (instrumentation; no map is involved).  The
+ * map's kernels are bound by random accesses to a large table, so the DRAM
+ * cost of one such access is measured on its own: n_access accesses at
+ * addresses drawn from a counter-based hash of (seed, access number),
+ * uniformly over the table and aligned to the access size.
+ *   ASH_ACC_READ / ASH_ACC_STORE: reads / stores of access_bytes in {4, 8,
+ *     16, 32, 64, 128, 256}; from 16 bytes on, access_bytes / 16 adjacent
+ *     lanes each move one 16-byte unit (a probe group reading a window);
+ *   ASH_ACC_CAS64: device-scope 64-bit compare-and-swap, returning
+ *     (access_bytes 8);
+ *   ASH_ACC_MIN32: device-scope 32-bit atomic minimum, no return
+ *     (access_bytes 4);
+ *   ASH_ACC_STREAM_READ: one coalesced read of the whole table
+ *     (n_access and access_bytes ignored);
+ *   ASH_ACC_STREAM_COPY: a coalesced copy of the table's first half onto
+ *     its second half (the same).
+ * table: device scratch of table_bytes (a multiple of 256, 256-byte
+ * aligned); stores, atomics and the copy overwrite it.  *out_ms (nullable)
+ * receives the kernel's duration from HIP events on `stream`.  Synchronizes.
+ * ASH_E_INVALID for other kinds, sizes or alignments. */
+#define ASH_ACC_READ 0
+#define ASH_ACC_STORE 1
+#define ASH_ACC_CAS64 2
+#define ASH_ACC_MIN32 3
+#define ASH_ACC_STREAM_READ 4
+#define ASH_ACC_STREAM_COPY 5
+ash_status_t ash_access_bench(int32_t kind, void* table, int64_t table_bytes, int32_t access_bytes,
+                              int64_t n_access, uint64_t seed, double* out_ms, void* stream);
 
 const char* ash_status_string(ash_status_t status);
 

@@ -7,6 +7,7 @@ libash.so has not been built; there is no fallback path.
 """
 import ctypes
 import os
+import sys
 
 import torch  # noqa: F401  (loads the HIP runtime the library binds to)
 
@@ -22,6 +23,7 @@ ASH_E_UNSUPPORTED = 5
 ASH_F_AUTOGROW = 1
 ASH_F_LDS_DEDUP = 2
 ASH_NB_RADIUS, ASH_NB_CUBE, ASH_NB_RING = 0, 1, 2
+ASH_ACC_READ, ASH_ACC_STORE, ASH_ACC_CAS64, ASH_ACC_MIN32, ASH_ACC_STREAM_READ, ASH_ACC_STREAM_COPY = range(6)
 
 ASH_U8, ASH_I32, ASH_F32, ASH_I64, ASH_F64, ASH_F16, ASH_BF16 = range(7)
 
@@ -96,14 +98,16 @@ SIGNATURES = {
     "ash_autotune_batched": (ST, [I64, I32, I32, P, P, I64, ctypes.c_double, P, P, ctypes.POINTER(AshTuning),
                                   ctypes.POINTER(ctypes.c_double)]),
     "ash_server_create": (ST, [P, P, ctypes.POINTER(P)]),
+    "ash_batched_fallbacks": (I64, []),
     "ash_batched_grid": (ST, [I32, ctypes.POINTER(I64), ctypes.POINTER(I64), P]),
     "ash_server_submit": (ST, [P, ctypes.POINTER(AshRequest), ctypes.POINTER(I64)]),
     "ash_server_wait": (ST, [P, I64, ctypes.POINTER(ctypes.c_double)]),
     "ash_server_replay": (ST, [P, ctypes.POINTER(AshRequest), I64, P, P, P, ctypes.POINTER(ctypes.c_double)]),
-    "ash_server_stats": (ST, [P, ctypes.POINTER(I64), ctypes.POINTER(I64)]),
+    "ash_server_stats": (ST, [P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(I64)]),
     "ash_server_destroy": (ST, [P]),
     "ash_profile_enable": (ST, [P, I32]),
     "ash_profile_collect": (ST, [P, ctypes.POINTER(AshKernelTime), I32, ctypes.POINTER(I32), P]),
+    "ash_access_bench": (ST, [I32, P, I64, I32, I64, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double), P]),
     "ash_status_string": (ctypes.c_char_p, [ST]),
 }
 
@@ -167,7 +171,7 @@ class TorchAllocator:
 
     def _do_free(self, ctx, ptr, stream):
         t = self.blocks.pop(ptr, None)
-        if t is not None and stream:
+        if t is not None and stream and not sys.is_finalizing():
             t.record_stream(self._stream(stream))
 
     def tensor(self, ptr):

@@ -14,7 +14,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libash.so")
-SOURCES = [os.path.join(HERE, "csrc", name) for name in ("ash_kernels.hip", "ash_api.hip", "ash_serve.hip", "ash_io.hip")]
+SOURCES = [os.path.join(HERE, "csrc", name) for name in ("ash_kernels.hip", "ash_api.hip", "ash_serve.hip", "ash_io.hip", "ash_membench.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -32,21 +32,41 @@ FLAGS = [
 ]
 
 
-def build(verbose=False):
-    """Compile every source into libash.so (always recompiles)."""
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-I" + os.path.join(ROOT, "include"), "-I" + os.path.join(HERE, "csrc"),
-           "-o", tmp, *SOURCES]
-    if verbose:
-        print(" ".join(cmd), flush=True)
+def _run(cmd):
     r = subprocess.run(cmd, capture_output=True, text=True)
     # hipcc's host pass does not know the packed-fp32 feature; that warning is harmless.
     noise = "'-packed-fp32-ops' is not a recognized feature"
     err = "\n".join(line for line in r.stderr.splitlines() if noise not in line)
-    if r.returncode != 0:
-        raise RuntimeError(f"hipcc failed ({r.returncode}):\n{err}")
-    if verbose and err.strip():
-        print(err, file=sys.stderr)
+    return r.returncode, err
+
+
+def build(verbose=False):
+    """Compile every source into libash.so (always recompiles; one hipcc per
+    source, in parallel, then one link)."""
+    from concurrent.futures import ThreadPoolExecutor
+    obj_dir = os.path.join(ROOT, "_build")
+    os.makedirs(obj_dir, exist_ok=True)
+    inc = ["-I" + os.path.join(ROOT, "include"), "-I" + os.path.join(HERE, "csrc")]
+    compile_flags = [f for f in FLAGS if f != "-shared"]
+    jobs = []
+    for src in SOURCES:
+        obj = os.path.join(obj_dir, os.path.basename(src) + ".o")
+        jobs.append((src, obj, [HIPCC, *compile_flags, *inc, "-c", "-o", obj, src]))
+    workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(workers) as ex:
+        outs = list(ex.map(lambda j: (j, _run(j[2])), jobs))
+    for (src, _, cmd), (rc, err) in outs:
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        if rc != 0:
+            raise RuntimeError(f"hipcc failed on {os.path.basename(src)} ({rc}):\n{err}")
+        if verbose and err.strip():
+            print(err, file=sys.stderr)
+    tmp = LIB + ".tmp"
+    link = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", tmp, *[j[1] for j in jobs]]
+    rc, err = _run(link)
+    if rc != 0:
+        raise RuntimeError(f"link failed ({rc}):\n{err}")
     os.replace(tmp, LIB)
     return LIB
 

@@ -91,7 +91,7 @@ struct ash_server {
   bool stop = false;
   bool worker_done = false;
   int device = 0;
-  int64_t batches = 0, fused_requests = 0;
+  int64_t batches = 0, fused_requests = 0, largest = 0;
   std::thread worker, completer;
 };
 
@@ -299,6 +299,7 @@ void worker_loop(ash_server* s) {
       s->flight.push_back(b);
       s->batches += 1;
       s->fused_requests += (int64_t)run.size();
+      s->largest = std::max<int64_t>(s->largest, (int64_t)run.size());
     }
     s->cv_flight.notify_one();
   }
@@ -465,11 +466,12 @@ ash_status_t ash_server_replay(ash_server_t s, const ash_request_t* reqs, int64_
   return ASH_OK;
 }
 
-ash_status_t ash_server_stats(ash_server_t s, int64_t* out_batches, int64_t* out_requests) {
+ash_status_t ash_server_stats(ash_server_t s, int64_t* out_batches, int64_t* out_requests, int64_t* out_largest) {
   if (!s) return ASH_E_INVALID;
   std::lock_guard<std::mutex> lk(s->mu);
   if (out_batches) *out_batches = s->batches;
   if (out_requests) *out_requests = s->fused_requests;
+  if (out_largest) *out_largest = s->largest;
   return ASH_OK;
 }
 

@@ -5,11 +5,33 @@ indices and masks; keys and values are read and modified in place through
 the key / value buffers (advanced indexing with the returned indices).
 Inputs and outputs are torch tensors on the GPU; all work runs in libash.so.
 """
+import atexit
 import ctypes
+import weakref
 
 import torch
 
 from . import _lib as L
+
+# Maps and servers still alive when the interpreter exits are released by an
+# exit hook, while torch and the HIP runtime are still whole (servers first:
+# they own a map's stream).  Their __del__ is then a no-op.
+_LIVE_SERVERS = weakref.WeakSet()
+_LIVE_MAPS = weakref.WeakSet()
+
+
+@atexit.register
+def _release_all():
+    for s in list(_LIVE_SERVERS):
+        try:
+            s.close()
+        except Exception:
+            pass
+    for m in list(_LIVE_MAPS):
+        try:
+            m.close()
+        except Exception:
+            pass
 
 _DTYPES = {
     torch.uint8: L.ASH_U8, torch.int32: L.ASH_I32, torch.float32: L.ASH_F32, torch.int64: L.ASH_I64,
@@ -59,6 +81,7 @@ class HashMap:
             L.check(self._lib.ash_create(int(capacity), self.key_dim, n, ctypes.cast(dts, ctypes.c_void_p),
                                          ctypes.cast(els, ctypes.c_void_p), ctypes.byref(self._alloc.struct),
                                          ctypes.byref(tun), _stream(), ctypes.byref(self._m)), "ash_create")
+        _LIVE_MAPS.add(self)
 
     def save(self, path):
         """Writes the map's state (capacity, heap, live indices, keys, value
@@ -81,6 +104,7 @@ class HashMap:
         with torch.cuda.device(self.device):
             L.check(self._lib.ash_load(str(path).encode(), ctypes.byref(self._alloc.struct), ctypes.byref(tun),
                                        _stream(), ctypes.byref(self._m)), "ash_load")
+        _LIVE_MAPS.add(self)
         kd, nv = ctypes.c_int32(), ctypes.c_int32()
         L.check(self._lib.ash_describe(self._m, ctypes.byref(kd), ctypes.byref(nv), None, None), "ash_describe")
         dts = (ctypes.c_int * max(nv.value, 1))()
@@ -92,11 +116,15 @@ class HashMap:
         self.value_specs = [(codes[dts[j]], int(els[j])) for j in range(nv.value)]
         return self
 
-    def __del__(self):
+    def close(self):
+        """Destroys the map now (its buffers return to torch's allocator)."""
         m = getattr(self, "_m", None)
         if m is not None and m.value:
-            self._lib.ash_destroy(m)
             self._m = None
+            self._lib.ash_destroy(m)
+
+    def __del__(self):
+        self.close()
 
     # -- operations ---------------------------------------------------------
     def insert(self, keys, values=()):
@@ -376,6 +404,7 @@ class Server:
         L.check(self._lib.ash_server_create(hashmap._m, ctypes.byref(cfg), ctypes.byref(self._s)),
                 "ash_server_create")
         self._keep = {}
+        _LIVE_SERVERS.add(self)
 
     def request(self, kind, keys, values=(), out_idx=None, out_mask=None, out_values=None):
         """Builds an ash_request_t over device tensors (kept alive by the caller)."""
@@ -424,14 +453,16 @@ class Server:
         return lat, sts, span.value
 
     def stats(self):
-        b, r = ctypes.c_int64(), ctypes.c_int64()
-        L.check(self._lib.ash_server_stats(self._s, ctypes.byref(b), ctypes.byref(r)), "ash_server_stats")
-        return dict(batches=b.value, requests=r.value)
+        b, r, g = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        L.check(self._lib.ash_server_stats(self._s, ctypes.byref(b), ctypes.byref(r), ctypes.byref(g)),
+                "ash_server_stats")
+        return dict(batches=b.value, requests=r.value, largest=g.value)
 
     def close(self):
-        if self._s is not None and self._s.value:
-            L.check(self._lib.ash_server_destroy(self._s), "ash_server_destroy")
+        s = getattr(self, "_s", None)
+        if s is not None and s.value:
             self._s = None
+            L.check(self._lib.ash_server_destroy(s), "ash_server_destroy")
 
     def __del__(self):
         try:

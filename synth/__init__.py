@@ -18,6 +18,8 @@ model, extended to 10M keys):
                 neighbor search (Listing 3 of Sec. 6.2.4)
   value_sweep   1M int32x3 keys (distinct ratio ~0.99) and a 50%-hit find
                 batch for value rows of 2^j floats (Setup 1's sweep)
+  setup1        n int32x3 keys at distinct ratio rho and a 50%-hit find
+                batch (Setup 1's capacities 10^3..10^6, rho in {0.1, 0.99})
   batched       64 maps with log-uniform distinct counts in [1e3, 1e6]
   served        request stream over a 318^3 key universe
 """
@@ -126,6 +128,34 @@ def value_sweep(n=1_000_000, side=368, seed=8):
     absent = rng.integers(side, 2 * side, size=(n - half, 3), dtype=np.int32)
     find_keys = np.concatenate([present, absent])[rng.permutation(n)]
     return dict(keys=keys, find_keys=np.ascontiguousarray(find_keys))
+
+
+def cube_for_ratio(n, rho, dims=3):
+    """Side L of a cube whose n uniform draws hold about rho * n distinct
+    cells: L^d (1 - exp(-n / L^d)) = rho n, solved for x = n / L^d by
+    bisection (input generation only)."""
+    lo, hi = 1e-9, 1e3
+    for _ in range(200):
+        x = 0.5 * (lo + hi)
+        if (1.0 - math.exp(-x)) / x > rho:
+            lo = x
+        else:
+            hi = x
+    return max(2, int(round((n / (0.5 * (lo + hi))) ** (1.0 / dims))))
+
+
+def setup1(n, rho, seed=10):
+    """Setup 1 of Sec. 5.1 at one (c, rho): n int32x3 keys uniform in a cube
+    sized for distinct ratio rho (the capacity is n), and n finds, half drawn
+    from the inserted keys and half from the cube shifted by its side."""
+    rng = np.random.default_rng([seed, n, int(round(rho * 100))])
+    side = cube_for_ratio(n, rho)
+    keys = rng.integers(0, side, size=(n, 3), dtype=np.int32)
+    half = n // 2
+    present = keys[rng.integers(0, n, size=half)]
+    absent = rng.integers(side, 2 * side, size=(n - half, 3), dtype=np.int32)
+    find_keys = np.concatenate([present, absent])[rng.permutation(n)]
+    return dict(keys=keys, find_keys=np.ascontiguousarray(find_keys), side=side)
 
 
 def batched(n_maps=64, channels=8, lo=1e3, hi=1e6, seed=6):

@@ -80,7 +80,7 @@ def test_server_and_batched_reject_bad_arguments_on_the_host(lib):
     req = _lib.AshRequest(0, None, 0, None, None, None, None)
     assert L.ash_server_submit(None, ctypes.byref(req), ctypes.byref(t)) == _lib.ASH_E_INVALID
     assert L.ash_server_wait(None, 0, None) == _lib.ASH_E_INVALID
-    assert L.ash_server_stats(None, None, None) == _lib.ASH_E_INVALID
+    assert L.ash_server_stats(None, None, None, None) == _lib.ASH_E_INVALID
     assert L.ash_server_destroy(None) == _lib.ASH_E_INVALID
     assert L.ash_server_replay(None, None, 0, None, None, None, None) == _lib.ASH_E_INVALID
 

@@ -363,15 +363,49 @@ def _pack(keys):
     return (k[:, 0] << 42) | (k[:, 1] << 21) | k[:, 2]
 
 
-@pytest.mark.parametrize("rho,channels", [(0.1, 1), (0.5, 8), (0.99, 32)])
+_CLOSED_FORMS = {}
+
+
+def _closed_forms(rho):
+    """numpy closed forms of the 10M-key workload at distinct ratio rho on a
+    fresh map (indices are ranks of first occurrences; erase winners are
+    the first occurrences in the erase batch, which push their indices in
+    batch order)."""
+    if rho not in _CLOSED_FORMS:
+        d = synth.plain_large(rho=rho, channels=1)
+        keys, fk, ek = d["keys"], d["find_keys"], d["erase_keys"]
+        pk = _pack(keys)
+        uniq, first = np.unique(pk, return_index=True)
+        rank_sorted = np.empty(len(uniq), np.int64)  # rank (insert order) of sorted distinct key j
+        rank_sorted[np.argsort(first)] = np.arange(len(first))
+        first = np.sort(first)
+        pf = _pack(fk)
+        pos = np.searchsorted(uniq, pf)
+        hit = (pos < len(uniq)) & (uniq[np.minimum(pos, len(uniq) - 1)] == pf)
+        pe = _pack(ek)
+        efirst = np.sort(np.unique(pe, return_index=True)[1])
+        erank = rank_sorted[np.searchsorted(uniq, pe[efirst])]  # every erase key was inserted
+        _CLOSED_FORMS[rho] = dict(first=first, uniq=uniq, rank_sorted=rank_sorted, pos=pos, hit=hit,
+                                  efirst=efirst, erank=erank, erased=np.isin(pf, pe))
+    return _CLOSED_FORMS[rho]
+
+
+@pytest.mark.parametrize("rho", [0.1, 0.5, 0.99])
+@pytest.mark.parametrize("channels", [1, 8, 32])
 def test_plain_large_properties(ash, rho, channels):
+    """The 10M-key workload at every (distinct ratio, channels) pair, in the
+    benchmark's launch configuration, checked for every position against
+    closed forms: insert masks and indices, k^B and v^B, find masks, indices
+    and gathered rows, erase masks, and after the 5M erase the whole heap,
+    t, the active indices and re-find masks."""
+    print(f"case: plain 10M rho={rho} C={channels}", flush=True)
     d = synth.plain_large(rho=rho, channels=channels)
     keys, vals = d["keys"], d["values"]
+    cf = _closed_forms(rho)
+    first = cf["first"]
     m = ash.HashMap(d["capacity"], 3, [(torch.float32, channels)])
     gi, gm = m.insert(dev(keys), [dev(vals)])
     gi, gm = host(gi), host(gm)
-    uniq, first = np.unique(_pack(keys), return_index=True)
-    first = np.sort(first)
     want_mask = np.zeros(len(keys), bool)
     want_mask[first] = True
     assert np.array_equal(gm, want_mask)
@@ -385,25 +419,29 @@ def test_plain_large_properties(ash, rho, channels):
     fk = d["find_keys"]
     fi, fm, (fv,) = m.find(dev(fk), gather=True)
     fi, fm, fv = host(fi), host(fm), host(fv)
-    pos = np.searchsorted(uniq, _pack(fk))
-    hit = (pos < len(uniq)) & (uniq[np.minimum(pos, len(uniq) - 1)] == _pack(fk))
+    hit, pos = cf["hit"], cf["pos"]
     assert np.array_equal(fm, hit)
-    rank_of_sorted = np.empty(len(uniq), np.int64)
-    order = np.argsort(_pack(keys[first]))
-    rank_of_sorted[:] = order  # sorted distinct key j has rank order[j]
-    assert np.array_equal(fi[hit], rank_of_sorted[pos[hit]].astype(np.int32))
+    assert np.array_equal(fi[hit], cf["rank_sorted"][pos[hit]].astype(np.int32))
     assert np.all(fi[~hit] == -1)
     assert np.array_equal(bits(fv[hit]), bits(vb[fi[hit]]))
+    assert np.all(bits(fv[~hit]) == 0)  # rows of misses untouched (zero-filled)
     ek = d["erase_keys"]
     em = host(m.erase(dev(ek)))
-    efirst = np.unique(_pack(ek), return_index=True)[1]
+    efirst, erank = cf["efirst"], cf["erank"]
     want = np.zeros(len(ek), bool)
     want[efirst] = True  # every erase key was inserted; its first occurrence wins
     assert np.array_equal(em, want)
-    assert m.size() == len(first) - len(efirst)
+    t0 = len(first)
+    t1 = t0 - len(efirst)
+    assert m.size() == t1
+    heap = np.arange(d["capacity"], dtype=np.int32)
+    heap[t0 - 1 - np.arange(len(efirst))] = erank  # the r-th winner pushes h[t0 - 1 - r]
+    assert np.array_equal(host(m.heap_buffer()), heap)
+    live = np.ones(t0, bool)
+    live[erank] = False
+    assert np.array_equal(host(m.active_indices()), np.flatnonzero(live).astype(np.int32))
     fi2, fm2 = m.find(dev(fk))
-    erased = np.isin(_pack(fk), _pack(ek))
-    assert np.array_equal(host(fm2), hit & ~erased)
+    assert np.array_equal(host(fm2), hit & ~cf["erased"])
     assert m.device_status() == 0
 
 

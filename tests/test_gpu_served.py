@@ -35,8 +35,8 @@ def make_stream(rng, n_req, side, lo=16, hi=4096, channels=4):
     return reqs
 
 
-def run_served(ash, capacity, preload, reqs, arrivals, channels=4, **cfg):
-    m = ash.HashMap(capacity, 3, [(torch.float32, channels)])
+def run_served(ash, capacity, preload, reqs, arrivals, channels=4, tuning=None, **cfg):
+    m = ash.HashMap(capacity, 3, [(torch.float32, channels)], **(tuning or {}))
     pk, pv = preload
     m.insert(dev(pk), [dev(pv)])
     torch.cuda.synchronize()
@@ -61,7 +61,7 @@ def run_served(ash, capacity, preload, reqs, arrivals, channels=4, **cfg):
     return m, outs, lat, sts, stats
 
 
-def check_against_oracle(capacity, preload, reqs, m, outs, channels=4):
+def check_against_oracle(capacity, preload, reqs, m, outs, channels=4, values=False):
     o = OracleMap(capacity, 3, [(np.float32, channels)])
     pk, pv = preload
     o.insert(pk, [pv])
@@ -85,6 +85,8 @@ def check_against_oracle(capacity, preload, reqs, m, outs, channels=4):
     act = host(m.active_indices())
     assert np.array_equal(act, o.active_indices())
     assert np.array_equal(host(m.key_buffer())[act], o.key_buffer()[act])
+    if values:  # every entry was inserted with its row
+        assert np.array_equal(bits(host(m.value_buffer(0))[act]), bits(o.value_buffer(0)[act]))
 
 
 @pytest.mark.parametrize("mode", ["burst", "spread", "unfused"])
@@ -169,3 +171,46 @@ def test_fused_finds_mixed_outputs(ash):
             assert np.array_equal(bits(got), bits(ov))
         else:
             assert np.all(got == 7.0)
+
+
+@pytest.mark.timeout(900)
+def test_served_benchmark_shape(ash):
+    """The served benchmark's own configuration: capacity 2^25, 20M keys
+    preloaded with f32x8 rows, one lane per key (g = 1, W = 4, max load
+    0.5), and the server settings it times (at most 256 requests and 2^22
+    positions per fused batch, 4 batches in flight).  The stream, all
+    arriving at once: 200 requests from the benchmark's distribution (60%
+    find / 30% insert / 10% erase, sizes log-uniform in [256, 2^20], keys
+    uniform over the 318^3 universe), then 300 consecutive small finds, 300
+    consecutive small inserts and 40 erases (so fused batches carry 256
+    requests), then 100 more benchmark requests.  Every request's indices,
+    masks and gathered rows must equal the oracle replaying the stream one
+    request after another, and afterwards the heap, t, the active indices,
+    k^B and v^B."""
+    import synth
+    w = synth.served(n_requests=300)
+    rng = np.random.default_rng(73)
+    side, ch = w["side"], w["channels"]
+    reqs = []
+    for i in range(300):
+        if i == 200:  # runs of one kind long enough to fill fused batches
+            for kind, count, hi in ((FIND, 300, 4096), (INSERT, 300, 8192), (ERASE, 40, 4096)):
+                for _ in range(count):
+                    n = int(np.exp(rng.uniform(np.log(256), np.log(hi))))
+                    keys = rng.integers(0, side, size=(n, 3), dtype=np.int32)
+                    vals = rng.standard_normal((n, ch), dtype=np.float32) if kind == INSERT else None
+                    reqs.append((kind, keys, vals))
+        keys, vals = synth.request_keys(w, i)
+        reqs.append((int(w["kinds"][i]), keys, vals))
+    total = sum(len(k) for _, k, _ in reqs)
+    print(f"case: served benchmark shape, {len(reqs)} requests, {total} positions, "
+          f"preload {len(w['preload_keys'])}", flush=True)
+    cfg = dict(fuse=True, max_fused=256, max_batch=1 << 22, in_flight=4)
+    tuning = dict(probe_group=1, bucket_width=4, max_load=0.5)
+    m, outs, lat, sts, stats = run_served(ash, w["capacity"], (w["preload_keys"], w["preload_values"]), reqs,
+                                          np.zeros(len(reqs)), channels=ch, tuning=tuning, **cfg)
+    print(f"served: {stats}", flush=True)
+    assert np.all(sts == 0) and np.all(lat >= 0)
+    assert stats["largest"] == 256  # the long runs filled fused batches
+    check_against_oracle(w["capacity"], (w["preload_keys"], w["preload_values"]), reqs, m, outs, channels=ch,
+                         values=True)
