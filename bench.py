@@ -8,12 +8,16 @@ with every input already resident in HBM.  `value` is key operations per
 second over the whole step (insert + find + erase positions / step time).
 
 Per-kernel durations come from HIP events the library records around each
-launch on the launch stream (ash_profile_enable) during the timed steps; the
-dominant kernel's roofline counts algorithmic DRAM bytes with the per-access
-costs measured on MI355X (a random read moves a 128-byte line, a 64-bit CAS
-64 bytes, a small store 32 bytes).  `traffic` is the HBM bytes per launch of
-that kernel measured with rocprofv3 counters on the same sources and workload
-(null otherwise).
+launch on the launch stream (ash_profile_enable) during the timed steps.  The
+roofline covers the dominant operation, insert (claim + commit): bytes per
+position under the granule accounting (every unavoidable random access one
+DRAM granule, g = 128 B measured on MI355X by `--workload access`) times the
+positions of one call, over the summed average durations of its kernels.
+`accounting` gives insert, find and erase under the payload and granule
+accountings (g = 128 and g = 64).  `traffic` is the L2-to-fabric bytes per
+insert measured with rocprofv3 counters on the same sources and workload
+(null otherwise).  `served` runs the served map beside the plain path:
+offered loads are 0.5x and 0.9x of the plain path's measured throughput.
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 3] [--rho 0.5] [--channels 8]
 """
@@ -31,12 +35,62 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
-# DRAM cost of one access of each kind on MI355X, measured with rocprofv3 on a
-# random-access microbenchmark (FETCH_SIZE x2 calibrated, WRITE_SIZE x1):
-READ_LINE = 128   # a random read fills one 128-byte L2 line
-CAS64 = 64        # a device-scope 64-bit CAS is done at the memory side
-ATOM32 = 32       # a 32-bit atomic
-STORE = 32        # a small random store writes a 32-byte sector
+# Cost of one random access on MI355X, measured by `--workload access` (the
+# access-cost summary in profiles/): every random read of 4 to 128 bytes is
+# one 128-byte request from L2 to memory (TCC_EA0_RDREQ_128B), and on a
+# 16 GiB table random reads of 16 B and of 128 B run at the same 49 G/s
+# (256 B reads at half that), so the DRAM granule of a random access is
+# 128 bytes.  A device-scope 64-bit CAS is one 64-byte atomic request at the
+# memory side, a 32-bit atomic one 32-byte request, and a random 16-byte
+# store one 32-byte write request.
+GRANULE_B = 128
+READ_LINE = GRANULE_B
+CAS64 = 64
+ATOM32 = 32
+STORE = 32
+
+
+def op_bytes(op, g, u=0.0, eta=0.0, e=0.0, C=8):
+    """Bytes per operation of a random-access hash map keyed by 12-byte keys
+    with 4-byte indices, 1-byte masks and 8-byte slot pairs (tag word, state),
+    under two accountings: payload (the bytes the method touches) and granule
+    (each unavoidable random access counted as one DRAM granule g).
+    u = fraction of insert positions that hold a new key, eta = find hit
+    rate, e = fraction of erase positions that free an index, C = float32
+    value channels.
+
+    insert  payload 25 + 12(1-u) + u(24 + 8C): key 12 in, index 4 and mask 1
+            out, the slot pair 8; a key already present is compared (12); a
+            new key writes its slot pair 8, k^B 12, reads its heap entry 4
+            and moves its value row 4C in and 4C out.
+            granule 17 + 2g + u(16 + 8C): streams 17, the probe window and a
+            second random access (the claim of a new key, the key compare of
+            an old one), k^B 12 + heap 4 + the value row per new key.
+    find    payload 25 + 12 eta; granule 17 + g(1 + eta) (a separate k^B read
+            per hit); find_in_slot: 17 + g for a table that holds the key in
+            its slot (this one), where a hit needs no second access.
+    erase   payload 37 + 13e; granule 13 + 3g + 5e."""
+    if op == "insert":
+        return {"payload": 25 + 12 * (1 - u) + u * (24 + 8 * C), "granule": 17 + 2 * g + u * (16 + 8 * C)}
+    if op == "find":
+        return {"payload": 25 + 12 * eta, "granule": 17 + g * (1 + eta)}
+    if op == "find_in_slot":
+        return {"payload": 25 + 12 * eta, "granule": 17 + g}
+    if op == "erase":
+        return {"payload": 37 + 13 * e, "granule": 13 + 3 * g + 5 * e}
+    raise ValueError(op)
+
+
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 # HBM bytes per launch at the default workload, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs scaled by what they read for a 256 MiB copy (fetch x1.9998,
@@ -126,7 +180,7 @@ def main():
                     help="after the timed steps, copy 256 MiB once (reference kernel for byte counters)")
     ap.add_argument("--workload", default="plain",
                     choices=["plain", "batched", "voxelize", "served", "neighbors", "values", "large", "access",
-                             "setup1", "construct"],
+                             "setup1", "construct", "ablation"],
                     help="plain: the headline 10M-key map; batched: 64 maps in one launch; voxelize: 5M points; "
                          "served: a Poisson request stream on a 2^25-capacity map")
     ap.add_argument("--requests", type=int, default=100_000, help="served: requests per run")
@@ -147,6 +201,9 @@ def main():
     ap.add_argument("--served-bucket-width", type=int, default=4, help="served: bucket width of the served map")
     ap.add_argument("--served-in-flight", type=int, default=4, help="served: device batches queued at once")
     ap.add_argument("--served-max-batch", type=int, default=1 << 22, help="served: positions per fused batch")
+    ap.add_argument("--served-basis-mops", type=float, default=0.0,
+                    help="served: offered loads are fractions of this rate (0: the server's burst capacity)")
+    ap.add_argument("--no-served", action="store_true", help="plain: skip the served-map leg of the bench line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU sharding is a design note only"}))
@@ -167,6 +224,8 @@ def main():
         return bench_setup1(args)
     if args.workload == "construct":
         return bench_construct(args)
+    if args.workload == "ablation":
+        return bench_ablation(args)
     if args.workload == "served":
         return bench_served(args)
 
@@ -252,46 +311,54 @@ def main():
     copy_gbs = 5 * 2 * (1 << 30) / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
     del ca, cb
 
-    # Per-operation byte accountings of insert and find.  payload: the bytes
-    # the method must touch; survey granule: the survey formulas, each
-    # unavoidable random access counted as one DRAM granule g (g = 128 B, the
-    # line a random 16 B read fills here; they assume a separate k^B read per
-    # find hit, which this design does not make); design: the per-kernel
-    # algorithmic bytes of this implementation (kernel_bytes).
     def avg_ms(name):
         return kernels[name][1] / kernels[name][0] if name in kernels else 0.0
-    g = READ_LINE
     C = args.channels
-    ins_ms = avg_ms("claim") + avg_ms("commit") + avg_ms("finalize") + avg_ms("sum_partials") + avg_ms("values")
+    claim_name = next((k for k in kernels if k.startswith("claim")), "claim")
+    ins_parts = [k for k in (claim_name, "sum_partials", "commit", "finalize", "values") if k in kernels]
+    ins_ms = sum(avg_ms(k) for k in ins_parts)
     find_ms = avg_ms("find")
-    accounting = {"granule_B": g, "copy_ceiling_GBps": round(copy_gbs, 1)}
-    ins_design = sum(kernel_bytes(k, n, u, dup, e, C, inline) for k in ("claim", "commit", "values")) / n
-    for op, cnt, ms, pay, gran, des in (
-            ("insert", n, ins_ms, 25 + 12 * (1 - u) + u * (24 + 8 * C), 17 + 2 * g + u * (16 + 8 * C), ins_design),
-            ("find", nf, find_ms, 25 + 12 * eta, 17 + g * (1 + eta), kernel_bytes("find", 1, u, dup, e, C))):
+    erase_ms = avg_ms("erase_mark") + avg_ms("erase_commit")
+    accounting = {"granule_B_measured": GRANULE_B, "copy_ceiling_GBps": round(copy_gbs, 1),
+                  "note": "granule: each unavoidable random access counted as one DRAM granule g; payload: the "
+                          "bytes the method touches; design: this implementation's per-kernel bytes"}
+    rates = {}
+    for op, cnt, ms in (("insert", n, ins_ms), ("find", nf, find_ms), ("erase", ne, erase_ms)):
         rate = cnt / (ms * 1e-3)
-        accounting[op] = {"Mops": round(rate / 1e6, 1), "ms": round(ms, 4),
-                          "payload_B_per_op": round(pay, 1), "payload_GBps": round(rate * pay / 1e9, 1),
-                          "survey_granule_B_per_op": round(gran, 1),
-                          "survey_granule_GBps": round(rate * gran / 1e9, 1),
-                          "design_B_per_op": round(des, 1), "design_GBps": round(rate * des / 1e9, 1),
-                          "design_frac_of_peak": round(rate * des / 1e9 / HBM_PEAK_GBS, 4),
-                          "design_frac_of_copy": round(rate * des / 1e9 / copy_gbs, 4)}
+        rates[op] = rate
+        ob = {g: op_bytes(op, g, u=u, eta=eta, e=e, C=C) for g in (GRANULE_B, 64)}
+        entry = {"Mops": round(rate / 1e6, 1), "ms": round(ms, 4)}
+        pay = ob[GRANULE_B]["payload"]
+        entry["payload"] = {"B_per_op": round(pay, 1), "GBps": round(rate * pay / 1e9, 1),
+                            "frac": round(rate * pay / 1e9 / HBM_PEAK_GBS, 4)}
+        for g in (GRANULE_B, 64):
+            gb = ob[g]["granule"]
+            entry[f"granule_g{g}"] = {"B_per_op": round(gb, 1), "GBps": round(rate * gb / 1e9, 1),
+                                      "frac": round(rate * gb / 1e9 / HBM_PEAK_GBS, 4)}
+        if op == "find":  # the key is compared in its slot: no separate k^B read per hit
+            gb = op_bytes("find_in_slot", GRANULE_B, eta=eta)["granule"]
+            entry[f"granule_g{GRANULE_B}_key_in_slot"] = {
+                "B_per_op": round(gb, 1), "GBps": round(rate * gb / 1e9, 1),
+                "frac": round(rate * gb / 1e9 / HBM_PEAK_GBS, 4)}
+        accounting[op] = entry
+    accounting["insert"]["kernels"] = ins_parts
 
     per_kernel = {}
     for name, (launches, total) in kernels.items():
         avg = total / launches
-        units = {"claim": n, "commit": n, "values": n, "find": nf, "erase_mark": ne, "erase_commit": ne}.get(name)
-        b = kernel_bytes(name, units, u, dup, e, args.channels, inline) if units else None
+        base = "claim" if name.startswith("claim") else name
+        units = {"claim": n, "commit": n, "values": n, "find": nf, "erase_mark": ne, "erase_commit": ne}.get(base)
+        b = kernel_bytes(base, units, u, dup, e, args.channels, inline) if units else None
         per_kernel[name] = {"launches_per_step": launches / args.steps, "avg_ms": round(avg, 4),
-                            "GBps": round(b / (avg * 1e-3) / 1e9, 1) if b else None}
-    dom = max((k for k in per_kernel if per_kernel[k]["GBps"] is not None),
-              key=lambda k: kernels[k][1])
-    dom_units = {"claim": n, "commit": n, "values": n, "find": nf, "erase_mark": ne, "erase_commit": ne}[dom]
-    dom_bytes = kernel_bytes(dom, dom_units, u, dup, e, args.channels, inline)
-    achieved = dom_bytes / (per_kernel[dom]["avg_ms"] * 1e-3) / 1e9
-    alg_bytes = dom_bytes
-    traffic = round(MEASURED_TRAFFIC[dom] / 1e9, 4) if dom in MEASURED_TRAFFIC and traffic_applies(args) else None
+                            "design_GBps": round(b / (avg * 1e-3) / 1e9, 1) if b else None}
+    # Roofline of the dominant operation, insert (its claim and commit take
+    # over half the step): granule bytes per insert position x positions per
+    # call / the summed average durations of its kernels.
+    ins_bytes = op_bytes("insert", GRANULE_B, u=u, C=C)["granule"] * n
+    achieved = ins_bytes / (ins_ms * 1e-3) / 1e9
+    traffic = None
+    if traffic_applies(args) and all(k in MEASURED_TRAFFIC for k in ins_parts):
+        traffic = round(sum(MEASURED_TRAFFIC[k] for k in ins_parts) / 1e9, 4)
 
     cpu = None
     if args.cpu_sample > 0:
@@ -304,9 +371,14 @@ def main():
         om.erase(d["erase_keys"][: s // 2])
         c1 = time.perf_counter()
         cpu = {"value": round((s + s + s // 2) / (c1 - c0) / 1e6, 3), "unit": "Mops/s", "cores": 1,
+               "of_cores": len(os.sched_getaffinity(0)), "host_cpus": os.cpu_count(), "cpu_model": cpu_model(),
                "kind": "oracle",
                "sample": f"insert first {s} keys, find first {s}, erase first {s // 2} of the same workload "
-                         f"(std::map oracle, one thread, {c1 - c0:.1f} s)"}
+                         f"(std::map oracle, one thread of {len(os.sched_getaffinity(0))}, {c1 - c0:.1f} s)"}
+
+    served = None
+    if not args.no_served:
+        served = served_leg(args, value * 1e6)
 
     out = {
         "metric": "Mops/s insert+find (10M int32×3 keys) & %HBM peak; served p50/p99 latency",
@@ -325,16 +397,22 @@ def main():
                                f"f32x{args.channels} values), find {nf} (50% hits), erase {ne}",
                    "capacity": d["capacity"], "ops_per_step": ops, "probe_group": args.probe_group,
                    "bucket_width": args.bucket_width, "max_load": args.max_load, "lds_dedup": args.lds_dedup,
-                   "sorted_keys": args.sorted_keys,
+                   "sorted_keys": args.sorted_keys, "claim_variant": claim_name,
                    "measured": {"new_key_fraction": round(u, 4), "find_hit_rate": round(eta, 4),
                                 "erase_win_fraction": round(e, 4)}},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "traffic_unit": "GB per launch", "algorithmic_GB_per_launch": round(alg_bytes / 1e9, 4),
-                     "access_bytes": {"read_line": READ_LINE, "cas64": CAS64, "atomic32": ATOM32, "store": STORE}},
+        "roofline": {"bound": "hbm", "kernel": "insert (" + " + ".join(ins_parts) + ")", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "traffic_note": "L2-to-fabric bytes per call (FETCH_SIZE x2 + WRITE_SIZE, Infinity Cache "
+                                     "hits included), from counter runs of these kernel sources",
+                     "accounting": "granule", "granule_B": GRANULE_B,
+                     "bytes_per_op": round(ins_bytes / n, 1), "units_per_launch": n,
+                     "frac_g64": round(op_bytes("insert", 64, u=u, C=C)["granule"] * n / (ins_ms * 1e-3) / 1e9
+                                       / HBM_PEAK_GBS, 4)},
         "kernels": per_kernel,
         "accounting": accounting,
         "cpu_baseline": cpu,
+        "served": served,
     }
     print(json.dumps(out), flush=True)
 
@@ -373,11 +451,12 @@ def bench_batched(args):
     P = ctypes.c_void_p
     keep = []
 
-    def build(batched_tuning):
+    def build(batched_tuning, grid=None):
         t0 = time.perf_counter()
         maps = []
         for w in work:
-            tun, _ = ash.autotune(w["capacity"], len(w["keys"]), 0.5, 3, [(torch.float32, 8)], batched=batched_tuning)
+            tun, _ = ash.autotune(w["capacity"], len(w["keys"]), 0.5, 3, [(torch.float32, 8)], batched=batched_tuning,
+                                  grid=grid)
             maps.append((ash.HashMap(w["capacity"], 3, [(torch.float32, 8)], **tun), tun))
         tune_s = time.perf_counter() - t0
         arr = (L.AshBatchOp * len(work))()
@@ -402,6 +481,10 @@ def bench_batched(args):
 
     maps_f, arr_f, shapes_f, tune_f = build(True)
     maps_p, arr_p, shapes_p, tune_p = build(False)
+    # the grid the batched workload states: W {4, 8, 16, 32} x max load {0.5,
+    # 0.7, 0.85} x probe group {8, 16, 64}, each point timed in the persistent launch
+    stated = ([4, 8, 16, 32], [8, 16, 64], [0.5, 0.7, 0.85])
+    maps_s, arr_s, shapes_s, tune_s = build(True, grid=stated)
     n_ops = sum(len(w["keys"]) + len(w["find_keys"]) for w in work)
 
     def clear_all(maps):
@@ -428,6 +511,7 @@ def bench_batched(args):
 
     ms_f = timed_hot(maps_f, arr_f, True)
     ms_p = timed_hot(maps_p, arr_p, False)
+    ms_s = timed_hot(maps_s, arr_s, True)
     ms_fc = _timed(lambda: (clear_all(maps_f), run(arr_f, True)), args.steps, args.warmup)
     ms_pc = _timed(lambda: (clear_all(maps_p), run(arr_p, False)), args.steps, args.warmup)
     print(json.dumps({
@@ -441,6 +525,10 @@ def bench_batched(args):
         "plain_path": {"ms_per_step": round(ms_p, 4), "value": round(n_ops / ms_p / 1e3, 1), "unit": "Mops/s",
                        "tuned_shapes": shapes_p, "autotune_s": round(tune_p, 2)},
         "speedup_vs_plain": round(ms_p / ms_f, 3),
+        "stated_grid": {"grid": {"bucket_width": stated[0], "probe_group": stated[1], "max_load": stated[2]},
+                        "ms_per_step": round(ms_s, 4), "value": round(n_ops / ms_s / 1e3, 1), "unit": "Mops/s",
+                        "tuned_shapes": shapes_s, "autotune_s": round(tune_s, 2)},
+        "fallbacks": int(lib.ash_batched_fallbacks()),
         "with_clears": {"fused_ms": round(ms_fc, 4), "plain_ms": round(ms_pc, 4),
                         "fused_Mops": round(n_ops / ms_fc / 1e3, 1), "plain_Mops": round(n_ops / ms_pc / 1e3, 1)}}),
           flush=True)
@@ -733,6 +821,103 @@ def bench_construct(args):
         "results": res, "cpu_baseline": None}), flush=True)
 
 
+def bench_ablation(args):
+    """Backend ablation (Sec. 5.2 and 5.3): the separate-chaining backend of
+    include/ash_slab.h (slab lists, index delegates, three-pass insertion)
+    beside the product's open addressing, on the same inputs.
+    Setup 2: scalar int32 keys -> f32, c = 10^3..10^6 keys into capacity c,
+    distinct ratio 0.1 / 0.5 / 0.99.  Setup 1 shape: int32x3 keys, c = 10^6,
+    distinct ratio 0.1 / 0.99, f32 x {1, 8, 64, 512} rows.  Per point the
+    median GPU time of 10 calls: insert into a cleared map, then a 50%-hit
+    find that gathers rows."""
+    import torch
+
+    import paper_2110_00511_amd as ash
+    import synth
+    from paper_2110_00511_amd import _lib as L
+    from paper_2110_00511_amd.ablation import SlabMap
+
+    torch.cuda.set_device(0)
+    lib = L.load()
+    sp = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    P = ctypes.c_void_p
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(12)
+
+    def one_point(kd, c, keys_np, fk_np, ch):
+        keys = torch.from_numpy(keys_np).cuda()
+        fkeys = torch.from_numpy(fk_np).cuda()
+        vals = torch.randn((c, ch), dtype=torch.float32, device="cuda", generator=gen)
+        idx = torch.empty(c, dtype=torch.int32, device="cuda")
+        mask = torch.empty(c, dtype=torch.uint8, device="cuda")
+        fidx = torch.empty(c, dtype=torch.int32, device="cuda")
+        fmask = torch.empty(c, dtype=torch.uint8, device="cuda")
+        outv = torch.empty((c, ch), dtype=torch.float32, device="cuda")
+        res = {}
+        # product: open addressing
+        m = ash.HashMap(c, kd, [(torch.float32, ch)])
+        vptr = (ctypes.c_void_p * 1)(vals.data_ptr())
+        optr = (ctypes.c_void_p * 1)(outv.data_ptr())
+        ts = []
+        for _ in range(11):
+            L.check(lib.ash_clear(m._m, sp), "clear")
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            L.check(lib.ash_insert(m._m, P(keys.data_ptr()), c, ctypes.cast(vptr, P), P(idx.data_ptr()),
+                                   P(mask.data_ptr()), sp), "insert")
+            b.record()
+            b.synchronize()
+            ts.append(a.elapsed_time(b))
+        u = int(mask.sum().item())
+        fnd = _event_ms(lambda: L.check(lib.ash_find(m._m, P(fkeys.data_ptr()), c, P(fidx.data_ptr()),
+                                                     P(fmask.data_ptr()), ctypes.cast(optr, P), sp), "find"), 10)
+        res["open_addressing"] = {"insert_us": round(float(np.median(ts[1:])) * 1e3, 2), "find_us": round(fnd * 1e3, 2)}
+        m.close()
+        # ablation: separate chaining
+        s = SlabMap(c, kd, 4 * ch)
+        ts = []
+        for _ in range(11):
+            L.check(lib.ash_slab_clear(s._m, sp), "slab clear")
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            L.check(lib.ash_slab_insert(s._m, P(keys.data_ptr()), c, P(vals.data_ptr()), P(idx.data_ptr()),
+                                        P(mask.data_ptr()), sp), "slab insert")
+            b.record()
+            b.synchronize()
+            ts.append(a.elapsed_time(b))
+        assert int(mask.sum().item()) == u  # the same keys were inserted
+        fnd = _event_ms(lambda: L.check(lib.ash_slab_find(s._m, P(fkeys.data_ptr()), c, P(fidx.data_ptr()),
+                                                          P(fmask.data_ptr()), P(outv.data_ptr()), sp),
+                                        "slab find"), 10)
+        res["separate_chaining"] = {"insert_us": round(float(np.median(ts[1:])) * 1e3, 2),
+                                    "find_us": round(fnd * 1e3, 2)}
+        s.close()
+        res["distinct"] = u
+        return res
+
+    setup2 = {}
+    for c in (1_000, 10_000, 100_000, 1_000_000):
+        for rho in (0.1, 0.5, 0.99):
+            d = synth.setup2(c, rho)
+            setup2[f"c={c},rho={rho}"] = one_point(1, c, d["keys"], d["find_keys"], 1)
+            print(f"# ablation setup2 c={c} rho={rho}: {setup2[f'c={c},rho={rho}']}", flush=True)
+    setup1 = {}
+    for rho in (0.1, 0.99):
+        d = synth.setup1(1_000_000, rho)
+        for ch in (1, 8, 64, 512):
+            setup1[f"rho={rho},row={4 * ch}B"] = one_point(3, 1_000_000, d["keys"], d["find_keys"], ch)
+            print(f"# ablation setup1 rho={rho} row={4 * ch}: {setup1[f'rho={rho},row={4 * ch}B']}", flush=True)
+    top = setup1["rho=0.99,row=4B"]
+    print(json.dumps({
+        "metric": "backend ablation: insert / find microseconds, open addressing vs separate chaining",
+        "value": round(top["separate_chaining"]["insert_us"] / top["open_addressing"]["insert_us"], 3),
+        "unit": "separate-chaining / open-addressing insert time (int32x3, 10^6 keys, rho 0.99, 4 B rows)",
+        "n_gpus": 1, "higher_is_better": False, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "Setup 2 (scalar int32 -> f32, c = 1e3..1e6, rho 0.1/0.5/0.99) and int32x3 keys "
+                               "at c = 1e6 with f32 x {1, 8, 64, 512} rows; median of 10 calls"},
+        "setup2": setup2, "setup1_rows": setup1, "cpu_baseline": None}), flush=True)
+
+
 def bench_large(args):
     """A hash set far beyond the caches: n int32x3 keys (default 1e9, distinct
     ratio ~0.5, drawn on the device from a seeded generator) inserted into a
@@ -968,82 +1153,131 @@ def bench_neighbors(args):
         "cpu_baseline": cpu}), flush=True)
 
 
-def bench_served(args):
-    """Served map: capacity 2^25, 20M preloaded keys, f32x8 values; a Poisson
-    stream of requests (60% find, 30% insert, 10% erase; sizes log-uniform in
-    [256, 2^20]; keys uniform over the 318^3 key universe, taken as slices of
-    device-resident key pools) replayed through the continuous-batching
-    server at 0.5x and 0.9x of its measured burst capacity, and through the
-    one-request-per-batch path at the same arrivals."""
-    import torch
+class ServedWorkload:
+    """The served map's workload: capacity 2^25, 20M keys preloaded with
+    f32x8 rows, and a Poisson stream of requests (60% find, 30% insert, 10%
+    erase; sizes log-uniform in [256, 2^20]; keys uniform over the 318^3 key
+    universe, taken as slices of device-resident key pools) replayed through
+    the continuous-batching server.  Offered load sets the mean arrival rate
+    in key operations per second."""
 
-    import paper_2110_00511_amd as ash
-    import synth
+    def __init__(self, args, n_requests):
+        import torch
 
-    torch.cuda.set_device(0)
-    w = synth.served(n_requests=args.requests)
-    m = ash.HashMap(w["capacity"], 3, [(torch.float32, 8)], max_load=args.served_max_load,
-                    probe_group=args.served_probe_group, bucket_width=args.served_bucket_width)
-    m.insert(torch.from_numpy(w["preload_keys"]).cuda(), [torch.from_numpy(w["preload_values"]).cuda()])
-    torch.cuda.synchronize()
-    pool = 1 << 24
-    g = torch.Generator(device="cuda").manual_seed(w["seed"])
-    kpool = torch.randint(0, w["side"], (pool + (1 << 20), 3), dtype=torch.int32, device="cuda", generator=g)
-    vpool = torch.randn((pool + (1 << 20), 8), dtype=torch.float32, device="cuda", generator=g)
-    opool = 1 << 25
-    oidx = torch.empty(opool + (1 << 20), dtype=torch.int32, device="cuda")
-    omask = torch.empty(opool + (1 << 20), dtype=torch.uint8, device="cuda")
-    rng = np.random.default_rng(w["seed"] + 1)
-    kinds, sizes = w["kinds"], w["sizes"]
-    offs = rng.integers(0, pool, size=len(kinds))
-    from paper_2110_00511_amd import _lib as L
-    vptrs = []
-    reqs = []
-    out_off = 0
-    for k, n, o in zip(kinds, sizes, offs):
-        o, n = int(o), int(n)
-        vp = None
-        if k == 1:
-            arr = (ctypes.c_void_p * 1)(vpool[o].data_ptr())
-            vptrs.append(arr)
-            vp = ctypes.cast(arr, ctypes.c_void_p)
-        reqs.append(L.AshRequest(int(k), kpool[o].data_ptr(), n, vp,
-                                 oidx[out_off].data_ptr() if k != 2 else None, omask[out_off].data_ptr(), None))
-        out_off = (out_off + n) % opool
-    total_ops = int(sizes.sum())
-    mean_ops = total_ops / len(sizes)
+        import paper_2110_00511_amd as ash
+        import synth
+        from paper_2110_00511_amd import _lib as L
 
-    def run(load_ops_per_s, fuse, count):
-        srv = ash.Server(m, fuse=fuse, in_flight=args.served_in_flight, max_batch=args.served_max_batch)
-        gaps = w["gaps"][:count] * (mean_ops / load_ops_per_s) if load_ops_per_s else np.zeros(count)
-        lat, sts, span = srv.replay(reqs[:count], np.cumsum(gaps) - gaps[0])
+        self.ash, self.args = ash, args
+        w = synth.served(n_requests=n_requests)
+        self.w = w
+        self.m = ash.HashMap(w["capacity"], 3, [(torch.float32, 8)], max_load=args.served_max_load,
+                             probe_group=args.served_probe_group, bucket_width=args.served_bucket_width)
+        self.m.insert(torch.from_numpy(w["preload_keys"]).cuda(), [torch.from_numpy(w["preload_values"]).cuda()])
+        torch.cuda.synchronize()
+        pool = 1 << 24
+        g = torch.Generator(device="cuda").manual_seed(w["seed"])
+        self.kpool = torch.randint(0, w["side"], (pool + (1 << 20), 3), dtype=torch.int32, device="cuda", generator=g)
+        self.vpool = torch.randn((pool + (1 << 20), 8), dtype=torch.float32, device="cuda", generator=g)
+        opool = 1 << 25
+        self.oidx = torch.empty(opool + (1 << 20), dtype=torch.int32, device="cuda")
+        self.omask = torch.empty(opool + (1 << 20), dtype=torch.uint8, device="cuda")
+        rng = np.random.default_rng(w["seed"] + 1)
+        kinds, sizes = w["kinds"], w["sizes"]
+        offs = rng.integers(0, pool, size=len(kinds))
+        self.vptrs, self.reqs = [], []
+        out_off = 0
+        for k, n, o in zip(kinds, sizes, offs):
+            o, n = int(o), int(n)
+            vp = None
+            if k == 1:
+                arr = (ctypes.c_void_p * 1)(self.vpool[o].data_ptr())
+                self.vptrs.append(arr)
+                vp = ctypes.cast(arr, ctypes.c_void_p)
+            self.reqs.append(L.AshRequest(int(k), self.kpool[o].data_ptr(), n, vp,
+                                          self.oidx[out_off].data_ptr() if k != 2 else None,
+                                          self.omask[out_off].data_ptr(), None))
+            out_off = (out_off + n) % opool
+        self.sizes = sizes
+        self.mean_ops = float(sizes.sum()) / len(sizes)
+
+    def run(self, load_ops_per_s, fuse, count):
+        """Replays the first `count` requests (None load: all arriving at once)."""
+        srv = self.ash.Server(self.m, fuse=fuse, in_flight=self.args.served_in_flight,
+                              max_batch=self.args.served_max_batch)
+        gaps = self.w["gaps"][:count] * (self.mean_ops / load_ops_per_s) if load_ops_per_s else np.zeros(count)
+        lat, sts, span = srv.replay(self.reqs[:count], np.cumsum(gaps) - gaps[0])
         st = srv.stats()
         srv.close()
-        ops = int(sizes[:count].sum())
+        ops = int(self.sizes[:count].sum())
         return dict(ops_per_s=ops / span, p50_ms=float(np.percentile(lat, 50) * 1e3),
                     p99_ms=float(np.percentile(lat, 99) * 1e3), span_s=span, batches=st["batches"],
-                    requests=count, ops=ops, failed=int((sts != 0).sum()))
+                    largest_batch_requests=st["largest"], requests=count, ops=ops, failed=int((sts != 0).sum()))
 
-    cal = run(None, True, min(len(reqs), 5000))  # burst: everything waiting, the server's capacity
+    def close(self):
+        self.m.close()
+
+
+def _rounded(d):
+    return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}
+
+
+def served_leg(args, plain_ops_per_s):
+    """The served map beside the plain path: its burst capacity (every
+    request waiting), then the stream offered at 0.5x and 0.9x of the plain
+    path's measured mixed throughput, fused and one request per batch."""
+    work = ServedWorkload(args, args.requests)
+    try:
+        cal = work.run(None, True, min(len(work.reqs), 5000))
+        out = {"offered_load_basis_Mops": round(plain_ops_per_s / 1e6, 1),
+               "burst_capacity_Mops": round(cal["ops_per_s"] / 1e6, 1)}
+        for load in (0.5, 0.9):
+            for fuse in (True, False):
+                r = work.run(load * plain_ops_per_s, fuse, len(work.reqs))
+                out[f"{'fused' if fuse else 'unfused'}_{load}x"] = _rounded(
+                    {"Mops": r["ops_per_s"] / 1e6, "p50_ms": r["p50_ms"], "p99_ms": r["p99_ms"],
+                     "span_s": r["span_s"], "batches": r["batches"], "largest_batch_requests":
+                     r["largest_batch_requests"], "failed": r["failed"]})
+        out["workload"] = (f"capacity 2^25, 20M preloaded int32x3 keys with f32x8 rows, {len(work.reqs)} Poisson "
+                           "requests (60% find / 30% insert / 10% erase, sizes log-uniform in [256, 2^20]); "
+                           "latency = completion - scheduled arrival")
+        out["server"] = {"max_load": args.served_max_load, "probe_group": args.served_probe_group,
+                         "bucket_width": args.served_bucket_width, "in_flight": args.served_in_flight,
+                         "max_batch": args.served_max_batch, "max_fused": 256}
+        return out
+    finally:
+        work.close()
+
+
+def bench_served(args):
+    """Served map on its own: burst capacity, then the stream at 0.5x and
+    0.9x of the burst capacity (or of --served-basis-mops), fused and one
+    request per batch."""
+    import torch
+    torch.cuda.set_device(0)
+    work = ServedWorkload(args, args.requests)
+    cal = work.run(None, True, min(len(work.reqs), 5000))  # burst: everything waiting, the server's capacity
     cap = cal["ops_per_s"]
+    basis = args.served_basis_mops * 1e6 if args.served_basis_mops else cap
     out = {}
     for load in (0.5, 0.9):
-        out[f"fused_{load}"] = run(load * cap, True, len(reqs))
-        out[f"unfused_{load}"] = run(load * cap, False, len(reqs))
+        out[f"fused_{load}"] = work.run(load * basis, True, len(work.reqs))
+        out[f"unfused_{load}"] = work.run(load * basis, False, len(work.reqs))
     head = out["fused_0.9"]
     print(json.dumps({
         "metric": "served map ops/s with p50/p99 latency (continuous batching)",
         "value": round(head["ops_per_s"] / 1e6, 1), "unit": "Mops/s", "n_gpus": 1,
         "higher_is_better": True, "dtype": "int32", "data": "synthetic",
         "p50_ms": round(head["p50_ms"], 3), "p99_ms": round(head["p99_ms"], 3),
-        "config": {"workload": f"capacity 2^25, 20M preloaded keys, f32x8 values, {len(reqs)} Poisson requests "
+        "config": {"workload": f"capacity 2^25, 20M preloaded keys, f32x8 values, {len(work.reqs)} Poisson requests "
                                "(60% find / 30% insert / 10% erase, sizes log-uniform in [256, 2^20])",
-                   "burst_capacity_Mops": round(cap / 1e6, 1), "mean_request_ops": round(mean_ops),
+                   "burst_capacity_Mops": round(cap / 1e6, 1), "offered_load_basis_Mops": round(basis / 1e6, 1),
+                   "mean_request_ops": round(work.mean_ops),
                    "max_load": args.served_max_load, "probe_group": args.served_probe_group,
                    "bucket_width": args.served_bucket_width, "in_flight": args.served_in_flight,
                    "max_batch": args.served_max_batch},
-        "runs": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
-                 for k, v in out.items()}}), flush=True)
+        "runs": {k: _rounded(v) for k, v in out.items()}}), flush=True)
+    work.close()
 
 
 if __name__ == "__main__":

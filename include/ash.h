@@ -332,7 +332,10 @@ typedef struct {
 
 ash_status_t ash_batched(const ash_batch_op_t* ops, int32_t n_ops, int32_t fused, void* stream);
 /* Fused ash_batched calls of this process that failed the arrival check and
- * ran op by op instead (instrumentation). */
+ * ran op by op instead (instrumentation).  Setting the environment variable
+ * ASH_BATCHED_FORCE_ARRIVAL_FAILURE=1 makes every fused launch fail that
+ * check (its blocks leave before touching any map), which tests use to take
+ * the fallback on purpose. */
 int64_t ash_batched_fallbacks(void);
 
 /* Autotuner for the table shape.  Times insert + find of a synthetic batch on
@@ -360,6 +363,21 @@ ash_status_t ash_autotune_batched(int64_t capacity, int32_t key_dim, int32_t n_v
                                   int64_t n_insert, double distinct_ratio,
                                   const ash_allocator_t* allocator, void* stream,
                                   ash_tuning_t* out, double* out_ms);
+
+/* The tuner over an explicit grid: every valid (bucket_width in widths,
+ * probe_group in groups, max_load in loads) is timed as in ash_autotune
+ * (fused = 0) or as in ash_autotune_batched (fused = 1); shapes ash_create
+ * would refuse are skipped.  Each list holds 1..64 entries; ASH_E_INVALID if
+ * no point of the grid is valid.  Cached per workload and grid.
+ * Synchronizes. */
+ash_status_t ash_autotune_sweep(int64_t capacity, int32_t key_dim, int32_t n_values,
+                                const ash_dtype_t* value_dtypes, const int64_t* value_elems,
+                                int64_t n_insert, double distinct_ratio,
+                                const int32_t* widths, int32_t n_widths,
+                                const int32_t* groups, int32_t n_groups,
+                                const float* loads, int32_t n_loads, int32_t fused,
+                                const ash_allocator_t* allocator, void* stream,
+                                ash_tuning_t* out, double* out_ms);
 
 /* Served map (continuous batching).  A server owns one map (the caller must
  * not use the map while it is served) and a worker thread with its own HIP

@@ -97,6 +97,8 @@ SIGNATURES = {
                           ctypes.POINTER(ctypes.c_double)]),
     "ash_autotune_batched": (ST, [I64, I32, I32, P, P, I64, ctypes.c_double, P, P, ctypes.POINTER(AshTuning),
                                   ctypes.POINTER(ctypes.c_double)]),
+    "ash_autotune_sweep": (ST, [I64, I32, I32, P, P, I64, ctypes.c_double, P, I32, P, I32, P, I32, I32, P, P,
+                                ctypes.POINTER(AshTuning), ctypes.POINTER(ctypes.c_double)]),
     "ash_server_create": (ST, [P, P, ctypes.POINTER(P)]),
     "ash_batched_fallbacks": (I64, []),
     "ash_batched_grid": (ST, [I32, ctypes.POINTER(I64), ctypes.POINTER(I64), P]),
@@ -109,6 +111,14 @@ SIGNATURES = {
     "ash_profile_collect": (ST, [P, ctypes.POINTER(AshKernelTime), I32, ctypes.POINTER(I32), P]),
     "ash_access_bench": (ST, [I32, P, I64, I32, I64, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double), P]),
     "ash_status_string": (ctypes.c_char_p, [ST]),
+    # include/ash_slab.h: the separate-chaining backend of the backend ablation
+    "ash_slab_create": (ST, [I64, I32, I64, P, ctypes.POINTER(P)]),
+    "ash_slab_destroy": (ST, [P]),
+    "ash_slab_clear": (ST, [P, P]),
+    "ash_slab_insert": (ST, [P, P, I64, P, P, P, P]),
+    "ash_slab_find": (ST, [P, P, I64, P, P, P, P]),
+    "ash_slab_size": (ST, [P, ctypes.POINTER(I64), P]),
+    "ash_slab_buffers": (ST, [P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P)]),
 }
 
 _lib = None

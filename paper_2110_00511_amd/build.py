@@ -14,7 +14,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libash.so")
-SOURCES = [os.path.join(HERE, "csrc", name) for name in ("ash_kernels.hip", "ash_api.hip", "ash_serve.hip", "ash_io.hip", "ash_membench.hip")]
+SOURCES = [os.path.join(HERE, "csrc", name) for name in ("ash_kernels.hip", "ash_api.hip", "ash_serve.hip", "ash_io.hip", "ash_membench.hip", "ash_slab.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

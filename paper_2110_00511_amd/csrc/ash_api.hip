@@ -252,7 +252,9 @@ ash_status_t insert_impl(ash_map* m, const int32_t* keys, int64_t n, const void*
   const uint32_t un = (uint32_t)n;
   const uint32_t blocks = ash::claim_blocks(m->G, un);
   auto claim = [&]() -> ash_status_t {
-    ASH_HIP(timed(m, "claim", st, [&] {
+    // the profile names the claim variant that ran (results are the same)
+    const char* label = m->tombs_possible ? "claim_reuse" : (m->keyed ? "claim_keyed" : "claim");
+    ASH_HIP(timed(m, label, st, [&] {
       return ash::launch_claim(m->key_dim, m->G, m->W, m->ref(), keys, un, m->slot_of, m->lost, m->partial, m->meta,
                                st);
     }));
@@ -700,75 +702,126 @@ ash_status_t ash_device_status(ash_map_t m, void* stream) {
   return (h.status & (ash::kStatusScanStall | ash::kStatusGridStall)) ? ASH_E_DEVICE : ASH_E_CAPACITY;
 }
 
-ash_status_t ash_voxelize(const float* points, int64_t n, float voxel, int32_t* out_point_voxel,
+}  // extern "C"
+
+namespace {
+
+// Workspace of one voxelization over n points (one block, 256-byte aligned
+// parts): the slot table (16 B slots, max load 0.5, W = g = 4), slot_of,
+// per-block claim counts, lost bytes, and the scan status words followed by
+// the Meta of the call.
+struct VoxelWork {
+  uint32_t nslots = 0;
+  size_t table = 0, slot_of = 0, partial = 0, lost = 0, status = 0, bytes = 0;
+  int64_t tiles = 0;
+  size_t lost_bytes = 0;
+};
+
+constexpr int kVoxW = 4, kVoxG = 4;  // four lanes per point, 4-slot buckets:
+// against one lane per point, equal at 5 mm and 1 cm, 3% faster at 2 cm and
+// 8% at 5 cm (5M points)
+constexpr float kVoxLoad = 0.5f;
+
+ash_status_t voxel_work(int64_t n, VoxelWork* w) {
+  ASH_TRY(slots_for(n, kVoxLoad, kVoxW, kVoxG, &w->nslots));
+  if (w->nslots >= 0x7FFFFFFFu) return ASH_E_UNSUPPORTED;  // slot_of keeps a candidate bit
+  auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+  w->tiles = (n + ash::kScanTile - 1) / ash::kScanTile;
+  w->lost_bytes = ((size_t)n + 3) / 4 * 4;
+  const uint32_t blocks = ash::claim_blocks(kVoxG, (uint32_t)n);
+  size_t o = 0;
+  w->table = o;
+  o += up((size_t)w->nslots * 16);
+  w->slot_of = o;
+  o += up((size_t)n * 4);
+  w->partial = o;
+  o += up((size_t)blocks * 4);
+  w->lost = o;
+  o += up(w->lost_bytes);
+  w->status = o;
+  o += up((size_t)w->tiles * 8 + sizeof(Meta));
+  w->bytes = o;
+  return ASH_OK;
+}
+
+// The kernels of one voxelization on a workspace laid out by voxel_work.
+ash_status_t voxelize_run(const float* points, int64_t n, float voxel, int32_t* out_point_voxel,
                           int32_t* out_voxel_keys, int32_t* out_voxel_counts, int64_t* out_n_voxels,
-                          const ash_allocator_t* allocator, void* stream) {
+                          const VoxelWork& w, uint8_t* base, hipStream_t st) {
+  const uint32_t un = (uint32_t)n;
+  uint32_t* table = (uint32_t*)(base + w.table);
+  uint32_t* slot_of = (uint32_t*)(base + w.slot_of);
+  uint32_t* partial = (uint32_t*)(base + w.partial);
+  uint8_t* lost = base + w.lost;
+  uint64_t* status = (uint64_t*)(base + w.status);
+  Meta* meta = (Meta*)(status + w.tiles);
+  const uint32_t blocks = ash::claim_blocks(kVoxG, un);
+  TableRef tb;
+  tb.words = table;
+  tb.nslots = w.nslots;
+  tb.bucket_width = kVoxW;
+  tb.nbuckets = w.nslots / kVoxW;
+  tb.window = kVoxG == 1 ? kVoxW : kVoxG;
+  tb.max_windows = w.nslots / tb.window + 1;
+  tb.dedup = kVoxelDedup;
+  tb.reuse = 0;
+  tb.keyed = 1;  // (the voxel claim always keeps pending keys in their slots)
+  tb.mirror = nullptr;
+  Meta h;
+  // every part that must start in a known state is written here by kernels
+  // (the workspace may hold an earlier call's contents): an empty table,
+  // zero status words and lost bytes, and zero counters with epoch 1
+  const bool ok = ash::launch_fill_u32(table, ash::kEmpty, (size_t)w.nslots * 4, st) == hipSuccess &&
+                  ash::launch_fill_u32((uint32_t*)status, 0u, (size_t)w.tiles * 2, st) == hipSuccess &&
+                  ash::launch_fill_u32((uint32_t*)lost, 0u, w.lost_bytes / 4, st) == hipSuccess &&
+                  ash::launch_fill_u32((uint32_t*)meta, 0u, sizeof(Meta) / 4, st) == hipSuccess &&
+                  ash::launch_reset_meta(meta, st) == hipSuccess &&
+                  ash::launch_voxel_claim(kVoxG, kVoxW, tb, points, voxel, un, slot_of, lost, partial, meta, st) ==
+                      hipSuccess &&
+                  ash::launch_sum_partials(partial, blocks, meta, st) == hipSuccess &&
+                  ash::launch_voxel_commit(tb, points, voxel, un, slot_of, lost, out_voxel_keys, out_voxel_counts,
+                                           out_point_voxel, meta, status, st) == hipSuccess &&
+                  ash::launch_voxel_resolve(tb, un, slot_of, out_point_voxel, out_voxel_counts, st) == hipSuccess &&
+                  hipMemcpyAsync(&h, meta, sizeof(Meta), hipMemcpyDeviceToHost, st) == hipSuccess &&
+                  hipStreamSynchronize(st) == hipSuccess;
+  if (!ok) return ASH_E_DEVICE;
+  if (h.fail) return ASH_E_CAPACITY;
+  *out_n_voxels = h.claims;
+  return ASH_OK;
+}
+
+ash_status_t voxelize_args(const float* points, int64_t n, float voxel, int32_t* out_point_voxel,
+                           int32_t* out_voxel_keys, int32_t* out_voxel_counts, int64_t* out_n_voxels) {
   if (!out_n_voxels || n < 0 || n > kMaxCount) return ASH_E_INVALID;
   if (!(voxel > 0.0f) || !std::isfinite(voxel)) return ASH_E_INVALID;
   if (n > 0 && (!points || !out_point_voxel || !out_voxel_keys || !out_voxel_counts)) return ASH_E_INVALID;
+  return ASH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ash_status_t ash_voxelize(const float* points, int64_t n, float voxel, int32_t* out_point_voxel,
+                          int32_t* out_voxel_keys, int32_t* out_voxel_counts, int64_t* out_n_voxels,
+                          const ash_allocator_t* allocator, void* stream) {
+  ASH_TRY(voxelize_args(points, n, voxel, out_point_voxel, out_voxel_keys, out_voxel_counts, out_n_voxels));
   if (allocator && (!allocator->alloc || !allocator->free)) return ASH_E_INVALID;
   if (n == 0) {
     *out_n_voxels = 0;
     return ASH_OK;
   }
   hipStream_t st = (hipStream_t)stream;
+  VoxelWork w;
+  ASH_TRY(voxel_work(n, &w));
   DevMem mem;
   mem.custom = allocator != nullptr;
   if (allocator) mem.a = *allocator;
-  // four lanes per point, 4-slot buckets: against one lane per point, equal
-  // at 5 mm and 1 cm, 3% faster at 2 cm and 8% at 5 cm (5M points)
-  constexpr int kW = 4, kG = 4;
-  constexpr float kLoad = 0.5f;
-  uint32_t nslots;
-  ASH_TRY(slots_for(n, kLoad, kW, kG, &nslots));
-  if (nslots >= 0x7FFFFFFFu) return ASH_E_UNSUPPORTED;  // slot_of keeps a candidate bit
-  const uint32_t un = (uint32_t)n;
-  const int64_t tiles = (n + ash::kScanTile - 1) / ash::kScanTile;
-  uint32_t* table = (uint32_t*)mem.get((size_t)nslots * 16, st);
-  uint32_t* slot_of = (uint32_t*)mem.get((size_t)n * 4, st);
-  const uint32_t blocks = ash::claim_blocks(kG, un);
-  uint32_t* partial = (uint32_t*)mem.get((size_t)blocks * 4, st);
-  const size_t lost_bytes = ((size_t)n + 3) / 4 * 4;
-  uint8_t* lost = (uint8_t*)mem.get(lost_bytes, st);
-  uint64_t* status = (uint64_t*)mem.get((size_t)tiles * 8 + sizeof(Meta), st);
-  ash_status_t rc = ASH_OK;
-  if (!table || !slot_of || !partial || !lost || !status) rc = ASH_E_NOMEM;
-  if (rc == ASH_OK) {
-    Meta* meta = (Meta*)(status + tiles);
-    TableRef tb;
-    tb.words = table;
-    tb.nslots = nslots;
-    tb.bucket_width = kW;
-    tb.nbuckets = nslots / kW;
-    tb.window = kG == 1 ? kW : kG;
-    tb.max_windows = nslots / tb.window + 1;
-    tb.dedup = kVoxelDedup;
-    tb.reuse = 0;
-    tb.keyed = 1;  // (the voxel claim always keeps pending keys in their slots)
-    tb.mirror = nullptr;
-    Meta h;
-    std::memset(&h, 0, sizeof(h));
-    h.epoch = 1;
-    bool ok = ash::launch_fill_u32(table, ash::kEmpty, (size_t)nslots * 4, st) == hipSuccess &&
-              ash::launch_fill_u32((uint32_t*)status, 0u, (size_t)tiles * 2, st) == hipSuccess &&
-              ash::launch_fill_u32((uint32_t*)lost, 0u, lost_bytes / 4, st) == hipSuccess &&
-              hipMemcpyAsync(meta, &h, sizeof(Meta), hipMemcpyHostToDevice, st) == hipSuccess &&
-              ash::launch_voxel_claim(kG, kW, tb, points, voxel, un, slot_of, lost, partial, meta, st) == hipSuccess &&
-              ash::launch_sum_partials(partial, blocks, meta, st) == hipSuccess &&
-              ash::launch_voxel_commit(tb, points, voxel, un, slot_of, lost, out_voxel_keys, out_voxel_counts,
-                                       out_point_voxel, meta, status, st) == hipSuccess &&
-              ash::launch_voxel_resolve(tb, un, slot_of, out_point_voxel, out_voxel_counts, st) == hipSuccess &&
-              hipMemcpyAsync(&h, meta, sizeof(Meta), hipMemcpyDeviceToHost, st) == hipSuccess &&
-              hipStreamSynchronize(st) == hipSuccess;
-    if (!ok) rc = ASH_E_DEVICE;
-    else if (h.fail) rc = ASH_E_CAPACITY;
-    else *out_n_voxels = h.claims;
-  }
-  mem.put(table, st);
-  mem.put(slot_of, st);
-  mem.put(partial, st);
-  mem.put(lost, st);
-  mem.put(status, st);
+  uint8_t* base = (uint8_t*)mem.get(w.bytes, st);
+  if (!base) return ASH_E_NOMEM;
+  const ash_status_t rc = voxelize_run(points, n, voxel, out_point_voxel, out_voxel_keys, out_voxel_counts,
+                                       out_n_voxels, w, base, st);
+  mem.put(base, st);
   return rc;
 }
 
@@ -801,7 +854,7 @@ static ash_status_t batched_resident(int kd, DevMem& mem, hipStream_t st, uint32
   for (int b = per_cu; b >= 1 && found == 0 && rc == ASH_OK; --b) {
     ash::GridSync h;
     if (ash::launch_fill_u32((uint32_t*)gs, 0u, sizeof(ash::GridSync) / 4, st) != hipSuccess ||
-        ash::launch_batched(kd, nullptr, 0, 0, 0, 0, 0, gs, (uint32_t)(cus * b), ash::kArrivalSpinLimit, st) !=
+        ash::launch_batched(kd, nullptr, 0, 0, 0, 0, 0, gs, (uint32_t)(cus * b), ash::kArrivalSpinLimit, 0u, st) !=
             hipSuccess ||
         hipMemcpyAsync(&h, gs, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess) {
@@ -842,17 +895,13 @@ namespace {
 // and ran op by op instead.
 std::atomic<int64_t> batched_fallbacks{0};
 
-// Bound of the arrival check: kArrivalSpinLimit polls, or the value of
-// ASH_BATCHED_ARRIVAL_SPINS.  The variable exists for tests: with 0 the
-// first block to arrive gives up at once, so the launch takes its fallback
-// while every kernel still exits normally.
-uint32_t arrival_spin_limit() {
-  const char* v = std::getenv("ASH_BATCHED_ARRIVAL_SPINS");
-  if (!v || !*v) return ash::kArrivalSpinLimit;
-  char* end = nullptr;
-  const unsigned long x = std::strtoul(v, &end, 10);
-  if (end == v || *end != '\0' || x > 0xFFFFFFFFul) return ash::kArrivalSpinLimit;
-  return (uint32_t)x;
+// ASH_BATCHED_FORCE_ARRIVAL_FAILURE=1 makes the arrival check of the
+// persistent launch fail (its blocks give up without counting themselves
+// in), so a test can take the fallback path while every kernel exits
+// normally.
+uint32_t force_arrival_failure() {
+  const char* v = std::getenv("ASH_BATCHED_FORCE_ARRIVAL_FAILURE");
+  return v && v[0] == '1' && v[1] == '\0' ? 1u : 0u;
 }
 
 // The single-map path, op by op: each op's insert, then its find.
@@ -947,13 +996,13 @@ ash_status_t ash_batched(const ash_batch_op_t* ops, int32_t n_ops, int32_t fused
   ash_status_t rc = ASH_OK;
   ash::GridSync h;
   std::memset(&h, 0, sizeof(h));
-  const uint32_t arrival_spins = arrival_spin_limit();
+  const uint32_t force_fail = force_arrival_failure();
   if (hipMemcpyAsync(dev_items, items.data(), sizeof(ash::BatchItem) * (size_t)n_ops, hipMemcpyHostToDevice, st) !=
           hipSuccess ||
       ash::launch_fill_u32((uint32_t*)gs, 0u, sizeof(ash::GridSync) / 4, st) != hipSuccess ||
       timed(m0, "batched", st, [&] {
         return ash::launch_batched(kd, dev_items, n_ops, claim_tiles, commit_tiles, find_tiles, any_check, gs,
-                                   resident, arrival_spins, st);
+                                   resident, ash::kArrivalSpinLimit, force_fail, st);
       }) != hipSuccess ||
       hipMemcpyAsync(&h, gs, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
@@ -979,7 +1028,9 @@ int64_t ash_batched_fallbacks(void) { return batched_fallbacks.load(); }
 
 namespace {
 
-typedef std::tuple<int, int64_t, int, int, int, int> TuneKey;  // ..., fused
+// (key_dim, value bytes, log2 capacity, log2 batch, distinct ratio in
+// tenths, fused, the swept grid)
+typedef std::tuple<int, int64_t, int, int, int, int, std::vector<int32_t>> TuneKey;
 std::mutex g_tune_mu;
 std::map<TuneKey, std::pair<ash_tuning_t, double>> g_tune_cache;
 
@@ -1006,22 +1057,44 @@ uint32_t cube_side(int64_t n, int kd, double ratio) {
   return (uint32_t)std::max(2.0, std::ceil(std::pow(cells, 1.0 / kd)));
 }
 
+// The shapes ash_create accepts, for a sweep.
+bool valid_shape(int32_t w, int32_t g, float lf) {
+  if (!pow2(w) || w > 64) return false;
+  if (g != 1 && g != 4 && g != 8 && g != 16 && g != 32 && g != 64) return false;
+  if (g == 1 && w != 2 && w != 4 && w != 8) return false;
+  return lf >= 0.1f && lf <= 0.9f;
+}
+
 }  // namespace
 
-// The sweep of ash_autotune; fused times each candidate as one map of the
-// persistent batched launch instead of the single-map insert and find.
+// Every (bucket_width, probe_group, max_load) of the grid is timed on a
+// synthetic batch: clear + insert + find through the single-map path, or as
+// one map of the persistent batched launch (fused).
 static ash_status_t autotune_impl(int64_t capacity, int32_t key_dim, int32_t n_values,
                                   const ash_dtype_t* value_dtypes, const int64_t* value_elems, int64_t n_insert,
-                                  double distinct_ratio, const ash_allocator_t* allocator, void* stream,
-                                  ash_tuning_t* out, double* out_ms, bool fused) {
+                                  double distinct_ratio, const std::vector<int32_t>& widths,
+                                  const std::vector<int32_t>& groups, const std::vector<float>& loads, bool fused,
+                                  const ash_allocator_t* allocator, void* stream, ash_tuning_t* out, double* out_ms) {
   if (!out || capacity <= 0 || capacity > kMaxCount || key_dim < 1 || key_dim > 4) return ASH_E_INVALID;
   if (n_insert <= 0 || n_insert > kMaxCount || !(distinct_ratio > 0.0) || distinct_ratio > 1.0) return ASH_E_INVALID;
   if (n_values < 0 || n_values > ash::kMaxValues || (n_values > 0 && (!value_dtypes || !value_elems)))
     return ASH_E_INVALID;
+  if (widths.empty() || groups.empty() || loads.empty()) return ASH_E_INVALID;
+  bool any = false;
+  for (int32_t g : groups)
+    for (int32_t w : widths)
+      for (float lf : loads) any = any || valid_shape(w, g, lf);
+  if (!any) return ASH_E_INVALID;
   int64_t row = 0;
   for (int j = 0; j < n_values; ++j) row += (int64_t)dtype_size(value_dtypes[j]) * value_elems[j];
+  std::vector<int32_t> grid;  // the grid is part of the cache key
+  for (int32_t w : widths) grid.push_back(w);
+  grid.push_back(-1);
+  for (int32_t g : groups) grid.push_back(g);
+  grid.push_back(-1);
+  for (float lf : loads) grid.push_back((int32_t)std::lround(lf * 1000.0f));
   const TuneKey key(key_dim, row, log2_floor(capacity), log2_floor(n_insert), (int)std::lround(distinct_ratio * 10),
-                    fused ? 1 : 0);
+                    fused ? 1 : 0, grid);
   {
     std::lock_guard<std::mutex> lock(g_tune_mu);
     auto it = g_tune_cache.find(key);
@@ -1051,21 +1124,11 @@ static ash_status_t autotune_impl(int64_t capacity, int32_t key_dim, int32_t n_v
   ash_tuning_t best;
   std::memset(&best, 0, sizeof(best));
   double best_ms = 1e30;
-  const int widths[] = {4, 8, 16, 32};
-  const int groups[] = {1, 4, 8, 16, 64};
-  const float loads[] = {0.5f, 0.7f, 0.85f};
-  // In the persistent batched launch every resident block takes its tiles
-  // one after another, so a tile's latency is not hidden by other blocks: a
-  // lane per key probes all 256 keys of a tile at once, while g >= 4 runs
-  // g rounds in sequence.  The batched sweep therefore keeps g = 1.
-  const int lane_widths[] = {2, 4, 8};
-  for (int g : groups) {
-    if (fused && g != 1) continue;
-    for (int w : (fused ? std::vector<int>(std::begin(lane_widths), std::end(lane_widths))
-                        : std::vector<int>(std::begin(widths), std::end(widths)))) {
-      if (g == 1 && w > 8) continue;
+  for (int32_t g : groups) {
+    for (int32_t w : widths) {
       for (float lf : loads) {
         if (!ok) break;
+        if (!valid_shape(w, g, lf)) continue;
         ash_tuning_t t = {w, g, lf, 0u};
         ash_map* m = nullptr;
         if (ash_create(capacity, key_dim, n_values, value_dtypes, value_elems, allocator, &t, stream, &m) != ASH_OK)
@@ -1110,16 +1173,33 @@ static ash_status_t autotune_impl(int64_t capacity, int32_t key_dim, int32_t n_v
 ash_status_t ash_autotune(int64_t capacity, int32_t key_dim, int32_t n_values, const ash_dtype_t* value_dtypes,
                           const int64_t* value_elems, int64_t n_insert, double distinct_ratio,
                           const ash_allocator_t* allocator, void* stream, ash_tuning_t* out, double* out_ms) {
-  return autotune_impl(capacity, key_dim, n_values, value_dtypes, value_elems, n_insert, distinct_ratio, allocator,
-                       stream, out, out_ms, false);
+  return autotune_impl(capacity, key_dim, n_values, value_dtypes, value_elems, n_insert, distinct_ratio,
+                       {4, 8, 16, 32}, {1, 4, 8, 16, 64}, {0.5f, 0.7f, 0.85f}, false, allocator, stream, out,
+                       out_ms);
 }
 
+// In the persistent batched launch every resident block takes its tiles one
+// after another, so a tile's latency is not hidden by other blocks: a lane
+// per key probes all 256 keys of a tile at once, while g >= 4 runs g rounds
+// in sequence.  The batched sweep therefore keeps g = 1.
 ash_status_t ash_autotune_batched(int64_t capacity, int32_t key_dim, int32_t n_values,
                                   const ash_dtype_t* value_dtypes, const int64_t* value_elems, int64_t n_insert,
                                   double distinct_ratio, const ash_allocator_t* allocator, void* stream,
                                   ash_tuning_t* out, double* out_ms) {
-  return autotune_impl(capacity, key_dim, n_values, value_dtypes, value_elems, n_insert, distinct_ratio, allocator,
-                       stream, out, out_ms, true);
+  return autotune_impl(capacity, key_dim, n_values, value_dtypes, value_elems, n_insert, distinct_ratio, {2, 4, 8},
+                       {1}, {0.5f, 0.7f, 0.85f}, true, allocator, stream, out, out_ms);
+}
+
+ash_status_t ash_autotune_sweep(int64_t capacity, int32_t key_dim, int32_t n_values, const ash_dtype_t* value_dtypes,
+                                const int64_t* value_elems, int64_t n_insert, double distinct_ratio,
+                                const int32_t* widths, int32_t n_widths, const int32_t* groups, int32_t n_groups,
+                                const float* loads, int32_t n_loads, int32_t fused,
+                                const ash_allocator_t* allocator, void* stream, ash_tuning_t* out, double* out_ms) {
+  if (n_widths < 1 || n_groups < 1 || n_loads < 1 || !widths || !groups || !loads) return ASH_E_INVALID;
+  if (n_widths > 64 || n_groups > 64 || n_loads > 64) return ASH_E_INVALID;
+  return autotune_impl(capacity, key_dim, n_values, value_dtypes, value_elems, n_insert, distinct_ratio,
+                       std::vector<int32_t>(widths, widths + n_widths), std::vector<int32_t>(groups, groups + n_groups),
+                       std::vector<float>(loads, loads + n_loads), fused != 0, allocator, stream, out, out_ms);
 }
 
 const char* ash_status_string(ash_status_t s) {

@@ -1391,15 +1391,19 @@ __device__ __forceinline__ void batched_find(const BatchItem& it, uint32_t tile,
 // passes (blocks that start later see the flag in the value their arrival
 // returns).  If the blocks cannot all be resident at once, the resident ones
 // give up and leave, the rest then start, see the flag and leave, and the
-// launch ends with no map changed.
+// launch ends with no map changed.  With force_fail (a test of that path)
+// no block counts itself in, so the first block to give up always succeeds.
 //
 // Later barriers wait on blocks that are all resident (each passed the
 // arrival check and stays until it exits), so they only end early after a
 // broken invariant: the bound then sets gs->late and marks every map.
-__device__ __forceinline__ bool arrival_check(GridSync* gs, uint32_t arrival_spins, uint32_t* s_ok) {
+__device__ __forceinline__ bool arrival_check(GridSync* gs, uint32_t arrival_spins, uint32_t force_fail,
+                                              uint32_t* s_ok) {
   __syncthreads();
   if (threadIdx.x == 0) {
-    uint32_t c = __hip_atomic_fetch_add(&gs->count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+    uint32_t c = force_fail ? __hip_atomic_load(&gs->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                            : __hip_atomic_fetch_add(&gs->count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+    if (force_fail) arrival_spins = 0;
     bool ok = false;
     uint32_t spins = 0;
     while (true) {
@@ -1460,10 +1464,11 @@ __device__ __forceinline__ bool grid_barrier(GridSync* gs, uint32_t& passed, con
 template <int KD>
 __global__ __launch_bounds__(kBlock) void k_batched(const BatchItem* __restrict__ items, int32_t n_items,
                                                     uint32_t claim_tiles, uint32_t commit_tiles, uint32_t find_tiles,
-                                                    int32_t any_check, GridSync* gs, uint32_t arrival_spins) {
+                                                    int32_t any_check, GridSync* gs, uint32_t arrival_spins,
+                                                    uint32_t force_fail) {
   __shared__ TileLds lds;
   __shared__ uint32_t s_ok;
-  if (!arrival_check(gs, arrival_spins, &s_ok)) return;  // all blocks resident, or none works
+  if (!arrival_check(gs, arrival_spins, force_fail, &s_ok)) return;  // all blocks resident, or none works
   uint32_t passed = 1;
   int cur = 0;
   for (uint32_t t = blockIdx.x; t < claim_tiles; t += gridDim.x) {
@@ -1978,12 +1983,12 @@ hipError_t launch_voxel_resolve(const TableRef& tb, uint32_t n, const uint32_t* 
 template <int KD>
 static hipError_t batched_k(const BatchItem* items, int32_t n_items, uint32_t claim_tiles, uint32_t commit_tiles,
                             uint32_t find_tiles, int32_t any_check, GridSync* gs, uint32_t resident,
-                            uint32_t arrival_spins, hipStream_t st) {
+                            uint32_t arrival_spins, uint32_t force_fail, hipStream_t st) {
   // n_items == 0 launches all `resident` blocks with no work: a residency probe
   const uint32_t work = std::max(std::max(claim_tiles, commit_tiles), std::max(find_tiles, (uint32_t)n_items));
   const uint32_t grid = n_items == 0 ? resident : std::max<uint32_t>(1, std::min<uint32_t>(resident, work));
   hipLaunchKernelGGL((k_batched<KD>), dim3(grid), dim3(kBlock), 0, st, items, n_items, claim_tiles, commit_tiles,
-                     find_tiles, any_check, gs, arrival_spins);
+                     find_tiles, any_check, gs, arrival_spins, force_fail);
   return hipGetLastError();
 }
 
@@ -1999,16 +2004,16 @@ hipError_t batched_occupancy(int kd, int* per_cu) {
 
 hipError_t launch_batched(int kd, const BatchItem* items, int32_t n_items, uint32_t claim_tiles, uint32_t commit_tiles,
                           uint32_t find_tiles, int32_t any_check, GridSync* gs, uint32_t resident,
-                          uint32_t arrival_spins, hipStream_t st) {
+                          uint32_t arrival_spins, uint32_t force_fail, hipStream_t st) {
   switch (kd) {
     case 1: return batched_k<1>(items, n_items, claim_tiles, commit_tiles, find_tiles, any_check, gs, resident,
-                                    arrival_spins, st);
+                                    arrival_spins, force_fail, st);
     case 2: return batched_k<2>(items, n_items, claim_tiles, commit_tiles, find_tiles, any_check, gs, resident,
-                                    arrival_spins, st);
+                                    arrival_spins, force_fail, st);
     case 3: return batched_k<3>(items, n_items, claim_tiles, commit_tiles, find_tiles, any_check, gs, resident,
-                                    arrival_spins, st);
+                                    arrival_spins, force_fail, st);
     case 4: return batched_k<4>(items, n_items, claim_tiles, commit_tiles, find_tiles, any_check, gs, resident,
-                                    arrival_spins, st);
+                                    arrival_spins, force_fail, st);
     default: return hipErrorInvalidValue;
   }
 }

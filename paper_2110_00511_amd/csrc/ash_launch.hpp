@@ -94,12 +94,13 @@ hipError_t launch_voxel_resolve(const TableRef& tb, uint32_t n, const uint32_t* 
 // One persistent launch over the items (grid = min(resident, work) blocks).
 // gs must be zero; resident is a block count the device runs all at once
 // (batched_occupancy gives the upper bound per CU); arrival_spins bounds the
-// arrival check (kArrivalSpinLimit).  Afterwards gs->count carries
+// arrival check (kArrivalSpinLimit); force_fail = 1 makes the check fail (a
+// test of the fallback path: no map is touched).  Afterwards gs->count carries
 // kArrivalFailed when the blocks were not all resident (no map touched) and
 // gs->late is nonzero when a later barrier gave up.
 hipError_t launch_batched(int kd, const BatchItem* items, int32_t n_items, uint32_t claim_tiles, uint32_t commit_tiles,
                           uint32_t find_tiles, int32_t any_check, GridSync* gs, uint32_t resident,
-                          uint32_t arrival_spins, hipStream_t st);
+                          uint32_t arrival_spins, uint32_t force_fail, hipStream_t st);
 hipError_t batched_occupancy(int kd, int* per_cu);
 
 // Synthetic keys of the autotuner (uniform in [0, side)^kd; finds half hits).

@@ -329,11 +329,13 @@ def voxelize(points, voxel_size):
     return pv, vk[:u], cnt[:u]
 
 
-def autotune(capacity, n_insert, distinct_ratio, key_dim=3, value_specs=(), device="cuda", batched=False):
+def autotune(capacity, n_insert, distinct_ratio, key_dim=3, value_specs=(), device="cuda", batched=False,
+             grid=None):
     """Table shape for a map of `capacity` receiving batches of `n_insert`
     keys with the given distinct ratio: times insert + find of a synthetic
     batch for every point of the sweep on this GPU (through the persistent
-    batched launch when batched=True).  Returns
+    batched launch when batched=True).  grid = (widths, groups, loads) sweeps
+    that grid instead of the library's default one.  Returns
     (dict(bucket_width, probe_group, max_load), milliseconds)."""
     lib = L.load()
     specs = [(dt, int(e)) for dt, e in value_specs]
@@ -343,6 +345,18 @@ def autotune(capacity, n_insert, distinct_ratio, key_dim=3, value_specs=(), devi
     alloc = L.TorchAllocator(device)
     out = L.AshTuning()
     ms = ctypes.c_double()
+    if grid is not None:
+        ws, gs, ls = [list(x) for x in grid]
+        wa = (ctypes.c_int32 * len(ws))(*ws)
+        ga = (ctypes.c_int32 * len(gs))(*gs)
+        la = (ctypes.c_float * len(ls))(*ls)
+        L.check(lib.ash_autotune_sweep(int(capacity), int(key_dim), n, ctypes.cast(dts, ctypes.c_void_p),
+                                       ctypes.cast(els, ctypes.c_void_p), int(n_insert), float(distinct_ratio),
+                                       ctypes.cast(wa, ctypes.c_void_p), len(ws), ctypes.cast(ga, ctypes.c_void_p),
+                                       len(gs), ctypes.cast(la, ctypes.c_void_p), len(ls), 1 if batched else 0,
+                                       ctypes.byref(alloc.struct), _stream(), ctypes.byref(out), ctypes.byref(ms)),
+                "ash_autotune_sweep")
+        return dict(bucket_width=out.bucket_width, probe_group=out.probe_group, max_load=out.max_load), ms.value
     fn = lib.ash_autotune_batched if batched else lib.ash_autotune
     L.check(fn(int(capacity), int(key_dim), n, ctypes.cast(dts, ctypes.c_void_p), ctypes.cast(els, ctypes.c_void_p),
                int(n_insert), float(distinct_ratio), ctypes.byref(alloc.struct), _stream(), ctypes.byref(out),

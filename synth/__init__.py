@@ -20,6 +20,8 @@ model, extended to 10M keys):
                 batch for value rows of 2^j floats (Setup 1's sweep)
   setup1        n int32x3 keys at distinct ratio rho and a 50%-hit find
                 batch (Setup 1's capacities 10^3..10^6, rho in {0.1, 0.99})
+  setup2        n scalar int32 keys at distinct ratio rho and a 50%-hit find
+                batch (Setup 2 of Sec. 5.2)
   batched       64 maps with log-uniform distinct counts in [1e3, 1e6]
   served        request stream over a 318^3 key universe
 """
@@ -142,6 +144,20 @@ def cube_for_ratio(n, rho, dims=3):
         else:
             hi = x
     return max(2, int(round((n / (0.5 * (lo + hi))) ** (1.0 / dims))))
+
+
+def setup2(n, rho, seed=11):
+    """Setup 2 of Sec. 5.2 at one (c, rho): n int32 scalar keys uniform in
+    [0, L) with L sized for distinct ratio rho, and n finds, half drawn from
+    the inserted keys and half from [L, 2L)."""
+    rng = np.random.default_rng([seed, n, int(round(rho * 100))])
+    side = cube_for_ratio(n, rho, dims=1)
+    keys = rng.integers(0, side, size=(n, 1), dtype=np.int32)
+    half = n // 2
+    present = keys[rng.integers(0, n, size=half)]
+    absent = rng.integers(side, 2 * side, size=(n - half, 1), dtype=np.int32)
+    find_keys = np.concatenate([present, absent])[rng.permutation(n)]
+    return dict(keys=keys, find_keys=np.ascontiguousarray(find_keys), side=side)
 
 
 def setup1(n, rho, seed=10):

@@ -205,8 +205,8 @@ def test_batched_arrival_failure_runs_op_by_op(ash, monkeypatch):
     """When the blocks of the persistent launch cannot all run at once, they
     leave before touching any map and the call runs the same work op by op,
     with the oracle's results.  The condition is forced from the host:
-    ASH_BATCHED_ARRIVAL_SPINS=0 makes the first block to arrive give up at
-    once, and every kernel still exits normally."""
+    ASH_BATCHED_FORCE_ARRIVAL_FAILURE=1 makes the blocks give up without
+    counting themselves in, and every kernel still exits normally."""
     from paper_2110_00511_amd import _lib as L
     lib = L.load()
     rng = np.random.default_rng(48)
@@ -215,11 +215,11 @@ def test_batched_arrival_failure_runs_op_by_op(ash, monkeypatch):
     oracles = [OracleMap(2 * u, 3, [(np.float32, 8)]) for u in sizes]
     run_round(ash, maps, oracles, [make_case(rng, u) for u in sizes], True)  # fused, caches the grid
     before = lib.ash_batched_fallbacks()
-    monkeypatch.setenv("ASH_BATCHED_ARRIVAL_SPINS", "0")
-    print("case: batched launch with a zero arrival bound", flush=True)
+    monkeypatch.setenv("ASH_BATCHED_FORCE_ARRIVAL_FAILURE", "1")
+    print("case: batched launch with a forced arrival failure", flush=True)
     run_round(ash, maps, oracles, [make_case(rng, max(u // 3, 1)) for u in sizes], True)
     assert lib.ash_batched_fallbacks() == before + 1
-    monkeypatch.delenv("ASH_BATCHED_ARRIVAL_SPINS")
+    monkeypatch.delenv("ASH_BATCHED_FORCE_ARRIVAL_FAILURE")
     check_maps(maps, oracles)
     assert [m.device_status() for m in maps] == [0, 0, 0, 0]
     run_round(ash, maps, oracles, [make_case(rng, max(u // 5, 1)) for u in sizes], True)  # fused again

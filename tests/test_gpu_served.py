@@ -179,21 +179,27 @@ def test_served_benchmark_shape(ash):
     preloaded with f32x8 rows, one lane per key (g = 1, W = 4, max load
     0.5), and the server settings it times (at most 256 requests and 2^22
     positions per fused batch, 4 batches in flight).  The stream, all
-    arriving at once: 200 requests from the benchmark's distribution (60%
+    arriving at once: 60 requests from the benchmark's distribution (60%
     find / 30% insert / 10% erase, sizes log-uniform in [256, 2^20], keys
     uniform over the 318^3 universe), then 300 consecutive small finds, 300
     consecutive small inserts and 40 erases (so fused batches carry 256
-    requests), then 100 more benchmark requests.  Every request's indices,
-    masks and gathered rows must equal the oracle replaying the stream one
-    request after another, and afterwards the heap, t, the active indices,
-    k^B and v^B."""
+    requests), then 40 more benchmark requests: about 15M key operations.
+    The preload is inserted in sorted key order (the same key set as the
+    benchmark's; only the indices it receives differ), which keeps the
+    oracle's 20M inserts to under a minute.  Every request's indices, masks
+    and gathered rows must equal the oracle replaying the stream one request
+    after another, and afterwards the heap, t, the active indices, k^B and
+    v^B."""
     import synth
-    w = synth.served(n_requests=300)
+    w = synth.served(n_requests=100)
+    order = np.lexsort(w["preload_keys"].T[::-1])
+    pk = np.ascontiguousarray(w["preload_keys"][order])
+    pv = np.ascontiguousarray(w["preload_values"][order])
     rng = np.random.default_rng(73)
     side, ch = w["side"], w["channels"]
     reqs = []
-    for i in range(300):
-        if i == 200:  # runs of one kind long enough to fill fused batches
+    for i in range(100):
+        if i == 60:  # runs of one kind long enough to fill fused batches
             for kind, count, hi in ((FIND, 300, 4096), (INSERT, 300, 8192), (ERASE, 40, 4096)):
                 for _ in range(count):
                     n = int(np.exp(rng.uniform(np.log(256), np.log(hi))))
@@ -204,13 +210,12 @@ def test_served_benchmark_shape(ash):
         reqs.append((int(w["kinds"][i]), keys, vals))
     total = sum(len(k) for _, k, _ in reqs)
     print(f"case: served benchmark shape, {len(reqs)} requests, {total} positions, "
-          f"preload {len(w['preload_keys'])}", flush=True)
+          f"preload {len(pk)}", flush=True)
     cfg = dict(fuse=True, max_fused=256, max_batch=1 << 22, in_flight=4)
     tuning = dict(probe_group=1, bucket_width=4, max_load=0.5)
-    m, outs, lat, sts, stats = run_served(ash, w["capacity"], (w["preload_keys"], w["preload_values"]), reqs,
-                                          np.zeros(len(reqs)), channels=ch, tuning=tuning, **cfg)
+    m, outs, lat, sts, stats = run_served(ash, w["capacity"], (pk, pv), reqs, np.zeros(len(reqs)), channels=ch,
+                                          tuning=tuning, **cfg)
     print(f"served: {stats}", flush=True)
     assert np.all(sts == 0) and np.all(lat >= 0)
     assert stats["largest"] == 256  # the long runs filled fused batches
-    check_against_oracle(w["capacity"], (w["preload_keys"], w["preload_values"]), reqs, m, outs, channels=ch,
-                         values=True)
+    check_against_oracle(w["capacity"], (pk, pv), reqs, m, outs, channels=ch, values=True)
