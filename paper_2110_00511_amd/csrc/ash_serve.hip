@@ -15,10 +15,11 @@
 // to `in_flight` batches are queued on the device while the worker forms the
 // next one, so arrivals overlap with device work.
 //
-// The host never waits for the device to learn t: every batch ends with an
-// asynchronous copy of the map's counters into pinned memory, and the bound
-// the worker uses is the last retired batch's exact counters plus what the
-// batches still in flight may add (their insert positions).
+// The host never waits for the device to learn t: the last tile of every
+// insert or erase commit writes the map's counters to a host-mapped mirror
+// (no copy is queued), the completion thread reads the mirror when such a
+// batch retires, and the bound the worker uses is those counters plus what
+// the batches still in flight may add (their insert positions).
 #include <hip/hip_runtime.h>
 
 #include <chrono>

@@ -363,31 +363,25 @@ def _pack(keys):
     return (k[:, 0] << 42) | (k[:, 1] << 21) | k[:, 2]
 
 
-_CLOSED_FORMS = {}
-
-
-def _closed_forms(rho):
-    """numpy closed forms of the 10M-key workload at distinct ratio rho on a
-    fresh map (indices are ranks of first occurrences; erase winners are
-    the first occurrences in the erase batch, which push their indices in
-    batch order)."""
-    if rho not in _CLOSED_FORMS:
-        d = synth.plain_large(rho=rho, channels=1)
-        keys, fk, ek = d["keys"], d["find_keys"], d["erase_keys"]
-        pk = _pack(keys)
-        uniq, first = np.unique(pk, return_index=True)
-        rank_sorted = np.empty(len(uniq), np.int64)  # rank (insert order) of sorted distinct key j
-        rank_sorted[np.argsort(first)] = np.arange(len(first))
-        first = np.sort(first)
-        pf = _pack(fk)
-        pos = np.searchsorted(uniq, pf)
-        hit = (pos < len(uniq)) & (uniq[np.minimum(pos, len(uniq) - 1)] == pf)
-        pe = _pack(ek)
-        efirst = np.sort(np.unique(pe, return_index=True)[1])
-        erank = rank_sorted[np.searchsorted(uniq, pe[efirst])]  # every erase key was inserted
-        _CLOSED_FORMS[rho] = dict(first=first, uniq=uniq, rank_sorted=rank_sorted, pos=pos, hit=hit,
-                                  efirst=efirst, erank=erank, erased=np.isin(pf, pe))
-    return _CLOSED_FORMS[rho]
+def _closed_forms(d):
+    """numpy closed forms of one 10M-key workload `d` (synth.plain_large) on a
+    fresh map: indices are ranks of first occurrences; erase winners are the
+    first occurrences in the erase batch, which push their indices in batch
+    order."""
+    keys, fk, ek = d["keys"], d["find_keys"], d["erase_keys"]
+    pk = _pack(keys)
+    uniq, first = np.unique(pk, return_index=True)
+    rank_sorted = np.empty(len(uniq), np.int64)  # rank (insert order) of sorted distinct key j
+    rank_sorted[np.argsort(first)] = np.arange(len(first))
+    first = np.sort(first)
+    pf = _pack(fk)
+    pos = np.searchsorted(uniq, pf)
+    hit = (pos < len(uniq)) & (uniq[np.minimum(pos, len(uniq) - 1)] == pf)
+    pe = _pack(ek)
+    efirst = np.sort(np.unique(pe, return_index=True)[1])
+    erank = rank_sorted[np.searchsorted(uniq, pe[efirst])]  # every erase key was inserted
+    return dict(first=first, uniq=uniq, rank_sorted=rank_sorted, pos=pos, hit=hit, efirst=efirst, erank=erank,
+                erased=np.isin(pf, pe))
 
 
 @pytest.mark.parametrize("rho", [0.1, 0.5, 0.99])
@@ -401,7 +395,7 @@ def test_plain_large_properties(ash, rho, channels):
     print(f"case: plain 10M rho={rho} C={channels}", flush=True)
     d = synth.plain_large(rho=rho, channels=channels)
     keys, vals = d["keys"], d["values"]
-    cf = _closed_forms(rho)
+    cf = _closed_forms(d)
     first = cf["first"]
     m = ash.HashMap(d["capacity"], 3, [(torch.float32, channels)])
     gi, gm = m.insert(dev(keys), [dev(vals)])
