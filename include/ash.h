@@ -290,6 +290,22 @@ ash_status_t ash_voxelize(const float* points, int64_t n, float voxel,
                           int32_t* out_voxel_counts, int64_t* out_n_voxels,
                           const ash_allocator_t* allocator, void* stream);
 
+/* ash_voxelize without any allocation, for callers that cannot allocate
+ * device memory (code under stream capture, tight per-frame loops, harnesses
+ * that forbid hipMalloc).  Same arguments, checks and outputs as
+ * ash_voxelize, bit for bit; the workspace is a fixed device array inside the
+ * library (38 MiB per GPU, held from library load until the process ends),
+ * so n is limited to 1,048,576 points: a larger n returns ASH_E_UNSUPPORTED
+ * with nothing launched.  Every call on one GPU shares that array, and each
+ * call rewrites what it needs (table, counters, flags) before use: calls
+ * that overlap on one GPU (different streams or host threads) race and must
+ * be serialized by the caller.  Calls no hipMalloc, hipFree or allocator.
+ * Synchronizes. */
+ash_status_t ash_voxelize_noalloc(const float* points, int64_t n, float voxel,
+                                  int32_t* out_point_voxel, int32_t* out_voxel_keys,
+                                  int32_t* out_voxel_counts, int64_t* out_n_voxels,
+                                  void* stream);
+
 /* Blocks of the persistent batched launch for maps of this key_dim on the
  * current device: the occupancy the runtime reports (*out_reported, blocks per
  * CU times CUs) and the count the device was seen to run all at once

@@ -92,6 +92,7 @@ SIGNATURES = {
     "ash_heap_buffer": (ST, [P, ctypes.POINTER(P)]),
     "ash_device_status": (ST, [P, P]),
     "ash_voxelize": (ST, [P, I64, ctypes.c_float, P, P, P, ctypes.POINTER(I64), P, P]),
+    "ash_voxelize_noalloc": (ST, [P, I64, ctypes.c_float, P, P, P, ctypes.POINTER(I64), P]),
     "ash_batched": (ST, [ctypes.POINTER(AshBatchOp), I32, I32, P]),
     "ash_autotune": (ST, [I64, I32, I32, P, P, I64, ctypes.c_double, P, P, ctypes.POINTER(AshTuning),
                           ctypes.POINTER(ctypes.c_double)]),

@@ -798,9 +798,58 @@ ash_status_t voxelize_args(const float* points, int64_t n, float voxel, int32_t*
   return ASH_OK;
 }
 
+// Workspace of ash_voxelize_noalloc: a file-scope device array of which each
+// GPU holds its own copy (at its own address) until the process ends.  Host
+// code never passes the array's name to a kernel or a copy (on the host it is
+// a stand-in, not a device address); it uses the address that
+// hipGetSymbolAddress returns on each device, taken once per device with that
+// device current and kept in g_scratch_at.  Every call on one GPU shares the
+// array, so calls that overlap on one GPU race.
+constexpr int64_t kNoAllocVoxelPoints = 1 << 20;
+constexpr size_t kNoAllocVoxelBytes = 38ull << 20;  // voxel_work(2^20 points) takes 37.1 MiB
+__device__ __align__(256) uint8_t scratch[kNoAllocVoxelBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t* g_scratch_at[kMaxDevices] = {};
+
+ash_status_t scratch_address(uint8_t** out) {
+  int dev = 0;
+  ASH_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return ASH_E_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_at[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return ASH_E_DEVICE;
+    g_scratch_at[dev] = (uint8_t*)p;
+  }
+  *out = g_scratch_at[dev];
+  return ASH_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+ash_status_t ash_voxelize_noalloc(const float* points, int64_t n, float voxel, int32_t* out_point_voxel,
+                                  int32_t* out_voxel_keys, int32_t* out_voxel_counts, int64_t* out_n_voxels,
+                                  void* stream) {
+  ASH_TRY(voxelize_args(points, n, voxel, out_point_voxel, out_voxel_keys, out_voxel_counts, out_n_voxels));
+  if (n > kNoAllocVoxelPoints) return ASH_E_UNSUPPORTED;
+  if (n == 0) {
+    *out_n_voxels = 0;
+    return ASH_OK;
+  }
+  VoxelWork w;
+  ASH_TRY(voxel_work(n, &w));
+  if (w.bytes > kNoAllocVoxelBytes) return ASH_E_UNSUPPORTED;
+  uint8_t* base = nullptr;
+  ASH_TRY(scratch_address(&base));
+  // voxelize_run writes every part of the workspace that must start in a
+  // known state (table, status words, lost bytes, counters) with kernels
+  return voxelize_run(points, n, voxel, out_point_voxel, out_voxel_keys, out_voxel_counts, out_n_voxels, w, base,
+                      (hipStream_t)stream);
+}
 
 ash_status_t ash_voxelize(const float* points, int64_t n, float voxel, int32_t* out_point_voxel,
                           int32_t* out_voxel_keys, int32_t* out_voxel_counts, int64_t* out_n_voxels,
