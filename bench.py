@@ -16,8 +16,10 @@ positions of one call, over the summed average durations of its kernels.
 `accounting` gives insert, find and erase under the payload and granule
 accountings (g = 128 and g = 64).  `traffic` is the L2-to-fabric bytes per
 insert measured with rocprofv3 counters on the same sources and workload
-(null otherwise).  `served` runs the served map beside the plain path:
-offered loads are 0.5x and 0.9x of the plain path's measured throughput.
+(null otherwise).  `served` runs the served map beside the plain path on
+the served request stream: the plain path's mixed throughput (each request
+a direct call, back to back on one stream), the server's burst capacity,
+and offered loads of 0.5x and 0.9x of that plain-path throughput.
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 3] [--rho 0.5] [--channels 8]
 """
@@ -93,30 +95,36 @@ def cpu_model():
     return None
 
 # HBM bytes per launch at the default workload, from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE runs scaled by what they read for a 256 MiB copy (fetch x1.9998,
-# write x1.0000).  They hold for the kernel sources with these SHA-256 digests
-# only: traffic is reported as null for any other sources or workload.
+# WRITE_SIZE runs scaled by what they read for the library's streaming copy of
+# 128 MiB (fetch x1.9996, write x1.0000).  They hold for the kernel sources
+# with these SHA-256 digests only: traffic is reported as null for any other
+# sources or workload.
 MEASURED_TRAFFIC = {
-    "claim": 2.4238e9,
-    "commit": 0.9230e9,
-    "find": 1.4430e9,
+    "claim": 2.4236e9,
+    "commit": 0.9229e9,
+    "find": 1.4428e9,
     "erase_mark": 0.8949e9,
     "erase_commit": 0.1803e9,
 }
 # The same for the neighbor search (radius 1 over the 4.8M surface cells,
-# one lane per key, W = 4, max load 0.5, queries in first-appearance order).
+# one lane per key, W = 4, max load 0.5, queries in first-appearance order),
+# taken on earlier kernel sources (their digests below).
 MEASURED_TRAFFIC_NEIGHBORS = 18.53e9
-MEASURED_SOURCES = {
+MEASURED_SOURCES_NEIGHBORS = {
     "ash_kernels.hip": "9aa07fbde7f01ef85767eb7069f9ff6269e8ec208ad736352051de68960ad34e",
     "ash_device.hpp": "ba74484c956976bcc00990e393b059cba2fda0194102c9a8e5ad03301a162bdc",
 }
+MEASURED_SOURCES = {
+    "ash_kernels.hip": "3031dedf7ad83fd10975e91925bbd764bd4c37c955279e8f0b23dc660924ddc9",
+    "ash_device.hpp": "5d73dcd29a226ed87f8f0a7b83b887da26247d80f16b25c7603da9ac1298343a",
+}
 
 
-def sources_measured():
+def sources_measured(digests=None):
     """True when the kernel sources are the ones the counters were taken on."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_2110_00511_amd", "csrc")
-    for name, digest in MEASURED_SOURCES.items():
+    for name, digest in (digests or MEASURED_SOURCES).items():
         with open(os.path.join(csrc, name), "rb") as f:
             if hashlib.sha256(f.read()).hexdigest() != digest:
                 return False
@@ -177,7 +185,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=2_000_000,
                     help="positions of the workload the oracle runs for cpu_baseline (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="after the timed steps, copy 256 MiB once (reference kernel for byte counters)")
+                    help="after the timed steps, copy 128 MiB once with the library's streaming copy (reference kernel for byte counters)")
     ap.add_argument("--workload", default="plain",
                     choices=["plain", "batched", "voxelize", "served", "neighbors", "values", "large", "access",
                              "setup1", "construct", "ablation"],
@@ -202,8 +210,10 @@ def main():
     ap.add_argument("--served-in-flight", type=int, default=4, help="served: device batches queued at once")
     ap.add_argument("--served-max-batch", type=int, default=1 << 22, help="served: positions per fused batch")
     ap.add_argument("--served-basis-mops", type=float, default=0.0,
-                    help="served: offered loads are fractions of this rate (0: the server's burst capacity)")
+                    help="served: offered loads are fractions of this rate (0: the plain path's mixed throughput)")
     ap.add_argument("--no-served", action="store_true", help="plain: skip the served-map leg of the bench line")
+    ap.add_argument("--served-burst-only", action="store_true",
+                    help="served: only the burst run (every request waiting), e.g. for a kernel trace of it")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU sharding is a design note only"}))
@@ -287,11 +297,17 @@ def main():
     kernels = m.profile_collect()
     m.profile(False)
     if args.copy_calibration:
-        a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda").fill_(1)
-        b = torch.empty_like(a)
+        # A kernel of known traffic for the counter runs: the library's
+        # streaming copy of a 256 MiB buffer's first half onto its second
+        # (128 MiB read, 128 MiB written).  (torch's device-to-device copy
+        # may run on a copy engine, which the counters do not see.)
+        cal = torch.ones(256 << 20, dtype=torch.uint8, device="cuda")
         torch.cuda.synchronize()
-        b.copy_(a)
+        cms = ctypes.c_double()
+        L.check(lib.ash_access_bench(L.ASH_ACC_STREAM_COPY, P(cal.data_ptr()), cal.numel(), 16, 0, 1,
+                                     ctypes.byref(cms), sp), "calibration copy")
         torch.cuda.synchronize()
+        del cal
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     inline = "values" not in kernels  # value rows copied inside the commit
     ops = n + nf + ne
@@ -378,7 +394,7 @@ def main():
 
     served = None
     if not args.no_served:
-        served = served_leg(args, value * 1e6)
+        served = served_leg(args)
 
     out = {
         "metric": "Mops/s insert+find (10M int32×3 keys) & %HBM peak; served p50/p99 latency",
@@ -1122,7 +1138,7 @@ def bench_neighbors(args):
     per_lookup = READ_LINE + 4 + 1 + 12.0 / k
     kern_s = outs["kernel_ms"] / 1e3
     nb_traffic = None
-    if (sources_measured() and args.query_order == "given" and args.max_load == 0.5
+    if (sources_measured(MEASURED_SOURCES_NEIGHBORS) and args.query_order == "given" and args.max_load == 0.5
             and (args.neighbors_probe_group, args.neighbors_bucket_width) == (1, 4)):
         nb_traffic = round(MEASURED_TRAFFIC_NEIGHBORS / 1e9, 2)
     achieved = per_lookup * n * k / kern_s / 1e9
@@ -1214,6 +1230,29 @@ class ServedWorkload:
                     p99_ms=float(np.percentile(lat, 99) * 1e3), span_s=span, batches=st["batches"],
                     largest_batch_requests=st["largest"], requests=count, ops=ops, failed=int((sts != 0).sum()))
 
+    def run_plain(self, count):
+        """The plain single-map path on the same stream: the first `count`
+        requests as direct ash_insert / ash_find / ash_erase calls on one
+        stream, one after another in arrival order, no server; returns the
+        throughput from the first call to the end of the last one."""
+        import torch
+
+        from paper_2110_00511_amd import _lib as L
+        lib = L.load()
+        sp = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        m = self.m._m
+        calls = {0: lambda r: lib.ash_find(m, r.keys, r.n, r.out_idx, r.out_mask, None, sp),
+                 1: lambda r: lib.ash_insert(m, r.keys, r.n, r.values, r.out_idx, r.out_mask, sp),
+                 2: lambda r: lib.ash_erase(m, r.keys, r.n, r.out_mask, sp)}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for r in self.reqs[:count]:
+            L.check(calls[r.kind](r), "plain-path request")
+        torch.cuda.synchronize()
+        span = time.perf_counter() - t0
+        ops = int(self.sizes[:count].sum())
+        return dict(ops_per_s=ops / span, span_s=span, requests=count, ops=ops)
+
     def close(self):
         self.m.close()
 
@@ -1222,18 +1261,22 @@ def _rounded(d):
     return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}
 
 
-def served_leg(args, plain_ops_per_s):
-    """The served map beside the plain path: its burst capacity (every
-    request waiting), then the stream offered at 0.5x and 0.9x of the plain
-    path's measured mixed throughput, fused and one request per batch."""
+def served_leg(args):
+    """The served map beside the plain path on the same request stream: the
+    plain path's mixed throughput (every request a direct call, one after
+    another on one stream), the server's burst capacity (every request
+    waiting), then the stream offered at 0.5x and 0.9x of the plain path's
+    mixed throughput, fused and one request per batch."""
     work = ServedWorkload(args, args.requests)
     try:
+        plain = work.run_plain(len(work.reqs))
+        basis = plain["ops_per_s"]
         cal = work.run(None, True, min(len(work.reqs), 5000))
-        out = {"offered_load_basis_Mops": round(plain_ops_per_s / 1e6, 1),
+        out = {"plain_path_mixed_Mops": round(basis / 1e6, 1), "offered_load_basis": "plain_path_mixed_Mops",
                "burst_capacity_Mops": round(cal["ops_per_s"] / 1e6, 1)}
         for load in (0.5, 0.9):
             for fuse in (True, False):
-                r = work.run(load * plain_ops_per_s, fuse, len(work.reqs))
+                r = work.run(load * basis, fuse, len(work.reqs))
                 out[f"{'fused' if fuse else 'unfused'}_{load}x"] = _rounded(
                     {"Mops": r["ops_per_s"] / 1e6, "p50_ms": r["p50_ms"], "p99_ms": r["p99_ms"],
                      "span_s": r["span_s"], "batches": r["batches"], "largest_batch_requests":
@@ -1251,14 +1294,25 @@ def served_leg(args, plain_ops_per_s):
 
 def bench_served(args):
     """Served map on its own: burst capacity, then the stream at 0.5x and
-    0.9x of the burst capacity (or of --served-basis-mops), fused and one
-    request per batch."""
+    0.9x of the plain path's mixed throughput on the same stream (or of
+    --served-basis-mops), fused and one request per batch."""
     import torch
     torch.cuda.set_device(0)
     work = ServedWorkload(args, args.requests)
     cal = work.run(None, True, min(len(work.reqs), 5000))  # burst: everything waiting, the server's capacity
     cap = cal["ops_per_s"]
-    basis = args.served_basis_mops * 1e6 if args.served_basis_mops else cap
+    if args.served_burst_only:
+        print(json.dumps({"metric": "served map burst capacity (every request waiting)",
+                          "value": round(cap / 1e6, 1), "unit": "Mops/s", "n_gpus": 1, "higher_is_better": True,
+                          "dtype": "int32", "data": "synthetic", "burst": _rounded(cal)}), flush=True)
+        work.close()
+        return
+    plain = None
+    if args.served_basis_mops:
+        basis = args.served_basis_mops * 1e6
+    else:
+        plain = work.run_plain(len(work.reqs))
+        basis = plain["ops_per_s"]
     out = {}
     for load in (0.5, 0.9):
         out[f"fused_{load}"] = work.run(load * basis, True, len(work.reqs))
@@ -1272,6 +1326,7 @@ def bench_served(args):
         "config": {"workload": f"capacity 2^25, 20M preloaded keys, f32x8 values, {len(work.reqs)} Poisson requests "
                                "(60% find / 30% insert / 10% erase, sizes log-uniform in [256, 2^20])",
                    "burst_capacity_Mops": round(cap / 1e6, 1), "offered_load_basis_Mops": round(basis / 1e6, 1),
+                   "offered_load_basis": "given" if plain is None else "plain path, same stream, back to back",
                    "mean_request_ops": round(work.mean_ops),
                    "max_load": args.served_max_load, "probe_group": args.served_probe_group,
                    "bucket_width": args.served_bucket_width, "in_flight": args.served_in_flight,

@@ -496,6 +496,24 @@ ash_status_t ash_find(ash_map_t m, const int32_t* keys, int64_t n, int32_t* out_
       if (!out_values[j]) return ASH_E_INVALID;
     vs = make_values(m, nullptr, out_values, false);
   }
+  uint32_t row_total = 0;
+  for (int j = 0; j < vs.n; ++j) row_total += vs.row_bytes[j];
+  if (vs.n > 0 && find_rows_apart(row_total, n)) {
+    // Long rows move in a pass of their own, sized by the bytes to copy (the
+    // find's blocks alone leave most of the chip idle when n is small).
+    int32_t* idx = out_idx;
+    if (!idx) {
+      ASH_TRY(ensure_scratch(m, n, st));
+      idx = m->aux;
+    }
+    ValueSet none;
+    std::memset(&none, 0, sizeof(none));
+    ASH_HIP(timed(m, "find", st, [&] {
+      return ash::launch_find(m->key_dim, m->G, m->W, m->ref(), keys, (uint32_t)n, idx, out_mask, none, st);
+    }));
+    ASH_HIP(timed(m, "gather", st, [&] { return ash::launch_gather_rows(vs, idx, (uint32_t)n, (uint32_t)m->c, st); }));
+    return ASH_OK;
+  }
   ASH_HIP(timed(m, "find", st, [&] { return ash::launch_find(m->key_dim, m->G, m->W, m->ref(), keys, (uint32_t)n, out_idx, out_mask, vs, st); }));
   return ASH_OK;
 }

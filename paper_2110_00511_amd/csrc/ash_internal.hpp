@@ -21,6 +21,20 @@ namespace ash_host {
 // after the commit instead of inside it (measured: 4 and 32 B rows copy
 // faster inside, 128 B rows 10-15% faster on their own).
 constexpr uint32_t kSplitRowBytes = 64;
+// Whether a find copies the hits' value rows (row_bytes per key over all
+// value buffers) in a pass of its own after the lookup instead of inside
+// it.  The find's blocks copy the rows of their own tiles, which overlaps the
+// copy with other blocks' probes but leaves most of the chip idle when there
+// are few tiles; the separate pass is sized by the bytes to copy.  Measured
+// on int32x3 maps with c keys and c finds (half hits), GPU time per find:
+//   16 KB rows: 26 against 153 us at c = 10^3, 3.16 against 3.38 ms at 10^6;
+//   4 KB rows: 24 against 42 us at 10^3, 77-114 against 80-144 us at 10^5,
+//              but 0.90 against 0.85 ms at 10^6;
+//   2 KB rows: 23-25 against 25-31 us at 10^3, 28-31 against 27-30 at 10^4;
+//   1 KB rows: slower split at every c (23 against 16 us at 10^3).
+inline bool find_rows_apart(uint32_t row_bytes, int64_t n) {
+  return row_bytes >= 16384 || (row_bytes >= 4096 && n <= (1 << 18)) || (row_bytes >= 2048 && n <= (1 << 12));
+}
 
 // Voxelization drops duplicate voxels within each block of points in LDS
 // before probing (ASH_F_LDS_DEDUP for its internal set).

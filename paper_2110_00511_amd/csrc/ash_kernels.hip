@@ -780,6 +780,48 @@ __global__ __launch_bounds__(kBlock) void k_scatter_values(const uint32_t* __res
   }
 }
 
+// Value rows of a find's hits, after the find: dst row p = src row idx[p]
+// for every p whose idx is a buffer index; rows of misses (idx -1) stay
+// untouched.  A pass over n * units items sized by the row bytes keeps the
+// whole chip copying even when n is small and rows are long, which a copy
+// by the find's own blocks (one block per tile of positions) does not.
+// Each thread takes U units a grid stride apart and loads them all before
+// storing any.
+template <typename V, int U>
+__global__ __launch_bounds__(kBlock) void k_gather_rows(const int32_t* __restrict__ idx,
+                                                        const uint8_t* __restrict__ src, uint8_t* __restrict__ dst,
+                                                        uint32_t row_bytes, uint32_t units_log2, uint32_t n,
+                                                        uint32_t cap) {
+  const uint32_t units = row_bytes / (uint32_t)sizeof(V);
+  const uint64_t items = (uint64_t)n * units;
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  for (uint64_t e0 = (uint64_t)blockIdx.x * kBlock + threadIdx.x; e0 < items; e0 += stride * U) {
+    V v[U];
+    V* to[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      to[k] = nullptr;
+      const uint64_t e = e0 + (uint64_t)k * stride;
+      if (e >= items) continue;
+      uint32_t p, c;
+      if (units_log2 != 0xFFu) {
+        p = (uint32_t)(e >> units_log2);
+        c = (uint32_t)e & (units - 1u);
+      } else {
+        p = (uint32_t)(e / units);
+        c = (uint32_t)(e - (uint64_t)p * units);
+      }
+      const int32_t i = idx[p];
+      if (i < 0 || (uint32_t)i >= cap) continue;  // a miss
+      v[k] = reinterpret_cast<const V*>(src + (size_t)(uint32_t)i * row_bytes)[c];
+      to[k] = reinterpret_cast<V*>(dst + (size_t)p * row_bytes) + c;
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k)
+      if (to[k]) *to[k] = v[k];
+  }
+}
+
 template <int KD, bool kInline>
 __global__ __launch_bounds__(kBlock) void k_commit(TableRef tb, const int32_t* __restrict__ keys, uint32_t n,
                                                    const uint32_t* __restrict__ slot_of, uint8_t* __restrict__ lost,
@@ -1855,6 +1897,35 @@ hipError_t launch_scatter_values(const ValueSet& vs, const uint32_t* wlist, cons
       case 4: scatter_values_v<uint32_t>(vs, j, wlist, heap, meta, n, cap, grid, st); break;
       case 2: scatter_values_v<uint16_t>(vs, j, wlist, heap, meta, n, cap, grid, st); break;
       default: scatter_values_v<uint8_t>(vs, j, wlist, heap, meta, n, cap, grid, st); break;
+    }
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+template <typename V>
+static void gather_rows_v(const ValueSet& vs, int j, const int32_t* idx, uint32_t n, uint32_t cap, uint32_t grid,
+                          hipStream_t st) {
+  if (vs.row_bytes[j] >= kUnrollRowBytes)
+    hipLaunchKernelGGL((k_gather_rows<V, 4>), dim3(grid), dim3(kBlock), 0, st, idx, vs.src[j], vs.dst[j],
+                       vs.row_bytes[j], vs.units_log2[j], n, cap);
+  else
+    hipLaunchKernelGGL((k_gather_rows<V, 1>), dim3(grid), dim3(kBlock), 0, st, idx, vs.src[j], vs.dst[j],
+                       vs.row_bytes[j], vs.units_log2[j], n, cap);
+}
+
+hipError_t launch_gather_rows(const ValueSet& vs, const int32_t* idx, uint32_t n, uint32_t cap, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  for (int j = 0; j < vs.n && e == hipSuccess; ++j) {
+    const uint64_t units = vs.row_bytes[j] / vs.vec[j];
+    const uint32_t grid =
+        (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(((uint64_t)n * units + kBlock - 1) / kBlock, 16384));
+    switch (vs.vec[j]) {
+      case 16: gather_rows_v<uint4>(vs, j, idx, n, cap, grid, st); break;
+      case 8: gather_rows_v<uint2>(vs, j, idx, n, cap, grid, st); break;
+      case 4: gather_rows_v<uint32_t>(vs, j, idx, n, cap, grid, st); break;
+      case 2: gather_rows_v<uint16_t>(vs, j, idx, n, cap, grid, st); break;
+      default: gather_rows_v<uint8_t>(vs, j, idx, n, cap, grid, st); break;
     }
     e = hipGetLastError();
   }

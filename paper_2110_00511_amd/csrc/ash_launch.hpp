@@ -54,6 +54,9 @@ hipError_t launch_commit(int kd, const TableRef& tb, const int32_t* keys, uint32
 // Value rows of the insert whose commit just finished (n = its batch size).
 hipError_t launch_scatter_values(const ValueSet& vs, const uint32_t* wlist, const int32_t* heap, const Meta* meta,
                                  uint32_t n, uint32_t cap, hipStream_t st);
+// Value rows of a find's hits in a separate pass: out row p = v^B row idx[p]
+// for idx[p] >= 0 (vs as made for a find: src = v^B, dst = outputs).
+hipError_t launch_gather_rows(const ValueSet& vs, const int32_t* idx, uint32_t n, uint32_t cap, hipStream_t st);
 hipError_t launch_find(int kd, int g, int w, const TableRef& tb, const int32_t* keys, uint32_t n, int32_t* out_idx,
                        uint8_t* out_mask, const ValueSet& vs, hipStream_t st);
 // Finds of keys[q] + offsets[o] for q < n / k, o < k (n = queries * k

@@ -144,3 +144,39 @@ def test_value_sweep_full_size_16k_rows(ash):
         r1 = min(r0 + chunk, len(mp))
         assert not torch.any(fv[mp[r0:r1]].view(torch.int32)), "rows of misses were modified"
     assert m.device_status() == 0
+
+
+@pytest.mark.parametrize("n_find", [1, 777, 5000])
+@pytest.mark.parametrize("specs", [
+    [(np.float32, 1024), (np.uint8, 1030)],  # 4 KB and an odd 1030 B row: rows copied by a pass of their own
+    [(np.float32, 16)],                      # 64 B rows: copied by the find's own blocks
+], ids=["rows_apart", "rows_inside"])
+def test_find_rows_without_index_output(ash, n_find, specs):
+    """A find that gathers rows while the caller passes no index (or mask)
+    output: long rows for a small batch move in a pass of their own after the
+    lookup, which reads the indices back from the map's scratch; short rows
+    move inside the find.  The gathered rows must equal the oracle's bit for
+    bit, and rows of misses stay untouched."""
+    import ctypes
+
+    from paper_2110_00511_amd import _lib as L
+    rng = np.random.default_rng(95)
+    pair = Pair(ash, 6_000, 3, specs)
+    keys, vals = row_batch(rng, 4000, specs)
+    pair.insert(keys, vals)
+    fk = np.concatenate([keys[: n_find // 2], rng.integers(24, 40, size=(n_find - n_find // 2, 3), dtype=np.int32)])
+    fk = fk[rng.permutation(n_find)]
+    _, oi, om, oout = pair.orc.find(fk, gather=True, fill=0)
+    outs = [torch.full((n_find, e), 7, dtype=torch.float32 if dt == np.float32 else torch.uint8, device="cuda")
+            for dt, e in specs]
+    arr = (ctypes.c_void_p * len(outs))(*[o.data_ptr() for o in outs])
+    fkd = dev(fk)
+    lib = L.load()
+    L.check(lib.ash_find(pair.gpu._m, ctypes.c_void_p(fkd.data_ptr()), n_find, None, None,
+                         ctypes.cast(arr, ctypes.c_void_p), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)),
+            "ash_find")
+    hit = om == 1
+    for g, o in zip(outs, oout):
+        g = host(g)
+        assert np.array_equal(g[hit].view(np.uint8), o[hit].view(np.uint8))
+        assert np.all(g[~hit] == 7)
