@@ -108,23 +108,19 @@ MEASURED_TRAFFIC = {
 }
 # The same for the neighbor search (radius 1 over the 4.8M surface cells,
 # one lane per key, W = 4, max load 0.5, queries in first-appearance order),
-# taken on earlier kernel sources (their digests below).
+# on the same kernel sources.
 MEASURED_TRAFFIC_NEIGHBORS = 18.53e9
-MEASURED_SOURCES_NEIGHBORS = {
-    "ash_kernels.hip": "9aa07fbde7f01ef85767eb7069f9ff6269e8ec208ad736352051de68960ad34e",
-    "ash_device.hpp": "ba74484c956976bcc00990e393b059cba2fda0194102c9a8e5ad03301a162bdc",
-}
 MEASURED_SOURCES = {
     "ash_kernels.hip": "3031dedf7ad83fd10975e91925bbd764bd4c37c955279e8f0b23dc660924ddc9",
     "ash_device.hpp": "5d73dcd29a226ed87f8f0a7b83b887da26247d80f16b25c7603da9ac1298343a",
 }
 
 
-def sources_measured(digests=None):
+def sources_measured():
     """True when the kernel sources are the ones the counters were taken on."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_2110_00511_amd", "csrc")
-    for name, digest in (digests or MEASURED_SOURCES).items():
+    for name, digest in MEASURED_SOURCES.items():
         with open(os.path.join(csrc, name), "rb") as f:
             if hashlib.sha256(f.read()).hexdigest() != digest:
                 return False
@@ -297,17 +293,7 @@ def main():
     kernels = m.profile_collect()
     m.profile(False)
     if args.copy_calibration:
-        # A kernel of known traffic for the counter runs: the library's
-        # streaming copy of a 256 MiB buffer's first half onto its second
-        # (128 MiB read, 128 MiB written).  (torch's device-to-device copy
-        # may run on a copy engine, which the counters do not see.)
-        cal = torch.ones(256 << 20, dtype=torch.uint8, device="cuda")
-        torch.cuda.synchronize()
-        cms = ctypes.c_double()
-        L.check(lib.ash_access_bench(L.ASH_ACC_STREAM_COPY, P(cal.data_ptr()), cal.numel(), 16, 0, 1,
-                                     ctypes.byref(cms), sp), "calibration copy")
-        torch.cuda.synchronize()
-        del cal
+        counter_calibration()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     inline = "values" not in kernels  # value rows copied inside the commit
     ops = n + nf + ne
@@ -431,6 +417,25 @@ def main():
         "served": served,
     }
     print(json.dumps(out), flush=True)
+
+
+def counter_calibration():
+    """A kernel of known traffic for counter runs: the library's streaming
+    copy of a 256 MiB buffer's first half onto its second (128 MiB read,
+    128 MiB written).  (torch's device-to-device copy may run on a copy
+    engine, which the counters do not see.)"""
+    import torch
+
+    from paper_2110_00511_amd import _lib as L
+    lib = L.load()
+    cal = torch.ones(256 << 20, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    cms = ctypes.c_double()
+    L.check(lib.ash_access_bench(L.ASH_ACC_STREAM_COPY, ctypes.c_void_p(cal.data_ptr()), cal.numel(), 16, 0, 1,
+                                 ctypes.byref(cms), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)),
+            "calibration copy")
+    torch.cuda.synchronize()
+    del cal
 
 
 def _timed(fn, steps, warmup):
@@ -1118,6 +1123,8 @@ def bench_neighbors(args):
         return k, ms, float(mask.float().mean().item())
 
     k, ms, hit = run("radius", 1, args.steps, args.warmup, profile=True)
+    if args.copy_calibration:
+        counter_calibration()
     sweep = {"radius1": {"offsets": k, "ms": round(ms, 4), "Mlookups_per_s": round(n * k / ms / 1e3, 1),
                          "hit_rate": round(hit, 4)}}
     for kind, r in (("ring", 1), ("cube", 1), ("radius", 2)):
@@ -1138,7 +1145,7 @@ def bench_neighbors(args):
     per_lookup = READ_LINE + 4 + 1 + 12.0 / k
     kern_s = outs["kernel_ms"] / 1e3
     nb_traffic = None
-    if (sources_measured(MEASURED_SOURCES_NEIGHBORS) and args.query_order == "given" and args.max_load == 0.5
+    if (sources_measured() and args.query_order == "given" and args.max_load == 0.5
             and (args.neighbors_probe_group, args.neighbors_bucket_width) == (1, 4)):
         nb_traffic = round(MEASURED_TRAFFIC_NEIGHBORS / 1e9, 2)
     achieved = per_lookup * n * k / kern_s / 1e9
