@@ -226,8 +226,14 @@ ValueSet make_values(const ash_map* m, const void* const* src, void* const* dst,
 }
 
 ash_status_t insert_impl(ash_map* m, const int32_t* keys, int64_t n, const void* const* values, int32_t* out_idx,
-                         uint8_t* out_mask, hipStream_t st) {
-  ASH_TRY(check_keys(m, keys, n));
+                         uint8_t* out_mask, hipStream_t st, const RequestSource* rs) {
+  if (rs) {
+    if (!m || n < 0 || n > kMaxCount || !rs->d || rs->nreq < 1 || (m->flags & ASH_F_AUTOGROW) ||
+        (m->flags & ASH_F_LDS_DEDUP))
+      return ASH_E_INVALID;
+  } else {
+    ASH_TRY(check_keys(m, keys, n));
+  }
   if (n == 0) return ASH_OK;
   if (values) {
     for (int j = 0; j < m->n_values; ++j)
@@ -235,7 +241,8 @@ ash_status_t insert_impl(ash_map* m, const int32_t* keys, int64_t n, const void*
   }
   ValueSet vs;
   std::memset(&vs, 0, sizeof(vs));
-  if (values && m->n_values > 0) vs = make_values(m, values, nullptr, true);
+  if (rs) vs = rs->vs;
+  else if (values && m->n_values > 0) vs = make_values(m, values, nullptr, true);
   ASH_TRY(ensure_scratch(m, n, st));
   ASH_TRY(maybe_clean(m, n, st));
   // Keeping pending keys in their slots pays when most positions repeat a
@@ -255,6 +262,9 @@ ash_status_t insert_impl(ash_map* m, const int32_t* keys, int64_t n, const void*
     // the profile names the claim variant that ran (results are the same)
     const char* label = m->tombs_possible ? "claim_reuse" : (m->keyed ? "claim_keyed" : "claim");
     ASH_HIP(timed(m, label, st, [&] {
+      if (rs)
+        return ash::launch_claim_requests(m->key_dim, m->G, m->W, m->ref(), rs->d, rs->nreq, un, m->slot_of, m->lost,
+                                          m->partial, m->meta, st);
       return ash::launch_claim(m->key_dim, m->G, m->W, m->ref(), keys, un, m->slot_of, m->lost, m->partial, m->meta,
                                st);
     }));
@@ -270,6 +280,14 @@ ash_status_t insert_impl(ash_map* m, const int32_t* keys, int64_t n, const void*
     // rows are copied inside the commit.
     uint32_t row_total = 0;
     for (int j = 0; j < vs.n; ++j) row_total += vs.row_bytes[j];
+    if (rs) {
+      if (row_total >= kSplitRowBytes) return ASH_E_INVALID;  // request rows are copied inside the commit only
+      ASH_HIP(timed(m, "commit", st, [&] {
+        return ash::launch_commit_requests(m->key_dim, m->ref(), rs->d, rs->nreq, un, m->slot_of, m->lost, m->kB,
+                                           m->heap, (uint32_t)m->c, vs, m->meta, m->scan_status, check, silent, st);
+      }));
+      return ASH_OK;
+    }
     uint32_t* wlist = row_total >= kSplitRowBytes ? reinterpret_cast<uint32_t*>(m->aux) : nullptr;
     ASH_HIP(timed(m, "commit", st, [&] {  // its last tile also finalizes the insert
       return ash::launch_commit(m->key_dim, m->ref(), keys, un, m->slot_of, m->lost, m->kB, m->heap,
@@ -330,6 +348,39 @@ ash_status_t reset_state(ash_map* m, hipStream_t st) {
   m->live_ub = 0;
   m->used_ub = 0;
   m->tombs_possible = false;
+  return ASH_OK;
+}
+
+ash_status_t erase_impl(ash_map* m, const int32_t* keys, int64_t n, uint8_t* out_mask, hipStream_t st,
+                        const RequestSource* rs) {
+  if (rs) {
+    if (!m || n < 0 || n > kMaxCount || !rs->d || rs->nreq < 1) return ASH_E_INVALID;
+  } else {
+    ASH_TRY(check_keys(m, keys, n));
+  }
+  if (n == 0) return ASH_OK;
+  ASH_TRY(ensure_scratch(m, n, st));
+  const uint32_t un = (uint32_t)n;
+  if (++m->erase_epoch == 0) {  // epochs wrapped: start the owner entries afresh
+    ASH_HIP(ash::launch_fill_u32((uint32_t*)m->owner, 0u, (size_t)m->c * 2, st));
+    m->erase_epoch = 1;
+  }
+  const uint32_t epoch = m->erase_epoch;
+  ASH_HIP(timed(m, "erase_mark", st, [&] {
+    if (rs)
+      return ash::launch_erase_mark_requests(m->key_dim, m->G, m->W, m->ref(), rs->d, rs->nreq, un, epoch,
+                                             m->slot_of, m->aux, m->owner, m->lost, st);
+    return ash::launch_erase_mark(m->key_dim, m->G, m->W, m->ref(), keys, un, epoch, m->slot_of, m->aux, m->owner,
+                                  m->lost, st);
+  }));
+  m->tombs_possible = true;
+  ASH_HIP(timed(m, "erase_commit", st, [&] {  // its last tile also finalizes the erase
+    if (rs)
+      return ash::launch_erase_commit_requests(m->key_dim, m->ref(), rs->d, rs->nreq, un, m->slot_of, m->aux, m->lost,
+                                               m->heap, m->meta, m->scan_status, st);
+    return ash::launch_erase_commit(m->key_dim, m->ref(), un, m->slot_of, m->aux, m->lost, m->heap, out_mask, m->meta,
+                                    m->scan_status, st);
+  }));
   return ASH_OK;
 }
 
@@ -519,26 +570,7 @@ ash_status_t ash_find(ash_map_t m, const int32_t* keys, int64_t n, int32_t* out_
 }
 
 ash_status_t ash_erase(ash_map_t m, const int32_t* keys, int64_t n, uint8_t* out_mask, void* stream) {
-  ASH_TRY(check_keys(m, keys, n));
-  if (n == 0) return ASH_OK;
-  hipStream_t st = (hipStream_t)stream;
-  ASH_TRY(ensure_scratch(m, n, st));
-  const uint32_t un = (uint32_t)n;
-  if (++m->erase_epoch == 0) {  // epochs wrapped: start the owner entries afresh
-    ASH_HIP(ash::launch_fill_u32((uint32_t*)m->owner, 0u, (size_t)m->c * 2, st));
-    m->erase_epoch = 1;
-  }
-  const uint32_t epoch = m->erase_epoch;
-  ASH_HIP(timed(m, "erase_mark", st, [&] {
-    return ash::launch_erase_mark(m->key_dim, m->G, m->W, m->ref(), keys, un, epoch, m->slot_of, m->aux, m->owner,
-                                  m->lost, st);
-  }));
-  m->tombs_possible = true;
-  ASH_HIP(timed(m, "erase_commit", st, [&] {  // its last tile also finalizes the erase
-    return ash::launch_erase_commit(m->key_dim, m->ref(), un, m->slot_of, m->aux, m->lost, m->heap, out_mask, m->meta,
-                                    m->scan_status, st);
-  }));
-  return ASH_OK;
+  return erase_impl(m, keys, n, out_mask, (hipStream_t)stream);
 }
 
 ash_status_t ash_find_offsets(ash_map_t m, const int32_t* keys, int64_t n, const int32_t* offsets, int32_t n_offsets,

@@ -213,7 +213,21 @@ ash_status_t ensure_scratch(ash_map* m, int64_t n, hipStream_t st);
 // Rebuilds the slot table from the committed slots of m->table (m->nslots of
 // them), which it frees; live = number of committed slots.  Synchronizes.
 ash_status_t rebuild_table(ash_map* m, int64_t live, hipStream_t st, int64_t room_for = 0);
+// Keys of a fused served batch read from its requests' buffers: device
+// descriptors d[0..nreq) in arrival order; vs: the insert's value rows
+// (dst = v^B; the source rows come from the requests).
+struct RequestSource {
+  const ash::ReqDesc* d = nullptr;
+  int nreq = 0;
+  ValueSet vs;
+};
+// Insert of n keys from `keys` (with `values`), or, with rs, from the
+// requests rs->d (keys, values and outputs unused; rows must be copied inside
+// the commit, and the map may not grow automatically).
 ash_status_t insert_impl(ash_map* m, const int32_t* keys, int64_t n, const void* const* values, int32_t* out_idx,
-                         uint8_t* out_mask, hipStream_t st);
+                         uint8_t* out_mask, hipStream_t st, const RequestSource* rs = nullptr);
+// Erase of n keys from `keys`, or from the requests rs->d (out_mask unused).
+ash_status_t erase_impl(ash_map* m, const int32_t* keys, int64_t n, uint8_t* out_mask, hipStream_t st,
+                        const RequestSource* rs = nullptr);
 
 }  // namespace ash_host

@@ -637,6 +637,100 @@ __device__ __forceinline__ void finalize_map(Meta* m, uint32_t cap, int mode, in
   finalize_total(m, cap, mode, silent, check, total, n);
 }
 
+// Where a find's, commit's or erase's results go: batch-indexed outputs
+// (DirectOut), or the requests of a fused served batch (ReqOut).  put()
+// writes a position's index (kNoSlot for a miss or a loser) and mask; rows()
+// copies the value rows of a find tile's hits, given as (buffer index,
+// position) pairs.
+struct DirectOut {
+  int32_t* __restrict__ idx;
+  uint8_t* __restrict__ mask;
+  __device__ __forceinline__ void put(uint32_t p, uint32_t i) const {
+    const bool hit = i != kNoSlot;
+    if (idx) idx[p] = hit ? (int32_t)i : -1;
+    if (mask) mask[p] = hit ? 1 : 0;
+  }
+  __device__ __forceinline__ void rows(const ValueSet& vs, int j, const uint2* pairs, uint32_t count) const {
+    copy_rows(vs, j, pairs, count);
+  }
+};
+
+struct ReqOut {
+  const ReqDesc* __restrict__ d;
+  const int64_t* s_off;  // LDS
+  int nreq;
+  __device__ __forceinline__ void put(uint32_t p, uint32_t i) const {
+    const int r = request_of(s_off, nreq, p);
+    const size_t q = p - s_off[r];
+    const bool hit = i != kNoSlot;
+    if (d[r].out_idx) d[r].out_idx[q] = hit ? (int32_t)i : -1;
+    if (d[r].out_mask) d[r].out_mask[q] = hit ? 1 : 0;
+  }
+  template <typename V>
+  __device__ __forceinline__ void rows_t(const ValueSet& vs, int j, const uint2* pairs, uint32_t count) const {
+    const uint32_t row = vs.row_bytes[j];
+    const uint32_t units = row / (uint32_t)sizeof(V);
+    for (uint32_t e = threadIdx.x; e < count * units; e += blockDim.x) {
+      const uint32_t w = e / units;
+      const uint32_t c = e - w * units;
+      const uint2 pr = pairs[w];  // (buffer index, position)
+      const int r = request_of(s_off, nreq, pr.y);
+      uint8_t* dst = d[r].outv[j];
+      if (!dst) continue;
+      const V v = reinterpret_cast<const V*>(vs.src[j] + (size_t)pr.x * row)[c];
+      reinterpret_cast<V*>(dst + (size_t)(pr.y - s_off[r]) * row)[c] = v;
+    }
+  }
+  __device__ __forceinline__ void rows(const ValueSet& vs, int j, const uint2* pairs, uint32_t count) const {
+    switch (vs.vec[j]) {
+      case 16: rows_t<uint4>(vs, j, pairs, count); break;
+      case 8: rows_t<uint2>(vs, j, pairs, count); break;
+      case 4: rows_t<uint32_t>(vs, j, pairs, count); break;
+      case 2: rows_t<uint16_t>(vs, j, pairs, count); break;
+      default: rows_t<uint8_t>(vs, j, pairs, count); break;
+    }
+  }
+};
+
+
+// Where a commit's value rows come from: the batch's rows (DirectRowsIn, row p
+// of vs.src), or the requests of a fused served batch (ReqRowsIn: row p is
+// row p - off[r] of its request's values).  copy() moves the rows of a tile's
+// winners, given as (position, buffer index) pairs, to v^B.
+struct DirectRowsIn {
+  __device__ __forceinline__ void copy(const ValueSet& vs, int j, const uint2* pairs, uint32_t count) const {
+    copy_rows(vs, j, pairs, count);
+  }
+};
+
+struct ReqRowsIn {
+  const ReqDesc* __restrict__ d;
+  const int64_t* s_off;  // LDS
+  int nreq;
+  template <typename V>
+  __device__ __forceinline__ void copy_t(const ValueSet& vs, int j, const uint2* pairs, uint32_t count) const {
+    const uint32_t row = vs.row_bytes[j];
+    const uint32_t units = row / (uint32_t)sizeof(V);
+    for (uint32_t e = threadIdx.x; e < count * units; e += blockDim.x) {
+      const uint32_t w = e / units;
+      const uint32_t c = e - w * units;
+      const uint2 pr = pairs[w];  // (position, buffer index)
+      const int r = request_of(s_off, nreq, pr.x);
+      const V v = reinterpret_cast<const V*>(d[r].vals[j] + (size_t)(pr.x - s_off[r]) * row)[c];
+      reinterpret_cast<V*>(vs.dst[j] + (size_t)pr.y * row)[c] = v;
+    }
+  }
+  __device__ __forceinline__ void copy(const ValueSet& vs, int j, const uint2* pairs, uint32_t count) const {
+    switch (vs.vec[j]) {
+      case 16: copy_t<uint4>(vs, j, pairs, count); break;
+      case 8: copy_t<uint2>(vs, j, pairs, count); break;
+      case 4: copy_t<uint32_t>(vs, j, pairs, count); break;
+      case 2: copy_t<uint16_t>(vs, j, pairs, count); break;
+      default: copy_t<uint8_t>(vs, j, pairs, count); break;
+    }
+  }
+};
+
 // ---------------------------------------------------------------------------
 // Commit (insert / activate pass 2).  Winners are the candidates not marked
 // lost; they are ranked in batch order and take i = h[t + rank].  The lost
@@ -647,14 +741,13 @@ __device__ __forceinline__ void finalize_map(Meta* m, uint32_t cap, int mode, in
 // finalize in a separate pass over the winners only.  The block copy is a
 // dependent chain per tile, which costs little for short rows; the separate
 // pass keeps many more loads in flight and wins for long rows.
-template <int KD, bool kInline>
-__device__ __forceinline__ void commit_tile(const TableRef& tb, const int32_t* __restrict__ keys, uint32_t n,
-                                            uint32_t tile, const uint32_t* __restrict__ slot_of,
-                                            uint8_t* __restrict__ lost, int32_t* __restrict__ kB,
-                                            const int32_t* __restrict__ heap, uint32_t cap, const ValueSet& vs,
-                                            int32_t* __restrict__ out_idx, uint8_t* __restrict__ out_mask,
-                                            Meta* meta, uint64_t* __restrict__ status, int check,
-                                            uint32_t* __restrict__ wlist, int fin, TileLds& lds) {
+template <int KD, bool kInline, typename Src, typename Out, typename Rows>
+__device__ __forceinline__ void commit_tile_src(const TableRef& tb, const Src& src, const Out& out, const Rows& rows,
+                                                uint32_t n, uint32_t tile, const uint32_t* __restrict__ slot_of,
+                                                uint8_t* __restrict__ lost, int32_t* __restrict__ kB,
+                                                const int32_t* __restrict__ heap, uint32_t cap, const ValueSet& vs,
+                                                Meta* meta, uint64_t* __restrict__ status, int check,
+                                                uint32_t* __restrict__ wlist, int fin, TileLds& lds) {
   constexpr int S = SlotWords<KD>::value;
   uint2* s_pairs = lds.pairs;
   const uint32_t t0 = meta->t;
@@ -708,27 +801,35 @@ __device__ __forceinline__ void commit_tile(const TableRef& tb, const int32_t* _
     if (win[r] && t0 + prefix + rank[r] < cap) {
       const uint32_t i = (uint32_t)heap[t0 + prefix + rank[r]];
       int32_t k[KD];
+      src.load(p, k);
 #pragma unroll
-      for (int d = 0; d < KD; ++d) {
-        k[d] = keys[(size_t)p * KD + d];
-        kB[(size_t)i * KD + d] = k[d];
-      }
+      for (int d = 0; d < KD; ++d) kB[(size_t)i * KD + d] = k[d];
       store_slot<S>(tb.words + (size_t)slot[r] * S, committed_slot<KD, S>(k, i));
       if constexpr (kInline) s_pairs[rank[r]] = make_uint2(p, i);
       else if (wlist) wlist[prefix + rank[r]] = p;
-      if (out_idx) out_idx[p] = (int32_t)i;
-      if (out_mask) out_mask[p] = 1;
+      out.put(p, i);
     } else {
-      if (out_idx) out_idx[p] = -1;
-      if (out_mask) out_mask[p] = 0;
+      out.put(p, kNoSlot);
     }
   }
   if constexpr (kInline) {
     if (vs.n > 0 && !__syncthreads_or(bad)) {
-      for (int j = 0; j < vs.n; ++j) copy_rows(vs, j, s_pairs, total);
+      for (int j = 0; j < vs.n; ++j) rows.copy(vs, j, s_pairs, total);
     }
   }
   __syncthreads();  // LDS is reused by the next tile of a persistent block
+}
+
+template <int KD, bool kInline>
+__device__ __forceinline__ void commit_tile(const TableRef& tb, const int32_t* __restrict__ keys, uint32_t n,
+                                            uint32_t tile, const uint32_t* __restrict__ slot_of,
+                                            uint8_t* __restrict__ lost, int32_t* __restrict__ kB,
+                                            const int32_t* __restrict__ heap, uint32_t cap, const ValueSet& vs,
+                                            int32_t* __restrict__ out_idx, uint8_t* __restrict__ out_mask,
+                                            Meta* meta, uint64_t* __restrict__ status, int check,
+                                            uint32_t* __restrict__ wlist, int fin, TileLds& lds) {
+  commit_tile_src<KD, kInline>(tb, BatchKeys<KD>{keys}, DirectOut{out_idx, out_mask}, DirectRowsIn{}, n, tile,
+                               slot_of, lost, kB, heap, cap, vs, meta, status, check, wlist, fin, lds);
 }
 
 // Value rows of an insert's winners, after its finalize: the finalize left
@@ -845,60 +946,6 @@ __global__ void k_finalize(Meta* m, uint32_t cap, int mode, int silent, int chec
 // the first window that holds an EMPTY slot: a key is always claimed at the
 // first EMPTY slot of its sequence and slots never return to EMPTY outside a
 // rebuild.
-// Where a find's results go: batch-indexed outputs (DirectOut), or the
-// requests of a fused served batch (ReqOut).  put() writes a position's index
-// (kNoSlot for a miss) and mask; rows() copies the value rows of the tile's
-// hits, given as (buffer index, position) pairs.
-struct DirectOut {
-  int32_t* __restrict__ idx;
-  uint8_t* __restrict__ mask;
-  __device__ __forceinline__ void put(uint32_t p, uint32_t i) const {
-    const bool hit = i != kNoSlot;
-    if (idx) idx[p] = hit ? (int32_t)i : -1;
-    if (mask) mask[p] = hit ? 1 : 0;
-  }
-  __device__ __forceinline__ void rows(const ValueSet& vs, int j, const uint2* pairs, uint32_t count) const {
-    copy_rows(vs, j, pairs, count);
-  }
-};
-
-struct ReqOut {
-  const ReqDesc* __restrict__ d;
-  const int64_t* s_off;  // LDS
-  int nreq;
-  __device__ __forceinline__ void put(uint32_t p, uint32_t i) const {
-    const int r = request_of(s_off, nreq, p);
-    const size_t q = p - s_off[r];
-    const bool hit = i != kNoSlot;
-    if (d[r].out_idx) d[r].out_idx[q] = hit ? (int32_t)i : -1;
-    if (d[r].out_mask) d[r].out_mask[q] = hit ? 1 : 0;
-  }
-  template <typename V>
-  __device__ __forceinline__ void rows_t(const ValueSet& vs, int j, const uint2* pairs, uint32_t count) const {
-    const uint32_t row = vs.row_bytes[j];
-    const uint32_t units = row / (uint32_t)sizeof(V);
-    for (uint32_t e = threadIdx.x; e < count * units; e += blockDim.x) {
-      const uint32_t w = e / units;
-      const uint32_t c = e - w * units;
-      const uint2 pr = pairs[w];  // (buffer index, position)
-      const int r = request_of(s_off, nreq, pr.y);
-      uint8_t* dst = d[r].outv[j];
-      if (!dst) continue;
-      const V v = reinterpret_cast<const V*>(vs.src[j] + (size_t)pr.x * row)[c];
-      reinterpret_cast<V*>(dst + (size_t)(pr.y - s_off[r]) * row)[c] = v;
-    }
-  }
-  __device__ __forceinline__ void rows(const ValueSet& vs, int j, const uint2* pairs, uint32_t count) const {
-    switch (vs.vec[j]) {
-      case 16: rows_t<uint4>(vs, j, pairs, count); break;
-      case 8: rows_t<uint2>(vs, j, pairs, count); break;
-      case 4: rows_t<uint32_t>(vs, j, pairs, count); break;
-      case 2: rows_t<uint16_t>(vs, j, pairs, count); break;
-      default: rows_t<uint8_t>(vs, j, pairs, count); break;
-    }
-  }
-};
-
 template <int KD, int G, int WL, typename Src, typename Out = DirectOut>
 __device__ __forceinline__ void find_tile(const TableRef& tb, const Src& src, uint32_t n,
                                           uint32_t tile, uint32_t rounds, const Out& out, const ValueSet& vs,
@@ -990,24 +1037,22 @@ __global__ __launch_bounds__(kBlock) void k_find_offsets(TableRef tb, OffsetKeys
 // ~p is the lowest p -- so owner never needs clearing.  The returned value
 // tells each position whether it displaced an earlier holder (lost[holder]
 // = 1) or lost itself.
-template <int KD, int G, int WL>
-__global__ __launch_bounds__(kBlock) void k_erase_mark(TableRef tb, const int32_t* __restrict__ keys, uint32_t n,
-                                                       uint32_t rounds, uint32_t epoch,
-                                                       uint32_t* __restrict__ slot_of,
-                                                       int32_t* __restrict__ found_idx, uint64_t* __restrict__ owner,
-                                                       uint8_t* __restrict__ lost) {
+template <int KD, int G, int WL, typename Src>
+__device__ __forceinline__ void erase_mark_tile(const TableRef& tb, const Src& src, uint32_t n, uint32_t tile,
+                                                uint32_t rounds, uint32_t epoch, uint32_t* __restrict__ slot_of,
+                                                int32_t* __restrict__ found_idx, uint64_t* __restrict__ owner,
+                                                uint8_t* __restrict__ lost) {
   using Win = Window<KD, G, WL>;
   constexpr int S = Win::S;
   constexpr uint32_t kGroups = kBlock / G;
   const uint32_t sub = G == 1 ? 0u : (threadIdx.x & (G - 1));
   const uint32_t grp = threadIdx.x / G;
-  const uint32_t tile_base = blockIdx.x * kGroups * rounds;
+  const uint32_t tile_base = tile * kGroups * rounds;
   for (uint32_t r = 0; r < rounds; ++r) {
     const uint32_t p = tile_base + r * kGroups + grp;
     if (p >= n) break;
     int32_t k[KD];
-#pragma unroll
-    for (int d = 0; d < KD; ++d) k[d] = keys[(size_t)p * KD + d];
+    src.load(p, k);
     const uint64_t h = key_hash<KD>(k);
     uint32_t base = home_slot(tb, h);
     uint32_t idx = kNoSlot, where = kNoSlot;
@@ -1046,19 +1091,26 @@ __global__ __launch_bounds__(kBlock) void k_erase_mark(TableRef tb, const int32_
   }
 }
 
+template <int KD, int G, int WL>
+__global__ __launch_bounds__(kBlock) void k_erase_mark(TableRef tb, const int32_t* __restrict__ keys, uint32_t n,
+                                                       uint32_t rounds, uint32_t epoch,
+                                                       uint32_t* __restrict__ slot_of,
+                                                       int32_t* __restrict__ found_idx, uint64_t* __restrict__ owner,
+                                                       uint8_t* __restrict__ lost) {
+  erase_mark_tile<KD, G, WL>(tb, BatchKeys<KD>{keys}, n, blockIdx.x, rounds, epoch, slot_of, found_idx, owner, lost);
+}
+
 // Erase pass 2: winners (candidates not marked lost) tombstone their slot and
 // push their index back on the heap in batch order: the r-th winner writes
-// h[t - 1 - r].
-template <int KD>
-__global__ __launch_bounds__(kBlock) void k_erase_commit(TableRef tb, uint32_t n, const uint32_t* __restrict__ slot_of,
-                                                         const int32_t* __restrict__ found_idx,
-                                                         uint8_t* __restrict__ lost, int32_t* __restrict__ heap,
-                                                         uint8_t* __restrict__ out_mask, Meta* meta,
-                                                         uint64_t* __restrict__ status) {
+// h[t - 1 - r].  Out receives each position's mask (put with kNoSlot: 0).
+template <int KD, typename Out>
+__device__ __forceinline__ void erase_commit_tile(const TableRef& tb, uint32_t n, uint32_t tile,
+                                                  const uint32_t* __restrict__ slot_of,
+                                                  const int32_t* __restrict__ found_idx, uint8_t* __restrict__ lost,
+                                                  int32_t* __restrict__ heap, const Out& out, Meta* meta,
+                                                  uint64_t* __restrict__ status, uint32_t* s_prefix,
+                                                  uint64_t* s_scan) {
   constexpr int S = SlotWords<KD>::value;
-  __shared__ uint32_t s_prefix;
-  __shared__ uint64_t s_scan[kBlock / 64 + 1];
-  const uint32_t tile = blockIdx.x;
   const uint32_t t0 = meta->t;
   const uint32_t base = tile * kScanTile;
   bool win[kScanItems];
@@ -1078,8 +1130,8 @@ __global__ __launch_bounds__(kBlock) void k_erase_commit(TableRef tb, uint32_t n
   uint32_t rank[kScanItems];
   uint32_t total;
   block_rank_rows(win, rank, total, s_scan);
-  block_lookback(status, tile, meta->epoch, total, &meta->status, &s_prefix);
-  const uint32_t prefix = s_prefix;
+  block_lookback(status, tile, meta->epoch, total, &meta->status, s_prefix);
+  const uint32_t prefix = *s_prefix;
   // the last tile finalizes the erase (every tile read t and the epoch before
   // publishing, see commit_tile)
   if (threadIdx.x == 0 && tile == (n - 1) / kScanTile) {
@@ -1094,8 +1146,86 @@ __global__ __launch_bounds__(kBlock) void k_erase_commit(TableRef tb, uint32_t n
       heap[t0 - 1u - (prefix + rank[r])] = idx[r];
       tb.words[(size_t)slot_of[p] * S + S - 1] = kTomb;
     }
-    if (out_mask) out_mask[p] = win[r] ? 1 : 0;
+    out.put(p, win[r] ? 0u : kNoSlot);
   }
+}
+
+template <int KD>
+__global__ __launch_bounds__(kBlock) void k_erase_commit(TableRef tb, uint32_t n, const uint32_t* __restrict__ slot_of,
+                                                         const int32_t* __restrict__ found_idx,
+                                                         uint8_t* __restrict__ lost, int32_t* __restrict__ heap,
+                                                         uint8_t* __restrict__ out_mask, Meta* meta,
+                                                         uint64_t* __restrict__ status) {
+  __shared__ uint32_t s_prefix;
+  __shared__ uint64_t s_scan[kBlock / 64 + 1];
+  erase_commit_tile<KD>(tb, n, blockIdx.x, slot_of, found_idx, lost, heap, DirectOut{nullptr, out_mask}, meta, status,
+                        &s_prefix, s_scan);
+}
+
+// ---------------------------------------------------------------------------
+// Fused served batches of inserts or erases read the keys (and value rows)
+// from the requests' own buffers and write each request's results there: the
+// same passes as above over a key source and an output that map a batch
+// position to its request (the offsets staged in LDS), with no staging copy
+// in or out.  Value rows are copied inside the commit (rows under 64 B per
+// key in total; longer rows take the staged path).
+__device__ __forceinline__ void stage_offsets(const ReqDesc* __restrict__ d, int nreq, int64_t* s_off) {
+  for (int r = threadIdx.x; r < nreq; r += kBlock) s_off[r] = d[r].off;
+  __syncthreads();
+}
+
+template <int KD, int G, int WL, bool kReuse, bool kKeep>
+__global__ __launch_bounds__(kBlock) void k_claim_requests(TableRef tb, const ReqDesc* __restrict__ d, int nreq,
+                                                           uint32_t n, uint32_t rounds, uint32_t* __restrict__ slot_of,
+                                                           uint8_t* __restrict__ lost, uint32_t* __restrict__ partial,
+                                                           Meta* meta) {
+  __shared__ TileLds lds;
+  __shared__ int64_t s_off[kMaxFusedRequests];
+  stage_offsets(d, nreq, s_off);
+  claim_tile<KD, G, WL, ReqKeys<KD>, false, kReuse, kKeep>(tb, ReqKeys<KD>{d, s_off, nreq}, n, blockIdx.x, rounds,
+                                                            slot_of, lost, partial, meta, lds);
+}
+
+template <int KD>
+__global__ __launch_bounds__(kBlock) void k_commit_requests(TableRef tb, const ReqDesc* __restrict__ d, int nreq,
+                                                            uint32_t n, const uint32_t* __restrict__ slot_of,
+                                                            uint8_t* __restrict__ lost, int32_t* __restrict__ kB,
+                                                            const int32_t* __restrict__ heap, uint32_t cap,
+                                                            ValueSet vs, Meta* meta, uint64_t* __restrict__ status,
+                                                            int check, int silent) {
+  __shared__ TileLds lds;
+  __shared__ int64_t s_off[kMaxFusedRequests];
+  stage_offsets(d, nreq, s_off);
+  commit_tile_src<KD, true>(tb, ReqKeys<KD>{d, s_off, nreq}, ReqOut{d, s_off, nreq}, ReqRowsIn{d, s_off, nreq}, n,
+                            blockIdx.x, slot_of, lost, kB, heap, cap, vs, meta, status, check, nullptr, silent, lds);
+}
+
+template <int KD, int G, int WL>
+__global__ __launch_bounds__(kBlock) void k_erase_mark_requests(TableRef tb, const ReqDesc* __restrict__ d, int nreq,
+                                                                uint32_t n, uint32_t rounds, uint32_t epoch,
+                                                                uint32_t* __restrict__ slot_of,
+                                                                int32_t* __restrict__ found_idx,
+                                                                uint64_t* __restrict__ owner,
+                                                                uint8_t* __restrict__ lost) {
+  __shared__ int64_t s_off[kMaxFusedRequests];
+  stage_offsets(d, nreq, s_off);
+  erase_mark_tile<KD, G, WL>(tb, ReqKeys<KD>{d, s_off, nreq}, n, blockIdx.x, rounds, epoch, slot_of, found_idx, owner,
+                             lost);
+}
+
+template <int KD>
+__global__ __launch_bounds__(kBlock) void k_erase_commit_requests(TableRef tb, const ReqDesc* __restrict__ d, int nreq,
+                                                                  uint32_t n, const uint32_t* __restrict__ slot_of,
+                                                                  const int32_t* __restrict__ found_idx,
+                                                                  uint8_t* __restrict__ lost,
+                                                                  int32_t* __restrict__ heap, Meta* meta,
+                                                                  uint64_t* __restrict__ status) {
+  __shared__ uint32_t s_prefix;
+  __shared__ uint64_t s_scan[kBlock / 64 + 1];
+  __shared__ int64_t s_off[kMaxFusedRequests];
+  stage_offsets(d, nreq, s_off);
+  erase_commit_tile<KD>(tb, n, blockIdx.x, slot_of, found_idx, lost, heap, ReqOut{d, s_off, nreq}, meta, status,
+                        &s_prefix, s_scan);
 }
 
 // ---------------------------------------------------------------------------
@@ -1750,6 +1880,36 @@ struct ClaimK {
 };
 
 template <int KD, int G, int WL>
+struct ClaimRequestsK {
+  static hipError_t run(const TableRef& tb, const ReqDesc* d, int nreq, uint32_t n, uint32_t* slot_of, uint8_t* lost,
+                        uint32_t* partial, Meta* meta, hipStream_t st) {
+    const uint32_t rounds = rounds_for<G>();
+    const dim3 grid(cdiv(n, (kBlock / G) * rounds));
+    if (tb.reuse)
+      hipLaunchKernelGGL((k_claim_requests<KD, G, WL, true, false>), grid, dim3(kBlock), 0, st, tb, d, nreq, n, rounds,
+                         slot_of, lost, partial, meta);
+    else if (tb.keyed)
+      hipLaunchKernelGGL((k_claim_requests<KD, G, WL, false, true>), grid, dim3(kBlock), 0, st, tb, d, nreq, n, rounds,
+                         slot_of, lost, partial, meta);
+    else
+      hipLaunchKernelGGL((k_claim_requests<KD, G, WL, false, false>), grid, dim3(kBlock), 0, st, tb, d, nreq, n,
+                         rounds, slot_of, lost, partial, meta);
+    return hipGetLastError();
+  }
+};
+
+template <int KD, int G, int WL>
+struct EraseMarkRequestsK {
+  static hipError_t run(const TableRef& tb, const ReqDesc* d, int nreq, uint32_t n, uint32_t epoch, uint32_t* slot_of,
+                        int32_t* found, uint64_t* owner, uint8_t* lost, hipStream_t st) {
+    const uint32_t rounds = rounds_for<G>();
+    hipLaunchKernelGGL((k_erase_mark_requests<KD, G, WL>), dim3(cdiv(n, (kBlock / G) * rounds)), dim3(kBlock), 0, st,
+                       tb, d, nreq, n, rounds, epoch, slot_of, found, owner, lost);
+    return hipGetLastError();
+  }
+};
+
+template <int KD, int G, int WL>
 struct FindK {
   static hipError_t run(const TableRef& tb, const int32_t* keys, uint32_t n, int32_t* out_idx, uint8_t* out_mask,
                         const ValueSet& vs, hipStream_t st) {
@@ -1998,6 +2158,65 @@ hipError_t launch_erase_commit(int kd, const TableRef& tb, uint32_t n, const uin
     case 2: return erase_commit_k<2>(tb, n, slot_of, found, lost, heap, out_mask, meta, status, st);
     case 3: return erase_commit_k<3>(tb, n, slot_of, found, lost, heap, out_mask, meta, status, st);
     case 4: return erase_commit_k<4>(tb, n, slot_of, found, lost, heap, out_mask, meta, status, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_claim_requests(int kd, int g, int w, const TableRef& tb, const ReqDesc* d, int nreq, uint32_t n,
+                                 uint32_t* slot_of, uint8_t* lost, uint32_t* partial, Meta* meta, hipStream_t st) {
+  if (nreq < 1 || nreq > kMaxFusedRequests || tb.dedup) return hipErrorInvalidValue;
+  return with_kd_probe<ClaimRequestsK>(kd, g, w, tb, d, nreq, n, slot_of, lost, partial, meta, st);
+}
+
+template <int KD>
+static hipError_t commit_requests_k(const TableRef& tb, const ReqDesc* d, int nreq, uint32_t n,
+                                    const uint32_t* slot_of, uint8_t* lost, int32_t* kB, const int32_t* heap,
+                                    uint32_t cap, const ValueSet& vs, Meta* meta, uint64_t* status, int check,
+                                    int silent, hipStream_t st) {
+  hipLaunchKernelGGL((k_commit_requests<KD>), dim3(cdiv(n, kScanTile)), dim3(kBlock), 0, st, tb, d, nreq, n, slot_of,
+                     lost, kB, heap, cap, vs, meta, status, check, silent);
+  return hipGetLastError();
+}
+
+hipError_t launch_commit_requests(int kd, const TableRef& tb, const ReqDesc* d, int nreq, uint32_t n,
+                                  const uint32_t* slot_of, uint8_t* lost, int32_t* kB, const int32_t* heap,
+                                  uint32_t cap, const ValueSet& vs, Meta* meta, uint64_t* status, int check,
+                                  int silent, hipStream_t st) {
+  if (nreq < 1 || nreq > kMaxFusedRequests) return hipErrorInvalidValue;
+  switch (kd) {
+    case 1: return commit_requests_k<1>(tb, d, nreq, n, slot_of, lost, kB, heap, cap, vs, meta, status, check, silent, st);
+    case 2: return commit_requests_k<2>(tb, d, nreq, n, slot_of, lost, kB, heap, cap, vs, meta, status, check, silent, st);
+    case 3: return commit_requests_k<3>(tb, d, nreq, n, slot_of, lost, kB, heap, cap, vs, meta, status, check, silent, st);
+    case 4: return commit_requests_k<4>(tb, d, nreq, n, slot_of, lost, kB, heap, cap, vs, meta, status, check, silent, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_erase_mark_requests(int kd, int g, int w, const TableRef& tb, const ReqDesc* d, int nreq, uint32_t n,
+                                      uint32_t epoch, uint32_t* slot_of, int32_t* found, uint64_t* owner,
+                                      uint8_t* lost, hipStream_t st) {
+  if (nreq < 1 || nreq > kMaxFusedRequests) return hipErrorInvalidValue;
+  return with_kd_probe<EraseMarkRequestsK>(kd, g, w, tb, d, nreq, n, epoch, slot_of, found, owner, lost, st);
+}
+
+template <int KD>
+static hipError_t erase_commit_requests_k(const TableRef& tb, const ReqDesc* d, int nreq, uint32_t n,
+                                          const uint32_t* slot_of, const int32_t* found, uint8_t* lost, int32_t* heap,
+                                          Meta* meta, uint64_t* status, hipStream_t st) {
+  hipLaunchKernelGGL((k_erase_commit_requests<KD>), dim3(cdiv(n, kScanTile)), dim3(kBlock), 0, st, tb, d, nreq, n,
+                     slot_of, found, lost, heap, meta, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_erase_commit_requests(int kd, const TableRef& tb, const ReqDesc* d, int nreq, uint32_t n,
+                                        const uint32_t* slot_of, const int32_t* found, uint8_t* lost, int32_t* heap,
+                                        Meta* meta, uint64_t* status, hipStream_t st) {
+  if (nreq < 1 || nreq > kMaxFusedRequests) return hipErrorInvalidValue;
+  switch (kd) {
+    case 1: return erase_commit_requests_k<1>(tb, d, nreq, n, slot_of, found, lost, heap, meta, status, st);
+    case 2: return erase_commit_requests_k<2>(tb, d, nreq, n, slot_of, found, lost, heap, meta, status, st);
+    case 3: return erase_commit_requests_k<3>(tb, d, nreq, n, slot_of, found, lost, heap, meta, status, st);
+    case 4: return erase_commit_requests_k<4>(tb, d, nreq, n, slot_of, found, lost, heap, meta, status, st);
     default: return hipErrorInvalidValue;
   }
 }

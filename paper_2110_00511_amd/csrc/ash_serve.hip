@@ -24,6 +24,7 @@
 
 #include <chrono>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <memory>
@@ -91,6 +92,7 @@ struct ash_server {
   int64_t add_live = 0, add_used = 0;  // summed over the batches in flight
   bool stop = false;
   bool worker_done = false;
+  bool staged = false;  // fused inserts and erases through staging buffers (ASH_SERVER_STAGED=1)
   int device = 0;
   int64_t batches = 0, fused_requests = 0, largest = 0;
   std::thread worker, completer;
@@ -152,10 +154,13 @@ ash_status_t run_one(ash_server* s, Req* q) {
   }
 }
 
-// Runs requests of one kind as one device batch.  A find is one kernel that
-// reads the keys from, and writes the results to, the requests' own buffers
-// (after one descriptor upload); inserts and erases go through staging
-// buffers: a gather kernel in, the operation, a scatter kernel out.
+// Runs requests of one kind as one device batch, after one descriptor
+// upload.  A find is one kernel that reads the keys from, and writes the
+// results to, the requests' own buffers; inserts and erases run their two
+// passes over the requests' buffers the same way (insert rows under 64 B
+// per key in total).  Otherwise, or with ASH_SERVER_STAGED=1 at create,
+// inserts and erases go through staging buffers: a gather kernel in, the
+// operation, a scatter kernel out.
 ash_status_t run_fused(ash_server* s, const std::vector<Req*>& run, Stage& g) {
   ash_map* m = s->map;
   hipStream_t st = s->stream;
@@ -203,6 +208,29 @@ ash_status_t run_fused(ash_server* s, const std::vector<Req*>& run, Stage& g) {
     }
     ASH_HIP(ash::launch_find_requests(m->key_dim, m->G, m->W, m->ref(), g.ddesc, nreq, (uint32_t)off, vs, st));
     return ASH_OK;
+  }
+  uint32_t row_total = 0;
+  for (int j = 0; j < m->n_values; ++j) row_total += m->row_bytes[j];
+  const bool direct = !s->staged && !(m->flags & ASH_F_LDS_DEDUP) &&
+                      (kind == ASH_REQ_ERASE || row_total < kSplitRowBytes);
+  if (direct) {
+    RequestSource rs;
+    rs.d = g.ddesc;
+    rs.nreq = nreq;
+    std::memset(&rs.vs, 0, sizeof(rs.vs));
+    if (kind == ASH_REQ_INSERT && m->n_values > 0) {
+      rs.vs.n = m->n_values;
+      for (int j = 0; j < m->n_values; ++j) {
+        rs.vs.dst[j] = m->vB[j];
+        rs.vs.row_bytes[j] = m->row_bytes[j];
+        uint32_t vec = 16;
+        for (int k = 0; k < nreq; ++k) vec = std::min(vec, copy_unit(m->row_bytes[j], g.hdesc[k].vals[j], m->vB[j]));
+        rs.vs.vec[j] = vec;
+        rs.vs.units_log2[j] = units_log2(m->row_bytes[j], vec);
+      }
+    }
+    if (kind == ASH_REQ_INSERT) return insert_impl(m, nullptr, off, nullptr, nullptr, nullptr, st, &rs);
+    return erase_impl(m, nullptr, off, nullptr, st, &rs);
   }
   ASH_HIP(ash::launch_gather_requests(g.ddesc, nreq, off, m->key_dim, rows, g.keys,
                                       kind == ASH_REQ_INSERT && m->n_values > 0 ? g.dvals : nullptr, st));
@@ -393,6 +421,10 @@ ash_status_t ash_server_create(ash_map_t map, const ash_server_config_t* cfg, as
   std::unique_ptr<ash_server> s(new ash_server);
   s->map = map;
   s->cfg = c;
+  {
+    const char* v = std::getenv("ASH_SERVER_STAGED");
+    s->staged = v && v[0] == '1' && v[1] == '\0';
+  }
   ash_status_t rc = setup(s.get());
   if (rc != ASH_OK) {
     release(s.get());
