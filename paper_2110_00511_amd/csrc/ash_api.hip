@@ -228,8 +228,8 @@ ValueSet make_values(const ash_map* m, const void* const* src, void* const* dst,
 ash_status_t insert_impl(ash_map* m, const int32_t* keys, int64_t n, const void* const* values, int32_t* out_idx,
                          uint8_t* out_mask, hipStream_t st, const RequestSource* rs) {
   if (rs) {
-    if (!m || n < 0 || n > kMaxCount || !rs->d || rs->nreq < 1 || (m->flags & ASH_F_AUTOGROW) ||
-        (m->flags & ASH_F_LDS_DEDUP))
+    if (!m || n < 0 || n > kMaxCount || !rs->args || rs->nreq < 1 || (rs->args->nreq == 0 && !rs->d) ||
+        (m->flags & ASH_F_AUTOGROW) || (m->flags & ASH_F_LDS_DEDUP))
       return ASH_E_INVALID;
   } else {
     ASH_TRY(check_keys(m, keys, n));
@@ -263,8 +263,8 @@ ash_status_t insert_impl(ash_map* m, const int32_t* keys, int64_t n, const void*
     const char* label = m->tombs_possible ? "claim_reuse" : (m->keyed ? "claim_keyed" : "claim");
     ASH_HIP(timed(m, label, st, [&] {
       if (rs)
-        return ash::launch_claim_requests(m->key_dim, m->G, m->W, m->ref(), rs->d, rs->nreq, un, m->slot_of, m->lost,
-                                          m->partial, m->meta, st);
+        return ash::launch_claim_requests(m->key_dim, m->G, m->W, m->ref(), *rs->args, rs->d, rs->nreq, un,
+                                          m->slot_of, m->lost, m->partial, m->meta, st);
       return ash::launch_claim(m->key_dim, m->G, m->W, m->ref(), keys, un, m->slot_of, m->lost, m->partial, m->meta,
                                st);
     }));
@@ -283,8 +283,9 @@ ash_status_t insert_impl(ash_map* m, const int32_t* keys, int64_t n, const void*
     if (rs) {
       if (row_total >= kSplitRowBytes) return ASH_E_INVALID;  // request rows are copied inside the commit only
       ASH_HIP(timed(m, "commit", st, [&] {
-        return ash::launch_commit_requests(m->key_dim, m->ref(), rs->d, rs->nreq, un, m->slot_of, m->lost, m->kB,
-                                           m->heap, (uint32_t)m->c, vs, m->meta, m->scan_status, check, silent, st);
+        return ash::launch_commit_requests(m->key_dim, m->ref(), *rs->args, rs->d, rs->nreq, un, m->slot_of, m->lost,
+                                           m->kB, m->heap, (uint32_t)m->c, vs, m->meta, m->scan_status, check, silent,
+                                           st);
       }));
       return ASH_OK;
     }
@@ -354,7 +355,8 @@ ash_status_t reset_state(ash_map* m, hipStream_t st) {
 ash_status_t erase_impl(ash_map* m, const int32_t* keys, int64_t n, uint8_t* out_mask, hipStream_t st,
                         const RequestSource* rs) {
   if (rs) {
-    if (!m || n < 0 || n > kMaxCount || !rs->d || rs->nreq < 1) return ASH_E_INVALID;
+    if (!m || n < 0 || n > kMaxCount || !rs->args || rs->nreq < 1 || (rs->args->nreq == 0 && !rs->d))
+      return ASH_E_INVALID;
   } else {
     ASH_TRY(check_keys(m, keys, n));
   }
@@ -368,7 +370,7 @@ ash_status_t erase_impl(ash_map* m, const int32_t* keys, int64_t n, uint8_t* out
   const uint32_t epoch = m->erase_epoch;
   ASH_HIP(timed(m, "erase_mark", st, [&] {
     if (rs)
-      return ash::launch_erase_mark_requests(m->key_dim, m->G, m->W, m->ref(), rs->d, rs->nreq, un, epoch,
+      return ash::launch_erase_mark_requests(m->key_dim, m->G, m->W, m->ref(), *rs->args, rs->d, rs->nreq, un, epoch,
                                              m->slot_of, m->aux, m->owner, m->lost, st);
     return ash::launch_erase_mark(m->key_dim, m->G, m->W, m->ref(), keys, un, epoch, m->slot_of, m->aux, m->owner,
                                   m->lost, st);
@@ -376,8 +378,8 @@ ash_status_t erase_impl(ash_map* m, const int32_t* keys, int64_t n, uint8_t* out
   m->tombs_possible = true;
   ASH_HIP(timed(m, "erase_commit", st, [&] {  // its last tile also finalizes the erase
     if (rs)
-      return ash::launch_erase_commit_requests(m->key_dim, m->ref(), rs->d, rs->nreq, un, m->slot_of, m->aux, m->lost,
-                                               m->heap, m->meta, m->scan_status, st);
+      return ash::launch_erase_commit_requests(m->key_dim, m->ref(), *rs->args, rs->d, rs->nreq, un, m->slot_of,
+                                               m->aux, m->lost, m->heap, m->meta, m->scan_status, st);
     return ash::launch_erase_commit(m->key_dim, m->ref(), un, m->slot_of, m->aux, m->lost, m->heap, out_mask, m->meta,
                                     m->scan_status, st);
   }));

@@ -83,6 +83,17 @@ struct ReqDesc {
 // Most requests one fused served batch may carry.
 constexpr int kMaxFusedRequestsHost = 256;
 
+// The descriptors of a fused batch of at most kArgRequests requests, passed
+// by value with each launch (kernel arguments), so that no upload has to be
+// queued before the batch's kernels.  nreq = 0: the kernels read the
+// descriptors from device memory instead.
+constexpr int kArgRequests = 16;
+struct ReqArgs {
+  int32_t nreq;
+  int32_t pad;
+  ReqDesc d[kArgRequests];
+};
+
 // Row layout of the value buffers of a map (bytes per row, j < n).
 struct RowSet {
   int32_t n;

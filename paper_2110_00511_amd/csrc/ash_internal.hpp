@@ -213,11 +213,13 @@ ash_status_t ensure_scratch(ash_map* m, int64_t n, hipStream_t st);
 // Rebuilds the slot table from the committed slots of m->table (m->nslots of
 // them), which it frees; live = number of committed slots.  Synchronizes.
 ash_status_t rebuild_table(ash_map* m, int64_t live, hipStream_t st, int64_t room_for = 0);
-// Keys of a fused served batch read from its requests' buffers: device
-// descriptors d[0..nreq) in arrival order; vs: the insert's value rows
+// Keys of a fused served batch read from its requests' buffers: descriptors
+// of nreq requests in arrival order, passed with each launch (args, when
+// args->nreq == nreq) or in device memory (d); vs: the insert's value rows
 // (dst = v^B; the source rows come from the requests).
 struct RequestSource {
-  const ash::ReqDesc* d = nullptr;
+  const ash::ReqDesc* d = nullptr;  // device descriptors (when args->nreq == 0)
+  const ash::ReqArgs* args = nullptr;  // descriptors passed with each launch
   int nreq = 0;
   ValueSet vs;
 };

@@ -51,6 +51,26 @@ __device__ __forceinline__ int request_of(const int64_t* s_off, int nreq, int64_
   return lo;
 }
 
+// Stages a fused batch's descriptors in LDS when the launch carries them
+// (else they stay in device memory, gd) and the requests' first positions;
+// returns where the kernel reads the descriptors.
+__device__ __forceinline__ const ReqDesc* stage_requests(const ReqArgs& args, const ReqDesc* gd, int nreq,
+                                                         ReqDesc* s_desc, int64_t* s_off) {
+  const ReqDesc* d = gd;
+  if (args.nreq > 0) {
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int k = 0; k < kArgRequests; ++k)
+        if (k < args.nreq) s_desc[k] = args.d[k];
+    }
+    __syncthreads();
+    d = s_desc;
+  }
+  for (int r = threadIdx.x; r < nreq; r += kBlock) s_off[r] = d[r].off;
+  __syncthreads();
+  return d;
+}
+
 // ---------------------------------------------------------------------------
 // Key sources: map keys read from the batch, or voxel keys computed from
 // points.  load() returns false for a point that is rejected.
@@ -1009,12 +1029,12 @@ __global__ __launch_bounds__(kBlock) void k_find(TableRef tb, const int32_t* __r
 // result goes straight to its request (vs: the map's rows as sources; rows
 // are copied for requests that asked for them).
 template <int KD, int G, int WL>
-__global__ __launch_bounds__(kBlock) void k_find_requests(TableRef tb, const ReqDesc* __restrict__ d, int nreq,
+__global__ __launch_bounds__(kBlock) void k_find_requests(TableRef tb, ReqArgs args, const ReqDesc* __restrict__ gd, int nreq,
                                                           uint32_t n, uint32_t rounds, ValueSet vs) {
   __shared__ TileLds lds;
   __shared__ int64_t s_off[kMaxFusedRequests];
-  for (int r = threadIdx.x; r < nreq; r += kBlock) s_off[r] = d[r].off;
-  __syncthreads();
+  __shared__ ReqDesc s_desc[kArgRequests];
+  const ReqDesc* d = stage_requests(args, gd, nreq, s_desc, s_off);
   find_tile<KD, G, WL>(tb, ReqKeys<KD>{d, s_off, nreq}, n, blockIdx.x, rounds, ReqOut{d, s_off, nreq}, vs, lds);
 }
 
@@ -1169,25 +1189,22 @@ __global__ __launch_bounds__(kBlock) void k_erase_commit(TableRef tb, uint32_t n
 // position to its request (the offsets staged in LDS), with no staging copy
 // in or out.  Value rows are copied inside the commit (rows under 64 B per
 // key in total; longer rows take the staged path).
-__device__ __forceinline__ void stage_offsets(const ReqDesc* __restrict__ d, int nreq, int64_t* s_off) {
-  for (int r = threadIdx.x; r < nreq; r += kBlock) s_off[r] = d[r].off;
-  __syncthreads();
-}
 
 template <int KD, int G, int WL, bool kReuse, bool kKeep>
-__global__ __launch_bounds__(kBlock) void k_claim_requests(TableRef tb, const ReqDesc* __restrict__ d, int nreq,
+__global__ __launch_bounds__(kBlock) void k_claim_requests(TableRef tb, ReqArgs args, const ReqDesc* __restrict__ gd, int nreq,
                                                            uint32_t n, uint32_t rounds, uint32_t* __restrict__ slot_of,
                                                            uint8_t* __restrict__ lost, uint32_t* __restrict__ partial,
                                                            Meta* meta) {
   __shared__ TileLds lds;
   __shared__ int64_t s_off[kMaxFusedRequests];
-  stage_offsets(d, nreq, s_off);
+  __shared__ ReqDesc s_desc[kArgRequests];
+  const ReqDesc* d = stage_requests(args, gd, nreq, s_desc, s_off);
   claim_tile<KD, G, WL, ReqKeys<KD>, false, kReuse, kKeep>(tb, ReqKeys<KD>{d, s_off, nreq}, n, blockIdx.x, rounds,
                                                             slot_of, lost, partial, meta, lds);
 }
 
 template <int KD>
-__global__ __launch_bounds__(kBlock) void k_commit_requests(TableRef tb, const ReqDesc* __restrict__ d, int nreq,
+__global__ __launch_bounds__(kBlock) void k_commit_requests(TableRef tb, ReqArgs args, const ReqDesc* __restrict__ gd, int nreq,
                                                             uint32_t n, const uint32_t* __restrict__ slot_of,
                                                             uint8_t* __restrict__ lost, int32_t* __restrict__ kB,
                                                             const int32_t* __restrict__ heap, uint32_t cap,
@@ -1195,26 +1212,28 @@ __global__ __launch_bounds__(kBlock) void k_commit_requests(TableRef tb, const R
                                                             int check, int silent) {
   __shared__ TileLds lds;
   __shared__ int64_t s_off[kMaxFusedRequests];
-  stage_offsets(d, nreq, s_off);
+  __shared__ ReqDesc s_desc[kArgRequests];
+  const ReqDesc* d = stage_requests(args, gd, nreq, s_desc, s_off);
   commit_tile_src<KD, true>(tb, ReqKeys<KD>{d, s_off, nreq}, ReqOut{d, s_off, nreq}, ReqRowsIn{d, s_off, nreq}, n,
                             blockIdx.x, slot_of, lost, kB, heap, cap, vs, meta, status, check, nullptr, silent, lds);
 }
 
 template <int KD, int G, int WL>
-__global__ __launch_bounds__(kBlock) void k_erase_mark_requests(TableRef tb, const ReqDesc* __restrict__ d, int nreq,
+__global__ __launch_bounds__(kBlock) void k_erase_mark_requests(TableRef tb, ReqArgs args, const ReqDesc* __restrict__ gd, int nreq,
                                                                 uint32_t n, uint32_t rounds, uint32_t epoch,
                                                                 uint32_t* __restrict__ slot_of,
                                                                 int32_t* __restrict__ found_idx,
                                                                 uint64_t* __restrict__ owner,
                                                                 uint8_t* __restrict__ lost) {
   __shared__ int64_t s_off[kMaxFusedRequests];
-  stage_offsets(d, nreq, s_off);
+  __shared__ ReqDesc s_desc[kArgRequests];
+  const ReqDesc* d = stage_requests(args, gd, nreq, s_desc, s_off);
   erase_mark_tile<KD, G, WL>(tb, ReqKeys<KD>{d, s_off, nreq}, n, blockIdx.x, rounds, epoch, slot_of, found_idx, owner,
                              lost);
 }
 
 template <int KD>
-__global__ __launch_bounds__(kBlock) void k_erase_commit_requests(TableRef tb, const ReqDesc* __restrict__ d, int nreq,
+__global__ __launch_bounds__(kBlock) void k_erase_commit_requests(TableRef tb, ReqArgs args, const ReqDesc* __restrict__ gd, int nreq,
                                                                   uint32_t n, const uint32_t* __restrict__ slot_of,
                                                                   const int32_t* __restrict__ found_idx,
                                                                   uint8_t* __restrict__ lost,
@@ -1223,7 +1242,8 @@ __global__ __launch_bounds__(kBlock) void k_erase_commit_requests(TableRef tb, c
   __shared__ uint32_t s_prefix;
   __shared__ uint64_t s_scan[kBlock / 64 + 1];
   __shared__ int64_t s_off[kMaxFusedRequests];
-  stage_offsets(d, nreq, s_off);
+  __shared__ ReqDesc s_desc[kArgRequests];
+  const ReqDesc* d = stage_requests(args, gd, nreq, s_desc, s_off);
   erase_commit_tile<KD>(tb, n, blockIdx.x, slot_of, found_idx, lost, heap, ReqOut{d, s_off, nreq}, meta, status,
                         &s_prefix, s_scan);
 }
@@ -1881,18 +1901,18 @@ struct ClaimK {
 
 template <int KD, int G, int WL>
 struct ClaimRequestsK {
-  static hipError_t run(const TableRef& tb, const ReqDesc* d, int nreq, uint32_t n, uint32_t* slot_of, uint8_t* lost,
-                        uint32_t* partial, Meta* meta, hipStream_t st) {
+  static hipError_t run(const TableRef& tb, const ReqArgs& args, const ReqDesc* d, int nreq, uint32_t n,
+                        uint32_t* slot_of, uint8_t* lost, uint32_t* partial, Meta* meta, hipStream_t st) {
     const uint32_t rounds = rounds_for<G>();
     const dim3 grid(cdiv(n, (kBlock / G) * rounds));
     if (tb.reuse)
-      hipLaunchKernelGGL((k_claim_requests<KD, G, WL, true, false>), grid, dim3(kBlock), 0, st, tb, d, nreq, n, rounds,
-                         slot_of, lost, partial, meta);
+      hipLaunchKernelGGL((k_claim_requests<KD, G, WL, true, false>), grid, dim3(kBlock), 0, st, tb, args, d, nreq, n,
+                         rounds, slot_of, lost, partial, meta);
     else if (tb.keyed)
-      hipLaunchKernelGGL((k_claim_requests<KD, G, WL, false, true>), grid, dim3(kBlock), 0, st, tb, d, nreq, n, rounds,
-                         slot_of, lost, partial, meta);
+      hipLaunchKernelGGL((k_claim_requests<KD, G, WL, false, true>), grid, dim3(kBlock), 0, st, tb, args, d, nreq, n,
+                         rounds, slot_of, lost, partial, meta);
     else
-      hipLaunchKernelGGL((k_claim_requests<KD, G, WL, false, false>), grid, dim3(kBlock), 0, st, tb, d, nreq, n,
+      hipLaunchKernelGGL((k_claim_requests<KD, G, WL, false, false>), grid, dim3(kBlock), 0, st, tb, args, d, nreq, n,
                          rounds, slot_of, lost, partial, meta);
     return hipGetLastError();
   }
@@ -1900,11 +1920,12 @@ struct ClaimRequestsK {
 
 template <int KD, int G, int WL>
 struct EraseMarkRequestsK {
-  static hipError_t run(const TableRef& tb, const ReqDesc* d, int nreq, uint32_t n, uint32_t epoch, uint32_t* slot_of,
-                        int32_t* found, uint64_t* owner, uint8_t* lost, hipStream_t st) {
+  static hipError_t run(const TableRef& tb, const ReqArgs& args, const ReqDesc* d, int nreq, uint32_t n,
+                        uint32_t epoch, uint32_t* slot_of, int32_t* found, uint64_t* owner, uint8_t* lost,
+                        hipStream_t st) {
     const uint32_t rounds = rounds_for<G>();
     hipLaunchKernelGGL((k_erase_mark_requests<KD, G, WL>), dim3(cdiv(n, (kBlock / G) * rounds)), dim3(kBlock), 0, st,
-                       tb, d, nreq, n, rounds, epoch, slot_of, found, owner, lost);
+                       tb, args, d, nreq, n, rounds, epoch, slot_of, found, owner, lost);
     return hipGetLastError();
   }
 };
@@ -1922,11 +1943,11 @@ struct FindK {
 
 template <int KD, int G, int WL>
 struct FindRequestsK {
-  static hipError_t run(const TableRef& tb, const ReqDesc* d, int nreq, uint32_t n, const ValueSet& vs,
-                        hipStream_t st) {
+  static hipError_t run(const TableRef& tb, const ReqArgs& args, const ReqDesc* d, int nreq, uint32_t n,
+                        const ValueSet& vs, hipStream_t st) {
     const uint32_t rounds = rounds_for<G>();
-    hipLaunchKernelGGL((k_find_requests<KD, G, WL>), dim3(cdiv(n, (kBlock / G) * rounds)), dim3(kBlock), 0, st, tb, d,
-                       nreq, n, rounds, vs);
+    hipLaunchKernelGGL((k_find_requests<KD, G, WL>), dim3(cdiv(n, (kBlock / G) * rounds)), dim3(kBlock), 0, st, tb,
+                       args, d, nreq, n, rounds, vs);
     return hipGetLastError();
   }
 };
@@ -2110,11 +2131,18 @@ hipError_t launch_find(int kd, int g, int w, const TableRef& tb, const int32_t* 
   return with_kd_probe<FindK>(kd, g, w, tb, keys, n, out_idx, out_mask, vs, st);
 }
 
-hipError_t launch_find_requests(int kd, int g, int w, const TableRef& tb, const ReqDesc* d, int nreq, uint32_t n,
-                                const ValueSet& vs, hipStream_t st) {
-  if (nreq < 1 || nreq > kMaxFusedRequests) return hipErrorInvalidValue;
+// The batch's descriptors: nreq of them, either all in the launch arguments
+// or all in device memory.
+static bool args_fit(const ReqArgs& args, int nreq) {
+  return nreq >= 1 && nreq <= kMaxFusedRequests && args.nreq >= 0 && args.nreq <= kArgRequests &&
+         (args.nreq == 0 || args.nreq == nreq);
+}
+
+hipError_t launch_find_requests(int kd, int g, int w, const TableRef& tb, const ReqArgs& args, const ReqDesc* d,
+                                int nreq, uint32_t n, const ValueSet& vs, hipStream_t st) {
+  if (!args_fit(args, nreq)) return hipErrorInvalidValue;
   if (n == 0) return hipSuccess;
-  return with_kd_probe<FindRequestsK>(kd, g, w, tb, d, nreq, n, vs, st);
+  return with_kd_probe<FindRequestsK>(kd, g, w, tb, args, d, nreq, n, vs, st);
 }
 
 hipError_t launch_find_offsets(int kd, int g, int w, const TableRef& tb, const int32_t* keys, const int32_t* offsets,
@@ -2162,61 +2190,62 @@ hipError_t launch_erase_commit(int kd, const TableRef& tb, uint32_t n, const uin
   }
 }
 
-hipError_t launch_claim_requests(int kd, int g, int w, const TableRef& tb, const ReqDesc* d, int nreq, uint32_t n,
-                                 uint32_t* slot_of, uint8_t* lost, uint32_t* partial, Meta* meta, hipStream_t st) {
-  if (nreq < 1 || nreq > kMaxFusedRequests || tb.dedup) return hipErrorInvalidValue;
-  return with_kd_probe<ClaimRequestsK>(kd, g, w, tb, d, nreq, n, slot_of, lost, partial, meta, st);
+hipError_t launch_claim_requests(int kd, int g, int w, const TableRef& tb, const ReqArgs& args, const ReqDesc* d,
+                                 int nreq, uint32_t n, uint32_t* slot_of, uint8_t* lost, uint32_t* partial, Meta* meta,
+                                 hipStream_t st) {
+  if (!args_fit(args, nreq) || tb.dedup) return hipErrorInvalidValue;
+  return with_kd_probe<ClaimRequestsK>(kd, g, w, tb, args, d, nreq, n, slot_of, lost, partial, meta, st);
 }
 
 template <int KD>
-static hipError_t commit_requests_k(const TableRef& tb, const ReqDesc* d, int nreq, uint32_t n,
+static hipError_t commit_requests_k(const TableRef& tb, const ReqArgs& args, const ReqDesc* d, int nreq, uint32_t n,
                                     const uint32_t* slot_of, uint8_t* lost, int32_t* kB, const int32_t* heap,
                                     uint32_t cap, const ValueSet& vs, Meta* meta, uint64_t* status, int check,
                                     int silent, hipStream_t st) {
-  hipLaunchKernelGGL((k_commit_requests<KD>), dim3(cdiv(n, kScanTile)), dim3(kBlock), 0, st, tb, d, nreq, n, slot_of,
-                     lost, kB, heap, cap, vs, meta, status, check, silent);
+  hipLaunchKernelGGL((k_commit_requests<KD>), dim3(cdiv(n, kScanTile)), dim3(kBlock), 0, st, tb, args, d, nreq, n,
+                     slot_of, lost, kB, heap, cap, vs, meta, status, check, silent);
   return hipGetLastError();
 }
 
-hipError_t launch_commit_requests(int kd, const TableRef& tb, const ReqDesc* d, int nreq, uint32_t n,
-                                  const uint32_t* slot_of, uint8_t* lost, int32_t* kB, const int32_t* heap,
+hipError_t launch_commit_requests(int kd, const TableRef& tb, const ReqArgs& args, const ReqDesc* d, int nreq,
+                                  uint32_t n, const uint32_t* slot_of, uint8_t* lost, int32_t* kB, const int32_t* heap,
                                   uint32_t cap, const ValueSet& vs, Meta* meta, uint64_t* status, int check,
                                   int silent, hipStream_t st) {
-  if (nreq < 1 || nreq > kMaxFusedRequests) return hipErrorInvalidValue;
+  if (!args_fit(args, nreq)) return hipErrorInvalidValue;
   switch (kd) {
-    case 1: return commit_requests_k<1>(tb, d, nreq, n, slot_of, lost, kB, heap, cap, vs, meta, status, check, silent, st);
-    case 2: return commit_requests_k<2>(tb, d, nreq, n, slot_of, lost, kB, heap, cap, vs, meta, status, check, silent, st);
-    case 3: return commit_requests_k<3>(tb, d, nreq, n, slot_of, lost, kB, heap, cap, vs, meta, status, check, silent, st);
-    case 4: return commit_requests_k<4>(tb, d, nreq, n, slot_of, lost, kB, heap, cap, vs, meta, status, check, silent, st);
+    case 1: return commit_requests_k<1>(tb, args, d, nreq, n, slot_of, lost, kB, heap, cap, vs, meta, status, check, silent, st);
+    case 2: return commit_requests_k<2>(tb, args, d, nreq, n, slot_of, lost, kB, heap, cap, vs, meta, status, check, silent, st);
+    case 3: return commit_requests_k<3>(tb, args, d, nreq, n, slot_of, lost, kB, heap, cap, vs, meta, status, check, silent, st);
+    case 4: return commit_requests_k<4>(tb, args, d, nreq, n, slot_of, lost, kB, heap, cap, vs, meta, status, check, silent, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_erase_mark_requests(int kd, int g, int w, const TableRef& tb, const ReqDesc* d, int nreq, uint32_t n,
-                                      uint32_t epoch, uint32_t* slot_of, int32_t* found, uint64_t* owner,
-                                      uint8_t* lost, hipStream_t st) {
-  if (nreq < 1 || nreq > kMaxFusedRequests) return hipErrorInvalidValue;
-  return with_kd_probe<EraseMarkRequestsK>(kd, g, w, tb, d, nreq, n, epoch, slot_of, found, owner, lost, st);
+hipError_t launch_erase_mark_requests(int kd, int g, int w, const TableRef& tb, const ReqArgs& args, const ReqDesc* d,
+                                      int nreq, uint32_t n, uint32_t epoch, uint32_t* slot_of, int32_t* found,
+                                      uint64_t* owner, uint8_t* lost, hipStream_t st) {
+  if (!args_fit(args, nreq)) return hipErrorInvalidValue;
+  return with_kd_probe<EraseMarkRequestsK>(kd, g, w, tb, args, d, nreq, n, epoch, slot_of, found, owner, lost, st);
 }
 
 template <int KD>
-static hipError_t erase_commit_requests_k(const TableRef& tb, const ReqDesc* d, int nreq, uint32_t n,
-                                          const uint32_t* slot_of, const int32_t* found, uint8_t* lost, int32_t* heap,
-                                          Meta* meta, uint64_t* status, hipStream_t st) {
-  hipLaunchKernelGGL((k_erase_commit_requests<KD>), dim3(cdiv(n, kScanTile)), dim3(kBlock), 0, st, tb, d, nreq, n,
-                     slot_of, found, lost, heap, meta, status);
+static hipError_t erase_commit_requests_k(const TableRef& tb, const ReqArgs& args, const ReqDesc* d, int nreq,
+                                          uint32_t n, const uint32_t* slot_of, const int32_t* found, uint8_t* lost,
+                                          int32_t* heap, Meta* meta, uint64_t* status, hipStream_t st) {
+  hipLaunchKernelGGL((k_erase_commit_requests<KD>), dim3(cdiv(n, kScanTile)), dim3(kBlock), 0, st, tb, args, d, nreq,
+                     n, slot_of, found, lost, heap, meta, status);
   return hipGetLastError();
 }
 
-hipError_t launch_erase_commit_requests(int kd, const TableRef& tb, const ReqDesc* d, int nreq, uint32_t n,
-                                        const uint32_t* slot_of, const int32_t* found, uint8_t* lost, int32_t* heap,
-                                        Meta* meta, uint64_t* status, hipStream_t st) {
-  if (nreq < 1 || nreq > kMaxFusedRequests) return hipErrorInvalidValue;
+hipError_t launch_erase_commit_requests(int kd, const TableRef& tb, const ReqArgs& args, const ReqDesc* d, int nreq,
+                                        uint32_t n, const uint32_t* slot_of, const int32_t* found, uint8_t* lost,
+                                        int32_t* heap, Meta* meta, uint64_t* status, hipStream_t st) {
+  if (!args_fit(args, nreq)) return hipErrorInvalidValue;
   switch (kd) {
-    case 1: return erase_commit_requests_k<1>(tb, d, nreq, n, slot_of, found, lost, heap, meta, status, st);
-    case 2: return erase_commit_requests_k<2>(tb, d, nreq, n, slot_of, found, lost, heap, meta, status, st);
-    case 3: return erase_commit_requests_k<3>(tb, d, nreq, n, slot_of, found, lost, heap, meta, status, st);
-    case 4: return erase_commit_requests_k<4>(tb, d, nreq, n, slot_of, found, lost, heap, meta, status, st);
+    case 1: return erase_commit_requests_k<1>(tb, args, d, nreq, n, slot_of, found, lost, heap, meta, status, st);
+    case 2: return erase_commit_requests_k<2>(tb, args, d, nreq, n, slot_of, found, lost, heap, meta, status, st);
+    case 3: return erase_commit_requests_k<3>(tb, args, d, nreq, n, slot_of, found, lost, heap, meta, status, st);
+    case 4: return erase_commit_requests_k<4>(tb, args, d, nreq, n, slot_of, found, lost, heap, meta, status, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -24,29 +24,31 @@ hipError_t launch_gather_requests(const ReqDesc* d, int nreq, int64_t total, int
 hipError_t launch_scatter_requests(const ReqDesc* d, int nreq, int64_t total, const int32_t* idx, const uint8_t* mask,
                                    hipStream_t st);
 // Fused served insert / erase batches reading keys (and value rows) from the
-// requests d[0..nreq) (device descriptors, positions in arrival order) and
+// requests d[0..nreq) (positions in arrival order; the descriptors are in
+// args when args.nreq == nreq, else in device memory at d) and
 // writing each request's results; n = total positions.  The commit copies
 // rows inside (rows under 64 B per key in total).  Otherwise as
 // launch_claim / launch_commit / launch_erase_mark / launch_erase_commit.
-hipError_t launch_claim_requests(int kd, int g, int w, const TableRef& tb, const ReqDesc* d, int nreq, uint32_t n,
-                                 uint32_t* slot_of, uint8_t* lost, uint32_t* partial, Meta* meta, hipStream_t st);
-hipError_t launch_commit_requests(int kd, const TableRef& tb, const ReqDesc* d, int nreq, uint32_t n,
-                                  const uint32_t* slot_of, uint8_t* lost, int32_t* kB, const int32_t* heap,
+hipError_t launch_claim_requests(int kd, int g, int w, const TableRef& tb, const ReqArgs& args, const ReqDesc* d,
+                                 int nreq, uint32_t n, uint32_t* slot_of, uint8_t* lost, uint32_t* partial, Meta* meta,
+                                 hipStream_t st);
+hipError_t launch_commit_requests(int kd, const TableRef& tb, const ReqArgs& args, const ReqDesc* d, int nreq,
+                                  uint32_t n, const uint32_t* slot_of, uint8_t* lost, int32_t* kB, const int32_t* heap,
                                   uint32_t cap, const ValueSet& vs, Meta* meta, uint64_t* status, int check,
                                   int silent, hipStream_t st);
-hipError_t launch_erase_mark_requests(int kd, int g, int w, const TableRef& tb, const ReqDesc* d, int nreq, uint32_t n,
-                                      uint32_t epoch, uint32_t* slot_of, int32_t* found, uint64_t* owner,
-                                      uint8_t* lost, hipStream_t st);
-hipError_t launch_erase_commit_requests(int kd, const TableRef& tb, const ReqDesc* d, int nreq, uint32_t n,
-                                        const uint32_t* slot_of, const int32_t* found, uint8_t* lost, int32_t* heap,
-                                        Meta* meta, uint64_t* status, hipStream_t st);
-// A fused served find over n positions of nreq requests (device
-// descriptors, offsets ascending from 0): keys are read from, and indices,
+hipError_t launch_erase_mark_requests(int kd, int g, int w, const TableRef& tb, const ReqArgs& args, const ReqDesc* d,
+                                      int nreq, uint32_t n, uint32_t epoch, uint32_t* slot_of, int32_t* found,
+                                      uint64_t* owner, uint8_t* lost, hipStream_t st);
+hipError_t launch_erase_commit_requests(int kd, const TableRef& tb, const ReqArgs& args, const ReqDesc* d, int nreq,
+                                        uint32_t n, const uint32_t* slot_of, const int32_t* found, uint8_t* lost,
+                                        int32_t* heap, Meta* meta, uint64_t* status, hipStream_t st);
+// A fused served find over n positions of nreq requests (descriptors in args
+// or in device memory at d, offsets ascending from 0): keys are read from, and indices,
 // masks and (vs.n > 0) the value rows of hits written to, each request's own
 // buffers; vs.src are the map's rows, vs.vec must divide every request's
 // output address.
-hipError_t launch_find_requests(int kd, int g, int w, const TableRef& tb, const ReqDesc* d, int nreq, uint32_t n,
-                                const ValueSet& vs, hipStream_t st);
+hipError_t launch_find_requests(int kd, int g, int w, const TableRef& tb, const ReqArgs& args, const ReqDesc* d,
+                                int nreq, uint32_t n, const ValueSet& vs, hipStream_t st);
 // dst row r = src row r where mask[r] == 1 (rows of row_bytes, copied in vec-byte units).
 hipError_t launch_copy_masked_rows(const uint8_t* mask, const void* src, void* dst, uint64_t rows,
                                    uint32_t row_bytes, uint32_t vec, hipStream_t st);

@@ -154,13 +154,15 @@ ash_status_t run_one(ash_server* s, Req* q) {
   }
 }
 
-// Runs requests of one kind as one device batch, after one descriptor
-// upload.  A find is one kernel that reads the keys from, and writes the
-// results to, the requests' own buffers; inserts and erases run their two
-// passes over the requests' buffers the same way (insert rows under 64 B
-// per key in total).  Otherwise, or with ASH_SERVER_STAGED=1 at create,
-// inserts and erases go through staging buffers: a gather kernel in, the
-// operation, a scatter kernel out.
+// Runs requests of one kind as one device batch.  A find is one kernel that
+// reads the keys from, and writes the results to, the requests' own buffers;
+// inserts and erases run their two passes over the requests' buffers the
+// same way (insert rows under 64 B per key in total).  The kernels of such a
+// batch carry the descriptors of up to kArgRequests requests in their
+// arguments; larger batches upload them once.  Otherwise, or with
+// ASH_SERVER_STAGED=1 at create, inserts and erases go through staging
+// buffers: a descriptor upload, a gather kernel in, the operation, a scatter
+// kernel out.
 ash_status_t run_fused(ash_server* s, const std::vector<Req*>& run, Stage& g) {
   ash_map* m = s->map;
   hipStream_t st = s->stream;
@@ -189,7 +191,21 @@ ash_status_t run_fused(ash_server* s, const std::vector<Req*>& run, Stage& g) {
   std::memset(&rows, 0, sizeof(rows));
   rows.n = m->n_values;
   for (int j = 0; j < m->n_values; ++j) rows.bytes[j] = m->row_bytes[j];
-  ASH_HIP(hipMemcpyAsync(g.ddesc, g.hdesc, sizeof(ash::ReqDesc) * nreq, hipMemcpyHostToDevice, st));
+  uint32_t row_total = 0;
+  for (int j = 0; j < m->n_values; ++j) row_total += m->row_bytes[j];
+  const bool direct = kind == ASH_REQ_FIND || (!s->staged && !(m->flags & ASH_F_LDS_DEDUP) &&
+                                               (kind == ASH_REQ_ERASE || row_total < kSplitRowBytes));
+  // A direct batch of few requests passes its descriptors with each launch;
+  // otherwise they are uploaded once.
+  ash::ReqArgs args;
+  args.nreq = 0;
+  args.pad = 0;
+  if (direct && nreq <= ash::kArgRequests) {
+    args.nreq = nreq;
+    std::memcpy(args.d, g.hdesc, sizeof(ash::ReqDesc) * nreq);
+  } else {
+    ASH_HIP(hipMemcpyAsync(g.ddesc, g.hdesc, sizeof(ash::ReqDesc) * nreq, hipMemcpyHostToDevice, st));
+  }
   if (kind == ASH_REQ_FIND) {
     // one kernel: keys read from the requests, results written to them
     ValueSet vs;
@@ -206,16 +222,13 @@ ash_status_t run_fused(ash_server* s, const std::vector<Req*>& run, Stage& g) {
         vs.units_log2[j] = units_log2(m->row_bytes[j], vec);
       }
     }
-    ASH_HIP(ash::launch_find_requests(m->key_dim, m->G, m->W, m->ref(), g.ddesc, nreq, (uint32_t)off, vs, st));
+    ASH_HIP(ash::launch_find_requests(m->key_dim, m->G, m->W, m->ref(), args, g.ddesc, nreq, (uint32_t)off, vs, st));
     return ASH_OK;
   }
-  uint32_t row_total = 0;
-  for (int j = 0; j < m->n_values; ++j) row_total += m->row_bytes[j];
-  const bool direct = !s->staged && !(m->flags & ASH_F_LDS_DEDUP) &&
-                      (kind == ASH_REQ_ERASE || row_total < kSplitRowBytes);
   if (direct) {
     RequestSource rs;
     rs.d = g.ddesc;
+    rs.args = &args;
     rs.nreq = nreq;
     std::memset(&rs.vs, 0, sizeof(rs.vs));
     if (kind == ASH_REQ_INSERT && m->n_values > 0) {
