@@ -255,6 +255,7 @@ ash_status_t insert_impl(ash_map* m, const int32_t* keys, int64_t n, const void*
     const volatile Meta* mr = m->mirror_h;
     const uint64_t last_n = mr->last_n, last_new = mr->result;
     m->keyed = last_n > 0 && last_new * 10 <= last_n * 4;
+    if (m->keyed_override >= 0) m->keyed = m->keyed_override != 0;
   }
   const uint32_t un = (uint32_t)n;
   const uint32_t blocks = ash::claim_blocks(m->G, un);
@@ -435,6 +436,10 @@ ash_status_t ash_create(int64_t capacity, int32_t key_dim, int32_t n_values, con
   m->max_load = lf;
   m->flags = flags;
   m->vB.assign(n_values, nullptr);
+  {
+    const char* v = std::getenv("ASH_CLAIM_KEYED");
+    if (v && (v[0] == '0' || v[0] == '1') && v[1] == '\0') m->keyed_override = v[0] - '0';
+  }
   ash_status_t s = slots_for(capacity, lf, W, G, &m->nslots);
   if (s != ASH_OK) {
     delete m;

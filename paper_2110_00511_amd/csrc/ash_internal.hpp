@@ -185,6 +185,9 @@ struct ash_map {
   // The next claim keeps pending keys in their slots (chosen per insert from
   // the last insert's new-key fraction; results are the same either way).
   bool keyed = false;
+  // ASH_CLAIM_KEYED=0 / 1 at create fixes the claim variant (-1: chosen per
+  // insert from the last insert's new-key fraction); results are the same
+  int keyed_override = -1;
 
   int slot_words() const { return key_dim == 1 ? 2 : (key_dim <= 3 ? 4 : 8); }
 

@@ -504,6 +504,12 @@ __device__ __forceinline__ void claim_tile(const TableRef& tb, const Src& src, u
           if (sub == 0) found = cas_pair(tb.words + (size_t)s * S + S - 2, expect, desired);
           found = leader_bcast64<G>(found);
           if (found == expect) {
+            // A map claim keeping pending keys publishes its key words right
+            // away, so later positions of the key compare against the slot
+            // instead of reading the batch (a reader that comes first still
+            // sees them unset and reads the batch).
+            if constexpr (kKeyed && !kVoxel)
+              if (sub == 0) publish_key_words<KD, S>(tb.words + (size_t)s * S, k);
             out = kVoxel ? (s | kCandidate) : s;
             claimed += sub == 0 ? 1u : 0u;
             resolved = true;
