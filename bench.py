@@ -589,13 +589,15 @@ def bench_voxelize(args):
     # Roofline of one whole call (its kernels are launched back to back on one
     # stream): algorithmic bytes per point with u = voxels / points --
     # claim: point 12 + window line + u * CAS + slot 4; commit: slot 4 +
-    # lost 1 + point id 4 + u * (voxel key 12 + count 4 + slot store 32);
-    # resolve: slot 4 + (1 - u) * (slot line + count atomic + point id 4);
-    # fills: the 16 B slots of a table at load 0.5 (32 B per point) and 1 B
-    # per point of scratch.
+    # lost 1 + point id 4 + u * (voxel key 12 + count 4 [+ slot store 32 when
+    # u <= 1/2, the voxel's id written into its slot]); resolve: slot 4 +
+    # (1 - u) * (slot line [+ the first point's id line when u > 1/2] + count
+    # atomic + point id 4); fills: the 16 B slots of a table at load 0.5
+    # (32 B per point) and 1 B per point of scratch.
     u = out["0.5cm"]["voxels"] / n
-    per_point = (12 + READ_LINE + u * CAS64 + 4) + (4 + 1 + 4 + u * (12 + 4 + STORE)) \
-        + (4 + (1 - u) * (READ_LINE + ATOM32 + 4)) + (32 + 1)
+    publish = u <= 0.5
+    per_point = (12 + READ_LINE + u * CAS64 + 4) + (4 + 1 + 4 + u * (12 + 4 + (STORE if publish else 0))) \
+        + (4 + (1 - u) * (READ_LINE + (0 if publish else READ_LINE) + ATOM32 + 4)) + (32 + 1)
     achieved = per_point * n / (ms0 / 1e3) / 1e9
     print(json.dumps({
         "metric": "Mpoints/s voxelization (5M points, 5 mm voxels)", "value": round(n / ms0 / 1e3, 1),

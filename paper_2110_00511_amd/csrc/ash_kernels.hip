@@ -1457,6 +1457,11 @@ __global__ __launch_bounds__(kBlock) void k_voxel_commit(TableRef tb, VoxelKeys 
       if (so == kNoSlot) point_voxel[p] = -1;  // rejected point
     }
   }
+  // Most points of a fine voxelization are alone in their voxel: then the
+  // voxel's id is not written into its slot (one random store per voxel),
+  // and the few later points find it through the first point's id instead
+  // (the slot still holds PENDING(first point); see k_voxel_resolve).
+  const bool publish = 2ull * meta->claims <= (uint64_t)n;
   uint32_t rank[kScanItems];
   uint32_t total;
   block_rank_rows(win, rank, total, s_scan);
@@ -1476,7 +1481,7 @@ __global__ __launch_bounds__(kBlock) void k_voxel_commit(TableRef tb, VoxelKeys 
     counts[id] = 1;
     point_voxel[p] = (int32_t)id;
     slot_of[p] = kNoSlot;
-    tb.words[(size_t)slot[r] * S + S - 1] = id;
+    if (publish) tb.words[(size_t)slot[r] * S + S - 1] = id;
   }
 }
 
@@ -1509,7 +1514,9 @@ __global__ __launch_bounds__(kBlock) void k_block_coords(const float* __restrict
 
 // Voxelization pass 3: voxel ids and counts of the points the commit left:
 // every accepted point that is not its voxel's first (the commit resolved
-// first points and rejected ones, and set their slot_of to kNoSlot).
+// first points and rejected ones, and set their slot_of to kNoSlot).  The
+// slot holds the voxel's id, or, when the commit did not write ids into
+// slots, PENDING(first point), whose id the commit wrote to point_voxel.
 __global__ __launch_bounds__(kBlock) void k_voxel_resolve(TableRef tb, uint32_t n, const uint32_t* __restrict__ slot_of,
                                                           int32_t* __restrict__ point_voxel,
                                                           int32_t* __restrict__ counts) {
@@ -1518,7 +1525,11 @@ __global__ __launch_bounds__(kBlock) void k_voxel_resolve(TableRef tb, uint32_t 
   if (p >= n) return;
   const uint32_t so = slot_of[p];
   if (so == kNoSlot) return;
-  const uint32_t id = tb.words[(size_t)(so & ~kCandidate) * S + S - 1];
+  uint32_t id = tb.words[(size_t)(so & ~kCandidate) * S + S - 1];
+  if (id >= kPending && id < kTomb) {
+    const uint32_t first = id - kPending;
+    id = first < n ? (uint32_t)point_voxel[first] : kNoSlot;  // the first point's id (always < n)
+  }
   if (id >= n) {  // cannot happen once every claimed slot is committed
     point_voxel[p] = -1;
     return;
