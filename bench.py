@@ -100,8 +100,8 @@ def cpu_model():
 # with these SHA-256 digests only: traffic is reported as null for any other
 # sources or workload.
 MEASURED_TRAFFIC = {
-    "claim": 2.4236e9,
-    "commit": 0.9229e9,
+    "claim": 2.4238e9,
+    "commit": 0.9239e9,
     "find": 1.4428e9,
     "erase_mark": 0.8949e9,
     "erase_commit": 0.1803e9,
@@ -111,8 +111,8 @@ MEASURED_TRAFFIC = {
 # on the same kernel sources.
 MEASURED_TRAFFIC_NEIGHBORS = 18.53e9
 MEASURED_SOURCES = {
-    "ash_kernels.hip": "3031dedf7ad83fd10975e91925bbd764bd4c37c955279e8f0b23dc660924ddc9",
-    "ash_device.hpp": "5d73dcd29a226ed87f8f0a7b83b887da26247d80f16b25c7603da9ac1298343a",
+    "ash_kernels.hip": "714c5a1ece7c23f11e97c2ce38858139411b9c9e30c440e5408aefc87fc145c4",
+    "ash_device.hpp": "a394506f8ba1d7d611ac3da4336cde6cb71196236c0bb65e99b7c8f6f10718a9",
 }
 
 
