@@ -111,6 +111,28 @@ def test_served_results_equal_serial_replay(ash, mode):
         assert stats["batches"] == len(reqs)
 
 
+@pytest.mark.parametrize("case", ["rows_64B", "staged_forced"])
+def test_served_staged_batches_equal_serial_replay(ash, case, monkeypatch):
+    """Fused batches that go through staging buffers: inserts whose rows
+    reach 64 B per key (their rows move in a pass of their own after the
+    commit), and every insert and erase batch with ASH_SERVER_STAGED=1.  Both
+    must give the serial replay's results, like the batches that run on the
+    requests' own buffers."""
+    channels = 16 if case == "rows_64B" else 4
+    if case == "staged_forced":
+        monkeypatch.setenv("ASH_SERVER_STAGED", "1")
+    rng = np.random.default_rng(74)
+    side, capacity = 40, 60_000
+    pre = rng.choice(side ** 3, size=20_000, replace=False)
+    pk = np.stack([pre // (side * side), (pre // side) % side, pre % side], axis=1).astype(np.int32)
+    pv = rng.standard_normal((len(pk), channels)).astype(np.float32)
+    reqs = make_stream(rng, 300, side, channels=channels)
+    m, outs, lat, sts, stats = run_served(ash, capacity, (pk, pv), reqs, np.zeros(len(reqs)), channels=channels,
+                                          fuse=True, max_fused=64, max_batch=1 << 16, in_flight=3)
+    assert np.all(sts == 0) and stats["batches"] < len(reqs)
+    check_against_oracle(capacity, (pk, pv), reqs, m, outs, channels=channels, values=True)
+
+
 def test_served_tight_capacity_matches_serial(ash):
     """Inserts that overflow fail on their own, exactly as in serial order,
     even when the server would fuse them."""
