@@ -1541,7 +1541,8 @@ __global__ __launch_bounds__(kBlock) void k_voxel_resolve(TableRef tb, uint32_t 
 // ---------------------------------------------------------------------------
 // Batched maps in one persistent cooperative launch.  Phases, separated by
 // grid barriers: claims of every item -> (per-map new-key sums, only when a
-// capacity check is needed) -> commits -> per-map finalize -> finds.  Each
+// capacity check is needed) -> commits (each map's last tile finalizes the
+// map) -> finds.  Each
 // phase walks a flat list of tiles strided over the resident blocks; a block
 // takes its tiles in increasing order and all blocks are co-resident, so the
 // per-map look-back of the commit phase (which only waits on lower tiles of
@@ -1697,15 +1698,9 @@ __global__ __launch_bounds__(kBlock) void k_batched(const BatchItem* __restrict_
   for (uint32_t t = blockIdx.x; t < commit_tiles; t += gridDim.x) {
     cur = advance_item<&BatchItem::commit0>(items, n_items, cur, t);
     const BatchItem& it = items[cur];
+    // each map's last commit tile finalizes that map (as in k_commit)
     commit_tile<KD, true>(it.tb, it.ikeys, it.n_insert, t - it.commit0, it.slot_of, it.lost, it.kB, it.heap, it.cap,
-                          it.vin, it.iidx, it.imask, it.meta, it.status, it.check, nullptr, -1, lds);
-  }
-  if (!grid_barrier(gs, passed, items, n_items, &s_ok)) return;
-  for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < n_items; m += gridDim.x * blockDim.x) {
-    const BatchItem& it = items[m];
-    if (it.n_insert)
-      finalize_map(it.meta, it.cap, kFinalizeInsert, 0, it.check, it.status, (it.n_insert + kScanTile - 1) / kScanTile - 1,
-                   it.n_insert);
+                          it.vin, it.iidx, it.imask, it.meta, it.status, it.check, nullptr, 0, lds);
   }
   if (!grid_barrier(gs, passed, items, n_items, &s_ok)) return;
   cur = 0;
