@@ -450,6 +450,19 @@ def _timed(fn, steps, warmup):
     return (time.perf_counter() - t0) * 1e3 / steps
 
 
+def batched_grid(lib, sp):
+    """Blocks of the persistent batched launch (int32x3 keys) per kernel
+    build: the count the device ran at once and the occupancy the runtime
+    reported."""
+    from paper_2110_00511_amd import _lib as L
+    out = {}
+    for narrow, name in ((1, "lane_w2_w4_build"), (0, "general_build")):
+        blocks, reported = ctypes.c_int64(0), ctypes.c_int64(0)
+        L.check(lib.ash_batched_grid(3, narrow, ctypes.byref(blocks), ctypes.byref(reported), sp), "batched grid")
+        out[name] = {"blocks": blocks.value, "reported": reported.value}
+    return out
+
+
 def bench_batched(args):
     """64 independent maps (distinct counts log-uniform in [1e3, 1e6], f32x8
     values): the inserts and finds of all maps in one persistent launch,
@@ -550,6 +563,7 @@ def bench_batched(args):
                         "ms_per_step": round(ms_s, 4), "value": round(n_ops / ms_s / 1e3, 1), "unit": "Mops/s",
                         "tuned_shapes": shapes_s, "autotune_s": round(tune_s, 2)},
         "fallbacks": int(lib.ash_batched_fallbacks()),
+        "resident_blocks": batched_grid(lib, sp),
         "with_clears": {"fused_ms": round(ms_fc, 4), "plain_ms": round(ms_pc, 4),
                         "fused_Mops": round(n_ops / ms_fc / 1e3, 1), "plain_Mops": round(n_ops / ms_pc / 1e3, 1)}}),
           flush=True)

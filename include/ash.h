@@ -309,10 +309,14 @@ ash_status_t ash_voxelize_noalloc(const float* points, int64_t n, float voxel,
 /* Blocks of the persistent batched launch for maps of this key_dim on the
  * current device: the occupancy the runtime reports (*out_reported, blocks per
  * CU times CUs) and the count the device was seen to run all at once
- * (*out_blocks), which ash_batched uses.  The first call per key_dim and
- * device makes an empty launch (touching no map) and synchronizes; later
- * calls return the cached count. */
-ash_status_t ash_batched_grid(int32_t key_dim, int64_t* out_blocks, int64_t* out_reported, void* stream);
+ * (*out_blocks), which ash_batched uses.  narrow = 1 asks about the kernel
+ * build ash_batched launches when every map of the call probes one lane per
+ * key (probe_group 1) with bucket_width 2 or 4: it holds fewer registers, so
+ * more of its blocks fit; narrow = 0 about the build for every other call.
+ * The first call per key_dim, build and device makes an empty launch
+ * (touching no map) and synchronizes; later calls return the cached count. */
+ash_status_t ash_batched_grid(int32_t key_dim, int32_t narrow, int64_t* out_blocks, int64_t* out_reported,
+                              void* stream);
 
 /* Batched maps (many independent maps of uneven sizes at once).  One op is
  * one map's work: an insert batch, then a find batch, with the meaning of
@@ -372,8 +376,10 @@ ash_status_t ash_autotune(int64_t capacity, int32_t key_dim, int32_t n_values,
  * insert and find of one map in the persistent batched launch.  That kernel
  * keeps a fixed number of blocks resident, each taking its tiles one after
  * another, so the sweep keeps the shapes that probe all keys of a tile at
- * once: g = 1 with W in {2, 4, 8}, max_load in {0.5, 0.7, 0.85}.  Cached
- * separately from ash_autotune.  Synchronizes. */
+ * once: g = 1 with W in {2, 4}, max_load in {0.5, 0.7, 0.85}.  A launch whose
+ * maps all have such shapes runs the kernel build with more blocks resident
+ * (ash_batched_grid, narrow = 1).  Cached separately from ash_autotune.
+ * Synchronizes. */
 ash_status_t ash_autotune_batched(int64_t capacity, int32_t key_dim, int32_t n_values,
                                   const ash_dtype_t* value_dtypes, const int64_t* value_elems,
                                   int64_t n_insert, double distinct_ratio,

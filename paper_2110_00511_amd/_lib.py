@@ -102,7 +102,7 @@ SIGNATURES = {
                                 ctypes.POINTER(AshTuning), ctypes.POINTER(ctypes.c_double)]),
     "ash_server_create": (ST, [P, P, ctypes.POINTER(P)]),
     "ash_batched_fallbacks": (I64, []),
-    "ash_batched_grid": (ST, [I32, ctypes.POINTER(I64), ctypes.POINTER(I64), P]),
+    "ash_batched_grid": (ST, [I32, I32, ctypes.POINTER(I64), ctypes.POINTER(I64), P]),
     "ash_server_submit": (ST, [P, ctypes.POINTER(AshRequest), ctypes.POINTER(I64)]),
     "ash_server_wait": (ST, [P, I64, ctypes.POINTER(ctypes.c_double)]),
     "ash_server_replay": (ST, [P, ctypes.POINTER(AshRequest), I64, P, P, P, ctypes.POINTER(ctypes.c_double)]),

@@ -932,35 +932,37 @@ ash_status_t ash_voxelize(const float* points, int64_t n, float voxel, int32_t* 
 }
 
 // Blocks of the persistent batched kernel that the device runs all at once,
-// found once per (key_dim, device): an empty launch at the occupancy the
-// runtime reports, lowered one block per CU at a time until every block
+// found once per (key_dim, build, device): an empty launch at the occupancy
+// the runtime reports, lowered one block per CU at a time until every block
 // passes the kernel's arrival check.  A failed try costs the barrier's
 // bounded wait and touches no map.
 std::mutex g_resident_mu;
-std::map<std::pair<int, int>, uint32_t> g_resident;
+std::map<std::tuple<int, bool, int>, uint32_t> g_resident;
 
-static ash_status_t batched_resident(int kd, DevMem& mem, hipStream_t st, uint32_t* out) {
+static ash_status_t batched_resident(int kd, bool narrow, DevMem& mem, hipStream_t st, uint32_t* out) {
   int dev = 0, cus = 0, per_cu = 0;
   ASH_HIP(hipGetDevice(&dev));
   {
     std::lock_guard<std::mutex> lock(g_resident_mu);
-    auto it = g_resident.find({kd, dev});
+    auto it = g_resident.find({kd, narrow, dev});
     if (it != g_resident.end()) {
       *out = it->second;
       return ASH_OK;
     }
   }
   ASH_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  ASH_HIP(ash::batched_occupancy(kd, &per_cu));
+  ASH_HIP(ash::batched_occupancy(kd, narrow, &per_cu));
   if (cus < 1 || per_cu < 1) return ASH_E_DEVICE;
-  ash::GridSync* gs = (ash::GridSync*)mem.get(sizeof(ash::GridSync), st);
+  const size_t gs_bytes = ash::grid_sync_bytes((uint32_t)(cus * per_cu));
+  ash::GridSync* gs = (ash::GridSync*)mem.get(gs_bytes, st);
   if (!gs) return ASH_E_NOMEM;
   uint32_t found = 0;
   ash_status_t rc = ASH_OK;
   for (int b = per_cu; b >= 1 && found == 0 && rc == ASH_OK; --b) {
     ash::GridSync h;
-    if (ash::launch_fill_u32((uint32_t*)gs, 0u, sizeof(ash::GridSync) / 4, st) != hipSuccess ||
-        ash::launch_batched(kd, nullptr, 0, 0, 0, 0, 0, gs, (uint32_t)(cus * b), ash::kArrivalSpinLimit, 0u, st) !=
+    if (ash::launch_fill_u32((uint32_t*)gs, 0u, gs_bytes / 4, st) != hipSuccess ||
+        ash::launch_batched(kd, narrow, nullptr, 0, 0, 0, 0, 0, gs, (uint32_t)(cus * b), ash::kArrivalSpinLimit, 0u,
+                            st) !=
             hipSuccess ||
         hipMemcpyAsync(&h, gs, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess) {
@@ -973,21 +975,22 @@ static ash_status_t batched_resident(int kd, DevMem& mem, hipStream_t st, uint32
   if (rc != ASH_OK) return rc;
   if (found == 0) return ASH_E_DEVICE;
   std::lock_guard<std::mutex> lock(g_resident_mu);
-  g_resident[{kd, dev}] = found;
+  g_resident[{kd, narrow, dev}] = found;
   *out = found;
   return ASH_OK;
 }
 
-ash_status_t ash_batched_grid(int32_t key_dim, int64_t* out_blocks, int64_t* out_reported, void* stream) {
-  if (key_dim < 1 || key_dim > 4 || !out_blocks) return ASH_E_INVALID;
+ash_status_t ash_batched_grid(int32_t key_dim, int32_t narrow, int64_t* out_blocks, int64_t* out_reported,
+                              void* stream) {
+  if (key_dim < 1 || key_dim > 4 || (narrow != 0 && narrow != 1) || !out_blocks) return ASH_E_INVALID;
   hipStream_t st = (hipStream_t)stream;
   int dev = 0, cus = 0, per_cu = 0;
   ASH_HIP(hipGetDevice(&dev));
   ASH_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  ASH_HIP(ash::batched_occupancy(key_dim, &per_cu));
+  ASH_HIP(ash::batched_occupancy(key_dim, narrow != 0, &per_cu));
   DevMem mem;
   uint32_t resident = 0;
-  ASH_TRY(batched_resident(key_dim, mem, st, &resident));
+  ASH_TRY(batched_resident(key_dim, narrow != 0, mem, st, &resident));
   *out_blocks = resident;
   if (out_reported) *out_reported = (int64_t)cus * per_cu;
   return ASH_OK;
@@ -1053,9 +1056,11 @@ ash_status_t ash_batched(const ash_batch_op_t* ops, int32_t n_ops, int32_t fused
   std::vector<ash::BatchItem> items(n_ops);
   uint32_t claim_tiles = 0, commit_tiles = 0, find_tiles = 0;
   int32_t any_check = 0;
+  bool narrow = true;  // every map probes one lane per key with W <= 4
   for (int32_t i = 0; i < n_ops; ++i) {
     const ash_batch_op_t& op = ops[i];
     ash_map* m = op.map;
+    narrow = narrow && m->G == 1 && (m->W == 2 || m->W == 4);
     ASH_TRY(ensure_scratch(m, std::max<int64_t>(op.n_insert, 1), st));
     ASH_TRY(maybe_clean(m, op.n_insert, st));
     ash::BatchItem& it = items[i];
@@ -1092,9 +1097,10 @@ ash_status_t ash_batched(const ash_batch_op_t* ops, int32_t n_ops, int32_t fused
   }
   ash_map* m0 = ops[0].map;
   uint32_t resident = 0;
-  ASH_TRY(batched_resident(kd, m0->mem, st, &resident));
+  ASH_TRY(batched_resident(kd, narrow, m0->mem, st, &resident));
   const size_t item_bytes = (sizeof(ash::BatchItem) * (size_t)n_ops + 255) / 256 * 256;
-  const size_t bytes = item_bytes + sizeof(ash::GridSync);
+  const size_t gs_bytes = ash::grid_sync_bytes(resident);
+  const size_t bytes = item_bytes + gs_bytes;
   uint8_t* dev = (uint8_t*)m0->mem.get(bytes, st);
   if (!dev) return ASH_E_NOMEM;
   ash::BatchItem* dev_items = (ash::BatchItem*)dev;
@@ -1105,10 +1111,10 @@ ash_status_t ash_batched(const ash_batch_op_t* ops, int32_t n_ops, int32_t fused
   const uint32_t force_fail = force_arrival_failure();
   if (hipMemcpyAsync(dev_items, items.data(), sizeof(ash::BatchItem) * (size_t)n_ops, hipMemcpyHostToDevice, st) !=
           hipSuccess ||
-      ash::launch_fill_u32((uint32_t*)gs, 0u, sizeof(ash::GridSync) / 4, st) != hipSuccess ||
+      ash::launch_fill_u32((uint32_t*)gs, 0u, gs_bytes / 4, st) != hipSuccess ||
       timed(m0, "batched", st, [&] {
-        return ash::launch_batched(kd, dev_items, n_ops, claim_tiles, commit_tiles, find_tiles, any_check, gs,
-                                   resident, ash::kArrivalSpinLimit, force_fail, st);
+        return ash::launch_batched(kd, narrow, dev_items, n_ops, claim_tiles, commit_tiles, find_tiles, any_check,
+                                   gs, resident, ash::kArrivalSpinLimit, force_fail, st);
       }) != hipSuccess ||
       hipMemcpyAsync(&h, gs, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
@@ -1287,13 +1293,16 @@ ash_status_t ash_autotune(int64_t capacity, int32_t key_dim, int32_t n_values, c
 // In the persistent batched launch every resident block takes its tiles one
 // after another, so a tile's latency is not hidden by other blocks: a lane
 // per key probes all 256 keys of a tile at once, while g >= 4 runs g rounds
-// in sequence.  The batched sweep therefore keeps g = 1.
+// in sequence.  The batched sweep therefore keeps g = 1, and W <= 4: a launch
+// whose maps all have those shapes runs the narrow build of the kernel (more
+// blocks resident), and one map with W = 8 would move the whole launch to
+// the general build, which a one-map timing does not see.
 ash_status_t ash_autotune_batched(int64_t capacity, int32_t key_dim, int32_t n_values,
                                   const ash_dtype_t* value_dtypes, const int64_t* value_elems, int64_t n_insert,
                                   double distinct_ratio, const ash_allocator_t* allocator, void* stream,
                                   ash_tuning_t* out, double* out_ms) {
-  return autotune_impl(capacity, key_dim, n_values, value_dtypes, value_elems, n_insert, distinct_ratio, {2, 4, 8},
-                       {1}, {0.5f, 0.7f, 0.85f}, true, allocator, stream, out, out_ms);
+  return autotune_impl(capacity, key_dim, n_values, value_dtypes, value_elems, n_insert, distinct_ratio, {2, 4}, {1},
+                       {0.5f, 0.7f, 0.85f}, true, allocator, stream, out, out_ms);
 }
 
 ash_status_t ash_autotune_sweep(int64_t capacity, int32_t key_dim, int32_t n_values, const ash_dtype_t* value_dtypes,

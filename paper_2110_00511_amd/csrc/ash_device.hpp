@@ -38,11 +38,12 @@ constexpr uint32_t kStatusGridStall = 8u;   // a persistent launch's blocks did 
 // Polls of a persistent launch's arrival check before its blocks give up
 // (about 0.1 s): no table has been touched then.
 constexpr uint32_t kArrivalSpinLimit = 1u << 20;
-// Polls of its later phase barriers.  Once every block has arrived, all
-// blocks are resident and every phase ends, so these waits only end early
-// for a broken invariant; they must outlast the slowest phase of the
-// largest batch (seconds), and are bounded so a launch still always ends.
-constexpr uint32_t kPhaseSpinLimit = 1u << 30;
+// Polls of its later phase barriers (about 1 us apart, so about 8 s).  Once
+// every block has arrived, all blocks are resident and every phase ends, so
+// these waits only end early for a broken invariant; they must outlast the
+// slowest phase of the largest batch, and are bounded so a launch still
+// always ends.
+constexpr uint32_t kPhaseSpinLimit = 1u << 23;
 constexpr uint32_t kLookbackSpinLimit = 1u << 24;
 
 template <int KD>
@@ -107,11 +108,29 @@ struct RowSet {
 // when a later phase barrier hit its bound (tables may be half updated;
 // every map of the launch then carries kStatusGridStall).
 constexpr uint32_t kArrivalFailed = 0x80000000u;
+// Barrier words and per-phase tile counters of a persistent launch, each on
+// a 128-byte line of its own (the barrier word is polled; each counter takes
+// one atomic per tile of its queue).  Zeroed before every launch.
+constexpr uint32_t kTileQueues = 8;
+constexpr uint32_t kMaxXcc = 16;  // the XCC_ID register holds 4 bits
 struct GridSync {
-  uint32_t count;
-  uint32_t late;
-  uint32_t pad[14];
+  uint32_t count;   // arrivals at the arrival check
+  uint32_t late;    // a phase barrier gave up
+  uint32_t n_xcc;   // XCCs the launch's blocks run on
+  uint32_t pad0[29];
+  uint32_t next[3][kTileQueues][32];  // next[phase][queue][0]: tiles handed out past the queue's first ones
+  uint32_t xcc_blocks[kMaxXcc][32];   // [x][0]: blocks on XCC x
+  uint32_t xcc_count[kMaxXcc][32];    // [x][0]: phase-barrier arrivals of XCC x's blocks
+  uint32_t xcc_done;                  // XCCs whose blocks have all arrived, over all barriers
+  uint32_t pad1[31];
 };
+// After the GridSync, one release flag per block, kFlagWords words apart (a
+// 128-byte line each): the block whose arrival completes a barrier writes the
+// barrier's number into every flag, and each block polls its own.
+constexpr uint32_t kFlagWords = 32;
+// Device bytes of the GridSync of a persistent launch of `blocks` blocks,
+// with their release flags.
+inline size_t grid_sync_bytes(uint32_t blocks) { return sizeof(GridSync) + (size_t)blocks * kFlagWords * 4; }
 
 struct TableRef {
   uint32_t* words;

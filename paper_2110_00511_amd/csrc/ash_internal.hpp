@@ -71,8 +71,8 @@ inline size_t dtype_size(ash_dtype_t t) {
 inline bool pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
 
 struct DevMem {
-  ash_allocator_t a;
-  bool custom;
+  ash_allocator_t a{};
+  bool custom = false;  // hipMalloc / hipFree unless an allocator was given
   // Kernels load 16-byte slots, CAS 8-byte pairs and fill 16 bytes at a
   // time from the start of each block, so a block that is not 256-byte
   // aligned is handed back and reported as an allocation failure.

@@ -1542,11 +1542,11 @@ __global__ __launch_bounds__(kBlock) void k_voxel_resolve(TableRef tb, uint32_t 
 // Batched maps in one persistent cooperative launch.  Phases, separated by
 // grid barriers: claims of every item -> (per-map new-key sums, only when a
 // capacity check is needed) -> commits (each map's last tile finalizes the
-// map) -> finds.  Each
-// phase walks a flat list of tiles strided over the resident blocks; a block
-// takes its tiles in increasing order and all blocks are co-resident, so the
-// per-map look-back of the commit phase (which only waits on lower tiles of
-// the same map) always completes.  Each item keeps its own probe shape.
+// map) -> finds.  Each phase walks a flat list of tiles handed out in
+// increasing order to the resident blocks (for_each_tile); all blocks are
+// co-resident, so the per-map look-back of the commit phase (which only
+// waits on lower tiles of the same map) always completes.  Each item keeps
+// its own probe shape.
 // The item that holds tile t of a phase: the last item whose first tile is
 // <= t.  A block visits its tiles in increasing order, so it moves its
 // current item forward instead of searching (usually one check per tile).
@@ -1556,9 +1556,17 @@ __device__ __forceinline__ int advance_item(const BatchItem* __restrict__ items,
   return cur;
 }
 
-template <int KD>
+// kNarrow: a build for launches whose items all probe one lane per key with
+// W <= 4 (what the batched tuner picks); leaving the wider windows out of
+// the kernel lowers its register count, so more blocks stay resident.
+template <int KD, bool kNarrow>
 __device__ __forceinline__ void batched_claim(const BatchItem& it, uint32_t tile, TileLds& lds) {
   const BatchKeys<KD> src{it.ikeys};
+  if constexpr (kNarrow) {
+    if (it.w == 2) claim_tile<KD, 1, 2, BatchKeys<KD>, false>(it.tb, src, it.n_insert, tile, rounds_for_dev<1>(), it.slot_of, it.lost, it.partial, it.meta, lds);
+    else claim_tile<KD, 1, 4, BatchKeys<KD>, false>(it.tb, src, it.n_insert, tile, rounds_for_dev<1>(), it.slot_of, it.lost, it.partial, it.meta, lds);
+    return;
+  }
   switch (it.g == 1 ? it.w : 100 + it.g) {
     case 2: claim_tile<KD, 1, 2, BatchKeys<KD>, false>(it.tb, src, it.n_insert, tile, rounds_for_dev<1>(), it.slot_of, it.lost, it.partial, it.meta, lds); break;
     case 4: claim_tile<KD, 1, 4, BatchKeys<KD>, false>(it.tb, src, it.n_insert, tile, rounds_for_dev<1>(), it.slot_of, it.lost, it.partial, it.meta, lds); break;
@@ -1572,8 +1580,13 @@ __device__ __forceinline__ void batched_claim(const BatchItem& it, uint32_t tile
   }
 }
 
-template <int KD>
+template <int KD, bool kNarrow>
 __device__ __forceinline__ void batched_find(const BatchItem& it, uint32_t tile, TileLds& lds) {
+  if constexpr (kNarrow) {
+    if (it.w == 2) find_tile<KD, 1, 2>(it.tb, BatchKeys<KD>{it.fkeys}, it.n_find, tile, rounds_for_dev<1>(), DirectOut{it.fidx, it.fmask}, it.vout, lds);
+    else find_tile<KD, 1, 4>(it.tb, BatchKeys<KD>{it.fkeys}, it.n_find, tile, rounds_for_dev<1>(), DirectOut{it.fidx, it.fmask}, it.vout, lds);
+    return;
+  }
   switch (it.g == 1 ? it.w : 100 + it.g) {
     case 2: find_tile<KD, 1, 2>(it.tb, BatchKeys<KD>{it.fkeys}, it.n_find, tile, rounds_for_dev<1>(), DirectOut{it.fidx, it.fmask}, it.vout, lds); break;
     case 4: find_tile<KD, 1, 4>(it.tb, BatchKeys<KD>{it.fkeys}, it.n_find, tile, rounds_for_dev<1>(), DirectOut{it.fidx, it.fmask}, it.vout, lds); break;
@@ -1587,12 +1600,10 @@ __device__ __forceinline__ void batched_find(const BatchItem& it, uint32_t tile,
   }
 }
 
-// Grid barriers of the persistent launch.  Every block adds itself to
-// gs->count (a release: its earlier writes become visible at agent scope)
-// and waits until all gridDim.x blocks have passed the same number of
-// barriers (then an acquire).
+// Grid barriers of the persistent launch: an arrival check, then the phase
+// barriers (grid_barrier).
 //
-// The first barrier is an arrival check before any table is touched, and it
+// The arrival check comes before any table is touched, and it
 // either lets every block through or none: a block that has waited
 // arrival_spins polls gives up by setting kArrivalFailed with a
 // compare-and-swap that only succeeds while some block has not arrived, and
@@ -1607,12 +1618,38 @@ __device__ __forceinline__ void batched_find(const BatchItem& it, uint32_t tile,
 // Later barriers wait on blocks that are all resident (each passed the
 // arrival check and stays until it exits), so they only end early after a
 // broken invariant: the bound then sets gs->late and marks every map.
+// The XCC (accelerator complex die, with its own L2) the calling wave runs on.
+__device__ __forceinline__ uint32_t xcc_id() {
+  return (uint32_t)__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & (kMaxXcc - 1u);  // XCC_ID[3:0]
+}
+
+// Barrier state of a block of the persistent launch (thread 0's copy is the
+// one used).
+struct BarrierState {
+  uint32_t passed = 0;      // phase barriers passed
+  uint32_t xcc = 0;         // this block's XCC
+  uint32_t xcc_blocks = 0;  // blocks of the launch on that XCC
+  uint32_t n_xcc = 0;       // XCCs the launch runs on
+};
+
 __device__ __forceinline__ bool arrival_check(GridSync* gs, uint32_t arrival_spins, uint32_t force_fail,
-                                              uint32_t* s_ok) {
+                                              BarrierState& bs, uint32_t* s_ok) {
   __syncthreads();
   if (threadIdx.x == 0) {
+    // Relaxed atomics: no block has written anything yet, and what the
+    // blocks read next was written before the launch (a release per block
+    // would write back its XCC's L2 once per block).  A block first counts
+    // itself on its XCC (and the XCC, when it is the first there), waits for
+    // those atomics to be done, and only then counts itself in, so a block
+    // that sees every arrival also sees every XCC count.
+    bs.xcc = xcc_id();
+    if (!force_fail) {
+      if (__hip_atomic_fetch_add(&gs->xcc_blocks[bs.xcc][0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u)
+        __hip_atomic_fetch_add(&gs->n_xcc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_s_waitcnt(0);
+    }
     uint32_t c = force_fail ? __hip_atomic_load(&gs->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                            : __hip_atomic_fetch_add(&gs->count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+                            : __hip_atomic_fetch_add(&gs->count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
     if (force_fail) arrival_spins = 0;
     bool ok = false;
     uint32_t spins = 0;
@@ -1634,30 +1671,72 @@ __device__ __forceinline__ bool arrival_check(GridSync* gs, uint32_t arrival_spi
       __builtin_amdgcn_s_sleep(2);
       c = __hip_atomic_load(&gs->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (ok) {
+      bs.xcc_blocks = __hip_atomic_load(&gs->xcc_blocks[bs.xcc][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      bs.n_xcc = __hip_atomic_load(&gs->n_xcc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     *s_ok = ok ? 1u : 0u;
   }
   __syncthreads();
   return *s_ok != 0u;
 }
 
-__device__ __forceinline__ bool grid_barrier(GridSync* gs, uint32_t& passed, const BatchItem* __restrict__ items, int32_t n_items,
-                             uint32_t* s_ok) {
+__device__ __forceinline__ uint32_t* release_flag(GridSync* gs, uint32_t b) {
+  return reinterpret_cast<uint32_t*>(gs + 1) + (size_t)b * kFlagWords;
+}
+
+// A phase barrier, in two levels.  Every wave first waits until its stores
+// of the phase are in its XCC's L2; each block then counts itself on its XCC
+// (a relaxed atomic).  The block that completes its XCC's count writes that
+// L2 back once (a release fence at agent scope), for every block of the XCC,
+// and counts the XCC done; the block that completes the count of XCCs
+// acquires and writes the barrier's number into every block's release flag.
+// Each block waits on its own flag, then acquires.  So a barrier costs one
+// L2 write-back per XCC instead of one per block (each write-back stalls the
+// XCC's L2 under the blocks still at work), and the polls are spread over
+// one line per block instead of queueing on one word at the memory side.
+__device__ __forceinline__ bool grid_barrier(GridSync* gs, BarrierState& bs, const BatchItem* __restrict__ items,
+                                             int32_t n_items, uint32_t* s_sh) {
+  __builtin_amdgcn_s_waitcnt(0);  // this wave's stores have reached the L2
   __syncthreads();
+  const uint32_t gen = ++bs.passed;
   if (threadIdx.x == 0) {
-    bool ok = __hip_atomic_load(&gs->late, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u;
-    passed += 1;
+    const bool ok = __hip_atomic_load(&gs->late, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u;
+    uint32_t last = 0;
     if (ok) {
-      __hip_atomic_fetch_add(&gs->count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      const uint32_t target = passed * gridDim.x;
+      const uint32_t c = __hip_atomic_fetch_add(&gs->xcc_count[bs.xcc][0], 1u, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT) + 1u;
+      if (c == gen * bs.xcc_blocks) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // the whole XCC's writes of the phase
+        const uint32_t d = __hip_atomic_fetch_add(&gs->xcc_done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+        if (d == gen * bs.n_xcc) {
+          last = 1u;
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+      }
+    }
+    s_sh[0] = ok ? 1u : 0u;
+    s_sh[1] = last;
+  }
+  __syncthreads();
+  if (s_sh[1] != 0u) {  // every block has arrived: release them all
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    for (uint32_t b = threadIdx.x; b < gridDim.x; b += kBlock)
+      __hip_atomic_store(release_flag(gs, b), gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (threadIdx.x == 0) {
+    bool ok = s_sh[0] != 0u;
+    if (ok) {
+      const uint32_t* flag = release_flag(gs, blockIdx.x);
       uint32_t spins = 0;
-      while (true) {
-        if (__hip_atomic_load(&gs->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
-        if (__hip_atomic_load(&gs->late, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u || ++spins == kPhaseSpinLimit) {
+      while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
+        ++spins;
+        if (spins == kPhaseSpinLimit ||
+            ((spins & 63u) == 0u && __hip_atomic_load(&gs->late, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)) {
           ok = false;
           break;
         }
-        __builtin_amdgcn_s_sleep(2);
+        __builtin_amdgcn_s_sleep(32);  // about 1 us
       }
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
@@ -1665,50 +1744,84 @@ __device__ __forceinline__ bool grid_barrier(GridSync* gs, uint32_t& passed, con
       for (int32_t m = 0; m < n_items; ++m)  // the first block to give up marks every map
         __hip_atomic_fetch_or(&items[m].meta->status, kStatusGridStall, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    *s_ok = ok ? 1u : 0u;
+    s_sh[0] = ok ? 1u : 0u;
   }
   __syncthreads();
-  return *s_ok != 0u;
+  return s_sh[0] != 0u;
 }
 
-template <int KD>
+// Tiles of one phase, handed out at run time.  The tiles are dealt over K =
+// min(kTileQueues, gridDim.x) queues (tile t is in queue t mod K), and
+// block b serves queue b mod K: its first tile is b itself, and each later
+// one comes from the queue's counter, fetched while the block works on its
+// current tile.  Blocks that run faster take more tiles (on a CU the older
+// waves win issue priority, so a static share leaves the later-placed
+// blocks last), and a phase ends with its work instead of with the slowest
+// block's share.  A single counter for all tiles would take one atomic per
+// tile on one address, which serializes at the memory side; K counters on
+// lines of their own split that.  Within a queue tiles go out in increasing
+// order, so the commit's look-back (which waits only on lower tiles of its
+// map) still always completes: take the lowest tile that has been handed out
+// and is unfinished; its block works on it (a block's fetched next tile is
+// above its current one), and a lower tile not yet handed out would sit in a
+// queue whose blocks all work on still lower tiles, so every lower tile is
+// done.
+template <typename F>
+__device__ __forceinline__ void for_each_tile(uint32_t (*next)[32], uint32_t n_tiles, uint32_t* s_next, F&& body) {
+  const uint32_t K = gridDim.x < kTileQueues ? gridDim.x : kTileQueues;
+  const uint32_t q = blockIdx.x % K;
+  const uint32_t first = (gridDim.x - q + K - 1) / K;  // blocks of queue q, which take its first tiles
+  uint32_t* ctr = &next[q][0];
+  uint32_t t = blockIdx.x;
+  while (t < n_tiles) {
+    uint32_t nxt = 0;
+    if (threadIdx.x == 0) nxt = q + K * (first + atomic_add_u32(ctr, 1u));
+    body(t);
+    __syncthreads();  // every thread has read *s_next for this tile
+    if (threadIdx.x == 0) *s_next = nxt;
+    __syncthreads();
+    t = *s_next;
+  }
+}
+
+template <int KD, bool kNarrow>
 __global__ __launch_bounds__(kBlock) void k_batched(const BatchItem* __restrict__ items, int32_t n_items,
                                                     uint32_t claim_tiles, uint32_t commit_tiles, uint32_t find_tiles,
                                                     int32_t any_check, GridSync* gs, uint32_t arrival_spins,
                                                     uint32_t force_fail) {
   __shared__ TileLds lds;
-  __shared__ uint32_t s_ok;
-  if (!arrival_check(gs, arrival_spins, force_fail, &s_ok)) return;  // all blocks resident, or none works
-  uint32_t passed = 1;
+  __shared__ uint32_t s_ok, s_next, s_sh[2];
+  BarrierState bs;
+  if (!arrival_check(gs, arrival_spins, force_fail, bs, &s_ok)) return;  // all blocks resident, or none works
   int cur = 0;
-  for (uint32_t t = blockIdx.x; t < claim_tiles; t += gridDim.x) {
+  for_each_tile(gs->next[0], claim_tiles, &s_next, [&](uint32_t t) {
     cur = advance_item<&BatchItem::claim0>(items, n_items, cur, t);
     const BatchItem& it = items[cur];
-    batched_claim<KD>(it, t - it.claim0, lds);
-  }
-  if (!grid_barrier(gs, passed, items, n_items, &s_ok)) return;
+    batched_claim<KD, kNarrow>(it, t - it.claim0, lds);
+  });
+  if (!grid_barrier(gs, bs, items, n_items, s_sh)) return;
   if (any_check) {
     for (int m = blockIdx.x; m < n_items; m += gridDim.x) {
       const BatchItem& it = items[m];
       if (it.check && it.n_insert) sum_partials_block<kBlock>(it.partial, (it.n_insert + 255u) / 256u, it.meta, lds);
     }
-    if (!grid_barrier(gs, passed, items, n_items, &s_ok)) return;
+    if (!grid_barrier(gs, bs, items, n_items, s_sh)) return;
   }
   cur = 0;
-  for (uint32_t t = blockIdx.x; t < commit_tiles; t += gridDim.x) {
+  for_each_tile(gs->next[1], commit_tiles, &s_next, [&](uint32_t t) {
     cur = advance_item<&BatchItem::commit0>(items, n_items, cur, t);
     const BatchItem& it = items[cur];
     // each map's last commit tile finalizes that map (as in k_commit)
     commit_tile<KD, true>(it.tb, it.ikeys, it.n_insert, t - it.commit0, it.slot_of, it.lost, it.kB, it.heap, it.cap,
                           it.vin, it.iidx, it.imask, it.meta, it.status, it.check, nullptr, 0, lds);
-  }
-  if (!grid_barrier(gs, passed, items, n_items, &s_ok)) return;
+  });
+  if (!grid_barrier(gs, bs, items, n_items, s_sh)) return;
   cur = 0;
-  for (uint32_t t = blockIdx.x; t < find_tiles; t += gridDim.x) {
+  for_each_tile(gs->next[2], find_tiles, &s_next, [&](uint32_t t) {
     cur = advance_item<&BatchItem::find0>(items, n_items, cur, t);
     const BatchItem& it = items[cur];
-    batched_find<KD>(it, t - it.find0, lds);
-  }
+    batched_find<KD, kNarrow>(it, t - it.find0, lds);
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -2311,42 +2424,57 @@ hipError_t launch_voxel_resolve(const TableRef& tb, uint32_t n, const uint32_t* 
   return hipGetLastError();
 }
 
-template <int KD>
+template <int KD, bool kNarrow>
 static hipError_t batched_k(const BatchItem* items, int32_t n_items, uint32_t claim_tiles, uint32_t commit_tiles,
                             uint32_t find_tiles, int32_t any_check, GridSync* gs, uint32_t resident,
                             uint32_t arrival_spins, uint32_t force_fail, hipStream_t st) {
   // n_items == 0 launches all `resident` blocks with no work: a residency probe
   const uint32_t work = std::max(std::max(claim_tiles, commit_tiles), std::max(find_tiles, (uint32_t)n_items));
   const uint32_t grid = n_items == 0 ? resident : std::max<uint32_t>(1, std::min<uint32_t>(resident, work));
-  hipLaunchKernelGGL((k_batched<KD>), dim3(grid), dim3(kBlock), 0, st, items, n_items, claim_tiles, commit_tiles,
-                     find_tiles, any_check, gs, arrival_spins, force_fail);
+  hipLaunchKernelGGL((k_batched<KD, kNarrow>), dim3(grid), dim3(kBlock), 0, st, items, n_items, claim_tiles,
+                     commit_tiles, find_tiles, any_check, gs, arrival_spins, force_fail);
   return hipGetLastError();
 }
 
-hipError_t batched_occupancy(int kd, int* per_cu) {
+template <bool kNarrow>
+static hipError_t batched_occupancy_k(int kd, int* per_cu) {
   switch (kd) {
-    case 1: return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batched<1>, kBlock, 0);
-    case 2: return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batched<2>, kBlock, 0);
-    case 3: return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batched<3>, kBlock, 0);
-    case 4: return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batched<4>, kBlock, 0);
+    case 1: return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batched<1, kNarrow>, kBlock, 0);
+    case 2: return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batched<2, kNarrow>, kBlock, 0);
+    case 3: return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batched<3, kNarrow>, kBlock, 0);
+    case 4: return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batched<4, kNarrow>, kBlock, 0);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_batched(int kd, const BatchItem* items, int32_t n_items, uint32_t claim_tiles, uint32_t commit_tiles,
-                          uint32_t find_tiles, int32_t any_check, GridSync* gs, uint32_t resident,
-                          uint32_t arrival_spins, uint32_t force_fail, hipStream_t st) {
+hipError_t batched_occupancy(int kd, bool narrow, int* per_cu) {
+  return narrow ? batched_occupancy_k<true>(kd, per_cu) : batched_occupancy_k<false>(kd, per_cu);
+}
+
+template <bool kNarrow>
+static hipError_t launch_batched_k(int kd, const BatchItem* items, int32_t n_items, uint32_t claim_tiles,
+                                   uint32_t commit_tiles, uint32_t find_tiles, int32_t any_check, GridSync* gs,
+                                   uint32_t resident, uint32_t arrival_spins, uint32_t force_fail, hipStream_t st) {
   switch (kd) {
-    case 1: return batched_k<1>(items, n_items, claim_tiles, commit_tiles, find_tiles, any_check, gs, resident,
-                                    arrival_spins, force_fail, st);
-    case 2: return batched_k<2>(items, n_items, claim_tiles, commit_tiles, find_tiles, any_check, gs, resident,
-                                    arrival_spins, force_fail, st);
-    case 3: return batched_k<3>(items, n_items, claim_tiles, commit_tiles, find_tiles, any_check, gs, resident,
-                                    arrival_spins, force_fail, st);
-    case 4: return batched_k<4>(items, n_items, claim_tiles, commit_tiles, find_tiles, any_check, gs, resident,
-                                    arrival_spins, force_fail, st);
+    case 1: return batched_k<1, kNarrow>(items, n_items, claim_tiles, commit_tiles, find_tiles, any_check, gs,
+                                         resident, arrival_spins, force_fail, st);
+    case 2: return batched_k<2, kNarrow>(items, n_items, claim_tiles, commit_tiles, find_tiles, any_check, gs,
+                                         resident, arrival_spins, force_fail, st);
+    case 3: return batched_k<3, kNarrow>(items, n_items, claim_tiles, commit_tiles, find_tiles, any_check, gs,
+                                         resident, arrival_spins, force_fail, st);
+    case 4: return batched_k<4, kNarrow>(items, n_items, claim_tiles, commit_tiles, find_tiles, any_check, gs,
+                                         resident, arrival_spins, force_fail, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_batched(int kd, bool narrow, const BatchItem* items, int32_t n_items, uint32_t claim_tiles,
+                          uint32_t commit_tiles, uint32_t find_tiles, int32_t any_check, GridSync* gs,
+                          uint32_t resident, uint32_t arrival_spins, uint32_t force_fail, hipStream_t st) {
+  return narrow ? launch_batched_k<true>(kd, items, n_items, claim_tiles, commit_tiles, find_tiles, any_check, gs,
+                                         resident, arrival_spins, force_fail, st)
+                : launch_batched_k<false>(kd, items, n_items, claim_tiles, commit_tiles, find_tiles, any_check, gs,
+                                          resident, arrival_spins, force_fail, st);
 }
 
 }  // namespace ash

@@ -114,16 +114,20 @@ hipError_t launch_voxel_resolve(const TableRef& tb, uint32_t n, const uint32_t* 
 // Inserts then finds of n_items independent maps in one persistent launch.
 // items is a device array; tile counts are the flat totals of each phase.
 // One persistent launch over the items (grid = min(resident, work) blocks).
-// gs must be zero; resident is a block count the device runs all at once
+// gs (grid_sync_bytes(resident) bytes) must be zero; resident is a block
+// count the device runs all at once
 // (batched_occupancy gives the upper bound per CU); arrival_spins bounds the
 // arrival check (kArrivalSpinLimit); force_fail = 1 makes the check fail (a
 // test of the fallback path: no map is touched).  Afterwards gs->count carries
 // kArrivalFailed when the blocks were not all resident (no map touched) and
-// gs->late is nonzero when a later barrier gave up.
-hipError_t launch_batched(int kd, const BatchItem* items, int32_t n_items, uint32_t claim_tiles, uint32_t commit_tiles,
-                          uint32_t find_tiles, int32_t any_check, GridSync* gs, uint32_t resident,
-                          uint32_t arrival_spins, uint32_t force_fail, hipStream_t st);
-hipError_t batched_occupancy(int kd, int* per_cu);
+// gs->late is nonzero when a later barrier gave up.  narrow selects the
+// build that holds only the one-lane-per-key probes with W <= 4 (every item
+// must have g == 1 and W <= 4); it needs fewer registers, so its resident
+// block count is its own.
+hipError_t launch_batched(int kd, bool narrow, const BatchItem* items, int32_t n_items, uint32_t claim_tiles,
+                          uint32_t commit_tiles, uint32_t find_tiles, int32_t any_check, GridSync* gs,
+                          uint32_t resident, uint32_t arrival_spins, uint32_t force_fail, hipStream_t st);
+hipError_t batched_occupancy(int kd, bool narrow, int* per_cu);
 
 // Synthetic keys of the autotuner (uniform in [0, side)^kd; finds half hits).
 hipError_t launch_synth_keys(int32_t* keys, uint32_t n, int kd, uint32_t side, uint64_t seed, int32_t* fkeys,

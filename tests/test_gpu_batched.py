@@ -115,7 +115,7 @@ def test_batched_empty_ops_and_hash_sets(ash):
 def test_autotune_picks_a_valid_shape(ash, batched):
     tun, ms = ash.autotune(40_000, 20_000, 0.5, key_dim=3, value_specs=[(torch.float32, 8)], batched=batched)
     if batched:  # the batched sweep keeps one lane per key
-        assert tun["probe_group"] == 1 and tun["bucket_width"] in (2, 4, 8)
+        assert tun["probe_group"] == 1 and tun["bucket_width"] in (2, 4)
     else:
         assert tun["probe_group"] in (1, 4, 8, 16, 64)
         assert tun["bucket_width"] in (4, 8, 16, 32)
@@ -156,6 +156,48 @@ def test_batched_other_key_dims(ash, key_dim):
         assert np.array_equal(bits(host(r["find_values"][0])), bits(fv))
     check_maps(maps, oracles)
     assert [m.device_status() for m in maps] == [0, 0, 0]
+
+
+@pytest.mark.parametrize("key_dim", [1, 2, 3, 4])
+def test_batched_narrow_build(ash, key_dim):
+    """Launches whose maps all probe one lane per key with W = 2 or 4 run the
+    build of the persistent kernel that holds only those probes; it needs
+    fewer registers, so more of its blocks run at once.  Two rounds against
+    the oracle, then the grid of both builds."""
+    import ctypes
+
+    from paper_2110_00511_amd import _lib as L
+    rng = np.random.default_rng(60 + key_dim)
+    sizes = [40000, 700, 9000, 120000, 3000]
+    maps, oracles, cases = [], [], []
+    for i, u in enumerate(sizes):
+        # room for both rounds' distinct keys (up to about 2.5u)
+        maps.append(ash.HashMap(3 * u, key_dim, [(torch.float32, 8)], probe_group=1, bucket_width=(2, 4)[i % 2],
+                                max_load=(0.5, 0.7, 0.85)[i % 3], lds_dedup=i % 2 == 0))
+        oracles.append(OracleMap(3 * u, key_dim, [(np.float32, 8)]))
+    for rnd in range(2):
+        cases = []
+        for u in sizes:
+            n = 2 * u if rnd == 0 else max(u // 3, 1)
+            side = max(2, int(round(n ** (1 / key_dim))))
+            k = rng.integers(-side, side, size=(n, key_dim), dtype=np.int32)
+            v = rng.standard_normal((n, 8)).astype(np.float32)
+            f = np.concatenate([k[rng.integers(0, n, size=n // 2)],
+                                rng.integers(2 * side, 3 * side, size=(n - n // 2, key_dim), dtype=np.int32)])
+            cases.append((k, v, np.ascontiguousarray(f)))
+        print(f"case: narrow batched build, key_dim {key_dim}, round {rnd}", flush=True)
+        assert run_round(ash, maps, oracles, cases, True) == [0] * len(sizes)
+        check_maps(maps, oracles)
+    assert [m.device_status() for m in maps] == [0] * len(sizes)
+    lib = L.load()
+    sp = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    got = {}
+    for narrow in (0, 1):
+        blocks, reported = ctypes.c_int64(0), ctypes.c_int64(0)
+        L.check(lib.ash_batched_grid(key_dim, narrow, ctypes.byref(blocks), ctypes.byref(reported), sp), "grid")
+        assert 0 < blocks.value <= reported.value
+        got[narrow] = reported.value
+    assert got[1] >= got[0]
 
 
 def test_batched_full_size(ash):
