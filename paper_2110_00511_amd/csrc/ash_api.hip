@@ -488,10 +488,12 @@ ash_status_t ash_destroy(ash_map_t m) {
   m->mem.put(m->partial, st);
   m->mem.put(m->lost, st);
   m->mem.put(m->scan_status, st);
+  m->mem.put(m->batch_dev, st);
   for (hipEvent_t e : m->prof.pool) (void)hipEventDestroy(e);
-  if (m->mirror_h) {
+  if (m->mirror_h || m->batch_host) {
     (void)hipDeviceSynchronize();  // no finalize may still write the mirror
-    (void)hipHostFree(m->mirror_h);
+    if (m->mirror_h) (void)hipHostFree(m->mirror_h);
+    if (m->batch_host) (void)hipHostFree(m->batch_host);
   }
   delete m;
   return ASH_OK;
@@ -1101,16 +1103,30 @@ ash_status_t ash_batched(const ash_batch_op_t* ops, int32_t n_ops, int32_t fused
   const size_t item_bytes = (sizeof(ash::BatchItem) * (size_t)n_ops + 255) / 256 * 256;
   const size_t gs_bytes = ash::grid_sync_bytes(resident);
   const size_t bytes = item_bytes + gs_bytes;
-  uint8_t* dev = (uint8_t*)m0->mem.get(bytes, st);
-  if (!dev) return ASH_E_NOMEM;
+  if (m0->batch_dev_bytes < bytes) {
+    m0->mem.put(m0->batch_dev, st);
+    m0->batch_dev_bytes = 0;
+    m0->batch_dev = (uint8_t*)m0->mem.get(bytes, st);
+    if (!m0->batch_dev) return ASH_E_NOMEM;
+    m0->batch_dev_bytes = bytes;
+  }
+  const size_t host_bytes = item_bytes + sizeof(ash::GridSync);
+  if (m0->batch_host_bytes < host_bytes) {  // every call ends synchronized, so no copy still reads the old one
+    if (m0->batch_host) (void)hipHostFree(m0->batch_host);
+    m0->batch_host = nullptr;
+    m0->batch_host_bytes = 0;
+    ASH_HIP(hipHostMalloc((void**)&m0->batch_host, host_bytes, hipHostMallocDefault));
+    m0->batch_host_bytes = host_bytes;
+  }
+  uint8_t* dev = m0->batch_dev;
   ash::BatchItem* dev_items = (ash::BatchItem*)dev;
   ash::GridSync* gs = (ash::GridSync*)(dev + item_bytes);
+  std::memcpy(m0->batch_host, items.data(), sizeof(ash::BatchItem) * (size_t)n_ops);
+  ash::GridSync& h = *(ash::GridSync*)(m0->batch_host + item_bytes);
   ash_status_t rc = ASH_OK;
-  ash::GridSync h;
-  std::memset(&h, 0, sizeof(h));
   const uint32_t force_fail = force_arrival_failure();
-  if (hipMemcpyAsync(dev_items, items.data(), sizeof(ash::BatchItem) * (size_t)n_ops, hipMemcpyHostToDevice, st) !=
-          hipSuccess ||
+  if (hipMemcpyAsync(dev_items, m0->batch_host, sizeof(ash::BatchItem) * (size_t)n_ops, hipMemcpyHostToDevice,
+                     st) != hipSuccess ||
       ash::launch_fill_u32((uint32_t*)gs, 0u, gs_bytes / 4, st) != hipSuccess ||
       timed(m0, "batched", st, [&] {
         return ash::launch_batched(kd, narrow, dev_items, n_ops, claim_tiles, commit_tiles, find_tiles, any_check,
@@ -1119,7 +1135,6 @@ ash_status_t ash_batched(const ash_batch_op_t* ops, int32_t n_ops, int32_t fused
       hipMemcpyAsync(&h, gs, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     rc = ASH_E_DEVICE;
-  m0->mem.put(dev, st);
   if (rc != ASH_OK) return rc;
   if (h.count & ash::kArrivalFailed) {
     // The blocks could not all run at once (other work holds CUs): the launch

@@ -188,6 +188,14 @@ struct ash_map {
   // ASH_CLAIM_KEYED=0 / 1 at create fixes the claim variant (-1: chosen per
   // insert from the last insert's new-key fraction); results are the same
   int keyed_override = -1;
+  // Buffers of the ash_batched launches that list this map first, kept
+  // between calls: on the device the items, the GridSync and the release
+  // flags; in pinned host memory a copy of the items (so their upload is a
+  // plain DMA) and the launch's GridSync as read back.
+  uint8_t* batch_dev = nullptr;
+  size_t batch_dev_bytes = 0;
+  uint8_t* batch_host = nullptr;
+  size_t batch_host_bytes = 0;
 
   int slot_words() const { return key_dim == 1 ? 2 : (key_dim <= 3 ? 4 : 8); }
 
