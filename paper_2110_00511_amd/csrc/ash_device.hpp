@@ -38,6 +38,10 @@ constexpr uint32_t kStatusGridStall = 8u;   // a persistent launch's blocks did 
 // Polls of a persistent launch's arrival check before its blocks give up
 // (about 0.1 s): no table has been touched then.
 constexpr uint32_t kArrivalSpinLimit = 1u << 20;
+// Polls after which a block that saw the arrival count complete stops waiting
+// for its release flag (about 3 s; the flag comes at once unless an invariant
+// is broken, and the launch then ends through the phase barriers' bound).
+constexpr uint32_t kArrivalWaitLimit = 1u << 26;
 // Polls of its later phase barriers (about 1 us apart, so about 8 s).  Once
 // every block has arrived, all blocks are resident and every phase ends, so
 // these waits only end early for a broken invariant; they must outlast the

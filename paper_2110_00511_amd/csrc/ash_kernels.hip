@@ -1603,17 +1603,20 @@ __device__ __forceinline__ void batched_find(const BatchItem& it, uint32_t tile,
 // Grid barriers of the persistent launch: an arrival check, then the phase
 // barriers (grid_barrier).
 //
-// The arrival check comes before any table is touched, and it
-// either lets every block through or none: a block that has waited
-// arrival_spins polls gives up by setting kArrivalFailed with a
-// compare-and-swap that only succeeds while some block has not arrived, and
-// no block passes while the flag is set.  So once one block has seen every
-// arrival, no give-up can succeed, and once a give-up has succeeded, no block
-// passes (blocks that start later see the flag in the value their arrival
-// returns).  If the blocks cannot all be resident at once, the resident ones
-// give up and leave, the rest then start, see the flag and leave, and the
-// launch ends with no map changed.  With force_fail (a test of that path)
-// no block counts itself in, so the first block to give up always succeeds.
+// The arrival check comes before any table is touched, and it either lets
+// every block through or none.  Each block counts itself in on gs->count;
+// the block whose arrival brings the count to gridDim.x writes every block's
+// release flag, and a block passes when it sees its flag.  A block that has
+// waited arrival_spins polls gives up by setting kArrivalFailed with a
+// compare-and-swap that only succeeds while some block has not arrived.  So
+// once the count is complete no give-up can succeed, and once a give-up has
+// succeeded the count never reads gridDim.x, no flag is written and no block
+// passes (blocks that start later see kArrivalFailed in the value their
+// arrival returns; waiting blocks reread the count).  If the blocks cannot
+// all be resident at once, the resident ones give up and leave, the rest
+// then start, see the flag and leave, and the launch ends with no map
+// changed.  With force_fail (a test of that path) no block counts itself in,
+// so the first block to give up always succeeds.
 //
 // Later barriers wait on blocks that are all resident (each passed the
 // arrival check and stays until it exits), so they only end early after a
@@ -1632,9 +1635,14 @@ struct BarrierState {
   uint32_t n_xcc = 0;       // XCCs the launch runs on
 };
 
+__device__ __forceinline__ uint32_t* release_flag(GridSync* gs, uint32_t b) {
+  return reinterpret_cast<uint32_t*>(gs + 1) + (size_t)b * kFlagWords;
+}
+
 __device__ __forceinline__ bool arrival_check(GridSync* gs, uint32_t arrival_spins, uint32_t force_fail,
-                                              BarrierState& bs, uint32_t* s_ok) {
+                                              BarrierState& bs, uint32_t* s_sh) {
   __syncthreads();
+  uint32_t c = 0;
   if (threadIdx.x == 0) {
     // Relaxed atomics: no block has written anything yet, and what the
     // blocks read next was written before the launch (a release per block
@@ -1648,18 +1656,26 @@ __device__ __forceinline__ bool arrival_check(GridSync* gs, uint32_t arrival_spi
         __hip_atomic_fetch_add(&gs->n_xcc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __builtin_amdgcn_s_waitcnt(0);
     }
-    uint32_t c = force_fail ? __hip_atomic_load(&gs->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                            : __hip_atomic_fetch_add(&gs->count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+    c = force_fail ? __hip_atomic_load(&gs->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                   : __hip_atomic_fetch_add(&gs->count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+    s_sh[1] = (!force_fail && c == gridDim.x) ? 1u : 0u;  // this arrival completed the count
+  }
+  __syncthreads();
+  if (s_sh[1] != 0u)  // every block has arrived: let them all through (flag value 1)
+    for (uint32_t b = threadIdx.x; b < gridDim.x; b += kBlock)
+      __hip_atomic_store(release_flag(gs, b), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0) {
     if (force_fail) arrival_spins = 0;
+    const uint32_t* flag = release_flag(gs, blockIdx.x);
     bool ok = false;
     uint32_t spins = 0;
     while (true) {
-      if (c & kArrivalFailed) break;
-      if (c >= gridDim.x) {
+      if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
         ok = true;
         break;
       }
-      if (spins >= arrival_spins) {
+      if ((c & kArrivalFailed) != 0u || spins == kArrivalWaitLimit) break;  // (the limit: a broken invariant)
+      if (c < gridDim.x && spins >= arrival_spins) {
         uint32_t expected = c;  // give up only while some block has not arrived
         if (__hip_atomic_compare_exchange_strong(&gs->count, &expected, c | kArrivalFailed, __ATOMIC_RELAXED,
                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
@@ -1669,20 +1685,16 @@ __device__ __forceinline__ bool arrival_check(GridSync* gs, uint32_t arrival_spi
       }
       ++spins;
       __builtin_amdgcn_s_sleep(2);
-      c = __hip_atomic_load(&gs->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if ((spins & 7u) == 0u) c = __hip_atomic_load(&gs->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     if (ok) {
       bs.xcc_blocks = __hip_atomic_load(&gs->xcc_blocks[bs.xcc][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       bs.n_xcc = __hip_atomic_load(&gs->n_xcc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    *s_ok = ok ? 1u : 0u;
+    s_sh[0] = ok ? 1u : 0u;
   }
   __syncthreads();
-  return *s_ok != 0u;
-}
-
-__device__ __forceinline__ uint32_t* release_flag(GridSync* gs, uint32_t b) {
-  return reinterpret_cast<uint32_t*>(gs + 1) + (size_t)b * kFlagWords;
+  return s_sh[0] != 0u;
 }
 
 // A phase barrier, in two levels.  Every wave first waits until its stores
@@ -1722,14 +1734,14 @@ __device__ __forceinline__ bool grid_barrier(GridSync* gs, BarrierState& bs, con
   if (s_sh[1] != 0u) {  // every block has arrived: release them all
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     for (uint32_t b = threadIdx.x; b < gridDim.x; b += kBlock)
-      __hip_atomic_store(release_flag(gs, b), gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(release_flag(gs, b), gen + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   if (threadIdx.x == 0) {
     bool ok = s_sh[0] != 0u;
     if (ok) {
       const uint32_t* flag = release_flag(gs, blockIdx.x);
       uint32_t spins = 0;
-      while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
+      while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen + 1u) {
         ++spins;
         if (spins == kPhaseSpinLimit ||
             ((spins & 63u) == 0u && __hip_atomic_load(&gs->late, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)) {
@@ -1790,9 +1802,9 @@ __global__ __launch_bounds__(kBlock) void k_batched(const BatchItem* __restrict_
                                                     int32_t any_check, GridSync* gs, uint32_t arrival_spins,
                                                     uint32_t force_fail) {
   __shared__ TileLds lds;
-  __shared__ uint32_t s_ok, s_next, s_sh[2];
+  __shared__ uint32_t s_next, s_sh[2];
   BarrierState bs;
-  if (!arrival_check(gs, arrival_spins, force_fail, bs, &s_ok)) return;  // all blocks resident, or none works
+  if (!arrival_check(gs, arrival_spins, force_fail, bs, s_sh)) return;  // all blocks resident, or none works
   int cur = 0;
   for_each_tile(gs->next[0], claim_tiles, &s_next, [&](uint32_t t) {
     cur = advance_item<&BatchItem::claim0>(items, n_items, cur, t);
