@@ -200,6 +200,23 @@ def test_batched_narrow_build(ash, key_dim):
     assert got[1] >= got[0]
 
 
+@pytest.mark.parametrize("sizes", [[1], [50, 300], [20, 700, 90, 5, 260]])
+def test_batched_small_grids(ash, sizes):
+    """Launches with fewer blocks than tile queues (a grid of one to a few
+    blocks, each block alone on its queue and XCD count), in both builds."""
+    rng = np.random.default_rng(70 + len(sizes))
+    for shape in ((1, 4), (4, 8)):
+        maps = [ash.HashMap(2 * u + 4, 3, [(torch.float32, 8)], probe_group=shape[0], bucket_width=shape[1])
+                for u in sizes]
+        oracles = [OracleMap(2 * u + 4, 3, [(np.float32, 8)]) for u in sizes]
+        print(f"case: small batched grid, sizes {sizes}, shape {shape}", flush=True)
+        for rnd in range(2):
+            cases = [make_case(rng, max(u // (1 + 2 * rnd), 1)) for u in sizes]
+            assert run_round(ash, maps, oracles, cases, True) == [0] * len(sizes)
+            check_maps(maps, oracles)
+        assert [m.device_status() for m in maps] == [0] * len(sizes)
+
+
 def test_batched_full_size(ash):
     """The benchmark's 64 maps (distinct counts log-uniform in [1e3, 1e6],
     f32x8 values) in one persistent launch with the batched tuner's shapes.
