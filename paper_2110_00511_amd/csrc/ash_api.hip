@@ -344,9 +344,8 @@ ash_status_t insert_impl(ash_map* m, const int32_t* keys, int64_t n, const void*
 }
 
 ash_status_t reset_state(ash_map* m, hipStream_t st) {
-  ASH_HIP(ash::launch_fill_u32(m->table, ash::kEmpty, (size_t)m->nslots * m->slot_words(), st));
-  ASH_HIP(ash::launch_iota(m->heap, 0, (uint32_t)m->c, st));
-  ASH_HIP(ash::launch_reset_meta(m->meta, st));
+  ASH_HIP(ash::launch_clear_map(m->table, (size_t)m->nslots * m->slot_words(), m->heap, (uint32_t)m->c, m->meta,
+                                st));
   m->live_ub = 0;
   m->used_ub = 0;
   m->tombs_possible = false;

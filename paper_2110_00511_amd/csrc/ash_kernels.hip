@@ -193,9 +193,23 @@ __global__ __launch_bounds__(kBlock) void k_iota(int32_t* __restrict__ h, uint32
   for (uint32_t i = from + blockIdx.x * blockDim.x + threadIdx.x; i < to; i += stride) h[i] = (int32_t)i;
 }
 
-__global__ void k_reset_meta(Meta* m) {
+__device__ __forceinline__ void reset_meta(Meta* m) {
   m->t = 0; m->claims = 0; m->used = 0; m->tombs = 0; m->status = 0; m->result = 0; m->fail = 0;
   m->epoch = m->epoch + 1u == 0u ? 1u : m->epoch + 1u;
+}
+
+__global__ void k_reset_meta(Meta* m) { reset_meta(m); }
+
+// A map emptied in one launch: every table word EMPTY (n_words, a multiple
+// of 4), the heap back to h[i] = i for i < c, and the counters reset.
+__global__ __launch_bounds__(kBlock) void k_clear_map(uint32_t* __restrict__ table, size_t n_words,
+                                                      int32_t* __restrict__ heap, uint32_t c, Meta* meta) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  const size_t i0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint4* t4 = reinterpret_cast<uint4*>(table);
+  for (size_t i = i0; i < n_words / 4; i += stride) t4[i] = make_uint4(kEmpty, kEmpty, kEmpty, kEmpty);
+  for (size_t i = i0; i < c; i += stride) heap[i] = (int32_t)i;
+  if (i0 == 0) reset_meta(meta);
 }
 
 // Positions per block of the probing kernels: 256 (G lanes per position, so a
@@ -1995,6 +2009,14 @@ hipError_t launch_iota(int32_t* h, uint32_t from, uint32_t to, hipStream_t st) {
 
 hipError_t launch_reset_meta(Meta* m, hipStream_t st) {
   hipLaunchKernelGGL(k_reset_meta, dim3(1), dim3(1), 0, st, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_clear_map(uint32_t* table, size_t n_words, int32_t* heap, uint32_t c, Meta* meta, hipStream_t st) {
+  if (n_words % 4 != 0) return hipErrorInvalidValue;
+  const size_t work = std::max<size_t>(n_words / 4, c);
+  const uint32_t grid = (uint32_t)std::max<size_t>(1, std::min<size_t>((work + kBlock - 1) / kBlock, 65536));
+  hipLaunchKernelGGL(k_clear_map, dim3(grid), dim3(kBlock), 0, st, table, n_words, heap, c, meta);
   return hipGetLastError();
 }
 
