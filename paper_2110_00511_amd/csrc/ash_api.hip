@@ -829,11 +829,10 @@ ash_status_t voxelize_run(const float* points, int64_t n, float voxel, int32_t* 
   // every part that must start in a known state is written here by kernels
   // (the workspace may hold an earlier call's contents): an empty table,
   // zero status words and lost bytes, and zero counters with epoch 1
-  const bool ok = ash::launch_fill_u32(table, ash::kEmpty, (size_t)w.nslots * 4, st) == hipSuccess &&
-                  ash::launch_fill_u32((uint32_t*)status, 0u, (size_t)w.tiles * 2, st) == hipSuccess &&
-                  ash::launch_fill_u32((uint32_t*)lost, 0u, w.lost_bytes / 4, st) == hipSuccess &&
-                  ash::launch_fill_u32((uint32_t*)meta, 0u, sizeof(Meta) / 4, st) == hipSuccess &&
-                  ash::launch_reset_meta(meta, st) == hipSuccess &&
+  // (one launch: the lost bytes and the status words are one range, the
+  // counters follow it)
+  const bool ok = ash::launch_voxel_init(table, (size_t)w.nslots * 4, (uint32_t*)lost,
+                                         (w.status - w.lost) / 4 + (size_t)w.tiles * 2, meta, st) == hipSuccess &&
                   ash::launch_voxel_claim(kVoxG, kVoxW, tb, points, voxel, un, slot_of, lost, partial, meta, st) ==
                       hipSuccess &&
                   ash::launch_sum_partials(partial, blocks, meta, st) == hipSuccess &&

@@ -200,6 +200,23 @@ __device__ __forceinline__ void reset_meta(Meta* m) {
 
 __global__ void k_reset_meta(Meta* m) { reset_meta(m); }
 
+// A voxelization workspace made ready in one launch: the table's words
+// EMPTY (n_table a multiple of 4), n_zero words from `zero` cleared (the lost
+// bytes and scan status words), and the counters zero with epoch 1.
+__global__ __launch_bounds__(kBlock) void k_voxel_init(uint32_t* __restrict__ table, size_t n_table,
+                                                       uint32_t* __restrict__ zero, size_t n_zero, Meta* meta) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  const size_t i0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint4* t4 = reinterpret_cast<uint4*>(table);
+  for (size_t i = i0; i < n_table / 4; i += stride) t4[i] = make_uint4(kEmpty, kEmpty, kEmpty, kEmpty);
+  for (size_t i = i0; i < n_zero; i += stride) zero[i] = 0u;
+  if (i0 == 0) {
+    uint32_t* w = reinterpret_cast<uint32_t*>(meta);
+    for (size_t k = 0; k < sizeof(Meta) / 4; ++k) w[k] = 0u;
+    meta->epoch = 1u;
+  }
+}
+
 // A map emptied in one launch: every table word EMPTY (n_words, a multiple
 // of 4), the heap back to h[i] = i for i < c, and the counters reset.
 __global__ __launch_bounds__(kBlock) void k_clear_map(uint32_t* __restrict__ table, size_t n_words,
@@ -2009,6 +2026,15 @@ hipError_t launch_iota(int32_t* h, uint32_t from, uint32_t to, hipStream_t st) {
 
 hipError_t launch_reset_meta(Meta* m, hipStream_t st) {
   hipLaunchKernelGGL(k_reset_meta, dim3(1), dim3(1), 0, st, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_voxel_init(uint32_t* table, size_t n_table, uint32_t* zero, size_t n_zero, Meta* meta,
+                             hipStream_t st) {
+  if (n_table % 4 != 0) return hipErrorInvalidValue;
+  const size_t work = std::max<size_t>(n_table / 4, n_zero);
+  const uint32_t grid = (uint32_t)std::max<size_t>(1, std::min<size_t>((work + kBlock - 1) / kBlock, 65536));
+  hipLaunchKernelGGL(k_voxel_init, dim3(grid), dim3(kBlock), 0, st, table, n_table, zero, n_zero, meta);
   return hipGetLastError();
 }
 

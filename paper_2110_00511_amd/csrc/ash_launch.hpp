@@ -57,6 +57,10 @@ hipError_t launch_reset_meta(Meta* m, hipStream_t st);
 // Table words (a multiple of 4) to EMPTY, h[i] = i for i < c, counters reset:
 // one launch.
 hipError_t launch_clear_map(uint32_t* table, size_t n_words, int32_t* heap, uint32_t c, Meta* meta, hipStream_t st);
+// Voxelization workspace: table words (a multiple of 4) to EMPTY, n_zero words
+// from `zero` to 0 (must not overlap meta), counters zero with epoch 1.
+hipError_t launch_voxel_init(uint32_t* table, size_t n_table, uint32_t* zero, size_t n_zero, Meta* meta,
+                             hipStream_t st);
 hipError_t launch_finalize(Meta* m, uint32_t cap, int mode, int silent, int check, const uint64_t* status,
                            uint32_t last_tile, hipStream_t st);
 hipError_t launch_sum_partials(const uint32_t* partial, uint32_t count, Meta* meta, hipStream_t st);
