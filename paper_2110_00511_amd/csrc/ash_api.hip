@@ -813,7 +813,6 @@ ash_status_t voxelize_run(const float* points, int64_t n, float voxel, int32_t* 
   uint8_t* lost = base + w.lost;
   uint64_t* status = (uint64_t*)(base + w.status);
   Meta* meta = (Meta*)(status + w.tiles);
-  const uint32_t blocks = ash::claim_blocks(kVoxG, un);
   TableRef tb;
   tb.words = table;
   tb.nslots = w.nslots;
@@ -835,7 +834,6 @@ ash_status_t voxelize_run(const float* points, int64_t n, float voxel, int32_t* 
                                          (w.status - w.lost) / 4 + (size_t)w.tiles * 2, meta, st) == hipSuccess &&
                   ash::launch_voxel_claim(kVoxG, kVoxW, tb, points, voxel, un, slot_of, lost, partial, meta, st) ==
                       hipSuccess &&
-                  ash::launch_sum_partials(partial, blocks, meta, st) == hipSuccess &&
                   ash::launch_voxel_commit(tb, points, voxel, un, slot_of, lost, out_voxel_keys, out_voxel_counts,
                                            out_point_voxel, meta, status, st) == hipSuccess &&
                   ash::launch_voxel_resolve(tb, un, slot_of, out_point_voxel, out_voxel_counts, st) == hipSuccess &&

@@ -1488,15 +1488,19 @@ __global__ __launch_bounds__(kBlock) void k_voxel_commit(TableRef tb, VoxelKeys 
       if (so == kNoSlot) point_voxel[p] = -1;  // rejected point
     }
   }
-  // Most points of a fine voxelization are alone in their voxel: then the
-  // voxel's id is not written into its slot (one random store per voxel),
-  // and the few later points find it through the first point's id instead
-  // (the slot still holds PENDING(first point); see k_voxel_resolve).
-  const bool publish = 2ull * meta->claims <= (uint64_t)n;
   uint32_t rank[kScanItems];
   uint32_t total;
   block_rank_rows(win, rank, total, s_scan);
   block_lookback(status, tile, meta->epoch, total, &meta->status, &s_prefix);
+  // the last tile's look-back saw every tile: it records the voxel count
+  if (threadIdx.x == 0 && tile == gridDim.x - 1) meta->claims = s_prefix + total;
+  // Where most points of a tile open a voxel (a fine voxelization), the
+  // tile does not write voxel ids into slots (one random store per voxel);
+  // the few later points find such an id through the voxel's first point
+  // instead (the slot still holds PENDING(first point); see
+  // k_voxel_resolve, which handles either state per slot).
+  const uint32_t tile_points = n - base < kScanTile ? n - base : kScanTile;
+  const bool publish = 2u * total <= tile_points;
 #pragma unroll
   for (int r = 0; r < kScanItems; ++r) {
     if (!win[r]) continue;
