@@ -94,24 +94,28 @@ def cpu_model():
         pass
     return None
 
-# HBM bytes per launch at the default workload, from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE runs scaled by what they read for the library's streaming copy of
-# 128 MiB (fetch x1.9996, write x1.0000).  They hold for the kernel sources
-# with these SHA-256 digests only: traffic is reported as null for any other
-# sources or workload.
+# HBM bytes per launch at the default workload, per table shape (probe_group,
+# bucket_width, max_load), from rocprofv3 FETCH_SIZE and WRITE_SIZE runs
+# scaled by what they read for the library's streaming copy of 128 MiB
+# (fetch x1.9996, write x1.0000).  They hold for the kernel sources with these
+# SHA-256 digests only: traffic is reported as null for any other sources,
+# workload or shape.
 MEASURED_TRAFFIC = {
-    "claim": 2.4238e9,
-    "commit": 0.9247e9,
-    "find": 1.4429e9,
-    "erase_mark": 0.8949e9,
-    "erase_commit": 0.1803e9,
+    (1, 2, 0.85): {"claim": 2.5071e9, "commit": 0.9230e9, "find": 1.5112e9, "erase_mark": 0.9211e9,
+                   "erase_commit": 0.1805e9},
+    (1, 4, 0.85): {"claim": 2.4555e9, "commit": 0.9230e9, "find": 1.4712e9, "erase_mark": 0.9001e9,
+                   "erase_commit": 0.1802e9},
+    (1, 2, 0.7): {"claim": 2.4860e9, "commit": 0.9231e9, "find": 1.4886e9, "erase_mark": 0.9223e9,
+                  "erase_commit": 0.1803e9},
+    (4, 4, 0.5): {"claim": 2.4237e9, "commit": 0.9226e9, "find": 1.4429e9, "erase_mark": 0.8949e9,
+                  "erase_commit": 0.1803e9},
 }
 # The same for the neighbor search (radius 1 over the 4.8M surface cells,
 # one lane per key, W = 4, max load 0.5, queries in first-appearance order),
 # on the same kernel sources.
 MEASURED_TRAFFIC_NEIGHBORS = 18.53e9
 MEASURED_SOURCES = {
-    "ash_kernels.hip": "6ef3f27a7eded86978caea5cef6f24549ce7060a6e0026919c982e36913321e6",
+    "ash_kernels.hip": "6124b26a2a74bc63c6ccaa96145e16c6310573c367bb8ebb8bdbbf2938978845",
     "ash_device.hpp": "cf221c03b17cac844c99a3452aaa61c4993f086eb01d64fc70f059fedac8000e",
 }
 
@@ -127,10 +131,15 @@ def sources_measured():
     return True
 
 
-def traffic_applies(args):
-    """True when the kernels and the workload are the ones the counters were taken on."""
-    return sources_measured() and ((args.rho, args.channels, args.probe_group, args.bucket_width, args.max_load) == (0.5, 8, 4, 4, 0.5)
-            and not args.lds_dedup and not args.sorted_keys)
+def measured_traffic(args, shape):
+    """The counters' bytes per kernel when the kernels, the workload and the
+    table shape are ones they were taken on, else None."""
+    if not sources_measured() or (args.rho, args.channels) != (0.5, 8) or args.lds_dedup or args.sorted_keys:
+        return None
+    for (pg, bw, ml), per_kernel in MEASURED_TRAFFIC.items():
+        if (pg, bw) == tuple(shape[:2]) and abs(ml - shape[2]) < 1e-4:
+            return per_kernel
+    return None
 
 
 def kernel_bytes(name, n, u, d, e, channels, inline_values=True):
@@ -175,6 +184,9 @@ def main():
     ap.add_argument("--probe-group", type=int, default=4)
     ap.add_argument("--bucket-width", type=int, default=4)
     ap.add_argument("--max-load", type=float, default=0.5)
+    ap.add_argument("--shape", choices=["tuned", "given"], default="tuned",
+                    help="plain map: table shape from ash_autotune for the workload (tuned) or from "
+                         "--probe-group/--bucket-width/--max-load (given)")
     ap.add_argument("--lds-dedup", action="store_true", help="drop block-local duplicates in LDS before probing")
     ap.add_argument("--sorted-keys", action="store_true",
                     help="insert the keys sorted (equal keys adjacent) instead of in random order")
@@ -257,8 +269,16 @@ def main():
     fidx = torch.empty(nf, dtype=torch.int32, device="cuda")
     fmask = torch.empty(nf, dtype=torch.uint8, device="cuda")
     emask = torch.empty(ne, dtype=torch.uint8, device="cuda")
-    m = ash.HashMap(d["capacity"], 3, [(torch.float32, args.channels)], probe_group=args.probe_group,
-                    bucket_width=args.bucket_width, max_load=args.max_load, lds_dedup=args.lds_dedup)
+    tune_s = None
+    if args.shape == "tuned":  # the shape the library's tuner picks for this workload on this GPU
+        t0 = time.perf_counter()
+        tun, _ = ash.autotune(d["capacity"], n, args.rho, 3, [(torch.float32, args.channels)])
+        tune_s = time.perf_counter() - t0
+        shape = (tun["probe_group"], tun["bucket_width"], round(float(tun["max_load"]), 4))
+    else:
+        shape = (args.probe_group, args.bucket_width, args.max_load)
+    m = ash.HashMap(d["capacity"], 3, [(torch.float32, args.channels)], probe_group=shape[0],
+                    bucket_width=shape[1], max_load=shape[2], lds_dedup=args.lds_dedup)
     lib = L.load()
     stream = torch.cuda.current_stream()
     sp = ctypes.c_void_p(stream.cuda_stream)
@@ -359,8 +379,9 @@ def main():
     ins_bytes = op_bytes("insert", GRANULE_B, u=u, C=C)["granule"] * n
     achieved = ins_bytes / (ins_ms * 1e-3) / 1e9
     traffic = None
-    if traffic_applies(args) and all(k in MEASURED_TRAFFIC for k in ins_parts):
-        traffic = round(sum(MEASURED_TRAFFIC[k] for k in ins_parts) / 1e9, 4)
+    mt = measured_traffic(args, shape)
+    if mt is not None and all(k in mt for k in ins_parts):
+        traffic = round(sum(mt[k] for k in ins_parts) / 1e9, 4)
 
     cpu = None
     if args.cpu_sample > 0:
@@ -397,8 +418,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"plain map at scale: insert {n} int32x3 keys (distinct ratio {args.rho}, "
                                f"f32x{args.channels} values), find {nf} (50% hits), erase {ne}",
-                   "capacity": d["capacity"], "ops_per_step": ops, "probe_group": args.probe_group,
-                   "bucket_width": args.bucket_width, "max_load": args.max_load, "lds_dedup": args.lds_dedup,
+                   "capacity": d["capacity"], "ops_per_step": ops, "probe_group": shape[0],
+                   "bucket_width": shape[1], "max_load": shape[2], "shape_from": args.shape,
+                   "autotune_s": None if tune_s is None else round(tune_s, 2), "lds_dedup": args.lds_dedup,
                    "sorted_keys": args.sorted_keys, "claim_variant": claim_name,
                    "measured": {"new_key_fraction": round(u, 4), "find_hit_rate": round(eta, 4),
                                 "erase_win_fraction": round(e, 4)}},

@@ -361,7 +361,7 @@ int64_t ash_batched_fallbacks(void);
 /* Autotuner for the table shape.  Times insert + find of a synthetic batch on
  * this device -- n_insert keys uniform in a cube sized for the expected ratio
  * of distinct keys, then n_insert finds with half hits -- for every
- * (bucket_width, probe_group, max_load) of the sweep W in {4, 8, 16, 32},
+ * (bucket_width, probe_group, max_load) of the sweep W in {2, 4, 8, 16, 32},
  * g in {1 (W <= 8), 4, 8, 16, 64}, max_load in {0.5, 0.7, 0.85}, and writes
  * the fastest to *out (flags 0) and its time in ms to *out_ms (nullable).
  * Results are cached per (key_dim, value bytes, log2 capacity, log2 n_insert,

@@ -1297,7 +1297,7 @@ ash_status_t ash_autotune(int64_t capacity, int32_t key_dim, int32_t n_values, c
                           const int64_t* value_elems, int64_t n_insert, double distinct_ratio,
                           const ash_allocator_t* allocator, void* stream, ash_tuning_t* out, double* out_ms) {
   return autotune_impl(capacity, key_dim, n_values, value_dtypes, value_elems, n_insert, distinct_ratio,
-                       {4, 8, 16, 32}, {1, 4, 8, 16, 64}, {0.5f, 0.7f, 0.85f}, false, allocator, stream, out,
+                       {2, 4, 8, 16, 32}, {1, 4, 8, 16, 64}, {0.5f, 0.7f, 0.85f}, false, allocator, stream, out,
                        out_ms);
 }
 

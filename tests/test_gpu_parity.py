@@ -388,16 +388,31 @@ def _closed_forms(d):
 @pytest.mark.parametrize("channels", [1, 8, 32])
 def test_plain_large_properties(ash, rho, channels):
     """The 10M-key workload at every (distinct ratio, channels) pair, in the
-    benchmark's launch configuration, checked for every position against
+    benchmark's launch configuration (the table shape the tuner picks for the
+    workload, as the benchmark takes it), checked for every position against
     closed forms: insert masks and indices, k^B and v^B, find masks, indices
     and gathered rows, erase masks, and after the 5M erase the whole heap,
     t, the active indices and re-find masks."""
-    print(f"case: plain 10M rho={rho} C={channels}", flush=True)
     d = synth.plain_large(rho=rho, channels=channels)
+    tun, _ = ash.autotune(d["capacity"], len(d["keys"]), rho, 3, [(torch.float32, channels)])
+    print(f"case: plain 10M rho={rho} C={channels} shape {tun}", flush=True)
+    _check_plain_large(ash, d, channels, tun)
+
+
+@pytest.mark.parametrize("g,w,lf", [(1, 2, 0.85), (1, 4, 0.85), (4, 4, 0.5), (1, 2, 0.7)])
+def test_plain_large_shapes(ash, g, w, lf):
+    """The benchmark's 10M-key workload (distinct ratio 0.5, f32x8) on the
+    shapes the tuner picks between for it, whatever it picks in this run."""
+    d = synth.plain_large(rho=0.5, channels=8)
+    print(f"case: plain 10M shape g={g} W={w} load={lf}", flush=True)
+    _check_plain_large(ash, d, 8, dict(probe_group=g, bucket_width=w, max_load=lf))
+
+
+def _check_plain_large(ash, d, channels, shape):
     keys, vals = d["keys"], d["values"]
     cf = _closed_forms(d)
     first = cf["first"]
-    m = ash.HashMap(d["capacity"], 3, [(torch.float32, channels)])
+    m = ash.HashMap(d["capacity"], 3, [(torch.float32, channels)], **shape)
     gi, gm = m.insert(dev(keys), [dev(vals)])
     gi, gm = host(gi), host(gm)
     want_mask = np.zeros(len(keys), bool)
