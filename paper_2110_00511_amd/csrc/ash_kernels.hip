@@ -198,8 +198,6 @@ __device__ __forceinline__ void reset_meta(Meta* m) {
   m->epoch = m->epoch + 1u == 0u ? 1u : m->epoch + 1u;
 }
 
-__global__ void k_reset_meta(Meta* m) { reset_meta(m); }
-
 // A voxelization workspace made ready in one launch: the table's words
 // EMPTY (n_table a multiple of 4), n_zero words from `zero` cleared (the lost
 // bytes and scan status words), and the counters zero with epoch 1.
@@ -2025,11 +2023,6 @@ hipError_t launch_iota(int32_t* h, uint32_t from, uint32_t to, hipStream_t st) {
   if (to <= from) return hipSuccess;
   uint32_t grid = std::min<uint32_t>(cdiv(to - from, kBlock), 65536);
   hipLaunchKernelGGL(k_iota, dim3(grid), dim3(kBlock), 0, st, h, from, to);
-  return hipGetLastError();
-}
-
-hipError_t launch_reset_meta(Meta* m, hipStream_t st) {
-  hipLaunchKernelGGL(k_reset_meta, dim3(1), dim3(1), 0, st, m);
   return hipGetLastError();
 }
 

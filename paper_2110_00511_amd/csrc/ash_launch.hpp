@@ -53,7 +53,6 @@ hipError_t launch_find_requests(int kd, int g, int w, const TableRef& tb, const 
 hipError_t launch_copy_masked_rows(const uint8_t* mask, const void* src, void* dst, uint64_t rows,
                                    uint32_t row_bytes, uint32_t vec, hipStream_t st);
 hipError_t launch_iota(int32_t* h, uint32_t from, uint32_t to, hipStream_t st);
-hipError_t launch_reset_meta(Meta* m, hipStream_t st);
 // Table words (a multiple of 4) to EMPTY, h[i] = i for i < c, counters reset:
 // one launch.
 hipError_t launch_clear_map(uint32_t* table, size_t n_words, int32_t* heap, uint32_t c, Meta* meta, hipStream_t st);
