@@ -101,21 +101,21 @@ def cpu_model():
 # SHA-256 digests only: traffic is reported as null for any other sources,
 # workload or shape.
 MEASURED_TRAFFIC = {
-    (1, 2, 0.85): {"claim": 2.5071e9, "commit": 0.9230e9, "find": 1.5112e9, "erase_mark": 0.9211e9,
-                   "erase_commit": 0.1805e9},
-    (1, 4, 0.85): {"claim": 2.4555e9, "commit": 0.9230e9, "find": 1.4712e9, "erase_mark": 0.9001e9,
-                   "erase_commit": 0.1802e9},
-    (1, 2, 0.7): {"claim": 2.4860e9, "commit": 0.9231e9, "find": 1.4886e9, "erase_mark": 0.9223e9,
-                  "erase_commit": 0.1803e9},
-    (4, 4, 0.5): {"claim": 2.4237e9, "commit": 0.9226e9, "find": 1.4429e9, "erase_mark": 0.8949e9,
-                  "erase_commit": 0.1803e9},
+    (1, 2, 0.85): {"claim": 2.5077e9, "commit": 0.9239e9, "find": 1.5109e9, "erase_mark": 0.9202e9,
+                   "erase_commit": 0.1806e9},
+    (1, 4, 0.85): {"claim": 2.4555e9, "commit": 0.9234e9, "find": 1.4713e9, "erase_mark": 0.8993e9,
+                   "erase_commit": 0.1803e9},
+    (1, 2, 0.7): {"claim": 2.4859e9, "commit": 0.9231e9, "find": 1.4886e9, "erase_mark": 0.9216e9,
+                  "erase_commit": 0.1802e9},
+    (4, 4, 0.5): {"claim": 2.4237e9, "commit": 0.9234e9, "find": 1.4429e9, "erase_mark": 0.8949e9,
+                  "erase_commit": 0.1804e9},
 }
 # The same for the neighbor search (radius 1 over the 4.8M surface cells,
 # one lane per key, W = 4, max load 0.5, queries in first-appearance order),
 # on the same kernel sources.
 MEASURED_TRAFFIC_NEIGHBORS = 18.53e9
 MEASURED_SOURCES = {
-    "ash_kernels.hip": "6124b26a2a74bc63c6ccaa96145e16c6310573c367bb8ebb8bdbbf2938978845",
+    "ash_kernels.hip": "c7732ebd7ee6e5352dfa1a20592b895ae015cf756efa188568efbcf3980a2bb3",
     "ash_device.hpp": "cf221c03b17cac844c99a3452aaa61c4993f086eb01d64fc70f059fedac8000e",
 }
 
