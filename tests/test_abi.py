@@ -87,6 +87,12 @@ def test_server_and_batched_reject_bad_arguments_on_the_host(lib):
     assert L.ash_server_stats(None, None, None, None) == _lib.ASH_E_INVALID
     assert L.ash_server_destroy(None) == _lib.ASH_E_INVALID
     assert L.ash_server_replay(None, None, 0, None, None, None, None) == _lib.ASH_E_INVALID
+    blocks, reported = ctypes.c_int64(), ctypes.c_int64()
+    for kd, narrow in ((0, 0), (5, 0), (3, 2), (3, -1)):  # key width 1-4, build 0 or 1
+        assert L.ash_batched_grid(kd, narrow, ctypes.byref(blocks), ctypes.byref(reported), None) == _lib.ASH_E_INVALID
+    assert L.ash_batched_grid(3, 1, None, ctypes.byref(reported), None) == _lib.ASH_E_INVALID
+    assert L.ash_batched(None, 2, 1, None) == _lib.ASH_E_INVALID
+    assert L.ash_batched(None, -1, 1, None) == _lib.ASH_E_INVALID
 
 
 def _offsets(L, kind, radius, kd):
