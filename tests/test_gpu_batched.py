@@ -217,23 +217,30 @@ def test_batched_small_grids(ash, sizes):
         assert [m.device_status() for m in maps] == [0] * len(sizes)
 
 
-def test_batched_full_size(ash):
+@pytest.mark.parametrize("grid", ["lane", "stated", "single_op_by_op"])
+def test_batched_full_size(ash, grid):
     """The benchmark's 64 maps (distinct counts log-uniform in [1e3, 1e6],
-    f32x8 values) in one persistent launch with the batched tuner's shapes.
-    Every map is fresh, so results follow from numpy alone: the insert mask
-    marks first occurrences, their indices are ranks, a find returns the rank
-    of its key and the first occurrence's row."""
+    f32x8 values) in one persistent launch with the shapes the benchmark
+    times: the batched tuner's (one lane per key, the narrow build) and the
+    stated grid's (W {4, 8, 16, 32} x g {8, 16, 64} x load {0.5, 0.7, 0.85},
+    the general build), and the single-map tuner's shapes run op by op (the
+    plain path the benchmark compares against).  Every map is fresh, so
+    results follow from numpy alone: the insert mask marks first occurrences, their indices are ranks,
+    a find returns the rank of its key and the first occurrence's row."""
     import synth
     maps_d = synth.batched()
     maps, ops = [], []
+    stated = ([4, 8, 16, 32], [8, 16, 64], [0.5, 0.7, 0.85]) if grid == "stated" else None
+    print(f"case: 64 batched maps, {grid} shapes", flush=True)
     for d in maps_d:
         n = len(d["keys"])
-        tun, _ = ash.autotune(d["capacity"], n, 0.5, value_specs=[(torch.float32, 8)], batched=True)
+        tun, _ = ash.autotune(d["capacity"], n, 0.5, value_specs=[(torch.float32, 8)],
+                              batched=grid != "single_op_by_op", grid=stated)
         m = ash.HashMap(d["capacity"], 3, [(torch.float32, 8)], **tun)
         maps.append(m)
         ops.append(dict(map=m, insert_keys=dev(d["keys"]), insert_values=[dev(d["values"])],
                         find_keys=dev(d["find_keys"]), gather=True))
-    res = ash.batched(ops, fused=True)
+    res = ash.batched(ops, fused=grid != "single_op_by_op")
     torch.cuda.synchronize()
     for d, r, m in zip(maps_d, res, maps):
         keys, vals, fk = d["keys"], d["values"], d["find_keys"]
