@@ -284,6 +284,8 @@ ash_status_t ash_device_status(ash_map_t map, void* stream);
  * out_point_voxel[n], out_voxel_keys[n][3] and out_voxel_counts[n], of which
  * the first *out_n_voxels rows are written.  *out_n_voxels is a host int64.
  * voxel > 0 and finite.  Workspace comes from `allocator` (hipMalloc if NULL).
+ * ASH_E_DEVICE if a HIP call failed or a ranking wait hit its bound (a
+ * broken invariant, not expected; the outputs are then not valid).
  * Synchronizes. */
 ash_status_t ash_voxelize(const float* points, int64_t n, float voxel,
                           int32_t* out_point_voxel, int32_t* out_voxel_keys,

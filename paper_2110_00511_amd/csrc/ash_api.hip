@@ -840,6 +840,7 @@ ash_status_t voxelize_run(const float* points, int64_t n, float voxel, int32_t* 
                   hipMemcpyAsync(&h, meta, sizeof(Meta), hipMemcpyDeviceToHost, st) == hipSuccess &&
                   hipStreamSynchronize(st) == hipSuccess;
   if (!ok) return ASH_E_DEVICE;
+  if (h.status & ash::kStatusScanStall) return ASH_E_DEVICE;  // a look-back wait hit its bound: ids not valid
   if (h.fail) return ASH_E_CAPACITY;
   *out_n_voxels = h.claims;
   return ASH_OK;
